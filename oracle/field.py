@@ -1,0 +1,140 @@
+"""Oracle: demag field, exchange field, energies (test infrastructure only).
+
+* demag (paper eq. (4), with the sign made explicit): H_d,i = -sum_j N(r_i-r_j) M_j,
+  M_j = Ms_j m_j.  ``demag_fft`` is the zero-padded FFT convolution (pad to L,
+  full complex DFT with numpy as the library step, pointwise 3x3 product,
+  inverse DFT, truncate); ``demag_direct`` is the O(N^2) sum over all pairs.
+* exchange (paper eq. (2) with uniform A): h_ex,i = 2A/(mu0 Ms_i) *
+  sum over the 6 neighbours j inside the grid of (m_j - m_i)/d_a^2 (a missing
+  neighbour contributes nothing).  A cell with Ms = 0 is vacuum: it is no
+  neighbour of anything and its own exchange field is 0.
+* energies: E = -(mu0/2) V sum_i Ms_i m_i . h_i for each term, in FP64.
+
+Pins (tests/test_oracle_field.py): direct sum == FFT convolution; naive DFT ==
+numpy.fft; a uniformly magnetised cube/prism block gives the block's Newell
+self term (Aharoni); exchange of a uniform m is 0; the discrete helix closed
+form; the exchange energy pair-sum identity.
+"""
+import numpy as np
+
+from .tensor import wrap_full, PARITY
+
+MU0 = 4e-7 * np.pi
+
+
+def _ms_array(Ms, shape):
+    Ms = np.asarray(Ms, dtype=np.float64)
+    if Ms.ndim == 0:
+        return np.full(shape, float(Ms))
+    assert Ms.shape == tuple(shape)
+    return Ms
+
+
+def naive_dft(x, axis=-1, inverse=False):
+    """X_k = sum_n x_n exp(-+2 pi i (k n mod L) / L), no normalisation; the
+    angle index is reduced in integers before the FP64 cos/sin."""
+    x = np.moveaxis(np.asarray(x, dtype=np.complex128), axis, -1)
+    L = x.shape[-1]
+    kn = (np.arange(L)[:, None] * np.arange(L)[None, :]) % L
+    sgn = 1.0 if inverse else -1.0
+    Wm = np.cos(2 * np.pi * kn / L) + 1j * sgn * np.sin(2 * np.pi * kn / L)
+    return np.moveaxis(x @ Wm.T, -1, axis)
+
+
+def demag_fft(m, Ms, octant, L, fft=np.fft):
+    """Zero-padded FFT convolution: H = -N (*) (Ms m) on the first n cells."""
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz, _ = m.shape
+    Lx, Ly, Lz = (int(v) for v in L)
+    M = m * _ms_array(Ms, (nx, ny, nz))[..., None]
+    Mp = np.zeros((3, Lx, Ly, Lz))
+    for a in range(3):
+        Mp[a, :nx, :ny, :nz] = M[..., a]
+    Mh = fft.fftn(Mp, axes=(1, 2, 3))
+    Nh = fft.fftn(wrap_full(octant, L), axes=(1, 2, 3))
+    idx = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (1, 0): 3, (0, 2): 4, (2, 0): 4, (1, 2): 5, (2, 1): 5}
+    H = np.zeros((nx, ny, nz, 3))
+    for a in range(3):
+        Ha = sum(Nh[idx[(a, b)]] * Mh[b] for b in range(3))
+        H[..., a] = -fft.ifftn(Ha, axes=(0, 1, 2)).real[:nx, :ny, :nz]
+    return H
+
+
+def full_tensor_at_offsets(octant, di, dj, dk):
+    """N at signed offsets (arrays) from the octant using each parity."""
+    out = np.empty(np.broadcast(di, dj, dk).shape + (6,))
+    base = octant[np.abs(di), np.abs(dj), np.abs(dk)]
+    for q in range(6):
+        px, py, pz = PARITY[q]
+        s = np.ones(base.shape[:-1])
+        if px:
+            s = s * np.where(di < 0, -1.0, 1.0)
+        if py:
+            s = s * np.where(dj < 0, -1.0, 1.0)
+        if pz:
+            s = s * np.where(dk < 0, -1.0, 1.0)
+        out[..., q] = base[..., q] * s
+    return out
+
+
+def demag_direct(m, Ms, octant, cells=None):
+    """O(N^2) direct sum H_i = -sum_j N(r_i - r_j) M_j, optionally only at the
+    listed target cells (K,3) -> (K,3); else at every cell -> (nx,ny,nz,3)."""
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz, _ = m.shape
+    M = (m * _ms_array(Ms, (nx, ny, nz))[..., None]).reshape(-1, 3)
+    I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    I, J, K = I.ravel(), J.ravel(), K.ravel()
+    targets = np.stack([I, J, K], 1) if cells is None else np.asarray(cells, dtype=np.int64).reshape(-1, 3)
+    H = np.zeros((targets.shape[0], 3))
+    for t, (i, j, k) in enumerate(targets):
+        Nt = full_tensor_at_offsets(octant, i - I, j - J, k - K)   # (N,6)
+        H[t, 0] = -(Nt[:, 0] * M[:, 0] + Nt[:, 3] * M[:, 1] + Nt[:, 4] * M[:, 2]).sum()
+        H[t, 1] = -(Nt[:, 3] * M[:, 0] + Nt[:, 1] * M[:, 1] + Nt[:, 5] * M[:, 2]).sum()
+        H[t, 2] = -(Nt[:, 4] * M[:, 0] + Nt[:, 5] * M[:, 1] + Nt[:, 2] * M[:, 2]).sum()
+    return H if cells is not None else H.reshape(nx, ny, nz, 3)
+
+
+def exchange_field(m, Ms, A, d):
+    """6-point exchange field with free (Neumann) boundaries and vacuum cells."""
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz, _ = m.shape
+    Msa = _ms_array(Ms, (nx, ny, nz))
+    mag = Msa > 0
+    lap = np.zeros_like(m)
+    for ax in range(3):
+        for s in (+1, -1):
+            nb = np.zeros_like(m)
+            nbmask = np.zeros(mag.shape, dtype=bool)
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            if s == +1:
+                src[ax], dst[ax] = slice(1, None), slice(0, -1)
+            else:
+                src[ax], dst[ax] = slice(0, -1), slice(1, None)
+            nb[tuple(dst)] = m[tuple(src)]
+            nbmask[tuple(dst)] = mag[tuple(src)]
+            lap += np.where(nbmask[..., None], nb - m, 0.0) / d[ax] ** 2
+    pref = np.where(mag, 2.0 * A / (MU0 * np.where(mag, Msa, 1.0)), 0.0)
+    return pref[..., None] * lap
+
+
+def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None):
+    h = np.zeros(np.asarray(m).shape)
+    if demag:
+        h = h + demag_fft(m, Ms, octant, L)
+    if exchange:
+        h = h + exchange_field(m, Ms, A, d)
+    if h_ext is not None:
+        h = h + np.asarray(h_ext, dtype=np.float64)
+    return h
+
+
+def energies(m, Ms, h_d, h_ex, d):
+    """(E_demag, E_exchange) = -(mu0/2) V sum Ms_i m_i . h_i."""
+    m = np.asarray(m, dtype=np.float64)
+    V = float(d[0]) * float(d[1]) * float(d[2])
+    Msa = _ms_array(Ms, m.shape[:3])
+    e_d = -0.5 * MU0 * V * float(np.sum(Msa[..., None] * m * h_d))
+    e_x = -0.5 * MU0 * V * float(np.sum(Msa[..., None] * m * h_ex))
+    return e_d, e_x
