@@ -1,0 +1,205 @@
+/*
+ * mmx.h -- C ABI of the MI355X (gfx950) demag + exchange + LLG hot path.
+ *
+ * The operations follow the paper's statement of the finite-difference
+ * micromagnetic problem (Cheng, Kurokawa, Yuasa, "Magnum.np.distributed"):
+ *   - the LLG equation, eq. (1), advanced here by classic fixed-step RK4;
+ *   - the effective field as a sum of terms (text after eq. (1));
+ *   - the Heisenberg exchange field, eq. (2), with uniform A;
+ *   - the demagnetisation field as the convolution of eq. (4) with the
+ *     cell-averaged Newell tensor, done as a zero-padded FFT convolution
+ *     (Implementation section and Fig. 1), on one GPU, unsharded;
+ *   - the mesh (cell counts and cell size) and the material {Ms, A, alpha}
+ *     of the paper's standard-problem listing.
+ *
+ * Units are SI: metres, A/m, J/m, seconds, gamma in m/(A s).
+ *
+ * Layout of every per-cell vector array (m, h, gradients): C-contiguous
+ * (nx, ny, nz, 3) -- x slowest, the vector component fastest -- in the plan's
+ * precision (float for MM_F32, double for MM_F64).  Per-cell scalars (Ms,
+ * its gradient) are (nx, ny, nz).  Such arrays are DEVICE pointers owned by
+ * the caller; the library never frees them.  A cell with Ms == 0 is vacuum:
+ * it has no moment, no exchange field and is nobody's exchange neighbour.
+ *
+ * Error behaviour: every call returns MM_OK (0) or a negative MM_E* code, and
+ * records a message retrievable with mm_last_error() (thread-local).  All
+ * argument validation happens on the host before anything is enqueued, so a
+ * rejected call has no device side effect.  Work is enqueued asynchronously
+ * on the plan's HIP stream; a device fault surfaces as MM_EHIP at the next
+ * call that synchronises.  No C++ exception crosses this boundary.
+ *
+ * Threading: a plan is not thread-safe; distinct plans are independent.
+ */
+#ifndef MMX_H
+#define MMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MM_OK 0
+#define MM_EINVAL (-1)      /* invalid argument                              */
+#define MM_ENOMEM (-2)      /* device or host allocation failed              */
+#define MM_EHIP (-3)        /* HIP runtime error (includes "no GPU")         */
+#define MM_ESTATE (-4)      /* call not valid in the plan's current state    */
+#define MM_ENOTSUP (-5)     /* valid request this build does not support     */
+
+/* precision of a plan: the type of m, h, Ms and of the FFT arithmetic */
+#define MM_F32 1
+#define MM_F64 2
+
+/* field terms for h_eff / h_eff_adjoint */
+#define MM_DEMAG 1u
+#define MM_EXCHANGE 2u
+
+/* llg_step flags */
+#define MM_NO_RENORM 1u     /* skip the end-of-step normalisation m <- m/|m| */
+#define MM_NO_GRAPH 2u      /* enqueue kernels directly, no HIP graph replay */
+
+typedef struct mm_plan mm_plan;
+typedef struct mm_batch mm_batch;
+
+/* Plan options.  Fill with mm_plan_opts_default() and change what you need. */
+typedef struct mm_plan_opts {
+    double far_radius;  /* P: the tensor uses Newell's closed form for offsets
+                           |r|_2 <= P*max(cell) and a 27-node moment-matched
+                           dipole quadrature beyond; P <= 0: Newell everywhere.
+                           Default 16. */
+    int64_t L[3];       /* zero-padded FFT length per axis; 0 = default (1 if
+                           n == 1, 2n if n is 7-smooth, else the smallest
+                           7-smooth length >= 2n-1).  A given L must be
+                           7-smooth and >= 2n-1 (any such L gives the same
+                           linear convolution). */
+    int autotune;       /* 0: default tile widths; 1: time the candidate tile
+                           widths of every pass at plan creation and keep the
+                           fastest. */
+    int reserved;
+} mm_plan_opts;
+
+int mm_plan_opts_default(mm_plan_opts *opts);
+
+/*
+ * demag_tensor_init -- create a plan for a grid and compute its demag tensor.
+ * Follows Mesh(n, dx) + DemagField() of the paper's listing; the tensor is
+ * the cell-averaged kernel of eq. (4) (Newell).
+ *   out        receives the plan (set to NULL on failure)
+ *   grid[3]    cells per axis nx, ny, nz >= 1 (host array)
+ *   cell[3]    cell size dx, dy, dz > 0 in metres (host array)
+ *   precision  MM_F32 or MM_F64; the tensor is always evaluated and
+ *              transformed in FP64 and rounded once to this precision
+ *   hip_stream hipStream_t the plan enqueues on (NULL = default stream)
+ *   opts       nullable
+ * Synchronises the stream before returning.  The plan owns its device memory
+ * (tensor spectrum, FFT workspace, twiddles) until mm_plan_destroy.
+ */
+int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3], int precision,
+                      void *hip_stream, const mm_plan_opts *opts);
+
+int mm_plan_destroy(mm_plan *plan);
+int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
+
+/* Padded lengths, device bytes held, and tile widths in use (each nullable). */
+int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
+
+/*
+ * h_eff -- effective field h = [H_demag] + [H_exchange] in A/m (eqs. (2), (4)).
+ *   m          device (nx,ny,nz,3) unit vectors
+ *   Ms         device per-cell (nx,ny,nz) saturation magnetisation, or NULL
+ *              to use Ms_scalar for every cell
+ *   A          exchange stiffness (J/m), uniform
+ *   h_out      device (nx,ny,nz,3); must not alias m
+ *   terms      MM_DEMAG | MM_EXCHANGE (non-zero)
+ *   energy_out host double[2] or NULL: receives (E_demag, E_exchange) in J,
+ *              E = -(mu0/2) V sum Ms m.h per term, accumulated in FP64 with a
+ *              fixed-order reduction; non-NULL makes the call synchronous.
+ */
+int h_eff(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A, void *h_out,
+          unsigned terms, double *energy_out);
+
+/*
+ * llg_step -- n_steps classic RK4 steps of eq. (1) for unit m:
+ *   dm/dt = -gamma/(1+alpha^2) [ m x h + alpha m x (m x h) ],
+ *   h = H_demag + H_exchange (+ h_ext).  Follows llg.step(state, dt).
+ *   m          device (nx,ny,nz,3), read and overwritten with m(t + n dt)
+ *   Ms, Ms_scalar, A  as in h_eff
+ *   alpha >= 0, gamma > 0, dt > 0, n_steps >= 0
+ *   h_ext      host double[3] uniform applied field (A/m) or NULL
+ *   flags      MM_NO_RENORM, MM_NO_GRAPH
+ * Stage inputs are not normalised; the step ends with m <- m/|m| unless
+ * MM_NO_RENORM.  The first call with a given argument set captures one step
+ * in a HIP graph that later calls replay.  Asynchronous.
+ */
+int llg_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A, double alpha,
+             double gamma, double dt, int n_steps, const double h_ext[3], unsigned flags);
+
+/*
+ * h_eff_adjoint -- vector-Jacobian product of h_eff (reverse-mode derivative
+ * used for inverse problems, paper Introduction).  For the cotangent g_h:
+ *   g_m  = Ms H_demag(g_h) + Lap(c g_h)          (c = 2A/(mu0 Ms))
+ *   g_Ms = m . H_demag(g_h) - g_h . H_exchange(m) / Ms
+ * The demag operator is self-adjoint, so it runs the same FFT pipeline and
+ * tensor on g_h.  g_m: device (nx,ny,nz,3), overwritten.  g_Ms: device
+ * (nx,ny,nz) or NULL, overwritten (per cell, also for a scalar Ms).
+ */
+int h_eff_adjoint(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A,
+                  const void *g_h, void *g_m, void *g_Ms, unsigned terms);
+
+/*
+ * llg_step_adjoint -- reverse of ONE llg_step (RK4 + normalisation) at state m.
+ *   g        device (nx,ny,nz,3): in = cotangent of m(t+dt), out = cotangent
+ *            of m(t)
+ *   g_Ms     device (nx,ny,nz) accumulated (+=) with d<g, m(t+dt)>/dMs, or NULL
+ * Other arguments as in llg_step.  Recomputes the four stages internally.
+ */
+int llg_step_adjoint(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A,
+                     double alpha, double gamma, double dt, const double h_ext[3], unsigned flags,
+                     void *g, void *g_Ms);
+
+/*
+ * Tensor test hooks.  host_octant is the real-space tensor N(i,j,k) for
+ * 0 <= i < nx, 0 <= j < ny, 0 <= k < nz as a HOST double array
+ * (nx,ny,nz,6), components xx,yy,zz,xy,xz,yz.
+ *   get: evaluates the GPU's FP64 real-space tensor and copies it out.
+ *   set: replaces the plan's tensor by the transform of the given octant
+ *        (same FP64 transform and rounding as demag_tensor_init).
+ * mm_demag_spectrum_get copies the stored, pre-scaled spectrum
+ * -N^(k)/(Lx Ly Lz) for 0 <= kx <= Lx/2, 0 <= ky <= Ly/2, 0 <= kz <= Lz/2
+ * into a HOST double array (Lx/2+1, Ly/2+1, Lz/2+1, 6).
+ * All three synchronise.
+ */
+int mm_demag_tensor_get(mm_plan *plan, double *host_octant);
+int mm_demag_tensor_set(mm_plan *plan, const double *host_octant);
+int mm_demag_spectrum_get(mm_plan *plan, double *host_spectrum);
+
+/*
+ * Batched parameter sweep: `count` independent geometries, each with its own
+ * grid, padded lengths, tensor and scalar Ms, advanced together; every pass
+ * is ONE grouped launch over a ragged table of tiles, and one step of all
+ * geometries is captured in one HIP graph.
+ *   grids[count][3], cells[count][3]: host arrays
+ *   m_ptrs[count]: host array of device pointers, each (nx,ny,nz,3)
+ *   h_ptrs[count]: host array of device pointers for mm_batch_h_eff
+ *   Ms[count]: host array of per-geometry scalar Ms
+ */
+int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const double (*cells)[3],
+                    int precision, void *hip_stream, const mm_plan_opts *opts);
+int mm_batch_h_eff(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, void *const *h_ptrs,
+                   unsigned terms);
+int mm_batch_llg_step(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, double alpha,
+                      double gamma, double dt, int n_steps, unsigned flags);
+int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes);
+int mm_batch_destroy(mm_batch *b);
+
+/* Message for a status code (static storage). */
+const char *mm_strerror(int status);
+/* Detail of the last error on this thread (static thread-local storage). */
+const char *mm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MMX_H */

@@ -1,0 +1,88 @@
+"""ctypes binding of libmmx.so: argument marshalling only.
+
+Every computation runs in the HIP library; this module checks tensor shapes,
+dtypes and devices, passes raw device pointers and the current torch stream,
+and turns status codes into exceptions.  There is no CPU fallback: if the
+library is missing, importing this module raises.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libmmx.so")
+
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_EHIP, MM_ESTATE, MM_ENOTSUP = 0, -1, -2, -3, -4, -5
+MM_F32, MM_F64 = 1, 2
+MM_DEMAG, MM_EXCHANGE = 1, 2
+MM_NO_RENORM, MM_NO_GRAPH = 1, 2
+
+# Exported names (kept in sync with include/mmx.h; a CPU test checks both).
+EXPORTS = [
+    "mm_plan_opts_default", "demag_tensor_init", "mm_plan_destroy", "mm_plan_set_stream", "mm_plan_info",
+    "h_eff", "llg_step", "h_eff_adjoint", "llg_step_adjoint",
+    "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
+    "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_info", "mm_batch_destroy",
+    "mm_strerror", "mm_last_error",
+]
+
+
+class MMError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (msg, code, _lib.mm_last_error().decode() if _lib else ""))
+        self.code = code
+
+
+class PlanOpts(ctypes.Structure):
+    _fields_ = [("far_radius", ctypes.c_double), ("L", ctypes.c_int64 * 3),
+                ("autotune", ctypes.c_int), ("reserved", ctypes.c_int)]
+
+
+def _load():
+    if not os.path.exists(LIBPATH):
+        raise ImportError("libmmx.so is not built (%s); run __graft_entry__.build() or "
+                          "python paper_2606_01114_amd/build.py" % LIBPATH)
+    L = ctypes.CDLL(LIBPATH)
+    vp, i64p, dp, ci, cu, cd = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
+                                ctypes.c_int, ctypes.c_uint, ctypes.c_double)
+    sig = {
+        "mm_plan_opts_default": [ctypes.POINTER(PlanOpts)],
+        "demag_tensor_init": [ctypes.POINTER(vp), i64p, dp, ci, vp, ctypes.POINTER(PlanOpts)],
+        "mm_plan_destroy": [vp],
+        "mm_plan_set_stream": [vp, vp],
+        "mm_plan_info": [vp, i64p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)],
+        "h_eff": [vp, vp, vp, cd, cd, vp, cu, dp],
+        "llg_step": [vp, vp, vp, cd, cd, cd, cd, cd, ci, dp, cu],
+        "h_eff_adjoint": [vp, vp, vp, cd, cd, vp, vp, vp, cu],
+        "llg_step_adjoint": [vp, vp, vp, cd, cd, cd, cd, cd, dp, cu, vp, vp],
+        "mm_demag_tensor_get": [vp, dp],
+        "mm_demag_tensor_set": [vp, dp],
+        "mm_demag_spectrum_get": [vp, dp],
+        "mm_batch_create": [ctypes.POINTER(vp), ci, i64p, dp, ci, vp, ctypes.POINTER(PlanOpts)],
+        "mm_batch_h_eff": [vp, ctypes.POINTER(vp), dp, cd, ctypes.POINTER(vp), cu],
+        "mm_batch_llg_step": [vp, ctypes.POINTER(vp), dp, cd, cd, cd, cd, ci, cu],
+        "mm_batch_info": [vp, i64p, ctypes.POINTER(ctypes.c_size_t)],
+        "mm_batch_destroy": [vp],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ctypes.c_int
+    L.mm_strerror.argtypes = [ctypes.c_int]
+    L.mm_strerror.restype = ctypes.c_char_p
+    L.mm_last_error.argtypes = []
+    L.mm_last_error.restype = ctypes.c_char_p
+    return L
+
+
+_lib = None
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def check(rc):
+    if rc != MM_OK:
+        raise MMError(rc, _lib.mm_strerror(rc).decode())
+    return rc

@@ -1,0 +1,267 @@
+"""Plans, batches and autograd wrappers over the C ABI (marshalling only)."""
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import MM_DEMAG, MM_EXCHANGE, MM_F32, MM_F64, MM_NO_GRAPH, MM_NO_RENORM, PlanOpts, check
+
+_DT = {MM_F32: torch.float32, MM_F64: torch.float64}
+
+
+def _prec(precision):
+    if precision in (MM_F32, "f32", "float32", torch.float32):
+        return MM_F32
+    if precision in (MM_F64, "f64", "float64", torch.float64):
+        return MM_F64
+    raise ValueError("precision must be f32 or f64")
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else None
+
+
+class DemagPlan:
+    """One geometry: grid (nx,ny,nz), cell (dx,dy,dz) in metres, FP32 or FP64.
+    Creating it computes the Newell tensor spectrum on the GPU (FP64)."""
+
+    def __init__(self, grid, cell, precision="f32", far_radius=16.0, L=None, autotune=False):
+        self.grid = tuple(int(v) for v in grid)
+        self.cell = tuple(float(v) for v in cell)
+        self.prec = _prec(precision)
+        self.dtype = _DT[self.prec]
+        opts = PlanOpts()
+        check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
+        opts.far_radius = float(far_radius)
+        if L is not None:
+            for a in range(3):
+                opts.L[a] = int(L[a])
+        opts.autotune = 1 if autotune else 0
+        g = (ctypes.c_int64 * 3)(*self.grid)
+        c = (ctypes.c_double * 3)(*self.cell)
+        self._h = ctypes.c_void_p()
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        check(_lib.lib().demag_tensor_init(ctypes.byref(self._h), g, c, self.prec, _stream(), ctypes.byref(opts)))
+
+    # -- helpers --------------------------------------------------------------
+    def _vec(self, t, name):
+        if not isinstance(t, torch.Tensor) or t.device.type != "cuda" or t.dtype != self.dtype:
+            raise TypeError("%s must be a CUDA %s tensor" % (name, self.dtype))
+        if tuple(t.shape) != self.grid + (3,) or not t.is_contiguous():
+            raise ValueError("%s must be contiguous with shape %s" % (name, self.grid + (3,)))
+        return t
+
+    def _ms(self, Ms):
+        if isinstance(Ms, torch.Tensor):
+            if Ms.device.type != "cuda" or Ms.dtype != self.dtype or tuple(Ms.shape) != self.grid or not Ms.is_contiguous():
+                raise ValueError("per-cell Ms must be a contiguous CUDA %s tensor of shape %s" % (self.dtype, self.grid))
+            return Ms, 0.0
+        return None, float(Ms)
+
+    def _sync_stream(self):
+        check(_lib.lib().mm_plan_set_stream(self._h, _stream()))
+
+    # -- API ------------------------------------------------------------------
+    def info(self):
+        L = (ctypes.c_int64 * 3)()
+        b = ctypes.c_size_t()
+        t = (ctypes.c_int * 5)()
+        check(_lib.lib().mm_plan_info(self._h, L, ctypes.byref(b), t))
+        return {"L": tuple(L), "device_bytes": b.value, "tiles": tuple(t)}
+
+    def h_eff(self, m, Ms, A, out=None, terms=MM_DEMAG | MM_EXCHANGE, energy=False):
+        self._vec(m, "m")
+        Mst, Mss = self._ms(Ms)
+        if out is None:
+            out = torch.empty_like(m)
+        self._vec(out, "out")
+        self._sync_stream()
+        E = (ctypes.c_double * 2)() if energy else None
+        check(_lib.lib().h_eff(self._h, _ptr(m), _ptr(Mst), Mss, float(A), _ptr(out), int(terms), E))
+        return (out, (E[0], E[1])) if energy else out
+
+    def llg_step(self, m, Ms, A, alpha, gamma, dt, n_steps=1, h_ext=None, renorm=True, graph=True):
+        self._vec(m, "m")
+        Mst, Mss = self._ms(Ms)
+        self._sync_stream()
+        he = (ctypes.c_double * 3)(*[float(v) for v in h_ext]) if h_ext is not None else None
+        flags = (0 if renorm else MM_NO_RENORM) | (0 if graph else MM_NO_GRAPH)
+        check(_lib.lib().llg_step(self._h, _ptr(m), _ptr(Mst), Mss, float(A), float(alpha), float(gamma), float(dt),
+                                  int(n_steps), he, flags))
+        return m
+
+    def h_eff_adjoint(self, m, Ms, A, g_h, terms=MM_DEMAG | MM_EXCHANGE, want_Ms=True):
+        self._vec(m, "m")
+        self._vec(g_h, "g_h")
+        Mst, Mss = self._ms(Ms)
+        g_m = torch.empty_like(m)
+        g_Ms = torch.empty(self.grid, dtype=self.dtype, device=m.device) if want_Ms else None
+        self._sync_stream()
+        check(_lib.lib().h_eff_adjoint(self._h, _ptr(m), _ptr(Mst), Mss, float(A), _ptr(g_h), _ptr(g_m), _ptr(g_Ms),
+                                       int(terms)))
+        return g_m, g_Ms
+
+    def llg_step_adjoint(self, m, Ms, A, alpha, gamma, dt, g, g_Ms=None, h_ext=None, renorm=True):
+        """In place: g <- cotangent of m(t) from that of m(t+dt); g_Ms += ..."""
+        self._vec(m, "m")
+        self._vec(g, "g")
+        Mst, Mss = self._ms(Ms)
+        self._sync_stream()
+        he = (ctypes.c_double * 3)(*[float(v) for v in h_ext]) if h_ext is not None else None
+        flags = 0 if renorm else MM_NO_RENORM
+        check(_lib.lib().llg_step_adjoint(self._h, _ptr(m), _ptr(Mst), Mss, float(A), float(alpha), float(gamma),
+                                          float(dt), he, flags, _ptr(g), _ptr(g_Ms)))
+        return g
+
+    def tensor_get(self):
+        import numpy as np
+        out = np.zeros(self.grid + (6,))
+        check(_lib.lib().mm_demag_tensor_get(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def tensor_set(self, octant):
+        import numpy as np
+        a = np.ascontiguousarray(octant, dtype=np.float64)
+        if a.shape != self.grid + (6,):
+            raise ValueError("octant must have shape %s" % (self.grid + (6,),))
+        check(_lib.lib().mm_demag_tensor_set(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def spectrum_get(self):
+        import numpy as np
+        L = self.info()["L"]
+        out = np.zeros((L[0] // 2 + 1, L[1] // 2 + 1, L[2] // 2 + 1, 6))
+        check(_lib.lib().mm_demag_spectrum_get(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().mm_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many independent geometries advanced by grouped launches (one HIP graph
+    per step of all of them)."""
+
+    def __init__(self, grids, cells, precision="f32", far_radius=16.0):
+        self.grids = [tuple(int(v) for v in g) for g in grids]
+        self.cells = [tuple(float(v) for v in c) for c in cells]
+        self.prec = _prec(precision)
+        self.dtype = _DT[self.prec]
+        n = len(self.grids)
+        G = (ctypes.c_int64 * (3 * n))(*[v for g in self.grids for v in g])
+        C = (ctypes.c_double * (3 * n))(*[v for c in self.cells for v in c])
+        opts = PlanOpts()
+        check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
+        opts.far_radius = float(far_radius)
+        self._h = ctypes.c_void_p()
+        check(_lib.lib().mm_batch_create(ctypes.byref(self._h), n, G, C, self.prec, _stream(), ctypes.byref(opts)))
+
+    def _ptrs(self, ts):
+        for t, g in zip(ts, self.grids):
+            if t.dtype != self.dtype or tuple(t.shape) != g + (3,) or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError("batch tensors must be contiguous CUDA %s of shape (nx,ny,nz,3)" % self.dtype)
+        return (ctypes.c_void_p * len(ts))(*[t.data_ptr() for t in ts])
+
+    def info(self):
+        n = ctypes.c_int64()
+        b = ctypes.c_size_t()
+        check(_lib.lib().mm_batch_info(self._h, ctypes.byref(n), ctypes.byref(b)))
+        return {"total_cells": n.value, "device_bytes": b.value}
+
+    def h_eff(self, ms, Ms, A, outs=None, terms=MM_DEMAG | MM_EXCHANGE):
+        if outs is None:
+            outs = [torch.empty_like(m) for m in ms]
+        M = (ctypes.c_double * len(ms))(*[float(v) for v in Ms])
+        check(_lib.lib().mm_batch_h_eff(self._h, self._ptrs(ms), M, float(A), self._ptrs(outs), int(terms)))
+        return outs
+
+    def llg_step(self, ms, Ms, A, alpha, gamma, dt, n_steps=1, renorm=True, graph=True):
+        M = (ctypes.c_double * len(ms))(*[float(v) for v in Ms])
+        flags = (0 if renorm else MM_NO_RENORM) | (0 if graph else MM_NO_GRAPH)
+        check(_lib.lib().mm_batch_llg_step(self._h, self._ptrs(ms), M, float(A), float(alpha), float(gamma), float(dt),
+                                           int(n_steps), flags))
+        return ms
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib.lib().mm_batch_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class HEff(torch.autograd.Function):
+    """h = h_eff(m, Ms) with its backward through the hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, m, Ms, plan, A, terms=MM_DEMAG | MM_EXCHANGE):
+        h = plan.h_eff(m.contiguous(), Ms.contiguous() if isinstance(Ms, torch.Tensor) else Ms, A, terms=terms)
+        ctx.save_for_backward(m, Ms if isinstance(Ms, torch.Tensor) else None)
+        ctx.plan, ctx.A, ctx.terms, ctx.Ms_scalar = plan, A, terms, None if isinstance(Ms, torch.Tensor) else Ms
+        return h
+
+    @staticmethod
+    def backward(ctx, g):
+        m, Ms = ctx.saved_tensors
+        Msv = Ms if Ms is not None else ctx.Ms_scalar
+        g_m, g_Ms = ctx.plan.h_eff_adjoint(m, Msv, ctx.A, g.contiguous(), terms=ctx.terms, want_Ms=Ms is not None)
+        return g_m, g_Ms, None, None, None
+
+
+class _LLGRun(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, m0, Ms, plan, A, alpha, gamma, dt, n_steps, every):
+        m = m0.detach().clone()
+        ckpts = []
+        done = 0
+        while done < n_steps:
+            k = min(every, n_steps - done)
+            ckpts.append((done, m.clone()))
+            plan.llg_step(m, Ms, A, alpha, gamma, dt, n_steps=k)
+            done += k
+        ctx.save_for_backward(Ms)
+        ctx.ckpts, ctx.args = ckpts, (plan, A, alpha, gamma, dt, n_steps)
+        return m
+
+    @staticmethod
+    def backward(ctx, g_out):
+        (Ms,) = ctx.saved_tensors
+        plan, A, alpha, gamma, dt, n_steps = ctx.args
+        g = g_out.detach().contiguous().clone()
+        gMs = torch.zeros_like(Ms)
+        for start, ck in reversed(ctx.ckpts):
+            k = min(n_steps - start, n_steps if not ctx.ckpts else n_steps)
+            # states of this segment, recomputed from its checkpoint
+            nxt = [s for s, _ in ctx.ckpts if s > start]
+            end = nxt[0] if nxt else n_steps
+            states = [ck.clone()]
+            for _ in range(end - start - 1):
+                s = states[-1].clone()
+                plan.llg_step(s, Ms, A, alpha, gamma, dt, n_steps=1)
+                states.append(s)
+            for s in reversed(states):
+                plan.llg_step_adjoint(s, Ms, A, alpha, gamma, dt, g, gMs)
+            del k
+        return g, gMs, None, None, None, None, None, None, None
+
+
+def llg_run_checkpointed(plan, m0, Ms, A, alpha, gamma, dt, n_steps, every=20):
+    """m after n_steps RK4 steps, differentiable w.r.t. m0 and per-cell Ms;
+    the backward pass recomputes each segment of `every` steps from its
+    checkpoint and reverses it with llg_step_adjoint."""
+    return _LLGRun.apply(m0, Ms, plan, A, alpha, gamma, dt, int(n_steps), int(every))

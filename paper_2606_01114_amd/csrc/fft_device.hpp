@@ -1,0 +1,258 @@
+// Device-side FFT building blocks for gfx950: complex helpers, small radix
+// DFTs held in registers, and one Stockham auto-sort stage over lines that
+// live in LDS.  Radices 2,3,4,5,7,8,16 cover every 7-smooth length.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mmx {
+
+template <typename T> struct cplx_of;
+template <> struct cplx_of<float> { using type = float2; };
+template <> struct cplx_of<double> { using type = double2; };
+template <typename T> using cplx = typename cplx_of<T>::type;
+
+template <typename C> __device__ __forceinline__ C cmake(decltype(C().x) a, decltype(C().x) b) { C r; r.x = a; r.y = b; return r; }
+template <typename C> __device__ __forceinline__ C cadd(C a, C b) { return cmake<C>(a.x + b.x, a.y + b.y); }
+template <typename C> __device__ __forceinline__ C csub(C a, C b) { return cmake<C>(a.x - b.x, a.y - b.y); }
+template <typename C> __device__ __forceinline__ C cmul(C a, C b) { return cmake<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x); }
+template <typename C> __device__ __forceinline__ C cconj(C a) { return cmake<C>(a.x, -a.y); }
+template <typename C> __device__ __forceinline__ C cscale(C a, decltype(C().x) s) { return cmake<C>(a.x * s, a.y * s); }
+// multiply by DIR*i  (DIR = -1 forward, +1 inverse)
+template <int DIR, typename C> __device__ __forceinline__ C cmul_i(C a) {
+    return DIR < 0 ? cmake<C>(a.y, -a.x) : cmake<C>(-a.y, a.x);
+}
+// multiply by cos(t) + DIR*i*sin(t) given c = cos, s = sin
+template <int DIR, typename C> __device__ __forceinline__ C crot(C a, decltype(C().x) c, decltype(C().x) s) {
+    const decltype(C().x) ss = DIR < 0 ? -s : s;
+    return cmake<C>(a.x * c - a.y * ss, a.x * ss + a.y * c);
+}
+
+// ---- small DFTs: X_k = sum_n x_n exp(DIR 2 pi i n k / R), in place -------
+template <int R, int DIR, typename C> struct Dft;
+
+template <int DIR, typename C> struct Dft<2, DIR, C> {
+    static __device__ __forceinline__ void run(C *v) { C t = v[0]; v[0] = cadd(t, v[1]); v[1] = csub(t, v[1]); }
+};
+
+template <int DIR, typename C> struct Dft<4, DIR, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        C t2 = cadd(v[1], v[3]), t3 = cmul_i<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2); v[2] = csub(t0, t2);
+        v[1] = cadd(t1, t3); v[3] = csub(t1, t3);
+    }
+};
+
+template <int DIR, typename C> struct Dft<8, DIR, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        using R = decltype(C().x);
+        const R h = R(0.70710678118654752440084436210484904);
+        C e[4] = {v[0], v[2], v[4], v[6]};
+        C o[4] = {v[1], v[3], v[5], v[7]};
+        Dft<4, DIR, C>::run(e);
+        Dft<4, DIR, C>::run(o);
+        o[1] = crot<DIR>(o[1], h, h);
+        o[2] = cmul_i<DIR>(o[2]);
+        o[3] = crot<DIR>(o[3], -h, h);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) { v[k] = cadd(e[k], o[k]); v[k + 4] = csub(e[k], o[k]); }
+    }
+};
+
+template <int DIR, typename C> struct Dft<16, DIR, C> {
+    // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2
+    static __device__ __forceinline__ void run(C *v) {
+        using R = decltype(C().x);
+        const R c1 = R(0.92387953251128675612818318939678829), s1 = R(0.38268343236508977172845998403039887);
+        const R h = R(0.70710678118654752440084436210484904);
+        C y[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+            C t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+            Dft<4, DIR, C>::run(t);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+        }
+        // twiddles W16^(n2 k1)
+        y[1][1] = crot<DIR>(y[1][1], c1, s1);
+        y[1][2] = crot<DIR>(y[1][2], h, h);
+        y[1][3] = crot<DIR>(y[1][3], s1, c1);
+        y[2][1] = crot<DIR>(y[2][1], h, h);
+        y[2][2] = cmul_i<DIR>(y[2][2]);
+        y[2][3] = crot<DIR>(y[2][3], -h, h);
+        y[3][1] = crot<DIR>(y[3][1], s1, c1);
+        y[3][2] = crot<DIR>(y[3][2], -h, h);
+        y[3][3] = crot<DIR>(y[3][3], -c1, -s1);
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            C t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<4, DIR, C>::run(t);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
+
+template <int DIR, typename C> struct Dft<3, DIR, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        using R = decltype(C().x);
+        const R s3 = R(0.86602540378443864676372317075293618);
+        C s = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+        C a = cmake<C>(v[0].x - R(0.5) * s.x, v[0].y - R(0.5) * s.y);
+        C b = cscale(cmul_i<DIR>(d), s3);
+        v[0] = cadd(v[0], s);
+        v[1] = cadd(a, b);
+        v[2] = csub(a, b);
+    }
+};
+
+// odd prime R: X_k = x0 + sum_{n=1}^{(R-1)/2} [ (x_n + x_{R-n}) cos(2pi nk/R)
+//                                      + DIR i (x_n - x_{R-n}) sin(2pi nk/R) ]
+template <int R_, int DIR, typename C> struct DftOddPrime {
+    static __device__ __forceinline__ void run(C *v, const double *cs, const double *sn) {
+        using R = decltype(C().x);
+        constexpr int H = (R_ - 1) / 2;
+        C p[H], q[H];
+#pragma unroll
+        for (int n = 1; n <= H; ++n) { p[n - 1] = cadd(v[n], v[R_ - n]); q[n - 1] = cmul_i<DIR>(csub(v[n], v[R_ - n])); }
+        C out[R_];
+        C s0 = v[0];
+#pragma unroll
+        for (int n = 0; n < H; ++n) s0 = cadd(s0, p[n]);
+        out[0] = s0;
+#pragma unroll
+        for (int k = 1; k <= H; ++k) {
+            C a = v[0], b = cmake<C>(R(0), R(0));
+#pragma unroll
+            for (int n = 1; n <= H; ++n) {
+                const int idx = (n * k) % R_;
+                const R c = R(cs[idx]), s = R(sn[idx]);
+                a = cmake<C>(a.x + p[n - 1].x * c, a.y + p[n - 1].y * c);
+                b = cmake<C>(b.x + q[n - 1].x * s, b.y + q[n - 1].y * s);
+            }
+            out[k] = cadd(a, b);
+            out[R_ - k] = csub(a, b);
+        }
+#pragma unroll
+        for (int k = 0; k < R_; ++k) v[k] = out[k];
+    }
+};
+
+template <int DIR, typename C> struct Dft<5, DIR, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        const double cs[5] = {1.0, 0.30901699437494742410229341718281906, -0.80901699437494742410229341718281906,
+                              -0.80901699437494742410229341718281906, 0.30901699437494742410229341718281906};
+        const double sn[5] = {0.0, 0.95105651629515357211643933337938214, 0.58778525229247312916870595463907277,
+                              -0.58778525229247312916870595463907277, -0.95105651629515357211643933337938214};
+        DftOddPrime<5, DIR, C>::run(v, cs, sn);
+    }
+};
+
+template <int DIR, typename C> struct Dft<7, DIR, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        const double cs[7] = {1.0, 0.62348980185873353052500488400423981, -0.22252093395631440428890256449679476,
+                              -0.90096886790241912623610231950744505, -0.90096886790241912623610231950744505,
+                              -0.22252093395631440428890256449679476, 0.62348980185873353052500488400423981};
+        const double sn[7] = {0.0, 0.78183148246802980870844452667405775, 0.97492791218182360701813168299393122,
+                              0.43388373911755812047576833284835875, -0.43388373911755812047576833284835875,
+                              -0.97492791218182360701813168299393122, -0.78183148246802980870844452667405775};
+        DftOddPrime<7, DIR, C>::run(v, cs, sn);
+    }
+};
+
+// ---- one FFT length: factorisation + twiddle-table offsets ---------------
+constexpr int kMaxStages = 12;
+struct FftDesc {
+    int L;                      // transform length
+    int nst;                    // number of stages (0 when L == 1)
+    int rad[kMaxStages];        // radix of each stage
+    int twoff[kMaxStages];      // offset (complex units) of the stage table
+};
+
+// Per-thread register budget: each thread holds at most kE complex values per
+// stage, i.e. floor(kE / R) butterflies of radix R.
+constexpr int kE = 16;
+
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t G) {
+    // Workgroups are dispatched round-robin over the 8 XCDs; give each XCD a
+    // contiguous run of tiles so neighbouring tiles share that XCD's L2.
+    const uint32_t q = G >> 3, r = G & 7u, x = b & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// One Stockham stage of radix R over `nlines` lines (line l at buf + l*pitch,
+// length L, natural order in and out).  Ns = product of earlier radices.
+// tw: forward table for this stage, tw[k*(R-1) + r-1] = exp(-2 pi i k r/(Ns R)).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void fft_stage(cplx<T> *buf, int nlines, int pitch, int L, int Ns,
+                                          const cplx<T> *__restrict__ tw, int tid, int nthr) {
+    using C = cplx<T>;
+    constexpr int U = kE / R;
+    C v[U][R];
+    const int nb = L / R;
+    const int total = nlines * nb;
+    int jj[U], ll[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * nthr;
+        ll[u] = -1;
+        if (b < total) {
+            const int line = b / nb, j = b - line * nb;
+            ll[u] = line;
+            jj[u] = j;
+            const C *src = buf + line * pitch;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = src[j + r * nb];
+            const int k = j % Ns;
+            if (Ns > 1) {
+                const C *t = tw + k * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = t[r - 1];
+                    if (DIR > 0) w = cconj(w);
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            }
+            Dft<R, DIR, C>::run(v[u]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (ll[u] >= 0) {
+            const int j = jj[u];
+            const int k = j % Ns;
+            const int d = (j / Ns) * Ns * R + k;
+            C *dst = buf + ll[u] * pitch;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[d + r * Ns] = v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Full transform of `nlines` LDS lines.  Natural order in, natural order out,
+// unnormalised.  Ends with a barrier.
+template <typename T, int DIR>
+__device__ void lds_fft(cplx<T> *buf, int nlines, int pitch, const FftDesc &f, const cplx<T> *__restrict__ tw,
+                        int tid, int nthr) {
+    int Ns = 1;
+    for (int s = 0; s < f.nst; ++s) {
+        const int R = f.rad[s];
+        const cplx<T> *t = tw + f.twoff[s];
+        switch (R) {
+        case 16: fft_stage<T, 16, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        case 8: fft_stage<T, 8, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        case 4: fft_stage<T, 4, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        case 2: fft_stage<T, 2, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        case 3: fft_stage<T, 3, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        case 5: fft_stage<T, 5, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        case 7: fft_stage<T, 7, DIR>(buf, nlines, pitch, f.L, Ns, t, tid, nthr); break;
+        default: break;
+        }
+        Ns *= R;
+    }
+}
+
+}  // namespace mmx

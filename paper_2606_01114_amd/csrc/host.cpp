@@ -1,0 +1,1051 @@
+// Host side of the library: argument validation, plans (FFT factorisation,
+// twiddle tables, tile choice, workspace), the C ABI declared in mmx.h, and
+// HIP-graph capture of the LLG step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/mmx.h"
+#include "kernels.hpp"
+#include "passes.hpp"
+
+using namespace mmx;
+
+namespace {
+
+thread_local std::string g_last = "";
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last = buf;
+    return code;
+}
+
+#define HIPCK(expr)                                                                             \
+    do {                                                                                        \
+        hipError_t e_ = (expr);                                                                 \
+        if (e_ != hipSuccess) return fail(MM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+const double kMu0 = 4e-7 * M_PI;
+const size_t kLdsMax = 160 * 1024;        // LDS per workgroup on gfx950
+const size_t kLdsTarget = 80 * 1024;      // default budget: two workgroups per CU
+
+bool is_7smooth(int64_t v) {
+    if (v < 1) return false;
+    for (int p : {2, 3, 5, 7})
+        while (v % p == 0) v /= p;
+    return v == 1;
+}
+
+int64_t default_L(int64_t n) {
+    if (n == 1) return 1;
+    if (is_7smooth(n)) return 2 * n;
+    int64_t L = 2 * n - 1;
+    while (!is_7smooth(L)) ++L;
+    return L;
+}
+
+// radices for a 7-smooth length (power-of-two part as 16s with an 8/4/2 tail)
+std::vector<int> factorize(int L) {
+    std::vector<int> r;
+    int p2 = 0;
+    while (L % 2 == 0) { L /= 2; ++p2; }
+    if (p2 == 1) r.push_back(2);
+    else if (p2 > 1) {
+        int a = p2 / 4, rem = p2 % 4;
+        if (rem == 1 && a >= 1) { a -= 1; r.insert(r.end(), a, 16); r.push_back(8); r.push_back(4); }
+        else {
+            r.insert(r.end(), a, 16);
+            if (rem == 3) r.push_back(8);
+            else if (rem == 2) r.push_back(4);
+            else if (rem == 1) r.push_back(2);
+        }
+    }
+    for (int p : {3, 5, 7})
+        while (L % p == 0) { L /= p; r.push_back(p); }
+    return r;
+}
+
+struct HostFft {
+    FftDesc d;
+    std::vector<long double> tw;   // interleaved re, im; forward sign
+};
+
+HostFft make_fft(int L) {
+    HostFft h;
+    std::memset(&h.d, 0, sizeof h.d);
+    h.d.L = L;
+    std::vector<int> rad = factorize(L);
+    h.d.nst = (int)rad.size();
+    int Ns = 1, off = 0;
+    for (size_t s = 0; s < rad.size(); ++s) {
+        const int R = rad[s];
+        h.d.rad[s] = R;
+        h.d.twoff[s] = off;
+        for (int k = 0; k < Ns; ++k)
+            for (int r = 1; r < R; ++r) {
+                const long long num = ((long long)k * r) % ((long long)Ns * R);
+                const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)num / (long double)(Ns * R);
+                h.tw.push_back(cosl(ang));
+                h.tw.push_back(sinl(ang));
+            }
+        off += Ns * (R - 1);
+        Ns *= R;
+    }
+    return h;
+}
+
+// threads needed so that every stage fits the per-thread register budget
+int fft_threads(const FftDesc &d, int nlines, int min_work) {
+    int need = 64;
+    for (int s = 0; s < d.nst; ++s) {
+        const int R = d.rad[s];
+        const int U = kE / R;
+        const long long bf = (long long)nlines * (d.L / R);
+        need = std::max<long long>(need, (bf + U - 1) / U);
+    }
+    need = std::max(need, std::min(min_work, 256));
+    need = (need + 63) / 64 * 64;
+    return need;
+}
+
+int pitch_of(int L) { return (L % 2 == 0) ? L + 1 : L; }
+
+}  // namespace
+
+struct mm_plan {
+    int prec = MM_F32;
+    size_t rsz = 4;
+    int64_t n[3] = {0, 0, 0};
+    double d[3] = {0, 0, 0};
+    int64_t L[3] = {0, 0, 0};
+    int hx = 0, hy = 0, hz = 0;
+    double P = 16.0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    // device memory
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    void *S1 = nullptr, *S2 = nullptr, *tensor = nullptr, *twT = nullptr, *tw64 = nullptr;
+    void *ms[2] = {nullptr, nullptr}, *acc = nullptr;
+    double *epart = nullptr, *esum = nullptr;
+    LinePass *d_lp = nullptr;   // [0] y forward, [1] y inverse
+    FusedPass *d_fp = nullptr;
+    // host copies
+    HostFft fx, fy, fz;
+    LinePass lp_fwd{}, lp_inv{};
+    FusedPass fp{};
+    ZGeom zg{};
+    size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
+    int tiles_fwd = 0, tiles_inv = 0;
+    // llg graph cache; graphs are captured on a private stream (capture is not
+    // permitted on the legacy default stream) and launched on `stream`
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey;
+    // adjoint scratch (allocated on first use)
+    void *adj = nullptr;
+};
+
+namespace {
+
+int dalloc(mm_plan *p, void **out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (getenv("MMX_TEST_FAIL_ALLOC")) return fail(MM_ENOMEM, "allocation of %zu bytes refused (MMX_TEST_FAIL_ALLOC)", bytes);
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        (void)hipGetLastError();
+        return fail(e == hipErrorOutOfMemory ? MM_ENOMEM : MM_EHIP, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    }
+    p->allocs.push_back(*out);
+    p->bytes += bytes;
+    return MM_OK;
+}
+
+void free_all(mm_plan *p) {
+    if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    if (p->cap) { (void)hipStreamDestroy(p->cap); p->cap = nullptr; }
+    for (void *q : p->allocs) (void)hipFree(q);
+    p->allocs.clear();
+}
+
+template <typename T>
+std::vector<T> round_tw(const HostFft &f) {
+    std::vector<T> v(f.tw.size());
+    for (size_t i = 0; i < v.size(); ++i) v[i] = (T)f.tw[i];
+    return v;
+}
+
+// Tile choice for a line pass of length L: columns W (power of two) within the
+// LDS budget, at most `inner`, with the FFT fitting 1024 threads.
+// Tile choice for a line pass of length L: the first candidate width (all
+// `inner` columns if few, else 64, 32, ..., 1) that fits the LDS budget and
+// 1024 threads; `want_W` > 0 forces a width (clamped to `inner`).
+void choose_line_tile(int L, int inner, size_t csz, size_t budget, int want_W, int &W, int &nthr, size_t &lds) {
+    const int pitch = pitch_of(L);
+    const FftDesc d = make_fft(L).d;
+    std::vector<int> cand;
+    if (want_W > 0) cand.push_back(std::min(want_W, inner));
+    if (inner <= 64) cand.push_back(inner);
+    for (int w = 64; w >= 1; w >>= 1)
+        if (w <= inner) cand.push_back(w);
+    W = 1;
+    for (int w : cand) {
+        if ((size_t)w * pitch * csz <= budget && fft_threads(d, w, w * L) <= 1024) { W = w; break; }
+    }
+    nthr = fft_threads(d, W, W * L);
+    lds = (size_t)W * pitch * csz;
+}
+
+int validate_grid(const int64_t grid[3], const double cell[3]) {
+    if (!grid || !cell) return fail(MM_EINVAL, "grid and cell must be non-NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (grid[a] < 1 || grid[a] > (1 << 20)) return fail(MM_EINVAL, "grid[%d]=%lld out of range [1, 2^20]", a, (long long)grid[a]);
+        if (!(cell[a] > 0.0) || !std::isfinite(cell[a])) return fail(MM_EINVAL, "cell[%d] must be finite and > 0", a);
+    }
+    return MM_OK;
+}
+
+template <typename T> int build_spectrum(mm_plan *p, const double *d_octant);
+
+// set up the FFT descriptors, tiles and workspace of a plan
+template <typename T>
+int setup_plan(mm_plan *p, const mm_plan_opts *o) {
+    typedef cplx<T> C;
+    const size_t csz = sizeof(C);
+    const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+    const int Lx = (int)p->L[0], Ly = (int)p->L[1], Lz = (int)p->L[2];
+    p->hx = Lx / 2 + 1;
+    p->hy = Ly / 2 + 1;
+    p->hz = Lz / 2 + 1;
+    p->fx = make_fft(Lx);
+    p->fy = make_fft(Ly);
+    p->fz = make_fft(Lz);
+    // twiddles (plan precision): x, y, z tables concatenated
+    std::vector<T> tw;
+    auto app = [&](const HostFft &f) { size_t off = tw.size() / 2; auto v = round_tw<T>(f); tw.insert(tw.end(), v.begin(), v.end()); return off; };
+    const size_t ox = app(p->fx), oy = app(p->fy), oz = app(p->fz);
+    int rc;
+    if ((rc = dalloc(p, &p->twT, std::max<size_t>(tw.size() * sizeof(T), 16)))) return rc;
+    HIPCK(hipMemcpy(p->twT, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+    const C *twc = reinterpret_cast<const C *>(p->twT);
+    // workspace
+    const int64_t hz3 = (int64_t)p->hz * 3;
+    const size_t s1 = (size_t)nx * ny * hz3 * csz, s2 = (size_t)nx * Ly * hz3 * csz;
+    const size_t tens = (size_t)p->hy * p->hz * p->hx * 6 * sizeof(T);
+    const size_t cells3 = (size_t)nx * ny * nz * 3 * sizeof(T);
+    if ((rc = dalloc(p, &p->S1, s1))) return rc;
+    if ((rc = dalloc(p, &p->S2, s2))) return rc;
+    if ((rc = dalloc(p, &p->tensor, tens))) return rc;
+    if ((rc = dalloc(p, &p->ms[0], cells3))) return rc;
+    if ((rc = dalloc(p, &p->ms[1], cells3))) return rc;
+    if ((rc = dalloc(p, &p->acc, cells3))) return rc;
+    const int want = 0;
+    (void)o;
+    // y passes
+    int W, nthr;
+    size_t lds;
+    choose_line_tile(Ly, (int)hz3, csz, kLdsTarget, want, W, nthr, lds);
+    LinePass &f = p->lp_fwd;
+    std::memset(&f, 0, sizeof f);
+    f.in = p->S1; f.out = p->S2; f.tw = twc + oy;
+    f.in_row = hz3; f.out_row = hz3; f.in_outer = ny * hz3; f.out_outer = (int64_t)Ly * hz3;
+    f.inner = (int)hz3; f.outer = (int)nx; f.n_in = (int)ny; f.n_out = Ly;
+    f.W = W; f.tiles_inner = (int)((hz3 + W - 1) / W); f.pitch = pitch_of(Ly); f.nthr = nthr; f.sym_axis = -1;
+    f.f = p->fy.d;
+    p->lds_fwd = lds;
+    p->tiles_fwd = f.tiles_inner * f.outer;
+    LinePass &g = p->lp_inv;
+    g = f;
+    g.in = p->S2; g.out = p->S1; g.in_outer = (int64_t)Ly * hz3; g.out_outer = ny * hz3; g.n_in = Ly; g.n_out = (int)ny;
+    p->lds_inv = lds;
+    p->tiles_inv = p->tiles_fwd;
+    // fused x pass
+    FusedPass &q = p->fp;
+    std::memset(&q, 0, sizeof q);
+    const int npos = Ly * p->hz;
+    const int px = pitch_of(Lx);
+    int Wp = 1;
+    for (int w : {32, 16, 8, 4, 2, 1}) {
+        if (w <= std::max(1, npos) && (size_t)3 * w * px * csz <= kLdsTarget && fft_threads(p->fx.d, 3 * w, 3 * w * Lx) <= 1024) { Wp = w; break; }
+    }
+    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + ox;
+    q.row = (int64_t)Ly * hz3; q.npos = npos; q.n = (int)nx; q.Ly = Ly; q.hz = p->hz; q.hx = p->hx;
+    q.W = Wp; q.tiles = (npos + Wp - 1) / Wp; q.pitch = px; q.nthr = fft_threads(p->fx.d, 3 * Wp, 3 * Wp * Lx);
+    q.f = p->fx.d;
+    p->lds_fp = (size_t)3 * Wp * px * csz;
+    if (p->lds_fp > kLdsMax) return fail(MM_ENOTSUP, "x length %d too long for one workgroup", Lx);
+    // z passes: P positions (even) per tile, about 512 cells per tile
+    ZGeom &z = p->zg;
+    std::memset(&z, 0, sizeof z);
+    z.nx = (int)nx; z.ny = (int)ny; z.nz = (int)nz; z.Lz = Lz; z.hz = p->hz;
+    const int pz = pitch_of(Lz);
+    int P = (int)std::max<int64_t>(2, (512 / nz) & ~1);
+    P = std::min<int64_t>(P, std::max<int64_t>(2, (nx * ny + 1) & ~1));
+    while (P > 2 && ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsTarget || fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz) > 1024)) P -= 2;
+    z.P = P; z.tiles = (int)((nx * ny + P - 1) / P); z.pitch = pz;
+    z.nthr = std::min(1024, fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz));
+    z.f = p->fz.d; z.tw = twc + oz; z.S1 = p->S1;
+    p->lds_z = std::max<size_t>((size_t)((3 * P + 1) / 2) * pz * csz, 16 * 2 * sizeof(double) + 64);
+    if ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsMax) return fail(MM_ENOTSUP, "z length %d too long", Lz);
+    // energy partials
+    if ((rc = dalloc(p, (void **)&p->epart, (size_t)z.tiles * 2 * sizeof(double)))) return rc;
+    if ((rc = dalloc(p, (void **)&p->esum, 2 * sizeof(double)))) return rc;
+    // device descriptor copies
+    if ((rc = dalloc(p, (void **)&p->d_lp, 2 * sizeof(LinePass)))) return rc;
+    if ((rc = dalloc(p, (void **)&p->d_fp, sizeof(FusedPass)))) return rc;
+    LinePass two[2] = {p->lp_fwd, p->lp_inv};
+    HIPCK(hipMemcpy(p->d_lp, two, sizeof two, hipMemcpyHostToDevice));
+    HIPCK(hipMemcpy(p->d_fp, &p->fp, sizeof(FusedPass), hipMemcpyHostToDevice));
+    // FP64 twiddles for the tensor transforms
+    std::vector<double> tw64;
+    auto app64 = [&](const HostFft &h) { size_t off = tw64.size() / 2; auto v = round_tw<double>(h); tw64.insert(tw64.end(), v.begin(), v.end()); return off; };
+    (void)app64(p->fx); (void)app64(p->fy); (void)app64(p->fz);
+    if ((rc = dalloc(p, &p->tw64, std::max<size_t>(tw64.size() * sizeof(double), 16)))) return rc;
+    HIPCK(hipMemcpy(p->tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
+    return MM_OK;
+}
+
+// One real symmetric (cosine / sine) transform pass of the FP64 tensor.
+int sym_pass(mm_plan *p, const double *in, double *out, int axis, int64_t outer, int inner, int64_t in_row,
+             int64_t in_outer, int64_t out_row, int64_t out_outer, int n_in, int L, const HostFft &hf,
+             const double2 *tw, void *d_desc) {
+    int W, nthr;
+    size_t lds;
+    choose_line_tile(L, inner, sizeof(double2), kLdsTarget, 0, W, nthr, lds);
+    LinePass a;
+    std::memset(&a, 0, sizeof a);
+    a.in = in; a.out = out; a.tw = tw;
+    a.in_row = in_row; a.out_row = out_row; a.in_outer = in_outer; a.out_outer = out_outer;
+    a.inner = inner; a.outer = (int)outer; a.n_in = n_in; a.n_out = L / 2 + 1;
+    a.W = W; a.tiles_inner = (inner + W - 1) / W; a.pitch = pitch_of(L); a.nthr = nthr; a.sym_axis = axis;
+    a.f = hf.d;
+    HIPCK(hipMemcpyAsync(d_desc, &a, sizeof a, hipMemcpyHostToDevice, p->stream));
+    const long long tiles = (long long)a.tiles_inner * outer;
+    if (tiles > 0x7fffffffLL) return fail(MM_ENOTSUP, "tensor transform grid too large");
+    HIPCK(launch_line_pass<double>((const LinePass *)d_desc, nullptr, (int)tiles, nthr, lds, -1, true, p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));
+    return MM_OK;
+}
+
+// real-space FP64 octant (device) -> stored spectrum in plan precision
+template <typename T>
+int build_spectrum(mm_plan *p, const double *d_oct) {
+    const int64_t nx = p->n[0], ny = p->n[1], nz = p->n[2];
+    const int Lx = (int)p->L[0], Ly = (int)p->L[1], Lz = (int)p->L[2];
+    const int hx = p->hx, hy = p->hy, hz = p->hz;
+    const size_t big = (size_t)std::max<int64_t>(nx, hx) * std::max<int64_t>(ny, hy) * std::max<int64_t>(nz, hz) * 6 * sizeof(double);
+    void *b0 = nullptr, *b1 = nullptr, *dd = nullptr;
+    hipError_t e;
+    if ((e = hipMalloc(&b0, big)) != hipSuccess) return fail(MM_ENOMEM, "tensor scratch: %s", hipGetErrorString(e));
+    if ((e = hipMalloc(&b1, big)) != hipSuccess) { (void)hipFree(b0); return fail(MM_ENOMEM, "tensor scratch: %s", hipGetErrorString(e)); }
+    if ((e = hipMalloc(&dd, sizeof(LinePass))) != hipSuccess) { (void)hipFree(b0); (void)hipFree(b1); return fail(MM_ENOMEM, "desc"); }
+    const double2 *tw = reinterpret_cast<const double2 *>(p->tw64);
+    const size_t ox = 0, oy = (size_t)std::max(p->fx.d.L - 1, 0), oz = oy + (size_t)std::max(p->fy.d.L - 1, 0);
+    int rc = MM_OK;
+    // z: [i][j][k][q] -> [i][j][kz][q]
+    rc = sym_pass(p, d_oct, (double *)b0, 2, nx * ny, 6, 6, nz * 6, 6, (int64_t)hz * 6, (int)nz, Lz, p->fz, tw + oz, dd);
+    // y: [i][j][kz][q] -> [i][ky][kz][q]
+    if (!rc) rc = sym_pass(p, (double *)b0, (double *)b1, 1, nx, hz * 6, (int64_t)hz * 6, ny * hz * 6, (int64_t)hz * 6,
+                           (int64_t)hy * hz * 6, (int)ny, Ly, p->fy, tw + oy, dd);
+    // x: [i][ky][kz][q] -> [kx][ky][kz][q]
+    if (!rc) rc = sym_pass(p, (double *)b1, (double *)b0, 0, 1, hy * hz * 6, (int64_t)hy * hz * 6, 0, (int64_t)hy * hz * 6,
+                           0, (int)nx, Lx, p->fx, tw + ox, dd);
+    if (!rc) {
+        const double inv = 1.0 / ((double)Lx * Ly * Lz);
+        hipError_t le = launch_tensor_finalize<T>((const double *)b0, (T *)p->tensor, hx, hy, hz, inv, p->stream);
+        if (le != hipSuccess) rc = fail(MM_EHIP, "tensor finalize: %s", hipGetErrorString(le));
+        else if ((le = hipStreamSynchronize(p->stream)) != hipSuccess) rc = fail(MM_EHIP, "tensor: %s", hipGetErrorString(le));
+    }
+    (void)hipFree(b0); (void)hipFree(b1); (void)hipFree(dd);
+    return rc;
+}
+
+int compute_tensor(mm_plan *p) {
+    const size_t oct = (size_t)p->n[0] * p->n[1] * p->n[2] * 6 * sizeof(double);
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, oct);
+    if (e != hipSuccess) return fail(MM_ENOMEM, "octant: %s", hipGetErrorString(e));
+    e = launch_tensor_octant((double *)d, (int)p->n[0], (int)p->n[1], (int)p->n[2], p->d[0], p->d[1], p->d[2], p->P, p->stream);
+    if (e != hipSuccess) { (void)hipFree(d); return fail(MM_EHIP, "tensor octant: %s", hipGetErrorString(e)); }
+    int rc = p->prec == MM_F32 ? build_spectrum<float>(p, (double *)d) : build_spectrum<double>(p, (double *)d);
+    (void)hipFree(d);
+    return rc;
+}
+
+// ---- pass launchers --------------------------------------------------------
+template <typename T>
+int run_zfwd(mm_plan *p, int src, const void *srcp, const void *Ms, double Ms_s, const void *s = nullptr,
+             const void *h = nullptr, const void *kb = nullptr, void *ym = nullptr, void *yh = nullptr, double gp = 0,
+             double alpha = 0) {
+    ZFwdArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.g = p->zg; a.src = srcp; a.Ms = Ms; a.Ms_scalar = Ms_s;
+    a.s = s; a.h = h; a.kb = kb; a.ym = ym; a.yh = yh; a.gp = gp; a.alpha = alpha;
+    HIPCK(launch_zfwd<T>(a, src, p->lds_z, p->stream));
+    return MM_OK;
+}
+
+template <typename T>
+int run_yxy(mm_plan *p) {
+    HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
+    HIPCK(launch_fused_x<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
+    HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
+    return MM_OK;
+}
+
+void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double Ms_s, double A) {
+    std::memset(&a, 0, sizeof a);
+    a.g = p->zg;
+    a.terms = terms;
+    a.Ms = Ms; a.Ms_scalar = Ms_s;
+    a.ex_pref = 2.0 * A / kMu0;
+    for (int i = 0; i < 3; ++i) a.inv_d2[i] = 1.0 / (p->d[i] * p->d[i]);
+}
+
+int check_plan(mm_plan *p) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    if (!p->tensor) return fail(MM_ESTATE, "plan has no tensor (demag_tensor_init did not complete)");
+    return MM_OK;
+}
+
+int check_material(const void *Ms, double Ms_scalar, double A, unsigned terms) {
+    if (!std::isfinite(Ms_scalar) || !std::isfinite(A)) return fail(MM_EINVAL, "Ms_scalar and A must be finite");
+    if (!Ms && !(Ms_scalar >= 0.0)) return fail(MM_EINVAL, "Ms_scalar must be >= 0");
+    if ((terms & MM_EXCHANGE) && !(A >= 0.0)) return fail(MM_EINVAL, "A must be >= 0");
+    return MM_OK;
+}
+
+template <typename T>
+int heff_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, void *h, unsigned terms, double *E) {
+    int rc;
+    if (terms & MM_DEMAG) {
+        if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
+        if ((rc = run_yxy<T>(p))) return rc;
+    }
+    ZInvArgs a;
+    fill_common(p, a, terms, Ms, Ms_s, A);
+    a.m = m; a.h_out = h; a.epart = E ? p->epart : nullptr;
+    HIPCK(launch_zinv<T>(a, EPI_HEFF, p->lds_z, p->stream));
+    if (E) {
+        HIPCK(launch_energy_reduce(p->epart, p->zg.tiles, p->esum, p->stream));
+        double s[2];
+        HIPCK(hipMemcpyAsync(s, p->esum, sizeof s, hipMemcpyDeviceToHost, p->stream));
+        HIPCK(hipStreamSynchronize(p->stream));
+        const double V = p->d[0] * p->d[1] * p->d[2];
+        E[0] = -0.5 * kMu0 * V * s[0];
+        E[1] = -0.5 * kMu0 * V * s[1];
+    }
+    return MM_OK;
+}
+
+// enqueue one RK4 step (17 launches)
+template <typename T>
+int enqueue_step(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, double alpha, double gamma, double dt,
+                 const double *hext, int renorm) {
+    int rc;
+    if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
+    for (int s = 0; s < 4; ++s) {
+        if ((rc = run_yxy<T>(p))) return rc;
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
+        if (hext) for (int i = 0; i < 3; ++i) a.hext[i] = hext[i];
+        a.stage = s;
+        a.next_r2c = s < 3;
+        a.renorm = renorm;
+        a.dt = dt; a.alpha = alpha; a.gp = gamma / (1.0 + alpha * alpha);
+        a.ms_in = s == 0 ? m : p->ms[(s - 1) & 1];
+        a.m_n = m; a.acc = p->acc;
+        a.ms_out = s < 3 ? p->ms[s & 1] : nullptr;
+        a.m_out = s == 3 ? m : nullptr;
+        HIPCK(launch_zinv<T>(a, EPI_STAGE, p->lds_z, p->stream));
+    }
+    return MM_OK;
+}
+
+template <typename T>
+int llg_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, double alpha, double gamma, double dt,
+             int n, const double *hext, unsigned flags) {
+    const int renorm = (flags & MM_NO_RENORM) ? 0 : 1;
+    if (flags & MM_NO_GRAPH) {
+        for (int k = 0; k < n; ++k) {
+            int rc = enqueue_step<T>(p, m, Ms, Ms_s, A, alpha, gamma, dt, hext, renorm);
+            if (rc) return rc;
+        }
+        return MM_OK;
+    }
+    // graph key: every argument baked into the captured launches
+    std::vector<unsigned char> key(128, 0);
+    double vals[10] = {Ms_s, A, alpha, gamma, dt, hext ? hext[0] : 0.0, hext ? hext[1] : 0.0, hext ? hext[2] : 0.0, (double)renorm, hext ? 1.0 : 0.0};
+    const void *ptrs[3] = {m, Ms, (const void *)p->stream};
+    std::memcpy(key.data(), vals, sizeof vals);
+    std::memcpy(key.data() + sizeof vals, ptrs, sizeof ptrs);
+    if (!p->gexec || key != p->gkey) {
+        if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+        hipGraph_t graph = nullptr;
+        if (!p->cap) HIPCK(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
+        hipStream_t user = p->stream;
+        p->stream = p->cap;
+        hipError_t e = hipStreamBeginCapture(p->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { p->stream = user; return fail(MM_EHIP, "begin capture: %s", hipGetErrorString(e)); }
+        int rc = enqueue_step<T>(p, m, Ms, Ms_s, A, alpha, gamma, dt, hext, renorm);
+        e = hipStreamEndCapture(p->cap, &graph);
+        p->stream = user;
+        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(MM_EHIP, "graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&p->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) { p->gexec = nullptr; return fail(MM_EHIP, "graph instantiate: %s", hipGetErrorString(e)); }
+        p->gkey = key;
+    }
+    for (int k = 0; k < n; ++k) HIPCK(hipGraphLaunch(p->gexec, p->stream));
+    return MM_OK;
+}
+
+template <typename T>
+int adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, const void *g_h, void *g_m,
+                 void *g_Ms, unsigned terms, int acc_gMs) {
+    int rc;
+    if (terms & MM_DEMAG) {
+        if ((rc = run_zfwd<T>(p, SRC_RAW, g_h, nullptr, 1.0))) return rc;
+        if ((rc = run_yxy<T>(p))) return rc;
+    }
+    ZInvArgs a;
+    fill_common(p, a, terms, Ms, Ms_s, A);
+    a.m = m; a.g_h = g_h; a.g_m = g_m; a.g_Ms = g_Ms; a.acc_gMs = acc_gMs;
+    HIPCK(launch_zinv<T>(a, EPI_ADJ, p->lds_z, p->stream));
+    return MM_OK;
+}
+
+// scratch of the RK4 adjoint: s1..s3, h0..h3, u, ub, kb, ym, yh, gmh (14 vector fields)
+template <typename T>
+int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, double alpha, double gamma,
+                     double dt, const double *hext, unsigned flags, void *g, void *g_Ms) {
+    const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
+    const size_t f3 = (size_t)ncell * 3 * sizeof(T);
+    int rc;
+    if (!p->adj && (rc = dalloc(p, &p->adj, 14 * f3))) return rc;
+    T *base = (T *)p->adj;
+    auto buf = [&](int i) { return (void *)(base + (size_t)i * ncell * 3); };
+    void *srec[4] = {(void *)m, buf(0), buf(1), buf(2)};
+    void *hrec[4] = {buf(3), buf(4), buf(5), buf(6)};
+    void *urec = buf(7), *ub = buf(8), *kb = buf(9), *ym = buf(10), *yh = buf(11), *gmh = buf(12);
+    const int renorm = (flags & MM_NO_RENORM) ? 0 : 1;
+    const double gp = gamma / (1.0 + alpha * alpha);
+    // forward recompute with stage records
+    if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
+    for (int s = 0; s < 4; ++s) {
+        if ((rc = run_yxy<T>(p))) return rc;
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
+        if (hext) for (int i = 0; i < 3; ++i) a.hext[i] = hext[i];
+        a.stage = s; a.next_r2c = s < 3; a.renorm = renorm;
+        a.dt = dt; a.alpha = alpha; a.gp = gp;
+        a.ms_in = srec[s]; a.m_n = m; a.acc = p->acc;
+        a.ms_out = s < 3 ? srec[s + 1] : nullptr;
+        a.m_out = nullptr; a.h_rec = hrec[s]; a.u_rec = s == 3 ? urec : nullptr;
+        HIPCK(launch_zinv<T>(a, EPI_STAGE, p->lds_z, p->stream));
+    }
+    // reverse
+    HIPCK(launch_adj_unorm<T>((const T *)g, (const T *)urec, (T *)ub, (T *)g, renorm, ncell, p->stream));
+    const double w[4] = {dt / 6.0, dt / 3.0, dt / 3.0, dt / 6.0};
+    const double coef[4] = {0.0, 0.5 * dt, 0.5 * dt, dt};
+    HIPCK(launch_scale_copy<T>((const T *)ub, (T *)kb, w[3], ncell * 3, p->stream));   // kb = (dt/6) u_bar
+    for (int q = 3; q >= 0; --q) {
+        if ((rc = run_zfwd<T>(p, SRC_ADJPRE, nullptr, nullptr, 1.0, srec[q], hrec[q], kb, ym, yh, gp, alpha))) return rc;
+        if ((rc = run_yxy<T>(p))) return rc;
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
+        a.m = srec[q]; a.g_h = yh; a.g_m = gmh; a.g_Ms = g_Ms; a.acc_gMs = 1;
+        HIPCK(launch_zinv<T>(a, EPI_ADJ, p->lds_z, p->stream));
+        HIPCK(launch_adj_combine<T>((const T *)ym, (const T *)gmh, (const T *)ub, (T *)g, q > 0 ? (T *)kb : nullptr,
+                                    q > 0 ? w[q - 1] : 0.0, coef[q], ncell * 3, p->stream));
+    }
+    return MM_OK;
+}
+
+}  // namespace
+
+// =============================== C ABI ======================================
+extern "C" {
+
+int mm_plan_opts_default(mm_plan_opts *o) {
+    if (!o) return fail(MM_EINVAL, "opts is NULL");
+    std::memset(o, 0, sizeof *o);
+    o->far_radius = 16.0;
+    return MM_OK;
+}
+
+int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3], int precision, void *hip_stream,
+                      const mm_plan_opts *opts) {
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int rc = validate_grid(grid, cell);
+    if (rc) return rc;
+    if (precision != MM_F32 && precision != MM_F64) return fail(MM_EINVAL, "precision must be MM_F32 or MM_F64");
+    mm_plan_opts o;
+    mm_plan_opts_default(&o);
+    if (opts) o = *opts;
+    if (!std::isfinite(o.far_radius)) return fail(MM_EINVAL, "far_radius must be finite");
+    int64_t L[3];
+    for (int a = 0; a < 3; ++a) {
+        L[a] = o.L[a] > 0 ? o.L[a] : default_L(grid[a]);
+        if (L[a] < 2 * grid[a] - 1 || !is_7smooth(L[a]))
+            return fail(MM_EINVAL, "L[%d]=%lld must be 7-smooth and >= 2n-1 = %lld", a, (long long)L[a], (long long)(2 * grid[a] - 1));
+        if (L[a] > 16384) return fail(MM_ENOTSUP, "L[%d]=%lld exceeds 16384", a, (long long)L[a]);
+    }
+    if (o.autotune < 0 || o.autotune > 1) return fail(MM_EINVAL, "autotune must be 0 or 1");
+    const int64_t ncell = grid[0] * grid[1] * grid[2];
+    if (grid[0] * grid[1] > 0x7fffffffLL / 2 || ncell > (1LL << 34)) return fail(MM_ENOTSUP, "grid too large");
+    int dev = 0;
+    HIPCK(hipGetDevice(&dev));
+    mm_plan *p = new (std::nothrow) mm_plan();
+    if (!p) return fail(MM_ENOMEM, "plan allocation");
+    p->prec = precision;
+    p->rsz = precision == MM_F32 ? 4 : 8;
+    p->device = dev;
+    p->stream = (hipStream_t)hip_stream;
+    p->P = o.far_radius;
+    for (int a = 0; a < 3; ++a) { p->n[a] = grid[a]; p->d[a] = cell[a]; p->L[a] = L[a]; }
+    rc = precision == MM_F32 ? setup_plan<float>(p, &o) : setup_plan<double>(p, &o);
+    if (!rc) rc = compute_tensor(p);
+    if (rc) {
+        std::string keep = g_last;
+        free_all(p);
+        delete p;
+        g_last = keep;
+        return rc;
+    }
+    *out = p;
+    return MM_OK;
+}
+
+int mm_plan_destroy(mm_plan *p) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    (void)hipStreamSynchronize(p->stream);
+    free_all(p);
+    delete p;
+    return MM_OK;
+}
+
+int mm_plan_set_stream(mm_plan *p, void *s) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    p->stream = (hipStream_t)s;
+    return MM_OK;
+}
+
+int mm_plan_info(const mm_plan *p, int64_t L[3], size_t *bytes, int tiles[5]) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    if (L) for (int a = 0; a < 3; ++a) L[a] = p->L[a];
+    if (bytes) *bytes = p->bytes;
+    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->fp.W; tiles[3] = p->lp_inv.W; tiles[4] = p->zg.P; }
+    return MM_OK;
+}
+
+int h_eff(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, double A, void *h_out, unsigned terms,
+          double *energy_out) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m || !h_out) return fail(MM_EINVAL, "m and h_out must be non-NULL");
+    if (m == h_out) return fail(MM_EINVAL, "h_out must not alias m");
+    if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "terms must be a non-empty subset of MM_DEMAG|MM_EXCHANGE");
+    if ((rc = check_material(Ms, Ms_scalar, A, terms))) return rc;
+    return p->prec == MM_F32 ? heff_impl<float>(p, m, Ms, Ms_scalar, A, h_out, terms, energy_out)
+                             : heff_impl<double>(p, m, Ms, Ms_scalar, A, h_out, terms, energy_out);
+}
+
+static int check_llg(double alpha, double gamma, double dt, const double *hext) {
+    if (!(alpha >= 0.0) || !std::isfinite(alpha)) return fail(MM_EINVAL, "alpha must be finite and >= 0");
+    if (!(gamma > 0.0) || !std::isfinite(gamma)) return fail(MM_EINVAL, "gamma must be finite and > 0");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(MM_EINVAL, "dt must be finite and > 0");
+    if (hext) for (int i = 0; i < 3; ++i) if (!std::isfinite(hext[i])) return fail(MM_EINVAL, "h_ext must be finite");
+    return MM_OK;
+}
+
+int llg_step(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double A, double alpha, double gamma, double dt,
+             int n_steps, const double h_ext[3], unsigned flags) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m) return fail(MM_EINVAL, "m must be non-NULL");
+    if (n_steps < 0) return fail(MM_EINVAL, "n_steps must be >= 0");
+    if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
+    if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;
+    if ((rc = check_llg(alpha, gamma, dt, h_ext))) return rc;
+    if (n_steps == 0) return MM_OK;
+    return p->prec == MM_F32 ? llg_impl<float>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, n_steps, h_ext, flags)
+                             : llg_impl<double>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, n_steps, h_ext, flags);
+}
+
+int h_eff_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, double A, const void *g_h, void *g_m,
+                  void *g_Ms, unsigned terms) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m || !g_h || !g_m) return fail(MM_EINVAL, "m, g_h and g_m must be non-NULL");
+    if (g_m == g_h || g_m == m) return fail(MM_EINVAL, "g_m must not alias m or g_h");
+    if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "terms must be a non-empty subset of MM_DEMAG|MM_EXCHANGE");
+    if ((rc = check_material(Ms, Ms_scalar, A, terms))) return rc;
+    return p->prec == MM_F32 ? adjoint_impl<float>(p, m, Ms, Ms_scalar, A, g_h, g_m, g_Ms, terms, 0)
+                             : adjoint_impl<double>(p, m, Ms, Ms_scalar, A, g_h, g_m, g_Ms, terms, 0);
+}
+
+int llg_step_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, double A, double alpha, double gamma,
+                     double dt, const double h_ext[3], unsigned flags, void *g, void *g_Ms) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m || !g) return fail(MM_EINVAL, "m and g must be non-NULL");
+    if (g == m) return fail(MM_EINVAL, "g must not alias m");
+    if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
+    if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;
+    if ((rc = check_llg(alpha, gamma, dt, h_ext))) return rc;
+    return p->prec == MM_F32 ? llg_adjoint_impl<float>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms)
+                             : llg_adjoint_impl<double>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms);
+}
+
+int mm_demag_tensor_get(mm_plan *p, double *host) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!host) return fail(MM_EINVAL, "host_octant is NULL");
+    const size_t bytes = (size_t)p->n[0] * p->n[1] * p->n[2] * 6 * sizeof(double);
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(MM_ENOMEM, "octant: %s", hipGetErrorString(e));
+    e = launch_tensor_octant((double *)d, (int)p->n[0], (int)p->n[1], (int)p->n[2], p->d[0], p->d[1], p->d[2], p->P, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(MM_EHIP, "tensor get: %s", hipGetErrorString(e));
+    return MM_OK;
+}
+
+int mm_demag_tensor_set(mm_plan *p, const double *host) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!host) return fail(MM_EINVAL, "host_octant is NULL");
+    const size_t bytes = (size_t)p->n[0] * p->n[1] * p->n[2] * 6 * sizeof(double);
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(MM_ENOMEM, "octant: %s", hipGetErrorString(e));
+    e = hipMemcpyAsync(d, host, bytes, hipMemcpyHostToDevice, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) { (void)hipFree(d); return fail(MM_EHIP, "tensor set: %s", hipGetErrorString(e)); }
+    rc = p->prec == MM_F32 ? build_spectrum<float>(p, (double *)d) : build_spectrum<double>(p, (double *)d);
+    (void)hipFree(d);
+    return rc;
+}
+
+int mm_demag_spectrum_get(mm_plan *p, double *host) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!host) return fail(MM_EINVAL, "host_spectrum is NULL");
+    const size_t bytes = (size_t)p->hx * p->hy * p->hz * 6 * sizeof(double);
+    void *d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(MM_ENOMEM, "spectrum: %s", hipGetErrorString(e));
+    e = p->prec == MM_F32 ? launch_tensor_export<float>((const float *)p->tensor, (double *)d, p->hx, p->hy, p->hz, p->stream)
+                          : launch_tensor_export<double>((const double *)p->tensor, (double *)d, p->hx, p->hy, p->hz, p->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(host, d, bytes, hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    (void)hipFree(d);
+    if (e != hipSuccess) return fail(MM_EHIP, "spectrum get: %s", hipGetErrorString(e));
+    return MM_OK;
+}
+
+const char *mm_strerror(int s) {
+    switch (s) {
+    case MM_OK: return "ok";
+    case MM_EINVAL: return "invalid argument";
+    case MM_ENOMEM: return "out of memory";
+    case MM_EHIP: return "HIP runtime error";
+    case MM_ESTATE: return "invalid plan state";
+    case MM_ENOTSUP: return "not supported";
+    default: return "unknown status";
+    }
+}
+
+const char *mm_last_error(void) { return g_last.c_str(); }
+
+}  // extern "C"
+
+// =============================== batch ======================================
+struct mm_batch {
+    int count = 0;
+    int prec = MM_F32;
+    hipStream_t stream = nullptr;
+    std::vector<mm_plan *> plans;
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    int2 *zmap = nullptr, *lmap = nullptr, *fmap = nullptr;
+    int zt = 0, lt = 0, ft = 0;
+    LinePass *d_lpf = nullptr, *d_lpi = nullptr;
+    FusedPass *d_fp = nullptr;
+    ZFwdArgs *d_zf = nullptr;
+    ZInvArgs *d_zi = nullptr;   // [5][count]: h_eff, stage 0..3
+    int nthr_z = 64, nthr_l = 64, nthr_f = 64;
+    size_t lds_z = 0, lds_l = 0, lds_f = 0;
+    hipStream_t cap = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    std::vector<unsigned char> gkey, akey;
+};
+
+namespace {
+
+int balloc(mm_batch *b, void **out, size_t bytes) {
+    *out = nullptr;
+    hipError_t e = hipMalloc(out, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) { *out = nullptr; (void)hipGetLastError(); return fail(MM_ENOMEM, "batch hipMalloc(%zu): %s", bytes, hipGetErrorString(e)); }
+    b->allocs.push_back(*out);
+    b->bytes += bytes;
+    return MM_OK;
+}
+
+void batch_free(mm_batch *b) {
+    if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+    if (b->cap) { (void)hipStreamDestroy(b->cap); b->cap = nullptr; }
+    for (void *q : b->allocs) (void)hipFree(q);
+    b->allocs.clear();
+    for (mm_plan *p : b->plans) if (p) { free_all(p); delete p; }
+    b->plans.clear();
+}
+
+// upload the per-call z-pass arguments of every geometry
+int batch_args(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, double alpha, double gamma, double dt,
+               void *const *h_ptrs, unsigned terms, int renorm) {
+    const int n = b->count;
+    std::vector<ZFwdArgs> zf(n);
+    std::vector<ZInvArgs> zi(5 * (size_t)n);
+    for (int g = 0; g < n; ++g) {
+        mm_plan *p = b->plans[g];
+        std::memset(&zf[g], 0, sizeof(ZFwdArgs));
+        zf[g].g = p->zg; zf[g].src = m_ptrs[g]; zf[g].Ms = nullptr; zf[g].Ms_scalar = Ms[g];
+        ZInvArgs &h = zi[g];
+        fill_common(p, h, terms, nullptr, Ms[g], A);
+        h.m = m_ptrs[g]; h.h_out = h_ptrs ? h_ptrs[g] : nullptr;
+        for (int s = 0; s < 4; ++s) {
+            ZInvArgs &a = zi[(size_t)(1 + s) * n + g];
+            fill_common(p, a, MM_DEMAG | MM_EXCHANGE, nullptr, Ms[g], A);
+            a.stage = s; a.next_r2c = s < 3; a.renorm = renorm;
+            a.dt = dt; a.alpha = alpha; a.gp = gamma / (1.0 + alpha * alpha);
+            a.ms_in = s == 0 ? m_ptrs[g] : p->ms[(s - 1) & 1];
+            a.m_n = m_ptrs[g]; a.acc = p->acc;
+            a.ms_out = s < 3 ? p->ms[s & 1] : nullptr;
+            a.m_out = s == 3 ? m_ptrs[g] : nullptr;
+        }
+    }
+    HIPCK(hipMemcpyAsync(b->d_zf, zf.data(), zf.size() * sizeof(ZFwdArgs), hipMemcpyHostToDevice, b->stream));
+    HIPCK(hipMemcpyAsync(b->d_zi, zi.data(), zi.size() * sizeof(ZInvArgs), hipMemcpyHostToDevice, b->stream));
+    HIPCK(hipStreamSynchronize(b->stream));
+    return MM_OK;
+}
+
+template <typename T>
+int batch_yxy(mm_batch *b) {
+    HIPCK(launch_line_pass<T>(b->d_lpf, b->lmap, b->lt, b->nthr_l, b->lds_l, -1, false, b->stream));
+    HIPCK(launch_fused_x<T>(b->d_fp, b->fmap, b->ft, b->nthr_f, b->lds_f, b->stream));
+    HIPCK(launch_line_pass<T>(b->d_lpi, b->lmap, b->lt, b->nthr_l, b->lds_l, +1, false, b->stream));
+    return MM_OK;
+}
+
+template <typename T>
+int batch_step(mm_batch *b) {
+    int rc;
+    HIPCK(launch_zfwd_batch<T>(b->d_zf, b->zmap, b->zt, b->nthr_z, SRC_MS_M, b->lds_z, b->stream));
+    for (int s = 0; s < 4; ++s) {
+        if ((rc = batch_yxy<T>(b))) return rc;
+        HIPCK(launch_zinv_batch<T>(b->d_zi + (size_t)(1 + s) * b->count, b->zmap, b->zt, b->nthr_z, EPI_STAGE, b->lds_z, b->stream));
+    }
+    return MM_OK;
+}
+
+template <typename T>
+int batch_heff(mm_batch *b, unsigned terms) {
+    int rc;
+    if (terms & MM_DEMAG) {
+        HIPCK(launch_zfwd_batch<T>(b->d_zf, b->zmap, b->zt, b->nthr_z, SRC_MS_M, b->lds_z, b->stream));
+        if ((rc = batch_yxy<T>(b))) return rc;
+    }
+    HIPCK(launch_zinv_batch<T>(b->d_zi, b->zmap, b->zt, b->nthr_z, EPI_HEFF, b->lds_z, b->stream));
+    return MM_OK;
+}
+
+std::vector<unsigned char> batch_key(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, double alpha,
+                                     double gamma, double dt, void *const *h_ptrs, unsigned terms, int renorm) {
+    std::vector<unsigned char> k;
+    auto put = [&](const void *p, size_t n) { const unsigned char *c = (const unsigned char *)p; k.insert(k.end(), c, c + n); };
+    put(m_ptrs, sizeof(void *) * b->count);
+    if (h_ptrs) put(h_ptrs, sizeof(void *) * b->count);
+    put(Ms, sizeof(double) * b->count);
+    double v[4] = {A, alpha, gamma, dt};
+    put(v, sizeof v);
+    put(&terms, sizeof terms);
+    put(&renorm, sizeof renorm);
+    put(&b->stream, sizeof b->stream);
+    return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const double (*cells)[3], int precision,
+                    void *hip_stream, const mm_plan_opts *opts) {
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (count < 1 || count > 65536) return fail(MM_EINVAL, "count must be in [1, 65536]");
+    if (!grids || !cells) return fail(MM_EINVAL, "grids and cells must be non-NULL");
+    if (precision != MM_F32 && precision != MM_F64) return fail(MM_EINVAL, "precision must be MM_F32 or MM_F64");
+    for (int g = 0; g < count; ++g) {
+        int rc = validate_grid(grids[g], cells[g]);
+        if (rc) return fail(rc, "geometry %d: %s", g, std::string(g_last).c_str());
+    }
+    mm_batch *b = new (std::nothrow) mm_batch();
+    if (!b) return fail(MM_ENOMEM, "batch allocation");
+    b->count = count; b->prec = precision; b->stream = (hipStream_t)hip_stream;
+    int rc = MM_OK;
+    for (int g = 0; g < count && !rc; ++g) {
+        mm_plan *p = nullptr;
+        rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, opts);
+        if (!rc) b->plans.push_back(p);
+    }
+    // grouped tile maps and descriptor tables
+    std::vector<int2> zm, lm, fm;
+    std::vector<LinePass> lf, li;
+    std::vector<FusedPass> fp;
+    for (int g = 0; g < count && !rc; ++g) {
+        mm_plan *p = b->plans[g];
+        for (int t = 0; t < p->zg.tiles; ++t) zm.push_back(make_int2(g, t));
+        for (int t = 0; t < p->tiles_fwd; ++t) lm.push_back(make_int2(g, t));
+        for (int t = 0; t < p->fp.tiles; ++t) fm.push_back(make_int2(g, t));
+        lf.push_back(p->lp_fwd); li.push_back(p->lp_inv); fp.push_back(p->fp);
+        b->nthr_z = std::max(b->nthr_z, p->zg.nthr); b->lds_z = std::max(b->lds_z, p->lds_z);
+        b->nthr_l = std::max(b->nthr_l, p->lp_fwd.nthr); b->lds_l = std::max(b->lds_l, p->lds_fwd);
+        b->nthr_f = std::max(b->nthr_f, p->fp.nthr); b->lds_f = std::max(b->lds_f, p->lds_fp);
+    }
+    if (!rc) {
+        b->zt = (int)zm.size(); b->lt = (int)lm.size(); b->ft = (int)fm.size();
+        if (!rc) rc = balloc(b, (void **)&b->zmap, zm.size() * sizeof(int2));
+        if (!rc) rc = balloc(b, (void **)&b->lmap, lm.size() * sizeof(int2));
+        if (!rc) rc = balloc(b, (void **)&b->fmap, fm.size() * sizeof(int2));
+        if (!rc) rc = balloc(b, (void **)&b->d_lpf, lf.size() * sizeof(LinePass));
+        if (!rc) rc = balloc(b, (void **)&b->d_lpi, li.size() * sizeof(LinePass));
+        if (!rc) rc = balloc(b, (void **)&b->d_fp, fp.size() * sizeof(FusedPass));
+        if (!rc) rc = balloc(b, (void **)&b->d_zf, (size_t)count * sizeof(ZFwdArgs));
+        if (!rc) rc = balloc(b, (void **)&b->d_zi, (size_t)5 * count * sizeof(ZInvArgs));
+    }
+    if (!rc) {
+        hipError_t e = hipSuccess;
+        if (e == hipSuccess) e = hipMemcpy(b->zmap, zm.data(), zm.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->lmap, lm.data(), lm.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->fmap, fm.data(), fm.size() * sizeof(int2), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_lpf, lf.data(), lf.size() * sizeof(LinePass), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_lpi, li.data(), li.size() * sizeof(LinePass), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(b->d_fp, fp.data(), fp.size() * sizeof(FusedPass), hipMemcpyHostToDevice);
+        if (e != hipSuccess) rc = fail(MM_EHIP, "batch tables: %s", hipGetErrorString(e));
+    }
+    if (rc) {
+        std::string keep = g_last;
+        batch_free(b);
+        delete b;
+        g_last = keep;
+        return rc;
+    }
+    *out = b;
+    return MM_OK;
+}
+
+int mm_batch_h_eff(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, void *const *h_ptrs, unsigned terms) {
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    if (!m_ptrs || !Ms || !h_ptrs) return fail(MM_EINVAL, "m_ptrs, Ms and h_ptrs must be non-NULL");
+    if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "bad terms");
+    for (int g = 0; g < b->count; ++g) {
+        if (!m_ptrs[g] || !h_ptrs[g] || m_ptrs[g] == h_ptrs[g]) return fail(MM_EINVAL, "geometry %d: bad m/h pointer", g);
+        if (!(Ms[g] >= 0.0) || !std::isfinite(Ms[g])) return fail(MM_EINVAL, "geometry %d: Ms must be finite and >= 0", g);
+    }
+    if (!std::isfinite(A) || A < 0) return fail(MM_EINVAL, "A must be finite and >= 0");
+    int rc = batch_args(b, m_ptrs, Ms, A, 0.0, 1.0, 1.0, h_ptrs, terms, 1);
+    if (rc) return rc;
+    b->akey.clear();   // the stage arguments now differ from any captured graph's
+    return b->prec == MM_F32 ? batch_heff<float>(b, terms) : batch_heff<double>(b, terms);
+}
+
+int mm_batch_llg_step(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, double alpha, double gamma,
+                      double dt, int n_steps, unsigned flags) {
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    if (!m_ptrs || !Ms) return fail(MM_EINVAL, "m_ptrs and Ms must be non-NULL");
+    if (n_steps < 0) return fail(MM_EINVAL, "n_steps must be >= 0");
+    if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
+    for (int g = 0; g < b->count; ++g) {
+        if (!m_ptrs[g]) return fail(MM_EINVAL, "geometry %d: m is NULL", g);
+        if (!(Ms[g] >= 0.0) || !std::isfinite(Ms[g])) return fail(MM_EINVAL, "geometry %d: Ms must be finite and >= 0", g);
+    }
+    if (!std::isfinite(A) || A < 0) return fail(MM_EINVAL, "A must be finite and >= 0");
+    int rc = check_llg(alpha, gamma, dt, nullptr);
+    if (rc) return rc;
+    if (n_steps == 0) return MM_OK;
+    const int renorm = (flags & MM_NO_RENORM) ? 0 : 1;
+    std::vector<unsigned char> key = batch_key(b, m_ptrs, Ms, A, alpha, gamma, dt, nullptr, 3u, renorm);
+    if (key != b->akey) {
+        if ((rc = batch_args(b, m_ptrs, Ms, A, alpha, gamma, dt, nullptr, 3u, renorm))) return rc;
+        b->akey = key;
+    }
+    if (flags & MM_NO_GRAPH) {
+        for (int k = 0; k < n_steps; ++k) {
+            rc = b->prec == MM_F32 ? batch_step<float>(b) : batch_step<double>(b);
+            if (rc) return rc;
+        }
+        return MM_OK;
+    }
+    if (!b->gexec || key != b->gkey) {
+        if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
+        hipGraph_t graph = nullptr;
+        if (!b->cap) HIPCK(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+        hipStream_t user = b->stream;
+        b->stream = b->cap;
+        hipError_t e = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { b->stream = user; return fail(MM_EHIP, "begin capture: %s", hipGetErrorString(e)); }
+        rc = b->prec == MM_F32 ? batch_step<float>(b) : batch_step<double>(b);
+        e = hipStreamEndCapture(b->cap, &graph);
+        b->stream = user;
+        if (rc) { if (graph) (void)hipGraphDestroy(graph); return rc; }
+        if (e != hipSuccess) return fail(MM_EHIP, "batch graph capture: %s", hipGetErrorString(e));
+        e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) { b->gexec = nullptr; return fail(MM_EHIP, "batch graph instantiate: %s", hipGetErrorString(e)); }
+        b->gkey = key;
+    }
+    for (int k = 0; k < n_steps; ++k) HIPCK(hipGraphLaunch(b->gexec, b->stream));
+    return MM_OK;
+}
+
+int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes) {
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    int64_t n = 0;
+    size_t by = b->bytes;
+    for (const mm_plan *p : b->plans) { n += p->n[0] * p->n[1] * p->n[2]; by += p->bytes; }
+    if (total_cells) *total_cells = n;
+    if (device_bytes) *device_bytes = by;
+    return MM_OK;
+}
+
+int mm_batch_destroy(mm_batch *b) {
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    (void)hipStreamSynchronize(b->stream);
+    batch_free(b);
+    delete b;
+    return MM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,437 @@
+// The z passes: forward real-to-complex along z (first pass of the
+// convolution, source = Ms m, or a cotangent) and the inverse complex-to-real
+// along z fused with its epilogue (exchange stencil, h_eff output and FP64
+// energy partials; or the LLG right-hand side and the RK4 stage update,
+// followed by the forward z transform of the next stage's input; or the
+// adjoint of h_eff).  Two real z-lines share one complex FFT.
+#include "passes.hpp"
+#include "kernels.hpp"
+
+namespace mmx {
+
+template <typename T>
+__device__ __forceinline__ void cross3(const T a[3], const T b[3], T o[3]) {
+    o[0] = a[1] * b[2] - a[2] * b[1];
+    o[1] = a[2] * b[0] - a[0] * b[2];
+    o[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+template <typename T>
+__device__ __forceinline__ T ms_at(const T *Ms, T Ms_s, int64_t cell) { return Ms ? Ms[cell] : Ms_s; }
+
+// zero the paired z-lines of a tile
+template <typename T>
+__device__ __forceinline__ void zero_lines(cplx<T> *lds, int nlc, int L, int pitch, int tid, int nthr) {
+    const cplx<T> z = cmake<cplx<T>>(T(0), T(0));
+    for (int e = tid; e < nlc * L; e += nthr) {
+        const int u = e / L, k = e - u * L;
+        lds[u * pitch + k] = z;
+    }
+}
+
+// forward z transform of the LDS lines and the split of each complex line
+// into the half spectra of its two real lines, written to S1 [pos][kz][c]
+template <typename T>
+__device__ __forceinline__ void zfwd_tail(cplx<T> *lds, const ZGeom &g, int64_t pos0, int wp, int tid, int ltid) {
+    using C = cplx<T>;
+    const int nlr = 3 * wp, nlc = (nlr + 1) / 2;
+    lds_fft<T, -1>(lds, nlc, g.pitch, g.f, reinterpret_cast<const C *>(g.tw), ltid, g.nthr);
+    if (tid < g.nthr) {
+        C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * g.hz * 3;
+        const int L = g.Lz, hz3 = g.hz * 3;
+        const T half = T(0.5);
+        for (int e = tid; e < wp * hz3; e += g.nthr) {
+            const int pl = e / hz3, rem = e - pl * hz3;
+            const int k = rem / 3, c = rem - k * 3;
+            const int l = pl * 3 + c, u = l >> 1;
+            const C zk = lds[u * g.pitch + k];
+            const C zm = lds[u * g.pitch + (k == 0 ? 0 : L - k)];
+            C v;
+            if ((l & 1) == 0) v = cmake<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
+            else v = cmake<C>(half * (zk.y + zm.y), -half * (zk.x - zm.x));
+            S1[e] = v;
+        }
+    }
+}
+
+template <typename T, int SRC>
+__device__ __forceinline__ void zfwd_body(const ZFwdArgs &a, uint32_t tile) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const ZGeom &g = a.g;
+    const int tid = threadIdx.x, ltid = tid < g.nthr ? tid : 1 << 30;
+    const int64_t npos = (int64_t)g.nx * g.ny;
+    const int64_t pos0 = (int64_t)tile * g.P;
+    const int wp = (int)min((int64_t)g.P, npos - pos0);
+    const int nlr = 3 * wp, nlc = (nlr + 1) / 2;
+    if (tid < g.nthr) zero_lines<T>(lds, nlc, g.Lz, g.pitch, tid, g.nthr);
+    __syncthreads();
+    if (tid < g.nthr) {
+        const int nz = g.nz;
+        const int64_t cell0 = pos0 * nz;
+        if (SRC != SRC_ADJPRE) {
+            const T *src = reinterpret_cast<const T *>(a.src) + cell0 * 3;
+            const T *Ms = reinterpret_cast<const T *>(a.Ms);
+            const T Ms_s = T(a.Ms_scalar);
+            const int nz3 = nz * 3;
+            for (int e = tid; e < wp * nz3; e += g.nthr) {
+                const int pl = e / nz3, rem = e - pl * nz3;
+                const int z = rem / 3, c = rem - z * 3;
+                T v = src[e];
+                if (SRC == SRC_MS_M) v *= ms_at(Ms, Ms_s, cell0 + (int64_t)pl * nz + z);
+                const int l = pl * 3 + c;
+                reinterpret_cast<T *>(&lds[(l >> 1) * g.pitch + z])[l & 1] = v;
+            }
+        } else {
+            // y = VJP of f(s, h) = -g'[s x h + alpha s x (s x h)] for cotangent kb
+            const T *s = reinterpret_cast<const T *>(a.s) + cell0 * 3;
+            const T *h = reinterpret_cast<const T *>(a.h) + cell0 * 3;
+            const T *kb = reinterpret_cast<const T *>(a.kb) + cell0 * 3;
+            T *ym = reinterpret_cast<T *>(a.ym) + cell0 * 3;
+            T *yh = reinterpret_cast<T *>(a.yh) + cell0 * 3;
+            const T gp = T(a.gp), al = T(a.alpha);
+            for (int e = tid; e < wp * nz; e += g.nthr) {
+                const int pl = e / nz, z = e - pl * nz;
+                T sv[3], hv[3], y[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { sv[c] = s[3 * e + c]; hv[c] = h[3 * e + c]; y[c] = kb[3 * e + c]; }
+                T av[3], yxm[3], hxy[3], axy[3], hxyxm[3], yxmxm[3];
+                cross3(sv, hv, av);
+                cross3(y, sv, yxm);
+                cross3(hv, y, hxy);
+                cross3(av, y, axy);
+                cross3(hv, yxm, hxyxm);
+                cross3(yxm, sv, yxmxm);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const T vm = -gp * (hxy[c] + al * (axy[c] + hxyxm[c]));
+                    const T vh = -gp * (yxm[c] + al * yxmxm[c]);
+                    ym[3 * e + c] = vm;
+                    yh[3 * e + c] = vh;
+                    const int l = pl * 3 + c;
+                    reinterpret_cast<T *>(&lds[(l >> 1) * g.pitch + z])[l & 1] = vh;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    zfwd_tail<T>(lds, g, pos0, wp, tid, ltid);
+}
+
+template <typename T, int EPI>
+__device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const ZGeom &g = a.g;
+    const int tid = threadIdx.x, ltid = tid < g.nthr ? tid : 1 << 30;
+    const int64_t npos = (int64_t)g.nx * g.ny;
+    const int64_t pos0 = (int64_t)blk * g.P;
+    const int wp = (int)min((int64_t)g.P, npos - pos0);
+    const int nlr = 3 * wp, nlc = (nlr + 1) / 2;
+    const int L = g.Lz, hz = g.hz, pitch = g.pitch;
+    const bool demag = (a.terms & 1u) != 0, exch = (a.terms & 2u) != 0;
+    // 1. Hermitian extension of the paired half spectra
+    if (demag && tid < g.nthr) {
+        const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * hz * 3;
+        for (int e = tid; e < nlc * hz; e += g.nthr) {
+            const int u = e / hz, k = e - u * hz;
+            const int l0 = 2 * u, l1 = 2 * u + 1;
+            C A = cmake<C>(T(0), T(0)), B = A;
+            if (l0 < nlr) A = S1[(int64_t)(l0 / 3) * hz * 3 + k * 3 + (l0 % 3)];
+            if (l1 < nlr) B = S1[(int64_t)(l1 / 3) * hz * 3 + k * 3 + (l1 % 3)];
+            if (k == 0 || 2 * k == L) {
+                lds[u * pitch + k] = cmake<C>(A.x, B.x);
+            } else {
+                lds[u * pitch + k] = cmake<C>(A.x - B.y, A.y + B.x);
+                lds[u * pitch + (L - k)] = cmake<C>(A.x + B.y, B.x - A.y);
+            }
+        }
+    }
+    __syncthreads();
+    if (demag) lds_fft<T, +1>(lds, nlc, pitch, g.f, reinterpret_cast<const C *>(g.tw), ltid, g.nthr);
+    // 2. epilogue per cell
+    double ed = 0.0, ex = 0.0;
+    const int nx = g.nx, ny = g.ny, nz = g.nz;
+    const int64_t sx = (int64_t)ny * nz, sy = nz;
+    const T *Ms = reinterpret_cast<const T *>(a.Ms);
+    const T Ms_s = T(a.Ms_scalar);
+    const T exp_ = T(a.ex_pref);
+    const T id2[3] = {T(a.inv_d2[0]), T(a.inv_d2[1]), T(a.inv_d2[2])};
+    const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
+    if (tid < g.nthr) {
+        for (int e = tid; e < wp * nz; e += g.nthr) {
+            const int pl = e / nz, z = e - pl * nz;
+            const int64_t pos = pos0 + pl;
+            const int i = (int)(pos / ny), j = (int)(pos - (int64_t)i * ny);
+            const int64_t cell = pos * nz + z;
+            T hd[3] = {T(0), T(0), T(0)};
+            if (demag) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int l = pl * 3 + c;
+                    hd[c] = reinterpret_cast<const T *>(&lds[(l >> 1) * pitch + z])[l & 1];
+                }
+            }
+            const T msi = ms_at(Ms, Ms_s, cell);
+            const bool magi = msi > T(0);
+            T mi[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mi[c] = mfield[cell * 3 + c];
+            // neighbours: (offset, in-grid, axis)
+            int64_t noff[6] = {-sx, sx, -sy, sy, -1, 1};
+            bool nin[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, z > 0, z < nz - 1};
+            T hex[3] = {T(0), T(0), T(0)};
+            T lap[3] = {T(0), T(0), T(0)};
+            if (exch && magi) {
+#pragma unroll
+                for (int q = 0; q < 6; ++q) {
+                    if (!nin[q]) continue;
+                    const int64_t nc = cell + noff[q];
+                    if (!(ms_at(Ms, Ms_s, nc) > T(0))) continue;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) lap[c] += (mfield[nc * 3 + c] - mi[c]) * id2[q >> 1];
+                }
+                const T ci = exp_ / msi;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) hex[c] = ci * lap[c];
+            }
+            if (EPI == EPI_HEFF) {
+                T *ho = reinterpret_cast<T *>(a.h_out) + cell * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) ho[c] = hd[c] + hex[c] + T(a.hext[c]);
+                if (a.epart) {
+                    ed += (double)msi * ((double)mi[0] * hd[0] + (double)mi[1] * hd[1] + (double)mi[2] * hd[2]);
+                    ex += (double)msi * ((double)mi[0] * hex[0] + (double)mi[1] * hex[1] + (double)mi[2] * hex[2]);
+                }
+            } else if (EPI == EPI_STAGE) {
+                T h[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + T(a.hext[c]);
+                if (a.h_rec) {
+                    T *hr = reinterpret_cast<T *>(a.h_rec) + cell * 3;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) hr[c] = h[c];
+                }
+                T mxh[3], mxmxh[3], f[3];
+                cross3(mi, h, mxh);
+                cross3(mi, mxh, mxmxh);
+                const T gp = T(a.gp), al = T(a.alpha), dt = T(a.dt);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) f[c] = -gp * (mxh[c] + al * mxmxh[c]);
+                const T *mn = reinterpret_cast<const T *>(a.m_n) + cell * 3;
+                T *acc = reinterpret_cast<T *>(a.acc) + cell * 3;
+                T nxt[3];
+                if (a.stage == 0) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { acc[c] = f[c]; nxt[c] = mn[c] + T(0.5) * dt * f[c]; }
+                } else if (a.stage == 1) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { acc[c] = acc[c] + T(2) * f[c]; nxt[c] = mn[c] + T(0.5) * dt * f[c]; }
+                } else if (a.stage == 2) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) { acc[c] = acc[c] + T(2) * f[c]; nxt[c] = mn[c] + dt * f[c]; }
+                } else {
+                    const T w = dt / T(6);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) nxt[c] = mn[c] + w * (acc[c] + f[c]);
+                    if (a.u_rec) {
+                        T *ur = reinterpret_cast<T *>(a.u_rec) + cell * 3;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) ur[c] = nxt[c];
+                    }
+                    if (a.renorm) {
+                        const T nn = sqrt(nxt[0] * nxt[0] + nxt[1] * nxt[1] + nxt[2] * nxt[2]);
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) nxt[c] = nxt[c] / nn;
+                    }
+                }
+                if (a.stage < 3) {
+                    T *mo = reinterpret_cast<T *>(a.ms_out) + cell * 3;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) mo[c] = nxt[c];
+                } else if (a.m_out) {
+                    T *mo = reinterpret_cast<T *>(a.m_out) + cell * 3;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) mo[c] = nxt[c];
+                }
+                if (a.next_r2c) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int l = pl * 3 + c;
+                        reinterpret_cast<T *>(&lds[(l >> 1) * pitch + z])[l & 1] = msi * nxt[c];
+                    }
+                }
+            } else {  // EPI_ADJ
+                const T *gh = reinterpret_cast<const T *>(a.g_h);
+                T gi[3];
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gi[c] = gh[cell * 3 + c];
+                T gm[3] = {T(0), T(0), T(0)};
+                T gms = T(0);
+                if (demag) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gm[c] = msi * hd[c];
+                    gms = mi[0] * hd[0] + mi[1] * hd[1] + mi[2] * hd[2];
+                }
+                if (exch && magi) {
+                    const T ci = exp_ / msi;
+                    T lg[3] = {T(0), T(0), T(0)};
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) {
+                        if (!nin[q]) continue;
+                        const int64_t nc = cell + noff[q];
+                        const T msn = ms_at(Ms, Ms_s, nc);
+                        if (!(msn > T(0))) continue;
+                        const T cn = exp_ / msn;
+#pragma unroll
+                        for (int c = 0; c < 3; ++c) lg[c] += (cn * gh[nc * 3 + c] - ci * gi[c]) * id2[q >> 1];
+                    }
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) gm[c] += lg[c];
+                    gms -= (gi[0] * hex[0] + gi[1] * hex[1] + gi[2] * hex[2]) / msi;
+                }
+                T *go = reinterpret_cast<T *>(a.g_m) + cell * 3;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) go[c] = gm[c];
+                if (a.g_Ms) {
+                    T *gM = reinterpret_cast<T *>(a.g_Ms) + cell;
+                    gM[0] = a.acc_gMs ? gM[0] + gms : gms;
+                }
+            }
+        }
+    }
+    if (EPI == EPI_HEFF && a.epart) {
+        // fixed-order block reduction of the two FP64 partial sums
+        double *red = reinterpret_cast<double *>(smem + a.g.P * 0);  // reuse LDS after the barrier
+        __syncthreads();
+        for (int off = 32; off > 0; off >>= 1) {
+            ed += __shfl_down(ed, off, 64);
+            ex += __shfl_down(ex, off, 64);
+        }
+        const int lane = tid & 63, wv = tid >> 6;
+        if (lane == 0) { red[2 * wv] = ed; red[2 * wv + 1] = ex; }
+        __syncthreads();
+        if (tid == 0) {
+            double s0 = 0.0, s1 = 0.0;
+            const int nw = (blockDim.x + 63) / 64;
+            for (int w = 0; w < nw; ++w) { s0 += red[2 * w]; s1 += red[2 * w + 1]; }
+            a.epart[2 * (int64_t)blk] = s0;
+            a.epart[2 * (int64_t)blk + 1] = s1;
+        }
+    }
+    if (EPI == EPI_STAGE && a.next_r2c) {
+        // zero the padding rows and the unused half of an odd last line, then
+        // transform the next stage's source along z
+        if (tid < g.nthr) {
+            const C zc = cmake<C>(T(0), T(0));
+            const int pad = L - nz;
+            for (int e = tid; e < nlc * pad; e += g.nthr) {
+                const int u = e / pad, k = nz + (e - u * pad);
+                lds[u * pitch + k] = zc;
+            }
+            if (nlr & 1) {
+                for (int k = tid; k < nz; k += g.nthr) reinterpret_cast<T *>(&lds[(nlc - 1) * pitch + k])[1] = T(0);
+            }
+        }
+        __syncthreads();
+        zfwd_tail<T>(lds, g, pos0, wp, tid, ltid);
+    }
+}
+
+template <typename T, int SRC>
+__global__ void __launch_bounds__(1024) k_zfwd(const ZFwdArgs a) { zfwd_body<T, SRC>(a, xcd_tile(blockIdx.x, gridDim.x)); }
+
+template <typename T, int SRC>
+__global__ void __launch_bounds__(1024) k_zfwd_b(const ZFwdArgs *__restrict__ d, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    zfwd_body<T, SRC>(d[e.x], (uint32_t)e.y);
+}
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(1024) k_zinv(const ZInvArgs a) { zinv_body<T, EPI>(a, xcd_tile(blockIdx.x, gridDim.x)); }
+
+template <typename T, int EPI>
+__global__ void __launch_bounds__(1024) k_zinv_b(const ZInvArgs *__restrict__ d, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    zinv_body<T, EPI>(d[e.x], (uint32_t)e.y);
+}
+
+// deterministic final sum of the per-block energy partials (one block)
+__global__ void __launch_bounds__(256) k_energy_reduce(const double *__restrict__ part, int nblk, double *out) {
+    __shared__ double r0[256], r1[256];
+    double s0 = 0.0, s1 = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += 256) { s0 += part[2 * b]; s1 += part[2 * b + 1]; }
+    r0[threadIdx.x] = s0;
+    r1[threadIdx.x] = s1;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) { r0[threadIdx.x] += r0[threadIdx.x + w]; r1[threadIdx.x] += r1[threadIdx.x + w]; }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) { out[0] = r0[0]; out[1] = r1[0]; }
+}
+
+template <typename T>
+hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s) {
+    if (a.g.tiles <= 0) return hipSuccess;
+    switch (src_mode) {
+    case SRC_MS_M: hipLaunchKernelGGL((k_zfwd<T, SRC_MS_M>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    case SRC_RAW: hipLaunchKernelGGL((k_zfwd<T, SRC_RAW>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    default: hipLaunchKernelGGL((k_zfwd<T, SRC_ADJPRE>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s) {
+    if (a.g.tiles <= 0) return hipSuccess;
+    switch (epi) {
+    case EPI_HEFF: hipLaunchKernelGGL((k_zinv<T, EPI_HEFF>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    case EPI_STAGE: hipLaunchKernelGGL((k_zinv<T, EPI_STAGE>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    default: hipLaunchKernelGGL((k_zinv<T, EPI_ADJ>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zfwd_batch(const ZFwdArgs *d, const int2 *map, int tiles, int nthr, int src_mode, size_t lds_bytes,
+                             hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    switch (src_mode) {
+    case SRC_MS_M: hipLaunchKernelGGL((k_zfwd_b<T, SRC_MS_M>), dim3(tiles), dim3(nthr), lds_bytes, s, d, map); break;
+    case SRC_RAW: hipLaunchKernelGGL((k_zfwd_b<T, SRC_RAW>), dim3(tiles), dim3(nthr), lds_bytes, s, d, map); break;
+    default: hipLaunchKernelGGL((k_zfwd_b<T, SRC_ADJPRE>), dim3(tiles), dim3(nthr), lds_bytes, s, d, map); break;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zinv_batch(const ZInvArgs *d, const int2 *map, int tiles, int nthr, int epi, size_t lds_bytes,
+                             hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    switch (epi) {
+    case EPI_HEFF: hipLaunchKernelGGL((k_zinv_b<T, EPI_HEFF>), dim3(tiles), dim3(nthr), lds_bytes, s, d, map); break;
+    case EPI_STAGE: hipLaunchKernelGGL((k_zinv_b<T, EPI_STAGE>), dim3(tiles), dim3(nthr), lds_bytes, s, d, map); break;
+    default: hipLaunchKernelGGL((k_zinv_b<T, EPI_ADJ>), dim3(tiles), dim3(nthr), lds_bytes, s, d, map); break;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_zfwd_batch<float>(const ZFwdArgs *, const int2 *, int, int, int, size_t, hipStream_t);
+template hipError_t launch_zfwd_batch<double>(const ZFwdArgs *, const int2 *, int, int, int, size_t, hipStream_t);
+template hipError_t launch_zinv_batch<float>(const ZInvArgs *, const int2 *, int, int, int, size_t, hipStream_t);
+template hipError_t launch_zinv_batch<double>(const ZInvArgs *, const int2 *, int, int, int, size_t, hipStream_t);
+
+hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
+
+template hipError_t launch_zfwd<float>(const ZFwdArgs &, int, size_t, hipStream_t);
+template hipError_t launch_zfwd<double>(const ZFwdArgs &, int, size_t, hipStream_t);
+template hipError_t launch_zinv<float>(const ZInvArgs &, int, size_t, hipStream_t);
+template hipError_t launch_zinv<double>(const ZInvArgs &, int, size_t, hipStream_t);
+
+}  // namespace mmx

@@ -1,0 +1,37 @@
+// Launch wrappers of the HIP kernels (host-callable).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "passes.hpp"
+
+namespace mmx {
+
+template <typename T>
+hipError_t launch_line_pass(const LinePass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes, int dir,
+                            bool sym, hipStream_t s);
+template <typename T>
+hipError_t launch_fused_x(const FusedPass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
+                          hipStream_t s);
+template <typename T> hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s);
+template <typename T> hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s);
+template <typename T>
+hipError_t launch_zfwd_batch(const ZFwdArgs *d, const int2 *map, int tiles, int nthr, int src_mode, size_t lds_bytes,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_zinv_batch(const ZInvArgs *d, const int2 *map, int tiles, int nthr, int epi, size_t lds_bytes,
+                             hipStream_t s);
+hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s);
+hipError_t launch_tensor_octant(double *out, int nx, int ny, int nz, double dx, double dy, double dz, double P,
+                                hipStream_t s);
+template <typename T>
+hipError_t launch_tensor_finalize(const double *in, T *out, int hx, int hy, int hz, double inv_ltot, hipStream_t s);
+template <typename T> hipError_t launch_tensor_export(const T *in, double *out, int hx, int hy, int hz, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_unorm(const T *g, const T *u, T *ub, T *gsum, int renorm, int64_t ncell, hipStream_t s);
+template <typename T>
+hipError_t launch_adj_combine(const T *ym, const T *gmh, const T *ub, T *gsum, T *kb, double w, double coef, int64_t n,
+                              hipStream_t s);
+
+template <typename T> hipError_t launch_scale_copy(const T *in, T *out, double s, int64_t n, hipStream_t st);
+
+}  // namespace mmx

@@ -1,0 +1,88 @@
+// Descriptors shared by the host planner and the pass kernels.  Every pass is
+// a launch over tiles; a descriptor holds one geometry's view of the pass, and
+// a batched launch maps each tile to (descriptor, local tile).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include "fft_device.hpp"
+
+namespace mmx {
+
+// Strided line transform: lines along one axis, batch columns contiguous.
+//   element (outer o, row r, column c) sits at  base + o*outer_stride + r*row + c
+// (complex units for complex data, real units in the symmetric mode).
+struct LinePass {
+    const void *in;
+    void *out;
+    const void *tw;            // twiddle table of f
+    int64_t in_row, out_row, in_outer, out_outer;
+    int inner, outer;          // columns per outer index, number of outer indices
+    int n_in, n_out;           // rows read (rest zero), rows written
+    int W, tiles_inner;        // columns per tile, tiles per outer index
+    int pitch, nthr;           // LDS line pitch (complex), threads used
+    int sym_axis;              // symmetric real transform: parity axis (0,1,2)
+    int pad_;
+    FftDesc f;
+};
+
+// Fused pass along x: forward FFT, 3x3 spectral product with the stored
+// tensor, inverse FFT; in place on S2 laid out [x][position][component].
+struct FusedPass {
+    void *data;
+    const void *tensor;        // [ky'][kz][kx'][6], pre-scaled
+    const void *tw;
+    int64_t row;               // stride between x rows (complex units)
+    int npos;                  // positions (ky, kz) per x row = Ly*hz
+    int n;                     // rows present (nx)
+    int Ly, hz, hx;            // spectral extents (hx = Lx/2+1)
+    int W, tiles, pitch, nthr; // positions per tile, tiles, LDS pitch, threads
+    FftDesc f;                 // length Lx
+};
+
+// Field constants for the z passes and the fused epilogue.
+struct ZGeom {
+    int nx, ny, nz, Lz, hz;
+    int P, tiles, pitch, nthr; // positions (x,y columns) per tile, ...
+    int pad_;
+    FftDesc f;                 // length Lz
+    const void *tw;
+    void *S1;                  // [pos][kz][c]
+};
+
+enum SrcMode { SRC_MS_M = 0, SRC_RAW = 1, SRC_ADJPRE = 2 };
+
+// Arguments of the z-forward (R2C) pass.
+struct ZFwdArgs {
+    ZGeom g;
+    const void *src;           // (nx,ny,nz,3)
+    const void *Ms;            // per-cell or null
+    double Ms_scalar;
+    // SRC_ADJPRE: y = VJP of the LLG right-hand side at (s, h) for cotangent kb
+    const void *s, *h, *kb;
+    void *ym, *yh;
+    double gp, alpha;          // gamma/(1+alpha^2), alpha
+};
+
+enum EpiMode { EPI_HEFF = 0, EPI_STAGE = 1, EPI_ADJ = 2 };
+
+// Arguments of the z-inverse (C2R) pass and its epilogue.
+struct ZInvArgs {
+    ZGeom g;
+    unsigned terms;            // MM_DEMAG | MM_EXCHANGE bits
+    const void *Ms; double Ms_scalar;
+    double ex_pref;            // 2A/mu0
+    double inv_d2[3];
+    double hext[3];
+    // heff
+    const void *m; void *h_out; double *epart;  // epart: per-block (E_d, E_ex) partials or null
+    // stage
+    int stage;                 // 0..3
+    int next_r2c;              // write the next stage's z spectrum into S1
+    int renorm;
+    double dt, gp, alpha;
+    const void *ms_in, *m_n; void *acc, *ms_out, *m_out, *h_rec, *u_rec;
+    // adjoint
+    const void *g_h; void *g_m, *g_Ms; int acc_gMs;
+};
+
+}  // namespace mmx

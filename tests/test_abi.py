@@ -1,0 +1,95 @@
+"""The C ABI library loads, exports every declared symbol, and rejects bad
+arguments on the host before touching a GPU (no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "mmx.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:int|const char \*)\s*(\w+)\s*\(", src, flags=re.M)))
+
+
+def test_header_declarations_are_exported():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(_lib.EXPORTS) == names
+
+
+def test_strerror():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    assert L.mm_strerror(0) == b"ok"
+    assert L.mm_strerror(-1) == b"invalid argument"
+    assert L.mm_strerror(-99) == b"unknown status"
+
+
+def _init(grid, cell, prec=1, opts=None):
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    h = ctypes.c_void_p()
+    g = (ctypes.c_int64 * 3)(*grid)
+    c = (ctypes.c_double * 3)(*cell)
+    return L.demag_tensor_init(ctypes.byref(h), g, c, prec, None, opts), h
+
+
+@pytest.mark.parametrize("grid,cell,prec", [
+    ((0, 4, 4), (1e-9, 1e-9, 1e-9), 1),
+    ((4, -1, 4), (1e-9, 1e-9, 1e-9), 1),
+    ((4, 4, 4), (1e-9, 0.0, 1e-9), 1),
+    ((4, 4, 4), (1e-9, float("nan"), 1e-9), 1),
+    ((4, 4, 4), (1e-9, 1e-9, 1e-9), 3),
+])
+def test_init_rejects_bad_arguments(grid, cell, prec):
+    from paper_2606_01114_amd import _lib
+    rc, h = _init(grid, cell, prec)
+    assert rc == _lib.MM_EINVAL and not h.value
+    assert len(_lib.lib().mm_last_error()) > 0
+
+
+def test_init_rejects_bad_padding():
+    from paper_2606_01114_amd import _lib
+    o = _lib.PlanOpts()
+    assert _lib.lib().mm_plan_opts_default(ctypes.byref(o)) == 0
+    assert o.far_radius == 16.0
+    o.L[0] = 11                                   # 11 is not 7-smooth
+    rc, _ = _init((4, 4, 4), (1e-9, 1e-9, 1e-9), 1, ctypes.byref(o))
+    assert rc == _lib.MM_EINVAL
+    o.L[0] = 6                                    # < 2n - 1
+    rc, _ = _init((4, 4, 4), (1e-9, 1e-9, 1e-9), 1, ctypes.byref(o))
+    assert rc == _lib.MM_EINVAL
+    o.L[0] = 0
+    o.autotune = 7
+    rc, _ = _init((4, 4, 4), (1e-9, 1e-9, 1e-9), 1, ctypes.byref(o))
+    assert rc == _lib.MM_EINVAL
+
+
+def test_calls_on_null_plan():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(16)
+    assert L.h_eff(None, dummy, None, 8e5, 1e-11, dummy, 3, None) == _lib.MM_EINVAL
+    assert L.llg_step(None, dummy, None, 8e5, 1e-11, 0.1, 2.2e5, 1e-13, 1, None, 0) == _lib.MM_EINVAL
+    assert L.h_eff_adjoint(None, dummy, None, 8e5, 1e-11, dummy, dummy, None, 3) == _lib.MM_EINVAL
+    assert L.mm_plan_destroy(None) == _lib.MM_EINVAL
+    assert L.mm_batch_destroy(None) == _lib.MM_EINVAL
+    h = ctypes.c_void_p()
+    assert L.mm_batch_create(ctypes.byref(h), 0, None, None, 1, None, None) == _lib.MM_EINVAL
+
+
+def test_no_gpu_is_a_hip_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    from paper_2606_01114_amd import _lib
+    rc, h = _init((4, 4, 2), (1e-9, 1e-9, 1e-9), 1)
+    assert rc == _lib.MM_EHIP and not h.value

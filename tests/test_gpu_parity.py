@@ -1,0 +1,231 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Bars: FP64 within 1e-12 relative L2 with the demag tensor held equal (the
+oracle's real-space octant is loaded with mm_demag_tensor_set and transformed
+by the GPU); FP32 within 1e-5 relative L2 against the FP64 oracle with the
+GPU's own tensor, for the full field and for the demag part alone.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import rel_l2, rounded, to_dev
+
+pytestmark = pytest.mark.gpu
+
+MS, A = 8e5, 1.3e-11
+GAMMA, ALPHA = 2.211e5, 0.02
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _plan(n, d, prec, L=None, hold=None, P=16.0):
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    plan = DemagPlan(n, d, prec, L=L, far_radius=P)
+    if hold is not None:
+        plan.tensor_set(hold)
+    dt = torch.float32 if prec == "f32" else torch.float64
+    return plan, dt
+
+
+CASES = [  # (grid, cell, L override)
+    ((4, 4, 2), (2e-9, 2e-9, 2e-9), None),
+    ((32, 32, 4), (2e-9, 2e-9, 2e-9), None),
+    ((7, 5, 3), (2.5e-9, 2e-9, 3e-9), (14, 9, 5)),
+    ((9, 6, 1), (2.5e-9, 2.5e-9, 3e-9), (18, 12, 1)),
+    ((1, 6, 5), (2e-9, 2e-9, 1e-9), None),
+    ((5, 1, 4), (2e-9, 2e-9, 1e-9), (9, 1, 7)),
+    ((53, 20, 3), (2.5e-9, 2.5e-9, 3e-9), None),
+    ((1, 1, 1), (2e-9, 2e-9, 2e-9), None),
+]
+
+
+@pytest.mark.parametrize("grid,cell,L", CASES)
+def test_h_eff_fp64_tensor_held_equal(grid, cell, L):
+    _say("case", grid, cell, L)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, "f64", L=L, hold=oct_)
+    Lp = plan.info()["L"]
+    m0 = synth.random_unit(grid, 1)
+    Msv = synth.ms_field(grid, 2)
+    for Ms in (MS, Msv):
+        m = to_dev(m0, dt)
+        Msd = to_dev(Ms, dt) if isinstance(Ms, np.ndarray) else Ms
+        for terms, dm, ex in ((3, True, True), (1, True, False), (2, False, True)):
+            h = plan.h_eff(m, Msd, A, terms=terms).cpu().numpy()
+            ref = oracle.h_eff(m0, Ms, A, cell, oct_, Lp, demag=dm, exchange=ex)
+            if np.linalg.norm(ref) == 0:
+                assert np.abs(h).max() == 0
+                continue
+            e = rel_l2(h, ref)
+            assert e <= 1e-12, (terms, e)
+
+
+@pytest.mark.parametrize("grid,cell,L", CASES[:4] + CASES[6:7])
+def test_h_eff_fp32_against_oracle(grid, cell, L):
+    _say("case", grid, cell, L)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, "f32", L=L)
+    Lp = plan.info()["L"]
+    m0 = rounded(synth.random_unit(grid, 1), dt)
+    m = to_dev(m0, dt)
+    h = plan.h_eff(m, MS, A).cpu().numpy()
+    assert rel_l2(h, oracle.h_eff(m0, MS, A, cell, oct_, Lp)) <= 1e-5
+    hd = plan.h_eff(m, MS, A, terms=1).cpu().numpy()
+    assert rel_l2(hd, oracle.demag_fft(m0, MS, oct_, Lp)) <= 1e-5
+
+
+def test_direct_sum_brute_force_4x4x2():
+    grid, cell = (4, 4, 2), (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant(grid, cell)
+    m0 = synth.random_unit(grid, 11)
+    ref = oracle.demag_direct(m0, MS, oct_)
+    plan, dt = _plan(grid, cell, "f64", hold=oct_)
+    h = plan.h_eff(to_dev(m0, dt), MS, A, terms=1).cpu().numpy()
+    assert rel_l2(h, ref) <= 1e-12
+    plan32, dt32 = _plan(grid, cell, "f32")
+    m32 = rounded(m0, dt32)
+    h32 = plan32.h_eff(to_dev(m32, dt32), MS, A, terms=1).cpu().numpy()
+    assert rel_l2(h32, oracle.demag_direct(m32, MS, oct_)) <= 1e-5
+
+
+@pytest.mark.parametrize("grid,cell", [((32, 32, 4), (2e-9, 2e-9, 2e-9)), ((20, 12, 6), (2.5e-9, 2.5e-9, 3e-9)),
+                                       ((40, 3, 2), (1e-9, 3e-9, 0.5e-9))])
+def test_gpu_tensor_octant_and_spectrum(grid, cell):
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, _ = _plan(grid, cell, "f64")
+    g = plan.tensor_get()
+    # near field: FP64 Newell loses digits to cancellation; bound each entry by
+    # the cancellation scale sum|w f|/(4 pi V) of its stencil
+    dmax = max(cell)
+    for idx in np.ndindex(*grid):
+        r = np.sqrt(sum((idx[a] * cell[a]) ** 2 for a in range(3)))
+        if r <= 16 * dmax:
+            sc = oracle.newell_scale_at(*idx, cell)
+            assert np.all(np.abs(g[idx] - oct_[idx]) <= 64 * 2.2e-16 * sc + 1e-300), idx
+    far = np.array([np.sqrt(sum((i[a] * cell[a]) ** 2 for a in range(3))) > 16 * dmax for i in np.ndindex(*grid)]).reshape(grid)
+    if far.any():
+        d = np.abs(g[far] - oct_[far]).max() / np.abs(oct_[far]).max()
+        assert d <= 1e-14
+    # spectrum of the held tensor vs the oracle's DFT of the wrapped octant
+    plan.tensor_set(oct_)
+    L = plan.info()["L"]
+    S = plan.spectrum_get()
+    ref = oracle.tensor_spectrum(oct_, L).real
+    h = [v // 2 + 1 for v in L]
+    ref = ref[:, :h[0], :h[1], :h[2]]
+    ref = np.moveaxis(ref, 0, -1) * (-1.0 / np.prod(L))
+    assert np.abs(S - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_energies():
+    grid, cell = (20, 12, 6), (2.5e-9, 2.5e-9, 3e-9)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, "f64", hold=oct_)
+    L = plan.info()["L"]
+    m0 = synth.random_unit(grid, 3)
+    Ms = synth.ms_field(grid, 4)
+    _, (ed, ex) = plan.h_eff(to_dev(m0, dt), to_dev(Ms, dt), A, energy=True)
+    hd = oracle.demag_fft(m0, Ms, oct_, L)
+    hx = oracle.exchange_field(m0, Ms, A, cell)
+    red, rex = oracle.energies(m0, Ms, hd, hx, cell)
+    assert abs(ed - red) <= 1e-12 * abs(red) and abs(ex - rex) <= 1e-12 * abs(rex)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_llg_step_increment(prec):
+    grid, cell = (32, 32, 4), (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, prec, hold=oct_ if prec == "f64" else None)
+    L = plan.info()["L"]
+    m0 = rounded(synth.random_unit(grid, 1), dt)
+    Msv = rounded(synth.ms_field(grid, 2), dt)
+    for Ms, hext in ((MS, None), (Msv, (1e4, -2e4, 3e4))):
+        m = to_dev(m0, dt)
+        Msd = to_dev(Ms, dt) if isinstance(Ms, np.ndarray) else Ms
+        plan.llg_step(m, Msd, A, ALPHA, GAMMA, 1e-13, n_steps=2, h_ext=hext)
+        ref = oracle.rk4_run(m0, 2, Ms, A, cell, oct_, L, ALPHA, GAMMA, 1e-13, h_ext=hext)
+        e = rel_l2(m.cpu().numpy() - m0, ref - m0)
+        assert e <= (1e-11 if prec == "f64" else 1e-5), e
+
+
+def test_llg_no_renorm_and_graph_equivalence():
+    import torch
+    grid, cell = (16, 10, 3), (2.5e-9, 2.5e-9, 3e-9)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, "f64", hold=oct_)
+    L = plan.info()["L"]
+    m0 = synth.random_unit(grid, 5)
+    a = to_dev(m0, dt)
+    b = to_dev(m0, dt)
+    plan.llg_step(a, MS, A, ALPHA, GAMMA, 1e-13, n_steps=3, renorm=False)
+    plan.llg_step(b, MS, A, ALPHA, GAMMA, 1e-13, n_steps=3, renorm=False, graph=False)
+    assert torch.equal(a, b)
+    ref = oracle.rk4_run(m0, 3, MS, A, cell, oct_, L, ALPHA, GAMMA, 1e-13, renorm=False)
+    assert rel_l2(a.cpu().numpy() - m0, ref - m0) <= 1e-11
+
+
+def test_macrospin_closed_form():
+    grid, cell = (1, 1, 1), (2e-9, 2e-9, 2e-9)
+    plan, dt = _plan(grid, cell, "f64")
+    th0, ph0, H, alpha = 1.0, 0.3, 2e5, 0.1
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(1, 1, 1, 3)
+    m = to_dev(m0, dt)
+    plan.llg_step(m, MS, A, alpha, GAMMA, 1e-13, n_steps=400, h_ext=(0, 0, H))
+    ref = oracle.macrospin_closed_form(th0, ph0, H, alpha, GAMMA, 400e-13)
+    assert np.abs(m.cpu().numpy().reshape(3) - ref).max() < 1e-10
+
+
+def test_determinism():
+    import torch
+    grid, cell = (32, 32, 4), (2e-9, 2e-9, 2e-9)
+    plan, dt = _plan(grid, cell, "f32")
+    m0 = synth.random_unit(grid, 1)
+    m = to_dev(m0, dt)
+    h1 = plan.h_eff(m, MS, A)
+    h2 = plan.h_eff(m, MS, A)
+    assert torch.equal(h1, h2)
+    a, b = to_dev(m0, dt), to_dev(m0, dt)
+    plan.llg_step(a, MS, A, ALPHA, GAMMA, 1e-13, n_steps=2)
+    plan.llg_step(b, MS, A, ALPHA, GAMMA, 1e-13, n_steps=2)
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_h_eff_adjoint(prec):
+    grid, cell = (12, 10, 3), (2.5e-9, 2.5e-9, 3e-9)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, prec, hold=oct_ if prec == "f64" else None)
+    L = plan.info()["L"]
+    m0 = rounded(synth.random_unit(grid, 1), dt)
+    Ms = rounded(synth.ms_field(grid, 5), dt)
+    g = rounded(synth.random_unit(grid, 3), dt)
+    gm, gMs = plan.h_eff_adjoint(to_dev(m0, dt), to_dev(Ms, dt), A, to_dev(g, dt))
+    rm, rMs = oracle.h_eff_vjp(m0, Ms, A, cell, oct_, L, g)
+    tol = 1e-12 if prec == "f64" else 1e-5
+    assert rel_l2(gm.cpu().numpy(), rm) <= tol
+    assert rel_l2(gMs.cpu().numpy(), rMs) <= tol
+
+
+def test_llg_step_adjoint_fp64():
+    grid, cell = (12, 10, 3), (2.5e-9, 2.5e-9, 3e-9)
+    oct_ = oracle.tensor_octant(grid, cell)
+    plan, dt = _plan(grid, cell, "f64", hold=oct_)
+    L = plan.info()["L"]
+    m0 = synth.smooth_film(grid, cell, 5)
+    Ms = synth.ms_field(grid, 5)
+    g0 = synth.random_unit(grid, 7)
+    g = to_dev(g0, dt)
+    import torch
+    gMs = torch.zeros(grid, dtype=dt, device="cuda")
+    plan.llg_step_adjoint(to_dev(m0, dt), to_dev(Ms, dt), A, ALPHA, GAMMA, 1e-13, g, gMs)
+    rm, rMs = oracle.rk4_step_vjp(m0, Ms, A, cell, oct_, L, ALPHA, GAMMA, 1e-13, g0)
+    assert rel_l2(g.cpu().numpy(), rm) <= 1e-11
+    assert rel_l2(gMs.cpu().numpy(), rMs) <= 1e-10
