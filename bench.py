@@ -1,0 +1,285 @@
+"""Benchmark: RK4 LLG steps (each = 4 h_eff evaluations: demag by pruned FFT
+convolution with the Newell tensor + exchange, fused with the stage updates)
+on one MI355X, through the HIP C ABI.
+
+Default workload: 1024 x 1024 x 128 cells (134,217,728), cell 2.5 x 2.5 x 3 nm,
+zero-padded 2048 x 2048 x 256, Ms 8e5 A/m, A 1.3e-11 J/m, alpha 0.02, dt 1e-13 s,
+m = 3D Voronoi grains of 20 nm mean spacing with a random unit vector each,
+FP32, FP64 tensor setup timed separately; the same workload in FP64 is timed
+too.  Prints one JSON line.
+"""
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK = 8.0e12   # MI355X HBM3E, bytes/s
+METRIC = "Mcell-updates/s of h_eff+LLG step, FP32 vs FP64 at stated error; % HBM roofline"
+
+WORKLOADS = {
+    "large": dict(grid=(1024, 1024, 128), cell=(2.5e-9, 2.5e-9, 3e-9), m="voronoi", seed=3,
+                  name="single grid 1024x1024x128 (134M cells, padded 2048x2048x256), Voronoi grains 20 nm, "
+                       "h_eff + RK4 LLG step, FP64 tensor setup timed separately"),
+    "film": dict(grid=(512, 512, 16), cell=(2.5e-9, 2.5e-9, 3e-9), m="smooth", seed=2,
+                 name="thin film 512x512x16 (padded 1024x1024x32), smooth texture + 1% noise, RK4 LLG steps"),
+    "small": dict(grid=(32, 32, 4), cell=(2e-9, 2e-9, 2e-9), m="random", seed=1,
+                  name="32x32x4 (padded 64x64x8), random unit m"),
+}
+MS, A, ALPHA, GAMMA, DT = 8e5, 1.3e-11, 0.02, 2.211e5, 1e-13
+PASS_NAMES = ["z_fwd", "y_fwd", "x_fused", "y_inv", "z_inv_stage", "z_inv_heff"]
+KERNEL_SYMBOL = {"z_fwd": "k_zfwd", "y_fwd": "k_line_pass", "x_fused": "k_fused_x", "y_inv": "k_line_pass",
+                 "z_inv_stage": "k_zinv", "z_inv_heff": "k_zinv"}
+
+
+def pass_bytes(grid, L, r):
+    """Algorithmic HBM bytes per launch of each pass: every array the pass must
+    read or write, once (no padding is ever materialised)."""
+    nx, ny, nz = grid
+    Lx, Ly, Lz = L
+    c = 2 * r
+    hx, hy, hz = Lx // 2 + 1, Ly // 2 + 1, Lz // 2 + 1
+    N3 = 3 * nx * ny * nz
+    S1 = 3 * nx * ny * hz
+    S2 = 3 * nx * Ly * hz
+    T6 = 6 * hx * hy * hz
+    b = {
+        "z_fwd": r * N3 + c * S1,
+        "y_fwd": c * (S1 + S2),
+        "x_fused": 2 * c * S2 + r * T6,
+        "y_inv": c * (S2 + S1),
+        # stage 1/2 of RK4: read S1, m_s, m_n, acc; write m_s', acc, S1 (next stage z spectrum)
+        "z_inv_stage": c * S1 + 3 * r * N3 + 2 * r * N3 + c * S1,
+        "z_inv_heff": c * S1 + r * N3 + r * N3,
+    }
+    stage = [c * S1 + r * N3 + 2 * r * N3 + c * S1,          # stage 0: m_s = m_n, writes acc, m_s'
+             b["z_inv_stage"], b["z_inv_stage"],
+             c * S1 + 3 * r * N3 + r * N3]                   # stage 3: writes m_n
+    step = b["z_fwd"] + 4 * (b["y_fwd"] + b["x_fused"] + b["y_inv"]) + sum(stage)
+    return b, step
+
+
+def make_m(w):
+    import numpy as np
+    import synth
+    if w["m"] == "voronoi":
+        # the grain assignment of 134M cells takes a minute; keep one copy per
+        # host in the temp directory for repeated runs
+        import tempfile
+        key = "mmx_voronoi_%s_%s_%d.npy" % ("x".join(map(str, w["grid"])), "_".join("%g" % c for c in w["cell"]), w["seed"])
+        path = os.path.join(tempfile.gettempdir(), key)
+        if os.path.exists(path):
+            return np.load(path, mmap_mode="r")
+        m = synth.voronoi_grains(w["grid"], w["cell"], w["seed"])
+        try:
+            np.save(path + ".tmp.npy", m)
+            os.replace(path + ".tmp.npy", path)
+        except OSError:
+            pass
+        return m
+    if w["m"] == "smooth":
+        return synth.smooth_film(w["grid"], w["cell"], w["seed"])
+    return synth.random_unit(w["grid"], w["seed"])
+
+
+def src_hash():
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_01114_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel, workload, prec):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(p) as f:
+            t = json.load(f)
+        e = t.get("%s/%s/%s" % (workload, prec, kernel))
+        if e and e.get("src_hash") == src_hash():
+            return e["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    return None
+
+
+def run_gpu(wname, prec, steps, warmup, m_host):
+    import torch
+    from paper_2606_01114_amd import DemagPlan, _lib
+    w = WORKLOADS[wname]
+    dt = torch.float32 if prec == "f32" else torch.float64
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = DemagPlan(w["grid"], w["cell"], prec)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    L = plan.info()["L"]
+    m = torch.tensor(m_host, dtype=dt).to("cuda")
+    for _ in range(warmup):
+        plan.llg_step(m, MS, A, ALPHA, GAMMA, DT, n_steps=1)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record()
+    plan.llg_step(m, MS, A, ALPHA, GAMMA, DT, n_steps=steps)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    # h_eff alone
+    h = torch.empty_like(m)
+    plan.h_eff(m, MS, A, out=h)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(max(3, steps)):
+        plan.h_eff(m, MS, A, out=h)
+    e1.record()
+    torch.cuda.synchronize()
+    heff_ms = e0.elapsed_time(e1) / max(3, steps)
+    # per-pass durations, HIP events on the plan stream
+    ms = (ctypes.c_double * 6)()
+    _lib.check(_lib.lib().mm_plan_time_passes(plan._h, 5, ms))
+    passes = dict(zip(PASS_NAMES, list(ms)))
+    finite = bool(torch.isfinite(m).all().item())
+    plan.close()
+    del m, h
+    torch.cuda.empty_cache()
+    return dict(setup_s=setup_s, wall_s=wall, ev_ms=ev_ms, heff_ms=heff_ms, passes=passes, L=L, finite=finite)
+
+
+def copy_bandwidth():
+    import torch
+    from paper_2606_01114_amd import _lib
+    n = 1 << 30
+    a = torch.empty(n, dtype=torch.uint8, device="cuda")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda")
+    s = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    for _ in range(3):
+        _lib.check(_lib.lib().mm_device_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), n, s))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        _lib.check(_lib.lib().mm_device_copy(ctypes.c_void_p(b.data_ptr()), ctypes.c_void_p(a.data_ptr()), n, s))
+    e1.record()
+    torch.cuda.synchronize()
+    return 2.0 * n * 10 / (e0.elapsed_time(e1) * 1e-3)
+
+
+def cpu_baseline(w, budget_s=20.0):
+    """The oracle as it stands, on a bounded sub-grid of the same workload."""
+    import numpy as np
+    import oracle
+    import synth
+    nx, ny, nz = w["grid"]
+    sub = (min(nx, 64), min(ny, 64), min(nz, 32))
+    if w["m"] == "voronoi":
+        m0 = synth.voronoi_grains(sub, w["cell"], w["seed"])
+    elif w["m"] == "smooth":
+        m0 = synth.smooth_film(sub, w["cell"], w["seed"])
+    else:
+        m0 = synth.random_unit(sub, w["seed"])
+    oct_ = oracle.tensor_octant(sub, w["cell"])
+    L = tuple(oracle.default_L(v) for v in sub)
+    t0 = time.perf_counter()
+    steps = 0
+    m = m0
+    while True:
+        m = oracle.rk4_step(m, MS, A, w["cell"], oct_, L, ALPHA, GAMMA, DT)
+        steps += 1
+        if time.perf_counter() - t0 > budget_s or steps >= 50:
+            break
+    el = time.perf_counter() - t0
+    cells = int(np.prod(sub))
+    return {"value": cells * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d RK4 steps of the FP64 oracle (numpy FFT, single thread) on a %dx%dx%d sub-grid "
+                      "of the same recipe (%.1f s)" % (steps, sub[0], sub[1], sub[2], el)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="large", choices=sorted(WORKLOADS))
+    ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    if not torch.cuda.is_available():
+        print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
+        sys.exit(2)
+    w = WORKLOADS[args.workload]
+    print("# generating inputs: %s" % w["name"], file=sys.stderr, flush=True)
+    m_host = make_m(w)
+    ncell = int(np.prod(w["grid"]))
+    print("# timing %s" % args.prec, file=sys.stderr, flush=True)
+    res = run_gpu(args.workload, args.prec, args.steps, args.warmup, m_host)
+    r = 4 if args.prec == "f32" else 8
+    pb, step_bytes = pass_bytes(w["grid"], res["L"], r)
+    ms_step = res["ev_ms"] / args.steps
+    value = ncell * args.steps / (res["wall_s"]) / 1e6
+    launches = {"z_fwd": 1, "y_fwd": 4, "x_fused": 4, "y_inv": 4, "z_inv_stage": 4, "z_inv_heff": 0}
+    share = {k: res["passes"][k] * launches[k] for k in launches}
+    dom = max(share, key=share.get)
+    ach = pb[dom] / (res["passes"][dom] * 1e-3)
+    roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom] + " (" + dom + ")", "achieved": ach / 1e9,
+            "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach / HBM_PEAK,
+            "traffic": load_traffic(dom, args.workload, args.prec),
+            "algorithmic_bytes_per_launch": pb[dom], "launch_ms": res["passes"][dom]}
+    extra = {
+        "ms_per_step_events": ms_step,
+        "step_algorithmic_bytes": step_bytes,
+        "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK,
+        "heff_ms": res["heff_ms"], "heff_Mcell_per_s": ncell / (res["heff_ms"] * 1e-3) / 1e6,
+        "tensor_setup_s": res["setup_s"],
+        "pass_ms": res["passes"],
+        "pass_GBps": {k: pb[k] / (res["passes"][k] * 1e-3) / 1e9 for k in pb},
+        "padded_L": list(res["L"]),
+        "finite": res["finite"],
+    }
+    try:
+        extra["copy_GBps"] = copy_bandwidth() / 1e9
+    except Exception as ex:  # measurement aid only
+        extra["copy_GBps"] = None
+        print("# copy bandwidth failed: %s" % ex, file=sys.stderr)
+    if not args.no_fp64 and args.prec == "f32":
+        print("# timing f64", file=sys.stderr, flush=True)
+        s64 = max(2, args.steps // 2)
+        r64 = run_gpu(args.workload, "f64", s64, 1, m_host)
+        v64 = ncell * s64 / r64["wall_s"] / 1e6
+        pb64, sb64 = pass_bytes(w["grid"], r64["L"], 8)
+        extra["fp64"] = {"value": v64, "ms_per_step": r64["ev_ms"] / s64, "heff_ms": r64["heff_ms"],
+                         "step_hbm_frac": sb64 / (r64["ev_ms"] / s64 * 1e-3) / HBM_PEAK,
+                         "tensor_setup_s": r64["setup_s"], "pass_ms": r64["passes"]}
+        extra["fp32_over_fp64"] = value / v64
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["wall_s"] * 1e3 / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.prec, "data": "synthetic",
+        "config": {"workload": w["name"], "grid": list(w["grid"]), "cell_m": list(w["cell"]), "cells": ncell,
+                   "Ms": MS, "A": A, "alpha": ALPHA, "gamma": GAMMA, "dt": DT},
+        "roofline": roof,
+        "extra": extra,
+    }
+    if not args.no_cpu:
+        print("# cpu baseline (oracle)", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(w)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -194,6 +194,22 @@ int mm_batch_llg_step(mm_batch *b, void *const *m_ptrs, const double *Ms, double
 int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes);
 int mm_batch_destroy(mm_batch *b);
 
+/*
+ * Measurement hooks (used by the benchmark; no effect on results).
+ * mm_plan_time_passes runs each pass of the pipeline `reps` times on the plan
+ * stream between HIP events and writes the mean duration in ms of
+ *   ms_out[0] z-forward (real-to-complex along z, source Ms m)
+ *   ms_out[1] y-forward        ms_out[2] fused x (FFT, tensor product, IFFT)
+ *   ms_out[3] y-inverse        ms_out[4] z-inverse + RK4 stage epilogue
+ *   ms_out[5] z-inverse + h_eff epilogue
+ * on the plan's own scratch arrays (contents irrelevant).  Synchronises.
+ * mm_device_copy copies `bytes` (a multiple of 16) between device buffers with
+ * a plain streaming kernel on `hip_stream` (the reference for bandwidth and
+ * for hardware byte counters).
+ */
+int mm_plan_time_passes(mm_plan *plan, int reps, double ms_out[6]);
+int mm_device_copy(void *dst, const void *src, size_t bytes, void *hip_stream);
+
 /* Message for a status code (static storage). */
 const char *mm_strerror(int status);
 /* Detail of the last error on this thread (static thread-local storage). */

@@ -22,6 +22,7 @@ EXPORTS = [
     "h_eff", "llg_step", "h_eff_adjoint", "llg_step_adjoint",
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
     "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_info", "mm_batch_destroy",
+    "mm_plan_time_passes", "mm_device_copy",
     "mm_strerror", "mm_last_error",
 ]
 
@@ -62,6 +63,8 @@ def _load():
         "mm_batch_llg_step": [vp, ctypes.POINTER(vp), dp, cd, cd, cd, cd, ci, cu],
         "mm_batch_info": [vp, i64p, ctypes.POINTER(ctypes.c_size_t)],
         "mm_batch_destroy": [vp],
+        "mm_plan_time_passes": [vp, ci, dp],
+        "mm_device_copy": [vp, vp, ctypes.c_size_t, vp],
     }
     for name, args in sig.items():
         f = getattr(L, name)

@@ -578,6 +578,32 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
     return MM_OK;
 }
 
+// one launch of pass k on the plan's scratch arrays (timing only)
+template <typename T>
+int time_one(mm_plan *p, int k) {
+    switch (k) {
+    case 0: return run_zfwd<T>(p, SRC_MS_M, p->ms[0], nullptr, 8e5);
+    case 1: HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream)); return MM_OK;
+    case 2: HIPCK(launch_fused_x<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream)); return MM_OK;
+    case 3: HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream)); return MM_OK;
+    case 4: {
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, nullptr, 8e5, 1.3e-11);
+        a.stage = 1; a.next_r2c = 1; a.renorm = 1; a.dt = 1e-13; a.alpha = 0.02; a.gp = 2.2e5;
+        a.ms_in = p->ms[0]; a.m_n = p->ms[0]; a.acc = p->acc; a.ms_out = p->ms[1];
+        HIPCK(launch_zinv<T>(a, EPI_STAGE, p->lds_z, p->stream));
+        return MM_OK;
+    }
+    default: {
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, nullptr, 8e5, 1.3e-11);
+        a.m = p->ms[0]; a.h_out = p->ms[1];
+        HIPCK(launch_zinv<T>(a, EPI_HEFF, p->lds_z, p->stream));
+        return MM_OK;
+    }
+    }
+}
+
 }  // namespace
 
 // =============================== C ABI ======================================
@@ -761,6 +787,40 @@ int mm_demag_spectrum_get(mm_plan *p, double *host) {
     if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
     (void)hipFree(d);
     if (e != hipSuccess) return fail(MM_EHIP, "spectrum get: %s", hipGetErrorString(e));
+    return MM_OK;
+}
+
+int mm_plan_time_passes(mm_plan *p, int reps, double *ms) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (reps < 1 || !ms) return fail(MM_EINVAL, "reps must be >= 1 and ms_out non-NULL");
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    for (int k = 0; k < 6 && !rc; ++k) {
+        for (int pass = 0; pass < 2 && !rc; ++pass) {   // first round warms up
+            const int n = pass == 0 ? 1 : reps;
+            (void)hipEventRecord(e0, p->stream);
+            for (int r = 0; r < n && !rc; ++r) {
+                if (p->prec == MM_F32) rc = time_one<float>(p, k);
+                else rc = time_one<double>(p, k);
+            }
+            (void)hipEventRecord(e1, p->stream);
+            hipError_t e = hipEventSynchronize(e1);
+            if (e != hipSuccess) rc = fail(MM_EHIP, "time passes: %s", hipGetErrorString(e));
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, e0, e1);
+            ms[k] = (double)t / n;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+int mm_device_copy(void *dst, const void *src, size_t bytes, void *stream) {
+    if (!dst || !src || bytes % 16) return fail(MM_EINVAL, "dst/src non-NULL and bytes a multiple of 16");
+    HIPCK(launch_copy16(src, dst, (int64_t)(bytes / 16), (hipStream_t)stream));
     return MM_OK;
 }
 

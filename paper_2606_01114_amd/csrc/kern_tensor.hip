@@ -4,6 +4,7 @@
 // Also the element-wise kernels of the RK4 adjoint.
 #include "passes.hpp"
 #include "kernels.hpp"
+#include <algorithm>
 
 namespace mmx {
 
@@ -183,6 +184,12 @@ __global__ void __launch_bounds__(256) k_scale_copy(const T *__restrict__ in, T 
     out[t] = T(s) * in[t];
 }
 
+// plain streaming copy, 16 bytes per lane per iteration
+__global__ void __launch_bounds__(256) k_copy16(const float4 *__restrict__ src, float4 *__restrict__ dst, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) dst[i] = src[i];
+}
+
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
 hipError_t launch_tensor_octant(double *out, int nx, int ny, int nz, double dx, double dy, double dz, double P,
@@ -216,6 +223,13 @@ template <typename T>
 hipError_t launch_adj_combine(const T *ym, const T *gmh, const T *ub, T *gsum, T *kb, double w, double coef, int64_t n,
                               hipStream_t s) {
     hipLaunchKernelGGL((k_adj_combine<T>), dim3(nblk(n, 256)), dim3(256), 0, s, ym, gmh, ub, gsum, kb, w, coef, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s) {
+    if (n16 <= 0) return hipSuccess;
+    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 1024);
+    hipLaunchKernelGGL(k_copy16, dim3((unsigned)blocks), dim3(256), 0, s, (const float4 *)src, (float4 *)dst, n16);
     return hipGetLastError();
 }
 

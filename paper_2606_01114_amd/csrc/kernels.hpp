@@ -20,6 +20,7 @@ hipError_t launch_zfwd_batch(const ZFwdArgs *d, const int2 *map, int tiles, int 
 template <typename T>
 hipError_t launch_zinv_batch(const ZInvArgs *d, const int2 *map, int tiles, int nthr, int epi, size_t lds_bytes,
                              hipStream_t s);
+hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s);
 hipError_t launch_tensor_octant(double *out, int nx, int ny, int nz, double dx, double dy, double dz, double P,
                                 hipStream_t s);
