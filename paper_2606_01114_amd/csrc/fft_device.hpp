@@ -255,4 +255,103 @@ __device__ void lds_fft(cplx<T> *buf, int nlines, int pitch, const FftDesc &f, c
     }
 }
 
+
+// ---- compile-time plans for power-of-two lengths ---------------------------
+// Same factorisation as the host planner: radix-16 stages with an 8/4/2 tail
+// (an exponent = 1 mod 4 ends in 8, 4 rather than 16, 2).
+namespace ct {
+constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
+constexpr int nst(int L) {
+    const int p = ilog2(L), a = p / 4, rem = p % 4;
+    return p == 0 ? 0 : p == 1 ? 1 : (rem == 1 && a >= 1) ? a + 1 : a + (rem ? 1 : 0);
+}
+constexpr int rad(int L, int s) {
+    const int p = ilog2(L), a = p / 4, rem = p % 4;
+    return p == 1 ? 2
+           : (rem == 1 && a >= 1) ? (s < a - 1 ? 16 : (s == a - 1 ? 8 : 4))
+                                  : (s < a ? 16 : (rem == 3 ? 8 : rem == 2 ? 4 : 2));
+}
+constexpr int ns_before(int L, int s) { return s == 0 ? 1 : ns_before(L, s - 1) * rad(L, s - 1); }
+constexpr int twoff(int L, int s) { return s == 0 ? 0 : twoff(L, s - 1) + ns_before(L, s - 1) * (rad(L, s - 1) - 1); }
+constexpr bool is_pow2(int L) { return L >= 1 && (L & (L - 1)) == 0; }
+}  // namespace ct
+
+// One Stockham stage with every size known at compile time.  NLMAX lines at
+// most, NT threads; each thread owns U = ceil(NLMAX*L/R / NT) butterflies.
+template <typename T, int L, int R, int Ns, int DIR, int NT, int NLMAX>
+__device__ __forceinline__ void fft_stage_ct(cplx<T> *buf, int nlines, int pitch, const cplx<T> *__restrict__ tw,
+                                             int tid) {
+    using C = cplx<T>;
+    constexpr int nb = L / R;
+    constexpr int U = (NLMAX * nb + NT - 1) / NT;
+    const int total = nlines * nb;
+    C v[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * NT;
+        if (b < total) {
+            const int line = b / nb, j = b % nb;
+            const C *src = buf + line * pitch;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = src[j + r * nb];
+            if (Ns > 1) {
+                const int k = j % Ns;
+                const C *t = tw + k * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = t[r - 1];
+                    if (DIR > 0) w = cconj(w);
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            }
+            Dft<R, DIR, C>::run(v[u]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * NT;
+        if (b < total) {
+            const int line = b / nb, j = b % nb;
+            const int d = (j / Ns) * Ns * R + (j % Ns);
+            C *dst = buf + line * pitch;
+#pragma unroll
+            for (int r = 0; r < R; ++r) dst[d + r * Ns] = v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <typename T, int L, int S, int DIR, int NT, int NLMAX>
+__device__ __forceinline__ void fft_ct_from(cplx<T> *buf, int nlines, int pitch, const cplx<T> *__restrict__ tw, int tid) {
+    if constexpr (S < ct::nst(L)) {
+        fft_stage_ct<T, L, ct::rad(L, S), ct::ns_before(L, S), DIR, NT, NLMAX>(buf, nlines, pitch, tw + ct::twoff(L, S), tid);
+        fft_ct_from<T, L, S + 1, DIR, NT, NLMAX>(buf, nlines, pitch, tw, tid);
+    }
+}
+
+// Full power-of-two transform of up to NLMAX LDS lines (threads >= NT idle).
+template <typename T, int L, int DIR, int NT, int NLMAX>
+__device__ __forceinline__ void lds_fft_ct(cplx<T> *buf, int nlines, int pitch, const cplx<T> *__restrict__ tw, int tid) {
+    fft_ct_from<T, L, 0, DIR, NT, NLMAX>(buf, nlines, pitch, tw, tid < NT ? tid : (1 << 29));
+}
+
+// Fast unsigned division by a runtime divisor d >= 1 (n < 2^31):
+// q = (umulhi(n, m) + n) >> s with s = ceil(log2 d), m = floor(2^32 (2^s - d) / d) + 1.
+struct FastDiv {
+    uint32_t d, m, s;
+};
+__device__ __forceinline__ uint32_t fdiv(uint32_t n, const FastDiv &f) {
+    return (__umulhi(n, f.m) + n) >> f.s;
+}
+__host__ __device__ inline FastDiv make_fastdiv(uint32_t d) {
+    FastDiv f;
+    f.d = d;
+    uint32_t s = 0;
+    while ((1ull << s) < d) ++s;
+    f.s = s;
+    f.m = (uint32_t)(((1ull << 32) * ((1ull << s) - d)) / d + 1);
+    return f;
+}
+
 }  // namespace mmx

@@ -1,0 +1,98 @@
+// Register-staged Stockham engine for power-of-two lengths known at compile
+// time.  A tile holds NL independent lines of length L.  The first stage
+// reads its inputs straight from global memory through a loader and the last
+// stage hands its outputs straight to a storer, so a transform of S stages
+// needs S-1 LDS exchanges instead of S+1.  Butterflies are numbered
+// b = line + NL * j (line fastest) so neighbouring threads touch neighbouring
+// columns of a row-major tile.
+#pragma once
+#include "fft_device.hpp"
+
+namespace mmx {
+namespace ct {
+// radix of stage s in forward (REV = false) or reversed order
+constexpr int prad(int L, bool rev, int s) { return rev ? rad(L, nst(L) - 1 - s) : rad(L, s); }
+constexpr int pns(int L, bool rev, int s) { return s == 0 ? 1 : pns(L, rev, s - 1) * prad(L, rev, s - 1); }
+constexpr int ptw(int L, bool rev, int s) { return s == 0 ? 0 : ptw(L, rev, s - 1) + pns(L, rev, s - 1) * (prad(L, rev, s - 1) - 1); }
+// LDS pitch so that 32 consecutive butterflies of a stage (NL lines
+// interleaved) fall into distinct banks
+constexpr int lds_pitch(int L, int NL) { return NL >= 32 ? L + 1 : (NL == 3 ? L + 11 : L + 32 / (NL < 1 ? 1 : NL)); }
+}  // namespace ct
+
+// One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
+// 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, class Ld, class St>
+__device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
+    using C = cplx<T>;
+    constexpr int R = ct::prad(L, REV, S);
+    constexpr int Ns = ct::pns(L, REV, S);
+    constexpr int NB = L / R;
+    constexpr int TOT = NL * NB;
+    constexpr int U = (TOT + NT - 1) / NT;
+    constexpr int P = ct::lds_pitch(L, NL);
+    const C *t = tw + ct::ptw(L, REV, S);
+    C v[U][R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * NT;
+        if (b < TOT) {
+            const int line = b % NL, j = b / NL;
+#pragma unroll
+            for (int r = 0; r < R; ++r) v[u][r] = IN ? lds[line * P + j + r * NB] : ld(line, j + r * NB);
+            if (Ns > 1) {
+                const C *tt = t + (j % Ns) * (R - 1);
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    C w = tt[r - 1];
+                    if (DIR > 0) w = cconj(w);
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            }
+            Dft<R, DIR, C>::run(v[u]);
+        }
+    }
+    if (IN && OUT) __syncthreads();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * NT;
+        if (b < TOT) {
+            const int line = b % NL, j = b / NL;
+            const int d = (j / Ns) * Ns * R + (j % Ns);
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                if (OUT) lds[line * P + d + r * Ns] = v[u][r];
+                else st(line, d + r * Ns, v[u][r]);
+            }
+        }
+    }
+    if (OUT) __syncthreads();
+}
+
+// stages [S, E) all LDS -> LDS
+template <typename T, int L, bool REV, int S, int E, int DIR, int NT, int NL>
+__device__ __forceinline__ void eng_mid(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid) {
+    if constexpr (S < E) {
+        auto nold = [](int, int) { return cplx<T>(); };
+        auto nost = [](int, int, cplx<T>) {};
+        eng_stage<T, L, REV, S, DIR, NT, NL, 1, 1>(lds, tw, tid, nold, nost);
+        eng_mid<T, L, REV, S + 1, E, DIR, NT, NL>(lds, tw, tid);
+    }
+}
+
+// Full transform: loader -> [LDS stages] -> storer.
+template <typename T, int L, bool REV, int DIR, int NT, int NL, class Ld, class St>
+__device__ __forceinline__ void eng_fft(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
+    constexpr int NS = ct::nst(L);
+    if constexpr (NS == 0) {
+        // length 1: identity
+        for (int line = tid; line < NL; line += NT) st(line, 0, ld(line, 0));
+    } else if constexpr (NS == 1) {
+        eng_stage<T, L, REV, 0, DIR, NT, NL, 0, 0>(lds, tw, tid, ld, st);
+    } else {
+        eng_stage<T, L, REV, 0, DIR, NT, NL, 0, 1>(lds, tw, tid, ld, st);
+        eng_mid<T, L, REV, 1, NS - 1, DIR, NT, NL>(lds, tw, tid);
+        eng_stage<T, L, REV, NS - 1, DIR, NT, NL, 1, 0>(lds, tw, tid, ld, st);
+    }
+}
+
+}  // namespace mmx

@@ -83,11 +83,12 @@ struct HostFft {
     std::vector<long double> tw;   // interleaved re, im; forward sign
 };
 
-HostFft make_fft(int L) {
+HostFft make_fft(int L, bool rev = false) {
     HostFft h;
     std::memset(&h.d, 0, sizeof h.d);
     h.d.L = L;
     std::vector<int> rad = factorize(L);
+    if (rev) std::reverse(rad.begin(), rad.end());
     h.d.nst = (int)rad.size();
     int Ns = 1, off = 0;
     for (size_t s = 0; s < rad.size(); ++s) {
@@ -149,6 +150,7 @@ struct mm_plan {
     FusedPass fp{};
     ZGeom zg{};
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
+    bool x_ct = false, y_ct = false;     // power-of-two specialised kernels in use
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -238,15 +240,17 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     // twiddles (plan precision): x, y, z tables concatenated
     std::vector<T> tw;
     auto app = [&](const HostFft &f) { size_t off = tw.size() / 2; auto v = round_tw<T>(f); tw.insert(tw.end(), v.begin(), v.end()); return off; };
-    const size_t ox = app(p->fx), oy = app(p->fy), oz = app(p->fz);
+    const size_t ox = app(p->fx), oy = app(p->fy);
+    (void)app(make_fft(Ly, true));   // reversed radix order, right after y's table (fused inverse)
+    const size_t oz = app(p->fz);
     int rc;
     if ((rc = dalloc(p, &p->twT, std::max<size_t>(tw.size() * sizeof(T), 16)))) return rc;
     HIPCK(hipMemcpy(p->twT, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
     const C *twc = reinterpret_cast<const C *>(p->twT);
-    // workspace
-    const int64_t hz3 = (int64_t)p->hz * 3;
-    const size_t s1 = (size_t)nx * ny * hz3 * csz, s2 = (size_t)nx * Ly * hz3 * csz;
-    const size_t tens = (size_t)p->hy * p->hz * p->hx * 6 * sizeof(T);
+    // workspace: S1 [kz][x][y][c] (kz < hz), S2 [kz][kx][y][c] (kx < Lx), tensor
+    const int64_t npos = nx * ny;
+    const size_t s1 = (size_t)p->hz * npos * 3 * csz, s2 = (size_t)p->hz * Lx * ny * 3 * csz;
+    const size_t tens = (size_t)p->hz * p->hx * p->hy * 6 * sizeof(T);
     const size_t cells3 = (size_t)nx * ny * nz * 3 * sizeof(T);
     if ((rc = dalloc(p, &p->S1, s1))) return rc;
     if ((rc = dalloc(p, &p->S2, s2))) return rc;
@@ -254,50 +258,57 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     if ((rc = dalloc(p, &p->ms[0], cells3))) return rc;
     if ((rc = dalloc(p, &p->ms[1], cells3))) return rc;
     if ((rc = dalloc(p, &p->acc, cells3))) return rc;
-    const int want = 0;
-    (void)o;
-    // y passes
+    // x passes: lines along x, columns (y, c) contiguous, one kz plane per outer index
+    const int64_t ny3 = ny * 3;
     int W, nthr;
     size_t lds;
-    choose_line_tile(Ly, (int)hz3, csz, kLdsTarget, want, W, nthr, lds);
+    choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
+    int Wct = 0, NTct = 0;
+    p->x_ct = line_ct_shape(Lx, csz, &Wct, &NTct) && !getenv("MMX_NO_CT");
+    if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);
-    f.in = p->S1; f.out = p->S2; f.tw = twc + oy;
-    f.in_row = hz3; f.out_row = hz3; f.in_outer = ny * hz3; f.out_outer = (int64_t)Ly * hz3;
-    f.inner = (int)hz3; f.outer = (int)nx; f.n_in = (int)ny; f.n_out = Ly;
-    f.W = W; f.tiles_inner = (int)((hz3 + W - 1) / W); f.pitch = pitch_of(Ly); f.nthr = nthr; f.sym_axis = -1;
-    f.f = p->fy.d;
+    f.in = p->S1; f.out = p->S2; f.tw = twc + ox;
+    f.in_row = ny3; f.out_row = ny3; f.in_outer = nx * ny3; f.out_outer = (int64_t)Lx * ny3;
+    f.inner = (int)ny3; f.outer = p->hz; f.n_in = (int)nx; f.n_out = Lx;
+    f.W = W; f.tiles_inner = (int)((ny3 + W - 1) / W); f.pitch = p->x_ct ? Lx + 1 : pitch_of(Lx); f.nthr = nthr; f.sym_axis = -1;
+    f.f = p->fx.d;
     p->lds_fwd = lds;
     p->tiles_fwd = f.tiles_inner * f.outer;
     LinePass &g = p->lp_inv;
     g = f;
-    g.in = p->S2; g.out = p->S1; g.in_outer = (int64_t)Ly * hz3; g.out_outer = ny * hz3; g.n_in = Ly; g.n_out = (int)ny;
+    g.in = p->S2; g.out = p->S1; g.in_outer = (int64_t)Lx * ny3; g.out_outer = nx * ny3; g.n_in = Lx; g.n_out = (int)nx;
     p->lds_inv = lds;
     p->tiles_inv = p->tiles_fwd;
-    // fused x pass
+    // fused y pass: one (kz, kx) pencil of three components per tile
     FusedPass &q = p->fp;
     std::memset(&q, 0, sizeof q);
-    const int npos = Ly * p->hz;
-    const int px = pitch_of(Lx);
+    const int npen = p->hz * Lx;
+    const int py = pitch_of(Ly);
     int Wp = 1;
-    for (int w : {32, 16, 8, 4, 2, 1}) {
-        if (w <= std::max(1, npos) && (size_t)3 * w * px * csz <= kLdsTarget && fft_threads(p->fx.d, 3 * w, 3 * w * Lx) <= 1024) { Wp = w; break; }
+    for (int w : {8, 4, 2, 1}) {
+        if (w <= std::max(1, npen) && (size_t)3 * w * py * csz <= kLdsTarget && fft_threads(p->fy.d, 3 * w, 3 * w * Ly) <= 1024) { Wp = w; break; }
     }
-    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + ox;
-    q.row = (int64_t)Ly * hz3; q.npos = npos; q.n = (int)nx; q.Ly = Ly; q.hz = p->hz; q.hx = p->hx;
-    q.W = Wp; q.tiles = (npos + Wp - 1) / Wp; q.pitch = px; q.nthr = fft_threads(p->fx.d, 3 * Wp, 3 * Wp * Lx);
-    q.f = p->fx.d;
-    p->lds_fp = (size_t)3 * Wp * px * csz;
-    if (p->lds_fp > kLdsMax) return fail(MM_ENOTSUP, "x length %d too long for one workgroup", Lx);
+    p->y_ct = fused_ct_threads(Ly) > 0 && !getenv("MMX_NO_CT");
+    if (p->y_ct) Wp = 1;
+    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy;
+    q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;
+    q.npos = npen; q.W = Wp; q.tiles = (npen + Wp - 1) / Wp;
+    q.pitch = p->y_ct ? Ly + 1 : py;
+    q.nthr = p->y_ct ? fused_ct_threads(Ly) : fft_threads(p->fy.d, 3 * Wp, 3 * Wp * Ly);
+    q.f = p->fy.d;
+    p->lds_fp = p->y_ct ? fused_ct_lds(Ly, csz) : (size_t)3 * Wp * q.pitch * csz;
+    if (p->lds_fp > kLdsMax) return fail(MM_ENOTSUP, "y length %d too long for one workgroup", Ly);
     // z passes: P positions (even) per tile, about 512 cells per tile
     ZGeom &z = p->zg;
     std::memset(&z, 0, sizeof z);
     z.nx = (int)nx; z.ny = (int)ny; z.nz = (int)nz; z.Lz = Lz; z.hz = p->hz;
     const int pz = pitch_of(Lz);
-    int P = (int)std::max<int64_t>(2, (512 / nz) & ~1);
+    int P = (int)std::max<int64_t>(2, (1024 / nz) & ~1);
     P = std::min<int64_t>(P, std::max<int64_t>(2, (nx * ny + 1) & ~1));
-    while (P > 2 && ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsTarget || fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz) > 1024)) P -= 2;
+    while (P > 2 && ((size_t)((3 * P + 1) / 2) * pz * csz > 48 * 1024 || fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz) > 1024)) P -= 2;
     z.P = P; z.tiles = (int)((nx * ny + P - 1) / P); z.pitch = pz;
+    z.dnz = make_fastdiv((uint32_t)nz); z.dny = make_fastdiv((uint32_t)ny);
     z.nthr = std::min(1024, fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz));
     z.f = p->fz.d; z.tw = twc + oz; z.S1 = p->S1;
     p->lds_z = std::max<size_t>((size_t)((3 * P + 1) / 2) * pz * csz, 16 * 2 * sizeof(double) + 64);
@@ -401,10 +412,13 @@ int run_zfwd(mm_plan *p, int src, const void *srcp, const void *Ms, double Ms_s,
 }
 
 template <typename T>
-int run_yxy(mm_plan *p) {
-    HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
-    HIPCK(launch_fused_x<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
-    HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
+int run_xyx(mm_plan *p) {
+    if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, p->lp_fwd.W, -1, p->stream));
+    else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
+    if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
+    else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
+    if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
+    else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
     return MM_OK;
 }
 
@@ -435,7 +449,7 @@ int heff_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, 
     int rc;
     if (terms & MM_DEMAG) {
         if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
-        if ((rc = run_yxy<T>(p))) return rc;
+        if ((rc = run_xyx<T>(p))) return rc;
     }
     ZInvArgs a;
     fill_common(p, a, terms, Ms, Ms_s, A);
@@ -460,7 +474,7 @@ int enqueue_step(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, dou
     int rc;
     if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
     for (int s = 0; s < 4; ++s) {
-        if ((rc = run_yxy<T>(p))) return rc;
+        if ((rc = run_xyx<T>(p))) return rc;
         ZInvArgs a;
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
         if (hext) for (int i = 0; i < 3; ++i) a.hext[i] = hext[i];
@@ -522,7 +536,7 @@ int adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double 
     int rc;
     if (terms & MM_DEMAG) {
         if ((rc = run_zfwd<T>(p, SRC_RAW, g_h, nullptr, 1.0))) return rc;
-        if ((rc = run_yxy<T>(p))) return rc;
+        if ((rc = run_xyx<T>(p))) return rc;
     }
     ZInvArgs a;
     fill_common(p, a, terms, Ms, Ms_s, A);
@@ -549,7 +563,7 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
     // forward recompute with stage records
     if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
     for (int s = 0; s < 4; ++s) {
-        if ((rc = run_yxy<T>(p))) return rc;
+        if ((rc = run_xyx<T>(p))) return rc;
         ZInvArgs a;
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
         if (hext) for (int i = 0; i < 3; ++i) a.hext[i] = hext[i];
@@ -567,7 +581,7 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
     HIPCK(launch_scale_copy<T>((const T *)ub, (T *)kb, w[3], ncell * 3, p->stream));   // kb = (dt/6) u_bar
     for (int q = 3; q >= 0; --q) {
         if ((rc = run_zfwd<T>(p, SRC_ADJPRE, nullptr, nullptr, 1.0, srec[q], hrec[q], kb, ym, yh, gp, alpha))) return rc;
-        if ((rc = run_yxy<T>(p))) return rc;
+        if ((rc = run_xyx<T>(p))) return rc;
         ZInvArgs a;
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
         a.m = srec[q]; a.g_h = yh; a.g_m = gmh; a.g_Ms = g_Ms; a.acc_gMs = 1;
@@ -583,9 +597,18 @@ template <typename T>
 int time_one(mm_plan *p, int k) {
     switch (k) {
     case 0: return run_zfwd<T>(p, SRC_MS_M, p->ms[0], nullptr, 8e5);
-    case 1: HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream)); return MM_OK;
-    case 2: HIPCK(launch_fused_x<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream)); return MM_OK;
-    case 3: HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream)); return MM_OK;
+    case 1:
+        if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, p->lp_fwd.W, -1, p->stream));
+        else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
+        return MM_OK;
+    case 2:
+        if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
+        else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
+        return MM_OK;
+    case 3:
+        if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
+        else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
+        return MM_OK;
     case 4: {
         ZInvArgs a;
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, nullptr, 8e5, 1.3e-11);
@@ -912,9 +935,9 @@ int batch_args(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, dou
 }
 
 template <typename T>
-int batch_yxy(mm_batch *b) {
+int batch_xyx(mm_batch *b) {
     HIPCK(launch_line_pass<T>(b->d_lpf, b->lmap, b->lt, b->nthr_l, b->lds_l, -1, false, b->stream));
-    HIPCK(launch_fused_x<T>(b->d_fp, b->fmap, b->ft, b->nthr_f, b->lds_f, b->stream));
+    HIPCK(launch_fused_y<T>(b->d_fp, b->fmap, b->ft, b->nthr_f, b->lds_f, b->stream));
     HIPCK(launch_line_pass<T>(b->d_lpi, b->lmap, b->lt, b->nthr_l, b->lds_l, +1, false, b->stream));
     return MM_OK;
 }
@@ -924,7 +947,7 @@ int batch_step(mm_batch *b) {
     int rc;
     HIPCK(launch_zfwd_batch<T>(b->d_zf, b->zmap, b->zt, b->nthr_z, SRC_MS_M, b->lds_z, b->stream));
     for (int s = 0; s < 4; ++s) {
-        if ((rc = batch_yxy<T>(b))) return rc;
+        if ((rc = batch_xyx<T>(b))) return rc;
         HIPCK(launch_zinv_batch<T>(b->d_zi + (size_t)(1 + s) * b->count, b->zmap, b->zt, b->nthr_z, EPI_STAGE, b->lds_z, b->stream));
     }
     return MM_OK;
@@ -935,7 +958,7 @@ int batch_heff(mm_batch *b, unsigned terms) {
     int rc;
     if (terms & MM_DEMAG) {
         HIPCK(launch_zfwd_batch<T>(b->d_zf, b->zmap, b->zt, b->nthr_z, SRC_MS_M, b->lds_z, b->stream));
-        if ((rc = batch_yxy<T>(b))) return rc;
+        if ((rc = batch_xyx<T>(b))) return rc;
     }
     HIPCK(launch_zinv_batch<T>(b->d_zi, b->zmap, b->zt, b->nthr_z, EPI_HEFF, b->lds_z, b->stream));
     return MM_OK;

@@ -1,13 +1,73 @@
-// Strided line passes (the y-axis passes of the convolution and the three
-// real symmetric transforms of the tensor setup) and the fused x pass
-// (forward FFT, spectral 3x3 product with the demag tensor, inverse FFT).
+// Strided line passes (the x-axis passes of the convolution and the three
+// real symmetric transforms of the tensor setup) and the fused y pass
+// (forward FFT, spectral 3x3 product with the demag tensor, inverse FFT) on
+// contiguous three-component pencils.  Each comes as a runtime-planned kernel
+// (any 7-smooth length, also used by grouped launches over many geometries)
+// and as compile-time specialisations for power-of-two lengths.
 #include "passes.hpp"
 #include "kernels.hpp"
+#include "fft_engine.hpp"
 
 namespace mmx {
 
 // parity of component q (xx,yy,zz,xy,xz,yz) along axis a
 __constant__ int kOdd[3][6] = {{0, 0, 0, 1, 1, 0}, {0, 0, 0, 1, 0, 1}, {0, 0, 0, 0, 1, 1}};
+
+// ---------------- strided line pass --------------------------------------
+template <typename T, bool SYM>
+__device__ __forceinline__ void line_load(cplx<T> *lds, const LinePass &a, int o, int c0, int wc, int tid, int nthr) {
+    using C = cplx<T>;
+    const int L = a.f.L, pitch = a.pitch, n_in = a.n_in;
+    if (!SYM) {
+        const C *in = reinterpret_cast<const C *>(a.in) + (int64_t)o * a.in_outer + c0;
+        for (int e = tid; e < n_in * wc; e += nthr) {
+            const int r = e / wc, c = e - r * wc;
+            lds[c * pitch + r] = in[(int64_t)r * a.in_row + c];
+        }
+        const C z = cmake<C>(T(0), T(0));
+        for (int e = tid; e < (L - n_in) * wc; e += nthr) {
+            const int r = n_in + e / wc, c = e % wc;
+            lds[c * pitch + r] = z;
+        }
+    } else {
+        // real line f(0..n-1) -> symmetric (even/odd) periodic extension
+        const T *in = reinterpret_cast<const T *>(a.in) + (int64_t)o * a.in_outer + c0;
+        for (int e = tid; e < n_in * wc; e += nthr) {
+            const int r = e / wc, c = e - r * wc;
+            const T v = in[(int64_t)r * a.in_row + c];
+            const int odd = kOdd[a.sym_axis][(c0 + c) % 6];
+            lds[c * pitch + r] = cmake<C>(v, T(0));
+            if (r > 0) lds[c * pitch + (L - r)] = cmake<C>(odd ? -v : v, T(0));
+        }
+        const int nz = L - 2 * n_in + 1;   // slots n_in .. L-n_in are zero
+        const C z = cmake<C>(T(0), T(0));
+        for (int e = tid; e < nz * wc; e += nthr) {
+            const int r = n_in + e / wc, c = e % wc;
+            lds[c * pitch + r] = z;
+        }
+    }
+}
+
+template <typename T, bool SYM>
+__device__ __forceinline__ void line_store(const cplx<T> *lds, const LinePass &a, int o, int c0, int wc, int tid, int nthr) {
+    using C = cplx<T>;
+    const int pitch = a.pitch;
+    if (!SYM) {
+        C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
+        for (int e = tid; e < a.n_out * wc; e += nthr) {
+            const int r = e / wc, c = e - r * wc;
+            out[(int64_t)r * a.out_row + c] = lds[c * pitch + r];
+        }
+    } else {
+        T *out = reinterpret_cast<T *>(a.out) + (int64_t)o * a.out_outer + c0;
+        for (int e = tid; e < a.n_out * wc; e += nthr) {
+            const int r = e / wc, c = e - r * wc;
+            const C v = lds[c * pitch + r];
+            const int odd = kOdd[a.sym_axis][(c0 + c) % 6];
+            out[(int64_t)r * a.out_row + c] = odd ? -v.y : v.x;
+        }
+    }
+}
 
 template <typename T, int DIR, bool SYM>
 __global__ void __launch_bounds__(1024) k_line_pass(const LinePass *__restrict__ descs, const int2 *__restrict__ map) {
@@ -22,60 +82,68 @@ __global__ void __launch_bounds__(1024) k_line_pass(const LinePass *__restrict__
     const int o = tile / a.tiles_inner;
     const int c0 = (tile - o * a.tiles_inner) * a.W;
     const int wc = min(a.W, a.inner - c0);
-    const int L = a.f.L, pitch = a.pitch, n_in = a.n_in;
-    if (tid < nthr) {
-        if (!SYM) {
-            const C *in = reinterpret_cast<const C *>(a.in) + (int64_t)o * a.in_outer + c0;
-            for (int e = tid; e < n_in * wc; e += nthr) {
-                const int r = e / wc, c = e - r * wc;
-                lds[c * pitch + r] = in[(int64_t)r * a.in_row + c];
-            }
-            const C z = cmake<C>(T(0), T(0));
-            for (int e = tid; e < (L - n_in) * wc; e += nthr) {
-                const int r = n_in + e / wc, c = e % wc;
-                lds[c * pitch + r] = z;
-            }
-        } else {
-            // real line f(0..n-1) -> symmetric (even/odd) periodic extension
-            const T *in = reinterpret_cast<const T *>(a.in) + (int64_t)o * a.in_outer + c0;
-            for (int e = tid; e < n_in * wc; e += nthr) {
-                const int r = e / wc, c = e - r * wc;
-                const T v = in[(int64_t)r * a.in_row + c];
-                const int odd = kOdd[a.sym_axis][(c0 + c) % 6];
-                lds[c * pitch + r] = cmake<C>(v, T(0));
-                if (r > 0) lds[c * pitch + (L - r)] = cmake<C>(odd ? -v : v, T(0));
-            }
-            const int nz = L - 2 * n_in + 1;   // slots n_in .. L-n_in are zero
-            const C z = cmake<C>(T(0), T(0));
-            for (int e = tid; e < nz * wc; e += nthr) {
-                const int r = n_in + e / wc, c = e % wc;
-                lds[c * pitch + r] = z;
-            }
-        }
-    }
+    if (tid < nthr) line_load<T, SYM>(lds, a, o, c0, wc, tid, nthr);
     __syncthreads();
-    lds_fft<T, DIR>(lds, wc, pitch, a.f, reinterpret_cast<const C *>(a.tw), tid < nthr ? tid : 1 << 30, nthr);
-    if (tid < nthr) {
-        if (!SYM) {
-            C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
-            for (int e = tid; e < a.n_out * wc; e += nthr) {
-                const int r = e / wc, c = e - r * wc;
-                out[(int64_t)r * a.out_row + c] = lds[c * pitch + r];
-            }
-        } else {
-            T *out = reinterpret_cast<T *>(a.out) + (int64_t)o * a.out_outer + c0;
-            for (int e = tid; e < a.n_out * wc; e += nthr) {
-                const int r = e / wc, c = e - r * wc;
-                const C v = lds[c * pitch + r];
-                const int odd = kOdd[a.sym_axis][(c0 + c) % 6];
-                out[(int64_t)r * a.out_row + c] = odd ? -v.y : v.x;
-            }
-        }
+    lds_fft<T, DIR>(lds, wc, a.pitch, a.f, reinterpret_cast<const C *>(a.tw), tid < nthr ? tid : 1 << 30, nthr);
+    if (tid < nthr) line_store<T, SYM>(lds, a, o, c0, wc, tid, nthr);
+}
+
+// compile-time length L (power of two), W columns per tile, NT threads; the
+// first stage loads from global memory, the last stores to global memory
+template <typename T, int L, int DIR, int NT, int W>
+__global__ void __launch_bounds__(NT) k_line_ct(const LinePass a) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int o = tile / a.tiles_inner;
+    const int c0 = (tile - o * a.tiles_inner) * W;
+    const int wc = min(W, a.inner - c0);
+    const int n_in = a.n_in, n_out = a.n_out;
+    const int64_t ir = a.in_row, orow = a.out_row;
+    const C *in = reinterpret_cast<const C *>(a.in) + (int64_t)o * a.in_outer + c0;
+    C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
+    auto ld = [&](int line, int pos) -> C {
+        return (pos < n_in && line < wc) ? in[pos * ir + line] : cmake<C>(T(0), T(0));
+    };
+    auto st = [&](int line, int pos, C v) {
+        if (pos < n_out && line < wc) out[pos * orow + line] = v;
+    };
+    eng_fft<T, L, false, DIR, NT, W>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
+}
+
+// ---------------- fused y pass -------------------------------------------
+// Pencil order within a kz plane pairs kx with Lx-kx (they read the same
+// tensor row) so the two run close together: 0, [Lx/2], 1, Lx-1, 2, Lx-2, ...
+__device__ __forceinline__ int pair_kx(int t, int Lx) {
+    if (t == 0) return 0;
+    if ((Lx & 1) == 0) {
+        if (t == 1) return Lx / 2;
+        const int u = (t - 2) / 2 + 1;
+        return (t & 1) ? Lx - u : u;
     }
+    const int u = (t - 1) / 2 + 1;
+    return (t & 1) ? u : Lx - u;
+}
+
+// spectral product for the lines of one pencil held in LDS (3 lines, pitch)
+template <typename T>
+__device__ __forceinline__ void spectral_product(cplx<T> *b, int pitch, int ky, int Ly, const T *__restrict__ Trow,
+                                                 T sx) {
+    using C = cplx<T>;
+    const bool ry = ky > Ly / 2;
+    const int kyp = ry ? Ly - ky : ky;
+    const T *N = Trow + (int64_t)kyp * 6;
+    const T sy = ry ? T(-1) : T(1);
+    const T nxx = N[0], nyy = N[1], nzz = N[2], nxy = N[3] * sx * sy, nxz = N[4] * sx, nyz = N[5] * sy;
+    const C mx = b[ky], my = b[pitch + ky], mz = b[2 * pitch + ky];
+    b[ky] = cmake<C>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
+    b[pitch + ky] = cmake<C>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
+    b[2 * pitch + ky] = cmake<C>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
 }
 
 template <typename T>
-__global__ void __launch_bounds__(1024) k_fused_x(const FusedPass *__restrict__ descs, const int2 *__restrict__ map) {
+__global__ void __launch_bounds__(1024) k_fused_y(const FusedPass *__restrict__ descs, const int2 *__restrict__ map) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
@@ -86,53 +154,168 @@ __global__ void __launch_bounds__(1024) k_fused_x(const FusedPass *__restrict__ 
     const int tid = threadIdx.x, nthr = a.nthr;
     const int p0 = tile * a.W;
     const int wp = min(a.W, a.npos - p0);
-    const int nl = 3 * wp;
-    const int L = a.f.L, pitch = a.pitch, n = a.n;
-    C *data = reinterpret_cast<C *>(a.data) + (int64_t)p0 * 3;
+    const int L = a.f.L, pitch = a.pitch, n = a.n, n3 = 3 * n;
     const C *tw = reinterpret_cast<const C *>(a.tw);
     const int ltid = tid < nthr ? tid : 1 << 30;
+    C *data = reinterpret_cast<C *>(a.data);
     if (tid < nthr) {
-        for (int e = tid; e < n * nl; e += nthr) {
-            const int r = e / nl, c = e - r * nl;
-            lds[c * pitch + r] = data[(int64_t)r * a.row + c];
-        }
-        const C z = cmake<C>(T(0), T(0));
-        for (int e = tid; e < (L - n) * nl; e += nthr) {
-            const int r = n + e / nl, c = e % nl;
-            lds[c * pitch + r] = z;
+        for (int pl = 0; pl < wp; ++pl) {
+            const int p = p0 + pl, kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+            const C *src = data + ((int64_t)kz * a.Lx + kx) * n3;
+            C *b = lds + pl * 3 * pitch;
+            for (int e = tid; e < n3; e += nthr) {
+                const int j = e / 3, c = e - 3 * j;
+                b[c * pitch + j] = src[e];
+            }
+            const C z = cmake<C>(T(0), T(0));
+            for (int e = tid; e < 3 * (L - n); e += nthr) {
+                const int c = e / (L - n), j = n + (e - c * (L - n));
+                b[c * pitch + j] = z;
+            }
         }
     }
     __syncthreads();
-    lds_fft<T, -1>(lds, nl, pitch, a.f, tw, ltid, nthr);
+    lds_fft<T, -1>(lds, 3 * wp, pitch, a.f, tw, ltid, nthr);
     if (tid < nthr) {
         const T *Nt = reinterpret_cast<const T *>(a.tensor);
-        const int halfL = L / 2, halfY = a.Ly / 2;
         for (int e = tid; e < wp * L; e += nthr) {
-            const int pl = e / L, kx = e - pl * L;
-            const int p = p0 + pl;
-            const int ky = p / a.hz, kz = p - ky * a.hz;
-            const bool ry = ky > halfY, rx = kx > halfL;
-            const int kyp = ry ? a.Ly - ky : ky, kxp = rx ? L - kx : kx;
-            const T *N = Nt + ((int64_t)(kyp * a.hz + kz) * a.hx + kxp) * 6;
-            const T sx = rx ? T(-1) : T(1), sy = ry ? T(-1) : T(1);
-            const T nxx = N[0], nyy = N[1], nzz = N[2], nxy = N[3] * sx * sy, nxz = N[4] * sx, nyz = N[5] * sy;
-            C *b = lds + (pl * 3) * pitch + kx;
-            const C mx = b[0], my = b[pitch], mz = b[2 * pitch];
-            b[0] = cmake<C>(nxx * mx.x + nxy * my.x + nxz * mz.x, nxx * mx.y + nxy * my.y + nxz * mz.y);
-            b[pitch] = cmake<C>(nxy * mx.x + nyy * my.x + nyz * mz.x, nxy * mx.y + nyy * my.y + nyz * mz.y);
-            b[2 * pitch] = cmake<C>(nxz * mx.x + nyz * my.x + nzz * mz.x, nxz * mx.y + nyz * my.y + nzz * mz.y);
+            const int pl = e / L, ky = e - pl * L;
+            const int p = p0 + pl, kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+            const bool rx = kx > a.Lx / 2;
+            const int kxp = rx ? a.Lx - kx : kx;
+            spectral_product<T>(lds + pl * 3 * pitch, pitch, ky, L, Nt + ((int64_t)kz * a.hxp + kxp) * a.hyp * 6,
+                                rx ? T(-1) : T(1));
         }
     }
     __syncthreads();
-    lds_fft<T, +1>(lds, nl, pitch, a.f, tw, ltid, nthr);
+    lds_fft<T, +1>(lds, 3 * wp, pitch, a.f, tw, ltid, nthr);
     if (tid < nthr) {
-        for (int e = tid; e < n * nl; e += nthr) {
-            const int r = e / nl, c = e - r * nl;
-            data[(int64_t)r * a.row + c] = lds[c * pitch + r];
+        for (int pl = 0; pl < wp; ++pl) {
+            const int p = p0 + pl, kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+            C *dst = data + ((int64_t)kz * a.Lx + kx) * n3;
+            const C *b = lds + pl * 3 * pitch;
+            for (int e = tid; e < n3; e += nthr) {
+                const int j = e / 3, c = e - 3 * j;
+                dst[e] = b[c * pitch + j];
+            }
         }
     }
 }
 
+// Convolution core of one three-line pencil: forward stages, then in one
+// register pass the last forward stage, the 3x3 spectral product and the first
+// inverse stage (the inverse runs its radices in reversed order, so that
+// stage reads exactly the positions the forward stage produced), then the
+// remaining inverse stages.  twf / twr: forward / reversed-order tables.
+template <typename T, int L, int NT, class Ld, class St, class Pr>
+__device__ __forceinline__ void conv_pencil(cplx<T> *lds, const cplx<T> *__restrict__ twf, const cplx<T> *__restrict__ twr,
+                                            int tid, const Ld &ld, const St &st, const Pr &prod) {
+    using C = cplx<T>;
+    constexpr int NS = ct::nst(L);
+    constexpr int P = ct::lds_pitch(L, 3);
+    if constexpr (NS == 0) {
+        if (tid == 0) {
+            C x = ld(0, 0), y = ld(1, 0), z = ld(2, 0);
+            prod(0, x, y, z);
+            st(0, 0, x); st(1, 0, y); st(2, 0, z);
+        }
+    } else {
+        if constexpr (NS >= 2) {
+            auto nost = [](int, int, C) {};
+            eng_stage<T, L, false, 0, -1, NT, 3, 0, 1>(lds, twf, tid, ld, nost);
+            eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, twf, tid);
+        }
+        constexpr int R = ct::prad(L, false, NS - 1);
+        constexpr int NB = L / R;
+        constexpr int Nsf = ct::pns(L, false, NS - 1);
+        constexpr int UJ = (NB + NT - 1) / NT;
+        C v[UJ][3][R];
+#pragma unroll
+        for (int u = 0; u < UJ; ++u) {
+            const int j = tid + u * NT;
+            if (j < NB) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                    for (int r = 0; r < R; ++r) v[u][c][r] = (NS >= 2) ? lds[c * P + j + r * NB] : ld(c, j + r * NB);
+                    if (Nsf > 1) {
+                        const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
+#pragma unroll
+                        for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
+                    }
+                    Dft<R, -1, C>::run(v[u][c]);
+                }
+#pragma unroll
+                for (int r = 0; r < R; ++r) prod(j + r * NB, v[u][0][r], v[u][1][r], v[u][2][r]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) Dft<R, +1, C>::run(v[u][c]);
+            }
+        }
+        if constexpr (NS >= 2) {
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < UJ; ++u) {
+                const int j = tid + u * NT;
+                if (j < NB) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) lds[c * P + j * R + r] = v[u][c][r];
+                }
+            }
+            __syncthreads();
+            eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
+            auto nold = [](int, int) { return C(); };
+            eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
+        } else {
+#pragma unroll
+            for (int u = 0; u < UJ; ++u) {
+                const int j = tid + u * NT;
+                if (j < NB) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c)
+#pragma unroll
+                        for (int r = 0; r < R; ++r) st(c, j * R + r, v[u][c][r]);
+                }
+            }
+        }
+    }
+}
+
+// compile-time Ly; one (kz, kx) pencil of three components per tile
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int p = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int n = a.n;
+    const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+    C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
+    const bool rx = kx > a.Lx / 2;
+    const int kxp = rx ? a.Lx - kx : kx;
+    const T sx = rx ? T(-1) : T(1);
+    const T *Trow = reinterpret_cast<const T *>(a.tensor) + ((int64_t)kz * a.hxp + kxp) * a.hyp * 6;
+    auto ld = [&](int c, int pos) -> C { return pos < n ? pen[pos * 3 + c] : cmake<C>(T(0), T(0)); };
+    auto st = [&](int c, int pos, C v) {
+        if (pos < n) pen[pos * 3 + c] = v;
+    };
+    auto prod = [&](int ky, C &mx, C &my, C &mz) {
+        const bool ry = ky > L / 2;
+        const int kyp = ry ? L - ky : ky;
+        const T *N = Trow + kyp * 6;
+        const T sy = ry ? T(-1) : T(1);
+        const T nxx = N[0], nyy = N[1], nzz = N[2], nxy = N[3] * sx * sy, nxz = N[4] * sx, nyz = N[5] * sy;
+        const C x = mx, y = my, z = mz;
+        mx = cmake<C>(nxx * x.x + nxy * y.x + nxz * z.x, nxx * x.y + nxy * y.y + nxz * z.y);
+        my = cmake<C>(nxy * x.x + nyy * y.x + nyz * z.x, nxy * x.y + nyy * y.y + nyz * z.y);
+        mz = cmake<C>(nxz * x.x + nyz * y.x + nzz * z.x, nxz * x.y + nyz * y.y + nzz * z.y);
+    };
+    const C *tw = reinterpret_cast<const C *>(a.tw);
+    conv_pencil<T, L, NT>(lds, tw, tw + (L > 1 ? L - 1 : 0), (int)threadIdx.x, ld, st, prod);
+}
+
+// ---------------- launchers -------------------------------------------------
 template <typename T>
 hipError_t launch_line_pass(const LinePass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
                             int dir, bool sym, hipStream_t s) {
@@ -148,16 +331,96 @@ hipError_t launch_line_pass(const LinePass *d_descs, const int2 *d_map, int tile
 }
 
 template <typename T>
-hipError_t launch_fused_x(const FusedPass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
+hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
                           hipStream_t s) {
     if (tiles <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k_fused_x<T>), dim3(tiles), dim3(nthr), lds_bytes, s, d_descs, d_map);
+    hipLaunchKernelGGL((k_fused_y<T>), dim3(tiles), dim3(nthr), lds_bytes, s, d_descs, d_map);
+    return hipGetLastError();
+}
+
+// Specialised shapes: (L, NT, W) chosen so each thread holds 16 complex values
+// and a tile's LDS stays within 64 KB (FP32) / 64 KB (FP64).
+template <typename T> struct LineCT;
+#define LINE_CASE(LL, NTT, WW)                                                                                      \
+    case LL:                                                                                                        \
+        if (W != WW) return hipErrorInvalidValue;                                                                   \
+        if (dir < 0) hipLaunchKernelGGL((k_line_ct<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, a);       \
+        else hipLaunchKernelGGL((k_line_ct<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, a);               \
+        return hipGetLastError();
+
+int line_ct_shape(int L, size_t csz, int *W, int *NT) {
+    // returns 1 if a specialised kernel exists for (L, precision)
+    const bool f32 = csz == 8;
+    switch (L) {
+    case 64: *W = 16; *NT = 64; return 1;
+    case 128: *W = 16; *NT = 128; return 1;
+    case 256: *W = 16; *NT = 256; return 1;
+    case 512: *W = f32 ? 16 : 8; *NT = f32 ? 512 : 256; return 1;
+    case 1024: *W = f32 ? 8 : 4; *NT = f32 ? 512 : 256; return 1;
+    case 2048: *W = f32 ? 4 : 2; *NT = f32 ? 512 : 256; return 1;
+    case 4096: *W = f32 ? 2 : 1; *NT = f32 ? 512 : 256; return 1;
+    default: return 0;
+    }
+}
+
+template <typename T>
+hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    const size_t lds = line_ct_lds(a.f.L, W, sizeof(cplx<T>));
+    constexpr bool f32 = sizeof(T) == 4;
+    switch (a.f.L) {
+        LINE_CASE(64, 64, 16)
+        LINE_CASE(128, 128, 16)
+        LINE_CASE(256, 256, 16)
+        LINE_CASE(512, (f32 ? 512 : 256), (f32 ? 16 : 8))
+        LINE_CASE(1024, (f32 ? 512 : 256), (f32 ? 8 : 4))
+        LINE_CASE(2048, (f32 ? 512 : 256), (f32 ? 4 : 2))
+        LINE_CASE(4096, (f32 ? 512 : 256), (f32 ? 2 : 1))
+    default: return hipErrorInvalidValue;
+    }
+}
+#undef LINE_CASE
+
+size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W) * csz; }
+size_t fused_ct_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L, 3) * csz; }
+
+int fused_ct_threads(int L) {
+    switch (L) {
+    case 64: return 64;
+    case 128: return 64;
+    case 256: return 64;
+    case 512: return 128;
+    case 1024: return 256;
+    case 2048: return 256;
+    case 4096: return 256;
+    default: return 0;
+    }
+}
+
+template <typename T>
+hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
+    if (a.npos <= 0) return hipSuccess;
+    const size_t lds = fused_ct_lds(a.f.L, sizeof(cplx<T>));
+    switch (a.f.L) {
+    case 64: hipLaunchKernelGGL((k_fused_y_ct<T, 64, 64>), dim3(a.npos), dim3(64), lds, s, a); break;
+    case 128: hipLaunchKernelGGL((k_fused_y_ct<T, 128, 64>), dim3(a.npos), dim3(64), lds, s, a); break;
+    case 256: hipLaunchKernelGGL((k_fused_y_ct<T, 256, 64>), dim3(a.npos), dim3(64), lds, s, a); break;
+    case 512: hipLaunchKernelGGL((k_fused_y_ct<T, 512, 128>), dim3(a.npos), dim3(128), lds, s, a); break;
+    case 1024: hipLaunchKernelGGL((k_fused_y_ct<T, 1024, 256>), dim3(a.npos), dim3(256), lds, s, a); break;
+    case 2048: hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 256>), dim3(a.npos), dim3(256), lds, s, a); break;
+    case 4096: hipLaunchKernelGGL((k_fused_y_ct<T, 4096, 256>), dim3(a.npos), dim3(256), lds, s, a); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 template hipError_t launch_line_pass<float>(const LinePass *, const int2 *, int, int, size_t, int, bool, hipStream_t);
 template hipError_t launch_line_pass<double>(const LinePass *, const int2 *, int, int, size_t, int, bool, hipStream_t);
-template hipError_t launch_fused_x<float>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
-template hipError_t launch_fused_x<double>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
+template hipError_t launch_fused_y<float>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
+template hipError_t launch_fused_y<double>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
+template hipError_t launch_line_ct<float>(const LinePass &, int, int, int, hipStream_t);
+template hipError_t launch_line_ct<double>(const LinePass &, int, int, int, hipStream_t);
+template hipError_t launch_fused_ct<float>(const FusedPass &, hipStream_t);
+template hipError_t launch_fused_ct<double>(const FusedPass &, hipStream_t);
 
 }  // namespace mmx

@@ -113,7 +113,7 @@ __global__ void __launch_bounds__(256) k_tensor_octant(double *out, int nx, int 
     for (int q = 0; q < 6; ++q) out[t * 6 + q] = v[q];
 }
 
-// [kx'][ky'][kz][6] FP64 -> [ky'][kz][kx'][6] in T, scaled: the stored value is
+// [kx'][ky'][kz][6] FP64 -> [kz][kx'][ky'][6] in T, scaled: the stored value is
 // -N^/(Lx Ly Lz); the separable cosine/sine transforms drop a factor (-i) per
 // odd axis, i.e. -1 for the off-diagonal components.
 template <typename T>
@@ -125,11 +125,11 @@ __global__ void __launch_bounds__(256) k_tensor_finalize(const double *__restric
     const int64_t kz = t % hz, r = t / hz;
     const int64_t ky = r % hy, kx = r / hy;
     const double *src = in + t * 6;
-    T *dst = out + (((ky * hz + kz) * hx) + kx) * 6;
+    T *dst = out + (((kz * hx + kx) * hy) + ky) * 6;
     for (int q = 0; q < 6; ++q) dst[q] = T((q < 3 ? -src[q] : src[q]) * inv_ltot);
 }
 
-// inverse permutation (test hook): [ky'][kz][kx'][6] T -> [kx'][ky'][kz][6] double
+// inverse permutation (test hook): [kz][kx'][ky'][6] T -> [kx'][ky'][kz][6] double
 template <typename T>
 __global__ void __launch_bounds__(256) k_tensor_export(const T *__restrict__ in, double *__restrict__ out, int hx,
                                                         int hy, int hz) {
@@ -138,7 +138,7 @@ __global__ void __launch_bounds__(256) k_tensor_export(const T *__restrict__ in,
     if (t >= total) return;
     const int64_t kz = t % hz, r = t / hz;
     const int64_t ky = r % hy, kx = r / hy;
-    const T *src = in + (((ky * hz + kz) * hx) + kx) * 6;
+    const T *src = in + (((kz * hx + kx) * hy) + ky) * 6;
     for (int q = 0; q < 6; ++q) out[t * 6 + q] = (double)src[q];
 }
 

@@ -30,26 +30,27 @@ __device__ __forceinline__ void zero_lines(cplx<T> *lds, int nlc, int L, int pit
 }
 
 // forward z transform of the LDS lines and the split of each complex line
-// into the half spectra of its two real lines, written to S1 [pos][kz][c]
+// into the half spectra of its two real lines, written to S1 [kz][pos][c]
 template <typename T>
 __device__ __forceinline__ void zfwd_tail(cplx<T> *lds, const ZGeom &g, int64_t pos0, int wp, int tid, int ltid) {
     using C = cplx<T>;
     const int nlr = 3 * wp, nlc = (nlr + 1) / 2;
     lds_fft<T, -1>(lds, nlc, g.pitch, g.f, reinterpret_cast<const C *>(g.tw), ltid, g.nthr);
     if (tid < g.nthr) {
-        C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * g.hz * 3;
-        const int L = g.Lz, hz3 = g.hz * 3;
+        const int64_t npos3 = (int64_t)g.nx * g.ny * 3;
+        C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * 3;
+        const int L = g.Lz;
         const T half = T(0.5);
-        for (int e = tid; e < wp * hz3; e += g.nthr) {
-            const int pl = e / hz3, rem = e - pl * hz3;
-            const int k = rem / 3, c = rem - k * 3;
-            const int l = pl * 3 + c, u = l >> 1;
+        const FastDiv dw = make_fastdiv((uint32_t)nlr);
+        for (int e = tid; e < g.hz * nlr; e += g.nthr) {
+            const int k = (int)fdiv((uint32_t)e, dw), l = e - k * nlr;
+            const int u = l >> 1;
             const C zk = lds[u * g.pitch + k];
             const C zm = lds[u * g.pitch + (k == 0 ? 0 : L - k)];
             C v;
             if ((l & 1) == 0) v = cmake<C>(half * (zk.x + zm.x), half * (zk.y - zm.y));
             else v = cmake<C>(half * (zk.y + zm.y), -half * (zk.x - zm.x));
-            S1[e] = v;
+            S1[k * npos3 + l] = v;
         }
     }
 }
@@ -75,8 +76,9 @@ __device__ __forceinline__ void zfwd_body(const ZFwdArgs &a, uint32_t tile) {
             const T *Ms = reinterpret_cast<const T *>(a.Ms);
             const T Ms_s = T(a.Ms_scalar);
             const int nz3 = nz * 3;
+            const FastDiv d3 = make_fastdiv((uint32_t)nz3);
             for (int e = tid; e < wp * nz3; e += g.nthr) {
-                const int pl = e / nz3, rem = e - pl * nz3;
+                const int pl = (int)fdiv((uint32_t)e, d3), rem = e - pl * nz3;
                 const int z = rem / 3, c = rem - z * 3;
                 T v = src[e];
                 if (SRC == SRC_MS_M) v *= ms_at(Ms, Ms_s, cell0 + (int64_t)pl * nz + z);
@@ -92,7 +94,7 @@ __device__ __forceinline__ void zfwd_body(const ZFwdArgs &a, uint32_t tile) {
             T *yh = reinterpret_cast<T *>(a.yh) + cell0 * 3;
             const T gp = T(a.gp), al = T(a.alpha);
             for (int e = tid; e < wp * nz; e += g.nthr) {
-                const int pl = e / nz, z = e - pl * nz;
+                const int pl = (int)fdiv((uint32_t)e, g.dnz), z = e - pl * nz;
                 T sv[3], hv[3], y[3];
 #pragma unroll
                 for (int c = 0; c < 3; ++c) { sv[c] = s[3 * e + c]; hv[c] = h[3 * e + c]; y[c] = kb[3 * e + c]; }
@@ -132,15 +134,18 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
     const int nlr = 3 * wp, nlc = (nlr + 1) / 2;
     const int L = g.Lz, hz = g.hz, pitch = g.pitch;
     const bool demag = (a.terms & 1u) != 0, exch = (a.terms & 2u) != 0;
-    // 1. Hermitian extension of the paired half spectra
+    // 1. Hermitian extension of the paired half spectra (S1 [kz][pos][c]:
+    //    line l of this tile at kz sits at (kz*npos + pos0)*3 + l)
     if (demag && tid < g.nthr) {
-        const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * hz * 3;
+        const int64_t npos3 = npos * 3;
+        const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * 3;
+        const FastDiv dl = make_fastdiv((uint32_t)nlc);
         for (int e = tid; e < nlc * hz; e += g.nthr) {
-            const int u = e / hz, k = e - u * hz;
+            const int k = (int)fdiv((uint32_t)e, dl), u = e - k * nlc;
             const int l0 = 2 * u, l1 = 2 * u + 1;
             C A = cmake<C>(T(0), T(0)), B = A;
-            if (l0 < nlr) A = S1[(int64_t)(l0 / 3) * hz * 3 + k * 3 + (l0 % 3)];
-            if (l1 < nlr) B = S1[(int64_t)(l1 / 3) * hz * 3 + k * 3 + (l1 % 3)];
+            A = S1[k * npos3 + l0];
+            if (l1 < nlr) B = S1[k * npos3 + l1];
             if (k == 0 || 2 * k == L) {
                 lds[u * pitch + k] = cmake<C>(A.x, B.x);
             } else {
@@ -162,9 +167,9 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
     if (tid < g.nthr) {
         for (int e = tid; e < wp * nz; e += g.nthr) {
-            const int pl = e / nz, z = e - pl * nz;
+            const int pl = (int)fdiv((uint32_t)e, g.dnz), z = e - pl * nz;
             const int64_t pos = pos0 + pl;
-            const int i = (int)(pos / ny), j = (int)(pos - (int64_t)i * ny);
+            const int i = (int)fdiv((uint32_t)pos, g.dny), j = (int)(pos - (int64_t)i * ny);
             const int64_t cell = pos * nz + z;
             T hd[3] = {T(0), T(0), T(0)};
             if (demag) {

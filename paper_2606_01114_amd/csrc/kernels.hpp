@@ -10,8 +10,16 @@ template <typename T>
 hipError_t launch_line_pass(const LinePass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes, int dir,
                             bool sym, hipStream_t s);
 template <typename T>
-hipError_t launch_fused_x(const FusedPass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
+hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
                           hipStream_t s);
+// power-of-two specialisations; line_ct_shape / fused_ct_threads report
+// whether one exists for a length (and its tile width / thread count)
+int line_ct_shape(int L, size_t csz, int *W, int *NT);
+int fused_ct_threads(int L);
+size_t line_ct_lds(int L, int W, size_t csz);
+size_t fused_ct_lds(int L, size_t csz);
+template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s);
+template <typename T> hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s);
 template <typename T> hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s);
 template <typename T> hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s);
 template <typename T>

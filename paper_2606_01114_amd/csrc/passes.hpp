@@ -25,18 +25,18 @@ struct LinePass {
     FftDesc f;
 };
 
-// Fused pass along x: forward FFT, 3x3 spectral product with the stored
-// tensor, inverse FFT; in place on S2 laid out [x][position][component].
+// Fused pass along y: forward FFT, 3x3 spectral product with the demag
+// tensor, inverse FFT; in place on S2 laid out [kz][kx][y][component], so the
+// three components of one (kz, kx) pencil are one contiguous block.
 struct FusedPass {
     void *data;
-    const void *tensor;        // [ky'][kz][kx'][6], pre-scaled
+    const void *tensor;        // [kz][kx'][ky'][6], pre-scaled, kx' <= Lx/2, ky' <= Ly/2
     const void *tw;
-    int64_t row;               // stride between x rows (complex units)
-    int npos;                  // positions (ky, kz) per x row = Ly*hz
-    int n;                     // rows present (nx)
-    int Ly, hz, hx;            // spectral extents (hx = Lx/2+1)
-    int W, tiles, pitch, nthr; // positions per tile, tiles, LDS pitch, threads
-    FftDesc f;                 // length Lx
+    int n;                     // rows present along y (ny)
+    int Lx, Ly, hz, hxp, hyp;  // hxp = Lx/2+1, hyp = Ly/2+1
+    int npos;                  // pencils = hz*Lx
+    int W, tiles, pitch, nthr; // pencils per tile, tiles, LDS pitch, threads
+    FftDesc f;                 // length Ly
 };
 
 // Field constants for the z passes and the fused epilogue.
@@ -46,7 +46,8 @@ struct ZGeom {
     int pad_;
     FftDesc f;                 // length Lz
     const void *tw;
-    void *S1;                  // [pos][kz][c]
+    void *S1;                  // [kz][pos][c], pos = x*ny + y
+    FastDiv dnz, dny;          // division by nz, ny
 };
 
 enum SrcMode { SRC_MS_M = 0, SRC_RAW = 1, SRC_ADJPRE = 2 };
