@@ -32,9 +32,18 @@ WORKLOADS = {
                   name="32x32x4 (padded 64x64x8), random unit m"),
 }
 MS, A, ALPHA, GAMMA, DT = 8e5, 1.3e-11, 0.02, 2.211e5, 1e-13
-PASS_NAMES = ["z_fwd", "y_fwd", "x_fused", "y_inv", "z_inv_stage", "z_inv_heff"]
-KERNEL_SYMBOL = {"z_fwd": "k_zfwd", "y_fwd": "k_line_pass", "x_fused": "k_fused_x", "y_inv": "k_line_pass",
-                 "z_inv_stage": "k_zinv", "z_inv_heff": "k_zinv"}
+PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
+# kernel-name patterns of each pass (specialised first, runtime-planned second)
+KERNEL_PATTERNS = {
+    "z_fwd": [r"k_zfwd_ct<float", r"k_zfwd<float"],
+    "x_fwd": [r"k_line_ct<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
+    "y_fused": [r"k_fused_y_ct<float", r"k_fused_y<float"],
+    "x_inv": [r"k_line_ct<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
+    "z_inv_stage": [r"k_zinv_ct<float, \d+, 1>", r"k_zinv<float, 1>"],
+    "z_inv_heff": [r"k_zinv_ct<float, \d+, 0>", r"k_zinv<float, 0>"],
+}
+KERNEL_SYMBOL = {"z_fwd": "k_zfwd_ct", "x_fwd": "k_line_ct", "y_fused": "k_fused_y_ct", "x_inv": "k_line_ct",
+                 "z_inv_stage": "k_zinv_ct", "z_inv_heff": "k_zinv_ct"}
 
 
 def pass_bytes(grid, L, r):
@@ -50,9 +59,9 @@ def pass_bytes(grid, L, r):
     T6 = 6 * hx * hy * hz
     b = {
         "z_fwd": r * N3 + c * S1,
-        "y_fwd": c * (S1 + S2),
-        "x_fused": 2 * c * S2 + r * T6,
-        "y_inv": c * (S2 + S1),
+        "x_fwd": c * (S1 + S2),
+        "y_fused": 2 * c * S2 + r * T6,
+        "x_inv": c * (S2 + S1),
         # stage 1/2 of RK4: read S1, m_s, m_n, acc; write m_s', acc, S1 (next stage z spectrum)
         "z_inv_stage": c * S1 + 3 * r * N3 + 2 * r * N3 + c * S1,
         "z_inv_heff": c * S1 + r * N3 + r * N3,
@@ -60,7 +69,7 @@ def pass_bytes(grid, L, r):
     stage = [c * S1 + r * N3 + 2 * r * N3 + c * S1,          # stage 0: m_s = m_n, writes acc, m_s'
              b["z_inv_stage"], b["z_inv_stage"],
              c * S1 + 3 * r * N3 + r * N3]                   # stage 3: writes m_n
-    step = b["z_fwd"] + 4 * (b["y_fwd"] + b["x_fused"] + b["y_inv"]) + sum(stage)
+    step = b["z_fwd"] + 4 * (b["x_fwd"] + b["y_fused"] + b["x_inv"]) + sum(stage)
     return b, step
 
 
@@ -118,10 +127,11 @@ def run_gpu(wname, prec, steps, warmup, m_host):
     dt = torch.float32 if prec == "f32" else torch.float64
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plan = DemagPlan(w["grid"], w["cell"], prec)
+    plan = DemagPlan(w["grid"], w["cell"], prec, autotune=True)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    L = plan.info()["L"]
+    info = plan.info()
+    L = info["L"]
     m = torch.tensor(m_host, dtype=dt).to("cuda")
     for _ in range(warmup):
         plan.llg_step(m, MS, A, ALPHA, GAMMA, DT, n_steps=1)
@@ -152,7 +162,8 @@ def run_gpu(wname, prec, steps, warmup, m_host):
     plan.close()
     del m, h
     torch.cuda.empty_cache()
-    return dict(setup_s=setup_s, wall_s=wall, ev_ms=ev_ms, heff_ms=heff_ms, passes=passes, L=L, finite=finite)
+    return dict(setup_s=setup_s, wall_s=wall, ev_ms=ev_ms, heff_ms=heff_ms, passes=passes, L=L, finite=finite,
+                tiles=info["tiles"])
 
 
 def copy_bandwidth():
@@ -203,7 +214,59 @@ def cpu_baseline(w, budget_s=20.0):
                       "of the same recipe (%.1f s)" % (steps, sub[0], sub[1], sub[2], el)}
 
 
+def _pmc_means(path, counter):
+    """Mean per-dispatch value of `counter` for every kernel name in a
+    rocprofv3 counter-collection CSV."""
+    import csv
+    vals = {}
+    with open(path) as f:
+        for row in csv.DictReader(f):
+            if row.get("Counter_Name") != counter:
+                continue
+            vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in vals.items()}
+
+
+def traffic_from(fetch_csv, write_csv, workload, prec):
+    """HBM bytes per launch of each pass from two rocprofv3 --pmc runs
+    (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the same
+    counter reads for the 1 GiB plain copy kernel; written to profiles/traffic.json."""
+    import re
+    f = _pmc_means(fetch_csv, "FETCH_SIZE")
+    w = _pmc_means(write_csv, "WRITE_SIZE")
+    copy_f = [v for k, v in f.items() if "k_copy16" in k]
+    copy_w = [v for k, v in w.items() if "k_copy16" in k]
+    if not copy_f or not copy_w:
+        raise SystemExit("no copy kernel in the counter runs")
+    kf = copy_f[0] * 1024.0 / float(1 << 30)
+    kw = copy_w[0] * 1024.0 / float(1 << 30)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            out = json.load(fh)
+    except (OSError, ValueError):
+        out = {}
+    h = src_hash()
+    for pname, pats in KERNEL_PATTERNS.items():
+        for pat in pats:
+            fk = [k for k in f if re.search(pat, k)]
+            wk = [k for k in w if re.search(pat, k)]
+            if fk and wk:
+                by = f[fk[0]] * 1024.0 / kf + w[wk[0]] * 1024.0 / kw
+                out["%s/%s/%s" % (workload, prec, pname)] = {
+                    "bytes_per_launch": by, "kernel": fk[0], "fetch_KiB": f[fk[0]], "write_KiB": w[wk[0]],
+                    "copy_scale_fetch": kf, "copy_scale_write": kw, "src_hash": h}
+                break
+    with open(path, "w") as fh:
+        json.dump(out, fh, indent=1, sort_keys=True)
+    print(json.dumps(out, indent=1, sort_keys=True))
+
+
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--traffic-from":
+        traffic_from(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else "large",
+                     sys.argv[5] if len(sys.argv) > 5 else "f32")
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -232,7 +295,7 @@ def main():
     pb, step_bytes = pass_bytes(w["grid"], res["L"], r)
     ms_step = res["ev_ms"] / args.steps
     value = ncell * args.steps / (res["wall_s"]) / 1e6
-    launches = {"z_fwd": 1, "y_fwd": 4, "x_fused": 4, "y_inv": 4, "z_inv_stage": 4, "z_inv_heff": 0}
+    launches = {"z_fwd": 1, "x_fwd": 4, "y_fused": 4, "x_inv": 4, "z_inv_stage": 4, "z_inv_heff": 0}
     share = {k: res["passes"][k] * launches[k] for k in launches}
     dom = max(share, key=share.get)
     ach = pb[dom] / (res["passes"][dom] * 1e-3)
@@ -245,10 +308,11 @@ def main():
         "step_algorithmic_bytes": step_bytes,
         "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK,
         "heff_ms": res["heff_ms"], "heff_Mcell_per_s": ncell / (res["heff_ms"] * 1e-3) / 1e6,
-        "tensor_setup_s": res["setup_s"],
+        "plan_setup_s": res["setup_s"],
         "pass_ms": res["passes"],
         "pass_GBps": {k: pb[k] / (res["passes"][k] * 1e-3) / 1e9 for k in pb},
         "padded_L": list(res["L"]),
+        "tiles": {"z_cols": res["tiles"][0], "x_cols": res["tiles"][1], "y_pencils": res["tiles"][2]},
         "finite": res["finite"],
     }
     try:
@@ -264,7 +328,7 @@ def main():
         pb64, sb64 = pass_bytes(w["grid"], r64["L"], 8)
         extra["fp64"] = {"value": v64, "ms_per_step": r64["ev_ms"] / s64, "heff_ms": r64["heff_ms"],
                          "step_hbm_frac": sb64 / (r64["ev_ms"] / s64 * 1e-3) / HBM_PEAK,
-                         "tensor_setup_s": r64["setup_s"], "pass_ms": r64["passes"]}
+                         "plan_setup_s": r64["setup_s"], "pass_ms": r64["passes"]}
         extra["fp32_over_fp64"] = value / v64
     out = {
         "metric": METRIC, "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps,

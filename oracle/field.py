@@ -77,22 +77,51 @@ def full_tensor_at_offsets(octant, di, dj, dk):
     return out
 
 
-def demag_direct(m, Ms, octant, cells=None):
+def demag_direct(m, Ms, octant, cells=None, chunk=1 << 22):
     """O(N^2) direct sum H_i = -sum_j N(r_i - r_j) M_j, optionally only at the
-    listed target cells (K,3) -> (K,3); else at every cell -> (nx,ny,nz,3)."""
+    listed target cells (K,3) -> (K,3); else at every cell -> (nx,ny,nz,3).
+    Sources are visited in chunks of ``chunk`` cells to bound memory."""
     m = np.asarray(m, dtype=np.float64)
     nx, ny, nz, _ = m.shape
     M = (m * _ms_array(Ms, (nx, ny, nz))[..., None]).reshape(-1, 3)
-    I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
-    I, J, K = I.ravel(), J.ravel(), K.ravel()
-    targets = np.stack([I, J, K], 1) if cells is None else np.asarray(cells, dtype=np.int64).reshape(-1, 3)
+    ntot = nx * ny * nz
+    if cells is None:
+        I, J, K = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+        targets = np.stack([I.ravel(), J.ravel(), K.ravel()], 1)
+    else:
+        targets = np.asarray(cells, dtype=np.int64).reshape(-1, 3)
     H = np.zeros((targets.shape[0], 3))
-    for t, (i, j, k) in enumerate(targets):
-        Nt = full_tensor_at_offsets(octant, i - I, j - J, k - K)   # (N,6)
-        H[t, 0] = -(Nt[:, 0] * M[:, 0] + Nt[:, 3] * M[:, 1] + Nt[:, 4] * M[:, 2]).sum()
-        H[t, 1] = -(Nt[:, 3] * M[:, 0] + Nt[:, 1] * M[:, 1] + Nt[:, 5] * M[:, 2]).sum()
-        H[t, 2] = -(Nt[:, 4] * M[:, 0] + Nt[:, 5] * M[:, 1] + Nt[:, 2] * M[:, 2]).sum()
+    for s0 in range(0, ntot, chunk):
+        idx = np.arange(s0, min(ntot, s0 + chunk))
+        I, r = np.divmod(idx, ny * nz)
+        J, K = np.divmod(r, nz)
+        Mc = M[idx]
+        for t, (i, j, k) in enumerate(targets):
+            Nt = full_tensor_at_offsets(octant, i - I, j - J, k - K)   # (chunk,6)
+            H[t, 0] -= (Nt[:, 0] * Mc[:, 0] + Nt[:, 3] * Mc[:, 1] + Nt[:, 4] * Mc[:, 2]).sum()
+            H[t, 1] -= (Nt[:, 3] * Mc[:, 0] + Nt[:, 1] * Mc[:, 1] + Nt[:, 5] * Mc[:, 2]).sum()
+            H[t, 2] -= (Nt[:, 4] * Mc[:, 0] + Nt[:, 5] * Mc[:, 1] + Nt[:, 2] * Mc[:, 2]).sum()
     return H if cells is not None else H.reshape(nx, ny, nz, 3)
+
+
+def exchange_at(m, Ms, A, d, cells):
+    """Exchange field at the listed cells only (K,3) -> (K,3), same rule as
+    ``exchange_field``."""
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz, _ = m.shape
+    Msa = _ms_array(Ms, (nx, ny, nz))
+    out = np.zeros((len(cells), 3))
+    for t, (i, j, k) in enumerate(np.asarray(cells, dtype=np.int64)):
+        if not Msa[i, j, k] > 0:
+            continue
+        lap = np.zeros(3)
+        for ax, (di, dj, dk) in enumerate(((1, 0, 0), (0, 1, 0), (0, 0, 1))):
+            for s in (1, -1):
+                a, b, c = i + s * di, j + s * dj, k + s * dk
+                if 0 <= a < nx and 0 <= b < ny and 0 <= c < nz and Msa[a, b, c] > 0:
+                    lap += (m[a, b, c] - m[i, j, k]) / d[ax] ** 2
+        out[t] = 2.0 * A / (MU0 * Msa[i, j, k]) * lap
+    return out
 
 
 def exchange_field(m, Ms, A, d):

@@ -244,11 +244,11 @@ class _LLGRun(torch.autograd.Function):
         plan, A, alpha, gamma, dt, n_steps = ctx.args
         g = g_out.detach().contiguous().clone()
         gMs = torch.zeros_like(Ms)
-        for start, ck in reversed(ctx.ckpts):
-            k = min(n_steps - start, n_steps if not ctx.ckpts else n_steps)
-            # states of this segment, recomputed from its checkpoint
-            nxt = [s for s, _ in ctx.ckpts if s > start]
-            end = nxt[0] if nxt else n_steps
+        starts = [s for s, _ in ctx.ckpts] + [n_steps]
+        for seg in range(len(ctx.ckpts) - 1, -1, -1):
+            start, ck = ctx.ckpts[seg]
+            end = starts[seg + 1]
+            # states m_start .. m_{end-1} of this segment, recomputed from its checkpoint
             states = [ck.clone()]
             for _ in range(end - start - 1):
                 s = states[-1].clone()
@@ -256,7 +256,6 @@ class _LLGRun(torch.autograd.Function):
                 states.append(s)
             for s in reversed(states):
                 plan.llg_step_adjoint(s, Ms, A, alpha, gamma, dt, g, gMs)
-            del k
         return g, gMs, None, None, None, None, None, None, None
 
 

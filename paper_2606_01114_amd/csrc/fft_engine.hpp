@@ -20,23 +20,25 @@ constexpr int lds_pitch(int L, int NL) { return NL >= 32 ? L + 1 : (NL == 3 ? L 
 }  // namespace ct
 
 // One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
-// 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).
-template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, class Ld, class St>
-__device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
+// 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
+// line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB: groups of LA lines
+// are interleaved (LA = NL: all lines; LA = 3: the components of one cell
+// column).  P = LDS pitch of a line.
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int LA, int P, class Ld, class St>
+__device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     using C = cplx<T>;
     constexpr int R = ct::prad(L, REV, S);
     constexpr int Ns = ct::pns(L, REV, S);
     constexpr int NB = L / R;
     constexpr int TOT = NL * NB;
     constexpr int U = (TOT + NT - 1) / NT;
-    constexpr int P = ct::lds_pitch(L, NL);
     const C *t = tw + ct::ptw(L, REV, S);
     C v[U][R];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int b = tid + u * NT;
         if (b < TOT) {
-            const int line = b % NL, j = b / NL;
+            const int line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB;
 #pragma unroll
             for (int r = 0; r < R; ++r) v[u][r] = IN ? lds[line * P + j + r * NB] : ld(line, j + r * NB);
             if (Ns > 1) {
@@ -56,7 +58,7 @@ __device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restric
     for (int u = 0; u < U; ++u) {
         const int b = tid + u * NT;
         if (b < TOT) {
-            const int line = b % NL, j = b / NL;
+            const int line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB;
             const int d = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
@@ -66,6 +68,50 @@ __device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restric
         }
     }
     if (OUT) __syncthreads();
+}
+
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, class Ld, class St>
+__device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
+    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL)>(lds, tw, tid, ld, st);
+}
+
+// stages [S, E) LDS -> LDS with interleave LA and pitch P
+template <typename T, int L, bool REV, int S, int E, int DIR, int NT, int NL, int LA, int P>
+__device__ __forceinline__ void eng_mid_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid) {
+    if constexpr (S < E) {
+        auto nold = [](int, int) { return cplx<T>(); };
+        auto nost = [](int, int, cplx<T>) {};
+        eng_stage_la<T, L, REV, S, DIR, NT, NL, 1, 1, LA, P>(lds, tw, tid, nold, nost);
+        eng_mid_la<T, L, REV, S + 1, E, DIR, NT, NL, LA, P>(lds, tw, tid);
+    }
+}
+
+// General transform: stage 0 from the loader (IN0 = 0) or LDS (IN0 = 1), the
+// last stage to the storer (OUTL = 0) or LDS (OUTL = 1).  With IN0 = 1 the
+// caller must have synchronised after filling LDS; with OUTL = 1 the call
+// ends with a barrier.
+template <typename T, int L, int DIR, int NT, int NL, int LA, int P, int IN0, int OUTL, class Ld, class St>
+__device__ __forceinline__ void eng_fft_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
+    constexpr int NS = ct::nst(L);
+    if constexpr (NS == 0) {
+        if constexpr (IN0 == 0) {
+            for (int line = tid; line < NL; line += NT) {
+                if constexpr (OUTL) lds[line * P] = ld(line, 0);
+                else st(line, 0, ld(line, 0));
+            }
+        } else if constexpr (OUTL == 0) {
+            for (int line = tid; line < NL; line += NT) st(line, 0, lds[line * P]);
+        }
+        if constexpr (OUTL) __syncthreads();
+    } else if constexpr (NS == 1) {
+        eng_stage_la<T, L, false, 0, DIR, NT, NL, IN0, OUTL, LA, P>(lds, tw, tid, ld, st);
+    } else {
+        auto nold = [](int, int) { return cplx<T>(); };
+        auto nost = [](int, int, cplx<T>) {};
+        eng_stage_la<T, L, false, 0, DIR, NT, NL, IN0, 1, LA, P>(lds, tw, tid, ld, nost);
+        eng_mid_la<T, L, false, 1, NS - 1, DIR, NT, NL, LA, P>(lds, tw, tid);
+        eng_stage_la<T, L, false, NS - 1, DIR, NT, NL, 1, OUTL, LA, P>(lds, tw, tid, nold, st);
+    }
 }
 
 // stages [S, E) all LDS -> LDS

@@ -150,7 +150,8 @@ struct mm_plan {
     FusedPass fp{};
     ZGeom zg{};
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
-    bool x_ct = false, y_ct = false;     // power-of-two specialised kernels in use
+    bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
+    int x_var = 0;                                  // tile-width variant of the specialised x pass
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -243,6 +244,16 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     const size_t ox = app(p->fx), oy = app(p->fy);
     (void)app(make_fft(Ly, true));   // reversed radix order, right after y's table (fused inverse)
     const size_t oz = app(p->fz);
+    // folded z transform (power-of-two Lz): table of length Lz/2, then exp(-2 pi i k / Lz), k <= Lz/2
+    size_t ozh = 0;
+    if (Lz >= 2 && (Lz & (Lz - 1)) == 0) {
+        ozh = app(make_fft(Lz / 2));
+        for (int k = 0; k <= Lz / 2; ++k) {
+            const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)Lz;
+            tw.push_back((T)cosl(ang));
+            tw.push_back((T)sinl(ang));
+        }
+    }
     int rc;
     if ((rc = dalloc(p, &p->twT, std::max<size_t>(tw.size() * sizeof(T), 16)))) return rc;
     HIPCK(hipMemcpy(p->twT, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -264,7 +275,8 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     size_t lds;
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
-    p->x_ct = line_ct_shape(Lx, csz, &Wct, &NTct) && !getenv("MMX_NO_CT");
+    if (getenv("MMX_XVAR")) p->x_var = atoi(getenv("MMX_XVAR")) ? 1 : 0;
+    p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && !getenv("MMX_NO_CT");
     if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);
@@ -307,11 +319,14 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     int P = (int)std::max<int64_t>(2, (1024 / nz) & ~1);
     P = std::min<int64_t>(P, std::max<int64_t>(2, (nx * ny + 1) & ~1));
     while (P > 2 && ((size_t)((3 * P + 1) / 2) * pz * csz > 48 * 1024 || fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz) > 1024)) P -= 2;
+    p->z_ct = zct_cols(Lz) > 0 && !getenv("MMX_NO_CT");
+    if (p->z_ct) P = zct_cols(Lz);
     z.P = P; z.tiles = (int)((nx * ny + P - 1) / P); z.pitch = pz;
     z.dnz = make_fastdiv((uint32_t)nz); z.dny = make_fastdiv((uint32_t)ny);
-    z.nthr = std::min(1024, fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz));
-    z.f = p->fz.d; z.tw = twc + oz; z.S1 = p->S1;
+    z.nthr = std::min(1024, std::max(256, fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz)));
+    z.f = p->fz.d; z.tw = twc + oz; z.twh = twc + ozh; z.S1 = p->S1;
     p->lds_z = std::max<size_t>((size_t)((3 * P + 1) / 2) * pz * csz, 16 * 2 * sizeof(double) + 64);
+    if (p->z_ct) p->lds_z = std::max(p->lds_z, zct_lds(Lz, csz));
     if ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsMax) return fail(MM_ENOTSUP, "z length %d too long", Lz);
     // energy partials
     if ((rc = dalloc(p, (void **)&p->epart, (size_t)z.tiles * 2 * sizeof(double)))) return rc;
@@ -386,6 +401,59 @@ int build_spectrum(mm_plan *p, const double *d_oct) {
     return rc;
 }
 
+// Switch the specialised x pass to tile-width variant v (descriptors, LDS).
+int configure_x(mm_plan *p, int v) {
+    const size_t csz = p->prec == MM_F32 ? sizeof(float2) : sizeof(double2);
+    int W = 0, NT = 0;
+    if (!p->x_ct || !line_ct_shape((int)p->L[0], csz, v, &W, &NT)) return MM_OK;
+    p->x_var = v;
+    for (LinePass *f : {&p->lp_fwd, &p->lp_inv}) {
+        f->W = W;
+        f->nthr = NT;
+        f->tiles_inner = (f->inner + W - 1) / W;
+    }
+    p->lds_fwd = p->lds_inv = line_ct_lds((int)p->L[0], W, csz);
+    p->tiles_fwd = p->tiles_inv = p->lp_fwd.tiles_inner * p->lp_fwd.outer;
+    LinePass two[2] = {p->lp_fwd, p->lp_inv};
+    HIPCK(hipMemcpy(p->d_lp, two, sizeof two, hipMemcpyHostToDevice));
+    return MM_OK;
+}
+
+// Autotuner: time each tile-width variant of the x passes on this plan's own
+// buffers and keep the fastest.
+template <typename T>
+int autotune_x(mm_plan *p) {
+    if (!p->x_ct) return MM_OK;
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    double best = 1e300;
+    int bestv = p->x_var, rc = MM_OK;
+    for (int v = 0; v < 2 && !rc; ++v) {
+        const size_t csz = sizeof(cplx<T>);
+        int W = 0, NT = 0;
+        if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT) || line_ct_lds((int)p->L[0], W, csz) > kLdsMax) continue;
+        if ((rc = configure_x(p, v))) break;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            (void)hipEventRecord(e0, p->stream);
+            for (int k = 0; k < 3; ++k) {
+                hipError_t e = launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, W, -1, p->stream);
+                if (e == hipSuccess) e = launch_line_ct<T>(p->lp_inv, p->tiles_inv, W, +1, p->stream);
+                if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
+            }
+            (void)hipEventRecord(e1, p->stream);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (!rc && ms < best) { best = ms; bestv = v; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!rc) rc = configure_x(p, bestv);
+    return rc;
+}
+
 int compute_tensor(mm_plan *p) {
     const size_t oct = (size_t)p->n[0] * p->n[1] * p->n[2] * 6 * sizeof(double);
     void *d = nullptr;
@@ -407,7 +475,8 @@ int run_zfwd(mm_plan *p, int src, const void *srcp, const void *Ms, double Ms_s,
     std::memset(&a, 0, sizeof a);
     a.g = p->zg; a.src = srcp; a.Ms = Ms; a.Ms_scalar = Ms_s;
     a.s = s; a.h = h; a.kb = kb; a.ym = ym; a.yh = yh; a.gp = gp; a.alpha = alpha;
-    HIPCK(launch_zfwd<T>(a, src, p->lds_z, p->stream));
+    if (p->z_ct && src != SRC_ADJPRE) HIPCK(launch_zfwd_ct<T>(a, src, p->stream));
+    else HIPCK(launch_zfwd<T>(a, src, p->lds_z, p->stream));
     return MM_OK;
 }
 
@@ -420,6 +489,12 @@ int run_xyx(mm_plan *p) {
     if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
     else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
     return MM_OK;
+}
+
+template <typename T>
+hipError_t zinv_any(mm_plan *p, const ZInvArgs &a, int epi) {
+    if (p->z_ct) return launch_zinv_ct<T>(a, epi, p->stream);
+    return launch_zinv<T>(a, epi, p->lds_z, p->stream);
 }
 
 void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double Ms_s, double A) {
@@ -454,7 +529,7 @@ int heff_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, 
     ZInvArgs a;
     fill_common(p, a, terms, Ms, Ms_s, A);
     a.m = m; a.h_out = h; a.epart = E ? p->epart : nullptr;
-    HIPCK(launch_zinv<T>(a, EPI_HEFF, p->lds_z, p->stream));
+    HIPCK(zinv_any<T>(p, a, EPI_HEFF));
     if (E) {
         HIPCK(launch_energy_reduce(p->epart, p->zg.tiles, p->esum, p->stream));
         double s[2];
@@ -486,7 +561,7 @@ int enqueue_step(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, dou
         a.m_n = m; a.acc = p->acc;
         a.ms_out = s < 3 ? p->ms[s & 1] : nullptr;
         a.m_out = s == 3 ? m : nullptr;
-        HIPCK(launch_zinv<T>(a, EPI_STAGE, p->lds_z, p->stream));
+        HIPCK(zinv_any<T>(p, a, EPI_STAGE));
     }
     return MM_OK;
 }
@@ -541,7 +616,7 @@ int adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double 
     ZInvArgs a;
     fill_common(p, a, terms, Ms, Ms_s, A);
     a.m = m; a.g_h = g_h; a.g_m = g_m; a.g_Ms = g_Ms; a.acc_gMs = acc_gMs;
-    HIPCK(launch_zinv<T>(a, EPI_ADJ, p->lds_z, p->stream));
+    HIPCK(zinv_any<T>(p, a, EPI_ADJ));
     return MM_OK;
 }
 
@@ -572,7 +647,7 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
         a.ms_in = srec[s]; a.m_n = m; a.acc = p->acc;
         a.ms_out = s < 3 ? srec[s + 1] : nullptr;
         a.m_out = nullptr; a.h_rec = hrec[s]; a.u_rec = s == 3 ? urec : nullptr;
-        HIPCK(launch_zinv<T>(a, EPI_STAGE, p->lds_z, p->stream));
+        HIPCK(zinv_any<T>(p, a, EPI_STAGE));
     }
     // reverse
     HIPCK(launch_adj_unorm<T>((const T *)g, (const T *)urec, (T *)ub, (T *)g, renorm, ncell, p->stream));
@@ -585,7 +660,7 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
         ZInvArgs a;
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
         a.m = srec[q]; a.g_h = yh; a.g_m = gmh; a.g_Ms = g_Ms; a.acc_gMs = 1;
-        HIPCK(launch_zinv<T>(a, EPI_ADJ, p->lds_z, p->stream));
+        HIPCK(zinv_any<T>(p, a, EPI_ADJ));
         HIPCK(launch_adj_combine<T>((const T *)ym, (const T *)gmh, (const T *)ub, (T *)g, q > 0 ? (T *)kb : nullptr,
                                     q > 0 ? w[q - 1] : 0.0, coef[q], ncell * 3, p->stream));
     }
@@ -614,14 +689,14 @@ int time_one(mm_plan *p, int k) {
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, nullptr, 8e5, 1.3e-11);
         a.stage = 1; a.next_r2c = 1; a.renorm = 1; a.dt = 1e-13; a.alpha = 0.02; a.gp = 2.2e5;
         a.ms_in = p->ms[0]; a.m_n = p->ms[0]; a.acc = p->acc; a.ms_out = p->ms[1];
-        HIPCK(launch_zinv<T>(a, EPI_STAGE, p->lds_z, p->stream));
+        HIPCK(zinv_any<T>(p, a, EPI_STAGE));
         return MM_OK;
     }
     default: {
         ZInvArgs a;
         fill_common(p, a, MM_DEMAG | MM_EXCHANGE, nullptr, 8e5, 1.3e-11);
         a.m = p->ms[0]; a.h_out = p->ms[1];
-        HIPCK(launch_zinv<T>(a, EPI_HEFF, p->lds_z, p->stream));
+        HIPCK(zinv_any<T>(p, a, EPI_HEFF));
         return MM_OK;
     }
     }
@@ -672,6 +747,7 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     for (int a = 0; a < 3; ++a) { p->n[a] = grid[a]; p->d[a] = cell[a]; p->L[a] = L[a]; }
     rc = precision == MM_F32 ? setup_plan<float>(p, &o) : setup_plan<double>(p, &o);
     if (!rc) rc = compute_tensor(p);
+    if (!rc && o.autotune) rc = precision == MM_F32 ? autotune_x<float>(p) : autotune_x<double>(p);
     if (rc) {
         std::string keep = g_last;
         free_all(p);

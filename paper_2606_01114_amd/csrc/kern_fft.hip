@@ -338,46 +338,51 @@ hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles
     return hipGetLastError();
 }
 
-// Specialised shapes: (L, NT, W) chosen so each thread holds 16 complex values
-// and a tile's LDS stays within 64 KB (FP32) / 64 KB (FP64).
-template <typename T> struct LineCT;
-#define LINE_CASE(LL, NTT, WW)                                                                                      \
-    case LL:                                                                                                        \
-        if (W != WW) return hipErrorInvalidValue;                                                                   \
-        if (dir < 0) hipLaunchKernelGGL((k_line_ct<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, a);       \
-        else hipLaunchKernelGGL((k_line_ct<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, a);               \
-        return hipGetLastError();
-
-int line_ct_shape(int L, size_t csz, int *W, int *NT) {
-    // returns 1 if a specialised kernel exists for (L, precision)
-    const bool f32 = csz == 8;
+// Specialised shapes of the x pass: for each power-of-two length two tile
+// widths W (columns per tile); NT = W L / 16 threads so each holds 16 complex
+// values.  Variant 0 keeps a tile's LDS near 64 KB, variant 1 doubles it.
+static int line_ct_w(int L, bool f32, int variant) {
+    int w;
     switch (L) {
-    case 64: *W = 16; *NT = 64; return 1;
-    case 128: *W = 16; *NT = 128; return 1;
-    case 256: *W = 16; *NT = 256; return 1;
-    case 512: *W = f32 ? 16 : 8; *NT = f32 ? 512 : 256; return 1;
-    case 1024: *W = f32 ? 8 : 4; *NT = f32 ? 512 : 256; return 1;
-    case 2048: *W = f32 ? 4 : 2; *NT = f32 ? 512 : 256; return 1;
-    case 4096: *W = f32 ? 2 : 1; *NT = f32 ? 512 : 256; return 1;
+    case 64: case 128: case 256: w = 16; break;
+    case 512: w = f32 ? 16 : 8; break;
+    case 1024: w = f32 ? 8 : 4; break;
+    case 2048: w = f32 ? 4 : 2; break;
+    case 4096: w = f32 ? 2 : 1; break;
     default: return 0;
     }
+    return variant ? 2 * w : w;
 }
+
+int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT) {
+    const int w = line_ct_w(L, csz == 8, variant);
+    if (!w) return 0;
+    *W = w;
+    *NT = w * L / 16;
+    return *NT >= 64 && *NT <= 1024;
+}
+
+#define LINE_CASE(LL, WW)                                                                                             \
+    if (a.f.L == LL && W == WW) {                                                                                     \
+        if (dir < 0) hipLaunchKernelGGL((k_line_ct<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a); \
+        else hipLaunchKernelGGL((k_line_ct<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a);       \
+        return hipGetLastError();                                                                                     \
+    }
 
 template <typename T>
 hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s) {
     if (tiles <= 0) return hipSuccess;
     const size_t lds = line_ct_lds(a.f.L, W, sizeof(cplx<T>));
-    constexpr bool f32 = sizeof(T) == 4;
-    switch (a.f.L) {
-        LINE_CASE(64, 64, 16)
-        LINE_CASE(128, 128, 16)
-        LINE_CASE(256, 256, 16)
-        LINE_CASE(512, (f32 ? 512 : 256), (f32 ? 16 : 8))
-        LINE_CASE(1024, (f32 ? 512 : 256), (f32 ? 8 : 4))
-        LINE_CASE(2048, (f32 ? 512 : 256), (f32 ? 4 : 2))
-        LINE_CASE(4096, (f32 ? 512 : 256), (f32 ? 2 : 1))
-    default: return hipErrorInvalidValue;
+    if constexpr (sizeof(T) == 4) {
+        LINE_CASE(64, 16) LINE_CASE(64, 32) LINE_CASE(128, 16) LINE_CASE(128, 32) LINE_CASE(256, 16) LINE_CASE(256, 32)
+        LINE_CASE(512, 16) LINE_CASE(512, 32) LINE_CASE(1024, 8) LINE_CASE(1024, 16) LINE_CASE(2048, 4) LINE_CASE(2048, 8)
+        LINE_CASE(4096, 2) LINE_CASE(4096, 4)
+    } else {
+        LINE_CASE(64, 16) LINE_CASE(64, 32) LINE_CASE(128, 16) LINE_CASE(128, 32) LINE_CASE(256, 16) LINE_CASE(256, 32)
+        LINE_CASE(512, 8) LINE_CASE(512, 16) LINE_CASE(1024, 4) LINE_CASE(1024, 8) LINE_CASE(2048, 2) LINE_CASE(2048, 4)
+        LINE_CASE(4096, 1) LINE_CASE(4096, 2)
     }
+    return hipErrorInvalidValue;
 }
 #undef LINE_CASE
 

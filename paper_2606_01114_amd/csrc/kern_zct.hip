@@ -1,0 +1,229 @@
+// Compile-time z passes for power-of-two Lz = 2N: each real z-line of a cell
+// column is folded into a complex line of length N (even samples real, odd
+// samples imaginary), transformed, and unfolded into the Lz/2+1 half
+// spectrum; the inverse folds the half spectrum back, transforms and reads
+// the even/odd samples out.  Lines are the 3 components of P cell columns.
+#include "kernels.hpp"
+#include "fft_engine.hpp"
+#include "zepi.hpp"
+
+namespace mmx {
+
+namespace {
+constexpr int zpitch(int N) { return N < 16 ? N + 1 : N + 11; }
+constexpr int zcols(int N) { return N >= 1024 ? 1 : 1024 / N; }   // P: ~3072 complex per tile
+constexpr int zthreads(int N) { return 256; }
+}  // namespace
+
+// unfold: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[N-k])/2, O = (Z[k] - conj Z[N-k])/(2i),
+// W = exp(-2 pi i / 2N); written to S1 [kz][pos][c] for the tile's lines
+template <typename T, int N, int NT, int NL, int PT>
+__device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g, int64_t pos0, int wp,
+                                              const cplx<T> *__restrict__ wt, int tid) {
+    using C = cplx<T>;
+    const int w3 = 3 * wp;
+    const int64_t npos3 = (int64_t)g.nx * g.ny * 3;
+    C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * 3;
+    const FastDiv dw = make_fastdiv((uint32_t)w3);
+    const T h = T(0.5);
+    for (int e = tid; e < (N + 1) * w3; e += NT) {
+        const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
+        const C za = lds[l * PT + (k % N)];
+        const C zb = lds[l * PT + ((N - k) % N)];
+        const C E = cmake<C>(h * (za.x + zb.x), h * (za.y - zb.y));
+        const C O = cmake<C>(h * (za.y + zb.y), -h * (za.x - zb.x));
+        const C w = wt[k];
+        S1[k * npos3 + l] = cmake<C>(E.x + w.x * O.x - w.y * O.y, E.y + w.x * O.y + w.y * O.x);
+    }
+}
+
+template <typename T, int N, int SRC>
+__global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct(const ZFwdArgs a) {
+    using C = cplx<T>;
+    constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const ZGeom &g = a.g;
+    const int tid = threadIdx.x;
+    const int64_t npos = (int64_t)g.nx * g.ny;
+    const int64_t pos0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * P;
+    const int wp = (int)min((int64_t)P, npos - pos0);
+    const int nz = g.nz;
+    const T *src = reinterpret_cast<const T *>(a.src);
+    const T *Ms = reinterpret_cast<const T *>(a.Ms);
+    const T Ms_s = T(a.Ms_scalar);
+    auto ld = [&](int l, int n) -> C {
+        const int pl = l / 3, c = l - 3 * pl;
+        const int z0 = 2 * n;
+        if (pl >= wp || z0 >= nz) return cmake<C>(T(0), T(0));
+        const int64_t cell = (pos0 + pl) * nz + z0;
+        T re = src[cell * 3 + c], im = T(0);
+        if (SRC == SRC_MS_M) re *= ms_at(Ms, Ms_s, cell);
+        if (z0 + 1 < nz) {
+            im = src[cell * 3 + 3 + c];
+            if (SRC == SRC_MS_M) im *= ms_at(Ms, Ms_s, cell + 1);
+        }
+        return cmake<C>(re, im);
+    };
+    auto nost = [](int, int, C) {};
+    const C *tw = reinterpret_cast<const C *>(g.twh);
+    eng_fft_la<T, N, -1, NT, NL, 3, PT, 0, 1>(lds, tw, tid, ld, nost);
+    zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, wp, tw + (N > 1 ? N - 1 : 0), tid);
+}
+
+template <typename T, int N, int EPI>
+__global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
+    using C = cplx<T>;
+    constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const ZGeom &g = a.g;
+    const int tid = threadIdx.x;
+    const int64_t npos = (int64_t)g.nx * g.ny;
+    const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
+    const int64_t pos0 = (int64_t)blk * P;
+    const int wp = (int)min((int64_t)P, npos - pos0);
+    const int w3 = 3 * wp;
+    const int nz = g.nz, ny = g.ny;
+    const bool demag = (a.terms & 1u) != 0;
+    const C *tw = reinterpret_cast<const C *>(g.twh);
+    const C *wt = tw + (N > 1 ? N - 1 : 0);
+    const FastDiv dw = make_fastdiv((uint32_t)w3);
+    if (demag) {
+        // 1. half spectra X[0..N] of the tile's lines (DC and Nyquist real)
+        const int64_t npos3 = npos * 3;
+        const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * 3;
+        for (int e = tid; e < (N + 1) * w3; e += NT) {
+            const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
+            C X = S1[k * npos3 + l];
+            if (k == 0 || k == N) X.y = T(0);
+            lds[l * PT + k] = X;
+        }
+        __syncthreads();
+        // 2. fold: Z[k] = (X[k] + conj X[N-k]) + i conj(W^k) (X[k] - conj X[N-k]), k < N
+        for (int e = tid; e < (N / 2 + 1) * w3; e += NT) {
+            const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
+            C *b = lds + l * PT;
+            if (k == 0) {
+                const C x0 = b[0], xn = b[N];
+                const C s = cmake<C>(x0.x + xn.x, x0.y - xn.y), d = cmake<C>(x0.x - xn.x, x0.y + xn.y);
+                b[0] = cmake<C>(s.x - d.y, s.y + d.x);
+            } else {
+                const C xk = b[k], xm = b[N - k];
+                const C wk = wt[k];
+                {
+                    const C s = cmake<C>(xk.x + xm.x, xk.y - xm.y), d = cmake<C>(xk.x - xm.x, xk.y + xm.y);
+                    // i conj(w) d
+                    const C cd = cmake<C>(wk.x * d.x + wk.y * d.y, wk.x * d.y - wk.y * d.x);
+                    b[k] = cmake<C>(s.x - cd.y, s.y + cd.x);
+                }
+                if (2 * k != N) {
+                    const C wm = wt[N - k];
+                    const C s = cmake<C>(xm.x + xk.x, xm.y - xk.y), d = cmake<C>(xm.x - xk.x, xm.y + xk.y);
+                    const C cd = cmake<C>(wm.x * d.x + wm.y * d.y, wm.x * d.y - wm.y * d.x);
+                    b[N - k] = cmake<C>(s.x - cd.y, s.y + cd.x);
+                }
+            }
+        }
+        __syncthreads();
+        auto nold = [](int, int) { return C(); };
+        auto nost = [](int, int, C) {};
+        eng_fft_la<T, N, +1, NT, NL, 3, PT, 1, 1>(lds, tw, tid, nold, nost);
+    }
+    // 3. epilogue per cell; demag field sample z of component c sits in line
+    //    3 pl + c, slot z/2, real part for even z
+    double ed = 0.0, ex = 0.0;
+    for (int e = tid; e < wp * nz; e += NT) {
+        const int pl = (int)fdiv((uint32_t)e, g.dnz), z = e - pl * nz;
+        const int64_t pos = pos0 + pl;
+        const int i = (int)fdiv((uint32_t)pos, g.dny), j = (int)(pos - (int64_t)i * ny);
+        const int64_t cell = pos * nz + z;
+        T hd[3] = {T(0), T(0), T(0)};
+        if (demag) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + (z >> 1)])[z & 1];
+        }
+        T srcn[3];
+        cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn);
+        if (EPI == EPI_STAGE && a.next_r2c) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + (z >> 1)])[z & 1] = srcn[c];
+        }
+    }
+    if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (EPI == EPI_STAGE && a.next_r2c) {
+        // 4. the next stage's source, already folded in LDS: clear the padding
+        //    and transform it forward
+        const int n0 = (nz + 1) / 2;
+        for (int e = tid; e < (N - n0) * w3; e += NT) {
+            const int k = n0 + (int)fdiv((uint32_t)e, dw), l = e - (k - n0) * w3;
+            lds[l * PT + k] = cmake<C>(T(0), T(0));
+        }
+        if (nz & 1) {
+            for (int l = tid; l < w3; l += NT) reinterpret_cast<T *>(&lds[l * PT + nz / 2])[1] = T(0);
+        }
+        __syncthreads();
+        auto nold = [](int, int) { return C(); };
+        auto nost = [](int, int, C) {};
+        eng_fft_la<T, N, -1, NT, NL, 3, PT, 1, 1>(lds, tw, tid, nold, nost);
+        zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, wp, wt, tid);
+    }
+}
+
+// ---------------- launchers -------------------------------------------------
+int zct_cols(int Lz) {
+    if (Lz < 2 || Lz > 2048 || (Lz & (Lz - 1))) return 0;
+    return zcols(Lz / 2);
+}
+
+size_t zct_lds(int Lz, size_t csz) {
+    const int N = Lz / 2;
+    return std::max<size_t>((size_t)3 * zcols(N) * zpitch(N) * csz, 512);
+}
+
+#define ZN_CASES(M)                                                                                                   \
+    M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024)
+
+template <typename T>
+hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s) {
+    const int N = a.g.Lz / 2;
+    const int tiles = (int)(((int64_t)a.g.nx * a.g.ny + zcols(N) - 1) / zcols(N));
+    const size_t lds = zct_lds(a.g.Lz, sizeof(cplx<T>));
+    switch (N) {
+#define ZF(NN)                                                                                                        \
+    case NN:                                                                                                          \
+        if (src_mode == SRC_MS_M) hipLaunchKernelGGL((k_zfwd_ct<T, NN, SRC_MS_M>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
+        else hipLaunchKernelGGL((k_zfwd_ct<T, NN, SRC_RAW>), dim3(tiles), dim3(zthreads(NN)), lds, s, a);          \
+        break;
+        ZN_CASES(ZF)
+#undef ZF
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
+    const int N = a.g.Lz / 2;
+    const int tiles = (int)(((int64_t)a.g.nx * a.g.ny + zcols(N) - 1) / zcols(N));
+    const size_t lds = zct_lds(a.g.Lz, sizeof(cplx<T>));
+    switch (N) {
+#define ZI(NN)                                                                                                        \
+    case NN:                                                                                                          \
+        if (epi == EPI_HEFF) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_HEFF>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
+        else if (epi == EPI_STAGE) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_STAGE>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
+        else hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_ADJ>), dim3(tiles), dim3(zthreads(NN)), lds, s, a);          \
+        break;
+        ZN_CASES(ZI)
+#undef ZI
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_zfwd_ct<float>(const ZFwdArgs &, int, hipStream_t);
+template hipError_t launch_zfwd_ct<double>(const ZFwdArgs &, int, hipStream_t);
+template hipError_t launch_zinv_ct<float>(const ZInvArgs &, int, hipStream_t);
+template hipError_t launch_zinv_ct<double>(const ZInvArgs &, int, hipStream_t);
+
+}  // namespace mmx

@@ -14,7 +14,7 @@ hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles
                           hipStream_t s);
 // power-of-two specialisations; line_ct_shape / fused_ct_threads report
 // whether one exists for a length (and its tile width / thread count)
-int line_ct_shape(int L, size_t csz, int *W, int *NT);
+int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT);
 int fused_ct_threads(int L);
 size_t line_ct_lds(int L, int W, size_t csz);
 size_t fused_ct_lds(int L, size_t csz);
@@ -29,6 +29,12 @@ template <typename T>
 hipError_t launch_zinv_batch(const ZInvArgs *d, const int2 *map, int tiles, int nthr, int epi, size_t lds_bytes,
                              hipStream_t s);
 hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
+// compile-time z passes (power-of-two Lz in [2, 2048]); zct_cols returns the
+// cell columns per tile (0 if no specialisation), zct_lds the LDS bytes
+int zct_cols(int Lz);
+size_t zct_lds(int Lz, size_t csz);
+template <typename T> hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s);
+template <typename T> hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s);
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s);
 hipError_t launch_tensor_octant(double *out, int nx, int ny, int nz, double dx, double dy, double dz, double P,
                                 hipStream_t s);

@@ -46,6 +46,7 @@ struct ZGeom {
     int pad_;
     FftDesc f;                 // length Lz
     const void *tw;
+    const void *twh;           // power-of-two Lz: table of length Lz/2, then exp(-2 pi i k/Lz), k <= Lz/2
     void *S1;                  // [kz][pos][c], pos = x*ny + y
     FastDiv dnz, dny;          // division by nz, ny
 };

@@ -154,3 +154,14 @@ def test_vacuum_cells():
     c = 2 * A / (oracle.MU0 * MS)
     e = c * ((m[0, 0, 0] - m[0, 1, 0]) + (m[0, 2, 0] - m[0, 1, 0]) + (m[0, 1, 1] - m[0, 1, 0])) / D2[0] ** 2
     assert np.allclose(h[0, 1, 0], e, rtol=1e-13)
+
+
+def test_exchange_at_matches_field():
+    n = (6, 5, 3)
+    d = (2.5e-9, 2e-9, 3e-9)
+    m = synth.random_unit(n, 1)
+    Ms = synth.ms_field(n, 2)
+    Ms[1, 1, 1] = 0.0
+    cells = synth.sample_cells(n, 3, 12)
+    full = oracle.exchange_field(m, Ms, A, d)
+    assert np.array_equal(oracle.exchange_at(m, Ms, A, d, cells), full[cells[:, 0], cells[:, 1], cells[:, 2]])
