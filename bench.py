@@ -224,7 +224,7 @@ def _pmc_means(path, counter):
             if row.get("Counter_Name") != counter:
                 continue
             vals.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
-    return {k: sum(v) / len(v) for k, v in vals.items()}
+    return {k: (sum(v) / len(v), len(v)) for k, v in vals.items()}
 
 
 def traffic_from(fetch_csv, write_csv, workload, prec):
@@ -234,8 +234,8 @@ def traffic_from(fetch_csv, write_csv, workload, prec):
     import re
     f = _pmc_means(fetch_csv, "FETCH_SIZE")
     w = _pmc_means(write_csv, "WRITE_SIZE")
-    copy_f = [v for k, v in f.items() if "k_copy16" in k]
-    copy_w = [v for k, v in w.items() if "k_copy16" in k]
+    copy_f = [v[0] for k, v in f.items() if "k_copy16" in k]
+    copy_w = [v[0] for k, v in w.items() if "k_copy16" in k]
     if not copy_f or not copy_w:
         raise SystemExit("no copy kernel in the counter runs")
     kf = copy_f[0] * 1024.0 / float(1 << 30)
@@ -249,12 +249,13 @@ def traffic_from(fetch_csv, write_csv, workload, prec):
     h = src_hash()
     for pname, pats in KERNEL_PATTERNS.items():
         for pat in pats:
-            fk = [k for k in f if re.search(pat, k)]
-            wk = [k for k in w if re.search(pat, k)]
+            # the most-dispatched matching kernel (autotuner trials dispatch others a few times)
+            fk = sorted((k for k in f if re.search(pat, k)), key=lambda k: -f[k][1])
+            wk = sorted((k for k in w if re.search(pat, k)), key=lambda k: -w[k][1])
             if fk and wk:
-                by = f[fk[0]] * 1024.0 / kf + w[wk[0]] * 1024.0 / kw
+                by = f[fk[0]][0] * 1024.0 / kf + w[wk[0]][0] * 1024.0 / kw
                 out["%s/%s/%s" % (workload, prec, pname)] = {
-                    "bytes_per_launch": by, "kernel": fk[0], "fetch_KiB": f[fk[0]], "write_KiB": w[wk[0]],
+                    "bytes_per_launch": by, "kernel": fk[0], "fetch_KiB": f[fk[0]][0], "write_KiB": w[wk[0]][0],
                     "copy_scale_fetch": kf, "copy_scale_write": kw, "src_hash": h}
                 break
     with open(path, "w") as fh:

@@ -14,10 +14,19 @@ namespace ct {
 constexpr int prad(int L, bool rev, int s) { return rev ? rad(L, nst(L) - 1 - s) : rad(L, s); }
 constexpr int pns(int L, bool rev, int s) { return s == 0 ? 1 : pns(L, rev, s - 1) * prad(L, rev, s - 1); }
 constexpr int ptw(int L, bool rev, int s) { return s == 0 ? 0 : ptw(L, rev, s - 1) + pns(L, rev, s - 1) * (prad(L, rev, s - 1) - 1); }
-// LDS pitch so that 32 consecutive butterflies of a stage (NL lines
-// interleaved) fall into distinct banks
-constexpr int lds_pitch(int L, int NL) { return NL >= 32 ? L + 1 : (NL == 3 ? L + 11 : L + 32 / (NL < 1 ? 1 : NL)); }
+// Within a line, position p is stored at p + p/16 (lines of 32 or more):
+// the radix-R scatter of the early Stockham stages then spreads over the
+// LDS banks instead of hitting every 16th word.
+constexpr int swz(int L, int p) { return L >= 32 ? p + (p >> 4) : p; }
+constexpr int line_len(int L) { return L >= 32 ? L + L / 16 : L; }
+// LDS pitch of a line (swizzled length plus a shift that spreads the NL
+// interleaved lines over the banks)
+constexpr int lds_pitch(int L, int NL) {
+    return line_len(L) + (NL >= 32 ? 1 : (NL == 3 ? 11 : 32 / (NL < 1 ? 1 : NL)));
+}
 }  // namespace ct
+
+template <int L> __device__ __forceinline__ int sw(int p) { return L >= 32 ? p + (p >> 4) : p; }
 
 // One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
 // 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
@@ -40,7 +49,7 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
         if (b < TOT) {
             const int line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB;
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = IN ? lds[line * P + j + r * NB] : ld(line, j + r * NB);
+            for (int r = 0; r < R; ++r) v[u][r] = IN ? lds[line * P + sw<L>(j + r * NB)] : ld(line, j + r * NB);
             if (Ns > 1) {
                 const C *tt = t + (j % Ns) * (R - 1);
 #pragma unroll
@@ -62,7 +71,7 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
             const int d = (j / Ns) * Ns * R + (j % Ns);
 #pragma unroll
             for (int r = 0; r < R; ++r) {
-                if (OUT) lds[line * P + d + r * Ns] = v[u][r];
+                if (OUT) lds[line * P + sw<L>(d + r * Ns)] = v[u][r];
                 else st(line, d + r * Ns, v[u][r]);
             }
         }

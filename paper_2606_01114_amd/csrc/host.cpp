@@ -276,7 +276,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
     if (getenv("MMX_XVAR")) p->x_var = atoi(getenv("MMX_XVAR")) ? 1 : 0;
-    p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && !getenv("MMX_NO_CT");
+    p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax && !getenv("MMX_NO_CT");
     if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);
@@ -301,7 +301,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     for (int w : {8, 4, 2, 1}) {
         if (w <= std::max(1, npen) && (size_t)3 * w * py * csz <= kLdsTarget && fft_threads(p->fy.d, 3 * w, 3 * w * Ly) <= 1024) { Wp = w; break; }
     }
-    p->y_ct = fused_ct_threads(Ly) > 0 && !getenv("MMX_NO_CT");
+    p->y_ct = fused_ct_threads(Ly) > 0 && fused_ct_lds(Ly, csz) <= kLdsMax && !getenv("MMX_NO_CT");
     if (p->y_ct) Wp = 1;
     q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy;
     q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;

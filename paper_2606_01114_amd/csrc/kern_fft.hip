@@ -237,7 +237,7 @@ __device__ __forceinline__ void conv_pencil(cplx<T> *lds, const cplx<T> *__restr
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                    for (int r = 0; r < R; ++r) v[u][c][r] = (NS >= 2) ? lds[c * P + j + r * NB] : ld(c, j + r * NB);
+                    for (int r = 0; r < R; ++r) v[u][c][r] = (NS >= 2) ? lds[c * P + sw<L>(j + r * NB)] : ld(c, j + r * NB);
                     if (Nsf > 1) {
                         const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
 #pragma unroll
@@ -260,7 +260,7 @@ __device__ __forceinline__ void conv_pencil(cplx<T> *lds, const cplx<T> *__restr
 #pragma unroll
                     for (int c = 0; c < 3; ++c)
 #pragma unroll
-                        for (int r = 0; r < R; ++r) lds[c * P + j * R + r] = v[u][c][r];
+                        for (int r = 0; r < R; ++r) lds[c * P + sw<L>(j * R + r)] = v[u][c][r];
                 }
             }
             __syncthreads();

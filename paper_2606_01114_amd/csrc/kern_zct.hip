@@ -10,7 +10,7 @@
 namespace mmx {
 
 namespace {
-constexpr int zpitch(int N) { return N < 16 ? N + 1 : N + 11; }
+constexpr int zpitch(int N) { return N < 16 ? N + 1 : ct::line_len(N) + 11; }
 constexpr int zcols(int N) { return N >= 1024 ? 1 : 1024 / N; }   // P: ~3072 complex per tile
 constexpr int zthreads(int N) { return 256; }
 }  // namespace
@@ -28,8 +28,8 @@ __device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g
     const T h = T(0.5);
     for (int e = tid; e < (N + 1) * w3; e += NT) {
         const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
-        const C za = lds[l * PT + (k % N)];
-        const C zb = lds[l * PT + ((N - k) % N)];
+        const C za = lds[l * PT + sw<N>(k % N)];
+        const C zb = lds[l * PT + sw<N>((N - k) % N)];
         const C E = cmake<C>(h * (za.x + zb.x), h * (za.y - zb.y));
         const C O = cmake<C>(h * (za.y + zb.y), -h * (za.x - zb.x));
         const C w = wt[k];
@@ -97,7 +97,7 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
             const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
             C X = S1[k * npos3 + l];
             if (k == 0 || k == N) X.y = T(0);
-            lds[l * PT + k] = X;
+            lds[l * PT + sw<N>(k)] = X;
         }
         __syncthreads();
         // 2. fold: Z[k] = (X[k] + conj X[N-k]) + i conj(W^k) (X[k] - conj X[N-k]), k < N
@@ -105,23 +105,23 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
             const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
             C *b = lds + l * PT;
             if (k == 0) {
-                const C x0 = b[0], xn = b[N];
+                const C x0 = b[0], xn = b[sw<N>(N)];
                 const C s = cmake<C>(x0.x + xn.x, x0.y - xn.y), d = cmake<C>(x0.x - xn.x, x0.y + xn.y);
                 b[0] = cmake<C>(s.x - d.y, s.y + d.x);
             } else {
-                const C xk = b[k], xm = b[N - k];
+                const C xk = b[sw<N>(k)], xm = b[sw<N>(N - k)];
                 const C wk = wt[k];
                 {
                     const C s = cmake<C>(xk.x + xm.x, xk.y - xm.y), d = cmake<C>(xk.x - xm.x, xk.y + xm.y);
                     // i conj(w) d
                     const C cd = cmake<C>(wk.x * d.x + wk.y * d.y, wk.x * d.y - wk.y * d.x);
-                    b[k] = cmake<C>(s.x - cd.y, s.y + cd.x);
+                    b[sw<N>(k)] = cmake<C>(s.x - cd.y, s.y + cd.x);
                 }
                 if (2 * k != N) {
                     const C wm = wt[N - k];
                     const C s = cmake<C>(xm.x + xk.x, xm.y - xk.y), d = cmake<C>(xm.x - xk.x, xm.y + xk.y);
                     const C cd = cmake<C>(wm.x * d.x + wm.y * d.y, wm.x * d.y - wm.y * d.x);
-                    b[N - k] = cmake<C>(s.x - cd.y, s.y + cd.x);
+                    b[sw<N>(N - k)] = cmake<C>(s.x - cd.y, s.y + cd.x);
                 }
             }
         }
@@ -141,13 +141,13 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
         T hd[3] = {T(0), T(0), T(0)};
         if (demag) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + (z >> 1)])[z & 1];
+            for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
         }
         T srcn[3];
         cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn);
         if (EPI == EPI_STAGE && a.next_r2c) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + (z >> 1)])[z & 1] = srcn[c];
+            for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
         }
     }
     if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
@@ -157,10 +157,10 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
         const int n0 = (nz + 1) / 2;
         for (int e = tid; e < (N - n0) * w3; e += NT) {
             const int k = n0 + (int)fdiv((uint32_t)e, dw), l = e - (k - n0) * w3;
-            lds[l * PT + k] = cmake<C>(T(0), T(0));
+            lds[l * PT + sw<N>(k)] = cmake<C>(T(0), T(0));
         }
         if (nz & 1) {
-            for (int l = tid; l < w3; l += NT) reinterpret_cast<T *>(&lds[l * PT + nz / 2])[1] = T(0);
+            for (int l = tid; l < w3; l += NT) reinterpret_cast<T *>(&lds[l * PT + sw<N>(nz / 2)])[1] = T(0);
         }
         __syncthreads();
         auto nold = [](int, int) { return C(); };
