@@ -152,6 +152,7 @@ struct mm_plan {
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
     int x_var = 0;                                  // tile-width variant of the specialised x pass
+    int y_pipe = 0;                                 // fused-y kernel variant (0: one pencil per workgroup)
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -276,6 +277,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
     if (getenv("MMX_XVAR")) p->x_var = atoi(getenv("MMX_XVAR")) ? 1 : 0;
+    if (getenv("MMX_YPIPE")) p->y_pipe = atoi(getenv("MMX_YPIPE"));
     p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax && !getenv("MMX_NO_CT");
     if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
@@ -484,7 +486,7 @@ template <typename T>
 int run_xyx(mm_plan *p) {
     if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, p->lp_fwd.W, -1, p->stream));
     else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
-    if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
+    if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->y_pipe, p->stream));
     else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
     if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
     else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
@@ -677,7 +679,7 @@ int time_one(mm_plan *p, int k) {
         else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
         return MM_OK;
     case 2:
-        if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
+        if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->y_pipe, p->stream));
         else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
         return MM_OK;
     case 3:

@@ -7,6 +7,7 @@
 #include "passes.hpp"
 #include "kernels.hpp"
 #include "fft_engine.hpp"
+#include <algorithm>
 
 namespace mmx {
 
@@ -202,105 +203,168 @@ __global__ void __launch_bounds__(1024) k_fused_y(const FusedPass *__restrict__ 
     }
 }
 
-// Convolution core of one three-line pencil: forward stages, then in one
-// register pass the last forward stage, the 3x3 spectral product and the first
-// inverse stage (the inverse runs its radices in reversed order, so that
-// stage reads exactly the positions the forward stage produced), then the
-// remaining inverse stages.  twf / twr: forward / reversed-order tables.
+// The middle of the convolution of one three-line pencil held in LDS: the
+// last forward radix stage, the 3x3 spectral product and the first inverse
+// stage, all in registers (the inverse runs its radices in reversed order, so
+// its first stage reads exactly the positions the last forward stage
+// produced).  Reads and writes LDS; ends with a barrier.
+template <typename T, int L, int NT, class Pr>
+__device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restrict__ twf, int tid, const Pr &prod) {
+    using C = cplx<T>;
+    constexpr int NS = ct::nst(L);
+    constexpr int P = ct::lds_pitch(L, 3);
+    constexpr int R = ct::prad(L, false, NS - 1);
+    constexpr int NB = L / R;
+    constexpr int Nsf = ct::pns(L, false, NS - 1);
+    constexpr int UJ = (NB + NT - 1) / NT;
+    C v[UJ][3][R];
+#pragma unroll
+    for (int u = 0; u < UJ; ++u) {
+        const int j = tid + u * NT;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sw<L>(j + r * NB)];
+                if (Nsf > 1) {
+                    const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
+                }
+                Dft<R, -1, C>::run(v[u][c]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) prod(j + r * NB, v[u][0][r], v[u][1][r], v[u][2][r]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Dft<R, +1, C>::run(v[u][c]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UJ; ++u) {
+        const int j = tid + u * NT;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[c * P + sw<L>(j * R + r)] = v[u][c][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Tensor values a thread of conv_middle needs, fetched before the transform
+// starts so their latency overlaps the first radix stages: tv[u][r][q] for
+// ky = j + r NB, j = tid + u NT, with the odd components' sign flips applied.
+template <typename T, int L, int NT>
+struct PencilTensor {
+    static constexpr int NS = ct::nst(L);
+    static constexpr int R = ct::prad(L, false, NS - 1);
+    static constexpr int NB = L / R;
+    static constexpr int UJ = (NB + NT - 1) / NT;
+    T tv[UJ][R][6];
+    __device__ __forceinline__ void load(const T *__restrict__ Trow, T sx, int tid) {
+#pragma unroll
+        for (int u = 0; u < UJ; ++u) {
+            const int j = tid + u * NT;
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const int ky = j + r * NB;
+                const bool ry = ky > L / 2;
+                const int kyp = ry ? L - ky : ky;
+                const T sy = ry ? T(-1) : T(1);
+                if (j < NB) {
+                    const T *N = Trow + kyp * 6;
+#pragma unroll
+                    for (int q = 0; q < 6; ++q) tv[u][r][q] = N[q];
+                    tv[u][r][3] *= sx * sy;
+                    tv[u][r][4] *= sx;
+                    tv[u][r][5] *= sy;
+                }
+            }
+        }
+    }
+};
+
+// conv_middle with the tensor already in registers
+template <typename T, int L, int NT>
+__device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__restrict__ twf, int tid,
+                                                const PencilTensor<T, L, NT> &pt) {
+    using C = cplx<T>;
+    constexpr int NS = ct::nst(L);
+    constexpr int P = ct::lds_pitch(L, 3);
+    constexpr int R = ct::prad(L, false, NS - 1);
+    constexpr int NB = L / R;
+    constexpr int Nsf = ct::pns(L, false, NS - 1);
+    constexpr int UJ = (NB + NT - 1) / NT;
+    C v[UJ][3][R];
+#pragma unroll
+    for (int u = 0; u < UJ; ++u) {
+        const int j = tid + u * NT;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sw<L>(j + r * NB)];
+                if (Nsf > 1) {
+                    const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
+#pragma unroll
+                    for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
+                }
+                Dft<R, -1, C>::run(v[u][c]);
+            }
+#pragma unroll
+            for (int r = 0; r < R; ++r) {
+                const T *N = pt.tv[u][r];
+                const C x = v[u][0][r], y = v[u][1][r], z = v[u][2][r];
+                v[u][0][r] = cmake<C>(N[0] * x.x + N[3] * y.x + N[4] * z.x, N[0] * x.y + N[3] * y.y + N[4] * z.y);
+                v[u][1][r] = cmake<C>(N[3] * x.x + N[1] * y.x + N[5] * z.x, N[3] * x.y + N[1] * y.y + N[5] * z.y);
+                v[u][2][r] = cmake<C>(N[4] * x.x + N[5] * y.x + N[2] * z.x, N[4] * x.y + N[5] * y.y + N[2] * z.y);
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Dft<R, +1, C>::run(v[u][c]);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < UJ; ++u) {
+        const int j = tid + u * NT;
+        if (j < NB) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c)
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[c * P + sw<L>(j * R + r)] = v[u][c][r];
+        }
+    }
+    __syncthreads();
+}
+
+// Convolution core of one three-line pencil: forward stages, conv_middle,
+// then the remaining inverse stages.  twf / twr: forward / reversed-order
+// tables.  Needs at least two radix stages.
 template <typename T, int L, int NT, class Ld, class St, class Pr>
 __device__ __forceinline__ void conv_pencil(cplx<T> *lds, const cplx<T> *__restrict__ twf, const cplx<T> *__restrict__ twr,
                                             int tid, const Ld &ld, const St &st, const Pr &prod) {
     using C = cplx<T>;
     constexpr int NS = ct::nst(L);
-    constexpr int P = ct::lds_pitch(L, 3);
-    if constexpr (NS == 0) {
-        if (tid == 0) {
-            C x = ld(0, 0), y = ld(1, 0), z = ld(2, 0);
-            prod(0, x, y, z);
-            st(0, 0, x); st(1, 0, y); st(2, 0, z);
-        }
-    } else {
-        if constexpr (NS >= 2) {
-            auto nost = [](int, int, C) {};
-            eng_stage<T, L, false, 0, -1, NT, 3, 0, 1>(lds, twf, tid, ld, nost);
-            eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, twf, tid);
-        }
-        constexpr int R = ct::prad(L, false, NS - 1);
-        constexpr int NB = L / R;
-        constexpr int Nsf = ct::pns(L, false, NS - 1);
-        constexpr int UJ = (NB + NT - 1) / NT;
-        C v[UJ][3][R];
-#pragma unroll
-        for (int u = 0; u < UJ; ++u) {
-            const int j = tid + u * NT;
-            if (j < NB) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-#pragma unroll
-                    for (int r = 0; r < R; ++r) v[u][c][r] = (NS >= 2) ? lds[c * P + sw<L>(j + r * NB)] : ld(c, j + r * NB);
-                    if (Nsf > 1) {
-                        const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
-#pragma unroll
-                        for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
-                    }
-                    Dft<R, -1, C>::run(v[u][c]);
-                }
-#pragma unroll
-                for (int r = 0; r < R; ++r) prod(j + r * NB, v[u][0][r], v[u][1][r], v[u][2][r]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) Dft<R, +1, C>::run(v[u][c]);
-            }
-        }
-        if constexpr (NS >= 2) {
-            __syncthreads();
-#pragma unroll
-            for (int u = 0; u < UJ; ++u) {
-                const int j = tid + u * NT;
-                if (j < NB) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int r = 0; r < R; ++r) lds[c * P + sw<L>(j * R + r)] = v[u][c][r];
-                }
-            }
-            __syncthreads();
-            eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
-            auto nold = [](int, int) { return C(); };
-            eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
-        } else {
-#pragma unroll
-            for (int u = 0; u < UJ; ++u) {
-                const int j = tid + u * NT;
-                if (j < NB) {
-#pragma unroll
-                    for (int c = 0; c < 3; ++c)
-#pragma unroll
-                        for (int r = 0; r < R; ++r) st(c, j * R + r, v[u][c][r]);
-                }
-            }
-        }
-    }
+    static_assert(NS >= 2, "conv_pencil needs two or more radix stages");
+    auto nost = [](int, int, C) {};
+    eng_stage<T, L, false, 0, -1, NT, 3, 0, 1>(lds, twf, tid, ld, nost);
+    eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, twf, tid);
+    conv_middle<T, L, NT>(lds, twf, tid, prod);
+    eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
+    auto nold = [](int, int) { return C(); };
+    eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
 }
 
-// compile-time Ly; one (kz, kx) pencil of three components per tile
-template <typename T, int L, int NT>
-__global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
-    using C = cplx<T>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    C *lds = reinterpret_cast<C *>(smem);
-    const int p = (int)xcd_tile(blockIdx.x, gridDim.x);
-    const int n = a.n;
-    const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
-    C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
-    const bool rx = kx > a.Lx / 2;
-    const int kxp = rx ? a.Lx - kx : kx;
-    const T sx = rx ? T(-1) : T(1);
-    const T *Trow = reinterpret_cast<const T *>(a.tensor) + ((int64_t)kz * a.hxp + kxp) * a.hyp * 6;
-    auto ld = [&](int c, int pos) -> C { return pos < n ? pen[pos * 3 + c] : cmake<C>(T(0), T(0)); };
-    auto st = [&](int c, int pos, C v) {
-        if (pos < n) pen[pos * 3 + c] = v;
-    };
-    auto prod = [&](int ky, C &mx, C &my, C &mz) {
+// tensor product of one (kz, kx) pencil: the tensor row (kz, |kx|) with the
+// sign flips of the odd components under kx -> Lx-kx and ky -> Ly-ky
+template <typename T, int L>
+struct PencilProduct {
+    const T *Trow;
+    T sx;
+    __device__ __forceinline__ void operator()(int ky, cplx<T> &mx, cplx<T> &my, cplx<T> &mz) const {
+        using C = cplx<T>;
         const bool ry = ky > L / 2;
         const int kyp = ry ? L - ky : ky;
         const T *N = Trow + kyp * 6;
@@ -310,9 +374,136 @@ __global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
         mx = cmake<C>(nxx * x.x + nxy * y.x + nxz * z.x, nxx * x.y + nxy * y.y + nxz * z.y);
         my = cmake<C>(nxy * x.x + nyy * y.x + nyz * z.x, nxy * x.y + nyy * y.y + nyz * z.y);
         mz = cmake<C>(nxz * x.x + nyz * y.x + nzz * z.x, nxz * x.y + nyz * y.y + nzz * z.y);
+    }
+};
+
+template <typename T, int L>
+__device__ __forceinline__ PencilProduct<T, L> pencil_product(const FusedPass &a, int kz, int kx) {
+    const bool rx = kx > a.Lx / 2;
+    const int kxp = rx ? a.Lx - kx : kx;
+    PencilProduct<T, L> pr;
+    pr.Trow = reinterpret_cast<const T *>(a.tensor) + ((int64_t)kz * a.hxp + kxp) * a.hyp * 6;
+    pr.sx = rx ? T(-1) : T(1);
+    return pr;
+}
+
+// Persistent, software-pipelined fused pass: each workgroup walks a run of
+// consecutive pencils (so kx and Lx-kx, which share a tensor row, follow each
+// other) and issues the global loads of the next pencil's first radix stage
+// before computing the current one.
+template <typename T, int L, int NT, int MINW>
+__global__ void __launch_bounds__(NT, MINW) k_fused_y_pipe(const FusedPass a, int chunk) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    constexpr int NS = ct::nst(L);
+    constexpr int P = ct::lds_pitch(L, 3);
+    constexpr int R0 = ct::prad(L, false, 0);
+    constexpr int NB0 = L / R0;
+    constexpr int TOT0 = 3 * NB0;
+    constexpr int U0 = (TOT0 + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    const int w = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int p_begin = w * chunk, p_end = min(a.npos, p_begin + chunk);
+    const int n = a.n;
+    const C *tw = reinterpret_cast<const C *>(a.tw);
+    const C *twr = tw + (L - 1);
+    // With L >= 2n-1 and L even, rows at or beyond L/2 are always zero: only
+    // the first half of each first-stage butterfly is loaded and kept.
+    constexpr int RH = R0 / 2;
+    C pre[U0][RH];
+    auto pencil_ptr = [&](int p) {
+        const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+        return reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
+    };
+    auto prefetch = [&](int p) {
+        const C *pen = pencil_ptr(p);
+#pragma unroll
+        for (int u = 0; u < U0; ++u) {
+            const int b = tid + u * NT;
+            const int c = b % 3, j = b / 3;
+#pragma unroll
+            for (int r = 0; r < RH; ++r) {
+                const int pos = j + r * NB0;
+                pre[u][r] = (b < TOT0 && pos < n) ? pen[pos * 3 + c] : cmake<C>(T(0), T(0));
+            }
+        }
+    };
+    if (p_begin < p_end) prefetch(p_begin);
+    for (int p = p_begin; p < p_end; ++p) {
+        C *pen = pencil_ptr(p);
+        const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+        __syncthreads();   // the previous pencil is done with LDS
+        // first radix stage (Ns = 1, no twiddles) from the prefetched registers
+#pragma unroll
+        for (int u = 0; u < U0; ++u) {
+            const int b = tid + u * NT;
+            if (b < TOT0) {
+                const int c = b % 3, j = b / 3;
+                C v[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) v[r] = r < RH ? pre[u][r] : cmake<C>(T(0), T(0));
+                Dft<R0, -1, C>::run(v);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) lds[c * P + sw<L>(j * R0 + r)] = v[r];
+            }
+        }
+        __syncthreads();
+        if (p + 1 < p_end) prefetch(p + 1);
+        eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, tw, tid);
+        conv_middle<T, L, NT>(lds, tw, tid, pencil_product<T, L>(a, kz, kx));
+        eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
+        auto st = [&](int c, int pos, C v) {
+            if (pos < n) pen[pos * 3 + c] = v;
+        };
+        auto nold = [](int, int) { return C(); };
+        eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
+    }
+}
+
+// compile-time Ly; one (kz, kx) pencil of three components per tile.  The
+// tensor row is fetched into registers together with the pencil's first
+// radix-stage inputs.
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    constexpr int NS = ct::nst(L);
+    static_assert(NS >= 2, "fused pencil needs two or more radix stages");
+    const int p = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int tid = threadIdx.x;
+    const int n = a.n;
+    const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+    C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
+    const bool rx = kx > a.Lx / 2;
+    const int kxp = rx ? a.Lx - kx : kx;
+    const T *Trow = reinterpret_cast<const T *>(a.tensor) + ((int64_t)kz * a.hxp + kxp) * a.hyp * 6;
+    const T sx = rx ? T(-1) : T(1);
+    // FP32: fetch the tensor early (registers to spare); FP64: at the product
+    constexpr bool early = sizeof(T) == 4;
+    PencilTensor<T, L, (early ? NT : 1)> pt;
+    if constexpr (early) pt.load(Trow, sx, tid);
+    auto ld = [&](int c, int pos) -> C { return pos < n ? pen[pos * 3 + c] : cmake<C>(T(0), T(0)); };
+    auto st = [&](int c, int pos, C v) {
+        if (pos < n) pen[pos * 3 + c] = v;
     };
     const C *tw = reinterpret_cast<const C *>(a.tw);
-    conv_pencil<T, L, NT>(lds, tw, tw + (L > 1 ? L - 1 : 0), (int)threadIdx.x, ld, st, prod);
+    const C *twr = tw + (L - 1);
+    auto nost = [](int, int, C) {};
+    auto nold = [](int, int) { return C(); };
+    eng_stage<T, L, false, 0, -1, NT, 3, 0, 1>(lds, tw, tid, ld, nost);
+    eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, tw, tid);
+    if constexpr (early) {
+        conv_middle_pre<T, L, NT>(lds, tw, tid, pt);
+    } else {
+        PencilProduct<T, L> pr;
+        pr.Trow = Trow;
+        pr.sx = sx;
+        conv_middle<T, L, NT>(lds, tw, tid, pr);
+    }
+    eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
+    eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
 }
 
 // ---------------- launchers -------------------------------------------------
@@ -396,26 +587,44 @@ int fused_ct_threads(int L) {
     case 256: return 64;
     case 512: return 128;
     case 1024: return 256;
-    case 2048: return 256;
-    case 4096: return 256;
+    case 2048: return 384;   // FP64; FP32 launches 256 (fused_ct_nt)
+    case 4096: return 768;
     default: return 0;
     }
 }
 
 template <typename T>
-hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
+hipError_t launch_fused_ct(const FusedPass &a, int pipe, hipStream_t s) {
     if (a.npos <= 0) return hipSuccess;
     const size_t lds = fused_ct_lds(a.f.L, sizeof(cplx<T>));
-    switch (a.f.L) {
-    case 64: hipLaunchKernelGGL((k_fused_y_ct<T, 64, 64>), dim3(a.npos), dim3(64), lds, s, a); break;
-    case 128: hipLaunchKernelGGL((k_fused_y_ct<T, 128, 64>), dim3(a.npos), dim3(64), lds, s, a); break;
-    case 256: hipLaunchKernelGGL((k_fused_y_ct<T, 256, 64>), dim3(a.npos), dim3(64), lds, s, a); break;
-    case 512: hipLaunchKernelGGL((k_fused_y_ct<T, 512, 128>), dim3(a.npos), dim3(128), lds, s, a); break;
-    case 1024: hipLaunchKernelGGL((k_fused_y_ct<T, 1024, 256>), dim3(a.npos), dim3(256), lds, s, a); break;
-    case 2048: hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 256>), dim3(a.npos), dim3(256), lds, s, a); break;
-    case 4096: hipLaunchKernelGGL((k_fused_y_ct<T, 4096, 256>), dim3(a.npos), dim3(256), lds, s, a); break;
-    default: return hipErrorInvalidValue;
+    // pipe = 0: one pencil per workgroup; pipe = 1, 2, 3: persistent,
+    // prefetching kernel with 2 or 3 workgroups per CU and 256 / 384 threads
+    const int per_cu = pipe == 1 ? 2 : 3;
+    const int groups = std::min(a.npos, 256 * per_cu * 2);
+    const int chunk = (a.npos + groups - 1) / groups;
+    const int G = (a.npos + chunk - 1) / chunk;
+#define FCASE(LL, NTT)                                                                                                \
+    case LL:                                                                                                          \
+        hipLaunchKernelGGL((k_fused_y_ct<T, LL, NTT>), dim3(a.npos), dim3(NTT), lds, s, a);                         \
+        break;
+    if (a.f.L == 2048 && pipe >= 4) {
+        // thread-count variants of the 2048-point pencil (measurement)
+        if (pipe == 4) hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 128>), dim3(a.npos), dim3(128), lds, s, a);
+        else if (pipe == 5) hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 256>), dim3(a.npos), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 384>), dim3(a.npos), dim3(384), lds, s, a);
+    } else if (pipe == 0 || a.f.L != 2048) {
+        switch (a.f.L) {
+            FCASE(64, 64) FCASE(128, 64) FCASE(256, 64) FCASE(512, 128) FCASE(1024, 256) FCASE(2048, (sizeof(T) == 4 ? 256 : 384)) FCASE(4096, 768)
+        default: return hipErrorInvalidValue;
+        }
+    } else if (pipe == 1) {
+        hipLaunchKernelGGL((k_fused_y_pipe<T, 2048, 256, 2>), dim3(G), dim3(256), lds, s, a, chunk);
+    } else if (pipe == 2) {
+        hipLaunchKernelGGL((k_fused_y_pipe<T, 2048, 256, 3>), dim3(G), dim3(256), lds, s, a, chunk);
+    } else {
+        hipLaunchKernelGGL((k_fused_y_pipe<T, 2048, 384, 3>), dim3(G), dim3(384), lds, s, a, chunk);
     }
+#undef FCASE
     return hipGetLastError();
 }
 
@@ -425,7 +634,7 @@ template hipError_t launch_fused_y<float>(const FusedPass *, const int2 *, int, 
 template hipError_t launch_fused_y<double>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
 template hipError_t launch_line_ct<float>(const LinePass &, int, int, int, hipStream_t);
 template hipError_t launch_line_ct<double>(const LinePass &, int, int, int, hipStream_t);
-template hipError_t launch_fused_ct<float>(const FusedPass &, hipStream_t);
-template hipError_t launch_fused_ct<double>(const FusedPass &, hipStream_t);
+template hipError_t launch_fused_ct<float>(const FusedPass &, int, hipStream_t);
+template hipError_t launch_fused_ct<double>(const FusedPass &, int, hipStream_t);
 
 }  // namespace mmx

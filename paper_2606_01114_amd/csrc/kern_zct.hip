@@ -89,6 +89,15 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
     const C *tw = reinterpret_cast<const C *>(g.twh);
     const C *wt = tw + (N > 1 ? N - 1 : 0);
     const FastDiv dw = make_fastdiv((uint32_t)w3);
+    // 0. each thread's first KPRE cells: own inputs fetched now, used after the transform
+    constexpr int KPRE = 0;   // prefetching own inputs costs occupancy more than it hides latency
+    OwnCell<T> own[KPRE > 0 ? KPRE : 1];
+    const int ncells = wp * nz;
+#pragma unroll
+    for (int k = 0; k < KPRE; ++k) {
+        const int e = tid + k * NT;
+        if (e < ncells) load_own<T, EPI>(a, pos0 * nz + e, own[k]);
+    }
     if (demag) {
         // 1. half spectra X[0..N] of the tile's lines (DC and Nyquist real)
         const int64_t npos3 = npos * 3;
@@ -133,7 +142,7 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
     // 3. epilogue per cell; demag field sample z of component c sits in line
     //    3 pl + c, slot z/2, real part for even z
     double ed = 0.0, ex = 0.0;
-    for (int e = tid; e < wp * nz; e += NT) {
+    auto do_cell = [&](int e, const OwnCell<T> *pre) {
         const int pl = (int)fdiv((uint32_t)e, g.dnz), z = e - pl * nz;
         const int64_t pos = pos0 + pl;
         const int i = (int)fdiv((uint32_t)pos, g.dny), j = (int)(pos - (int64_t)i * ny);
@@ -144,12 +153,18 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
             for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
         }
         T srcn[3];
-        cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn);
+        cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn, pre);
         if (EPI == EPI_STAGE && a.next_r2c) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
         }
+    };
+#pragma unroll
+    for (int k = 0; k < KPRE; ++k) {
+        const int e = tid + k * NT;
+        if (e < ncells) do_cell(e, &own[k]);
     }
+    for (int e = tid + KPRE * NT; e < ncells; e += NT) do_cell(e, nullptr);
     if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_STAGE && a.next_r2c) {
         // 4. the next stage's source, already folded in LDS: clear the padding

@@ -19,7 +19,7 @@ int fused_ct_threads(int L);
 size_t line_ct_lds(int L, int W, size_t csz);
 size_t fused_ct_lds(int L, size_t csz);
 template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s);
-template <typename T> hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s);
+template <typename T> hipError_t launch_fused_ct(const FusedPass &a, int pipe, hipStream_t s);
 template <typename T> hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s);
 template <typename T> hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s);
 template <typename T>

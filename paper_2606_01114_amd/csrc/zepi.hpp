@@ -18,12 +18,39 @@ __device__ __forceinline__ void cross3(const T a[3], const T b[3], T o[3]) {
 template <typename T>
 __device__ __forceinline__ T ms_at(const T *Ms, T Ms_s, int64_t cell) { return Ms ? Ms[cell] : Ms_s; }
 
+// The cell's own inputs, fetched ahead of the z transform so their latency
+// overlaps it: m (stage input or h_eff input), m_n, the RK4 accumulator, Ms.
+template <typename T>
+struct OwnCell {
+    T mi[3], mn[3], acc[3], ms;
+};
+
+template <typename T, int EPI>
+__device__ __forceinline__ void load_own(const ZInvArgs &a, int64_t cell, OwnCell<T> &o) {
+    const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
+    const T *Ms = reinterpret_cast<const T *>(a.Ms);
+    o.ms = Ms ? Ms[cell] : T(a.Ms_scalar);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) o.mi[c] = mfield[cell * 3 + c];
+    if (EPI == EPI_STAGE) {
+        const T *mn = reinterpret_cast<const T *>(a.m_n);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) o.mn[c] = mn[cell * 3 + c];
+        if (a.stage > 0) {
+            const T *acc = reinterpret_cast<const T *>(a.acc);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) o.acc[c] = acc[cell * 3 + c];
+        }
+    }
+}
+
 // cell (i, j, z) with flat index `cell`; hd = demag field there (0 if not
 // requested).  Returns in src_next the next stage's z-transform source
-// Ms * m_next (EPI_STAGE with next_r2c only).
+// Ms * m_next (EPI_STAGE with next_r2c only).  `pre` (nullable) holds the
+// cell's own inputs already loaded.
 template <typename T, int EPI>
 __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
-                                              double &ed, double &ex, T src_next[3]) {
+                                              double &ed, double &ex, T src_next[3], const OwnCell<T> *pre = nullptr) {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int64_t sx = (int64_t)ny * nz, sy = nz;
     const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
@@ -31,11 +58,11 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
     const T Ms_s = T(a.Ms_scalar);
     const T exp_ = T(a.ex_pref);
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
-    const T msi = ms_at(Ms, Ms_s, cell);
+    const T msi = pre ? pre->ms : ms_at(Ms, Ms_s, cell);
     const bool magi = msi > T(0);
     T mi[3];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mi[c] = mfield[cell * 3 + c];
+    for (int c = 0; c < 3; ++c) mi[c] = pre ? pre->mi[c] : mfield[cell * 3 + c];
     const int64_t noff[6] = {-sx, sx, -sy, sy, -1, 1};
     const bool nin[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, z > 0, z < nz - 1};
     T hex[3] = {T(0), T(0), T(0)};
@@ -77,22 +104,29 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
         const T gp = T(a.gp), al = T(a.alpha), dt = T(a.dt);
 #pragma unroll
         for (int c = 0; c < 3; ++c) f[c] = -gp * (mxh[c] + al * mxmxh[c]);
-        const T *mn = reinterpret_cast<const T *>(a.m_n) + cell * 3;
+        const T *mnp = reinterpret_cast<const T *>(a.m_n) + cell * 3;
         T *acc = reinterpret_cast<T *>(a.acc) + cell * 3;
+        T mn[3], ac[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) mn[c] = pre ? pre->mn[c] : mnp[c];
+        if (a.stage > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ac[c] = pre ? pre->acc[c] : acc[c];
+        }
         T nxt[3];
         if (a.stage == 0) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) { acc[c] = f[c]; nxt[c] = mn[c] + T(0.5) * dt * f[c]; }
         } else if (a.stage == 1) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { acc[c] = acc[c] + T(2) * f[c]; nxt[c] = mn[c] + T(0.5) * dt * f[c]; }
+            for (int c = 0; c < 3; ++c) { acc[c] = ac[c] + T(2) * f[c]; nxt[c] = mn[c] + T(0.5) * dt * f[c]; }
         } else if (a.stage == 2) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { acc[c] = acc[c] + T(2) * f[c]; nxt[c] = mn[c] + dt * f[c]; }
+            for (int c = 0; c < 3; ++c) { acc[c] = ac[c] + T(2) * f[c]; nxt[c] = mn[c] + dt * f[c]; }
         } else {
             const T w = dt / T(6);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) nxt[c] = mn[c] + w * (acc[c] + f[c]);
+            for (int c = 0; c < 3; ++c) nxt[c] = mn[c] + w * (ac[c] + f[c]);
             if (a.u_rec) {
                 T *ur = reinterpret_cast<T *>(a.u_rec) + cell * 3;
 #pragma unroll
