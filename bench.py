@@ -30,6 +30,12 @@ WORKLOADS = {
                  name="thin film 512x512x16 (padded 1024x1024x32), smooth texture + 1% noise, RK4 LLG steps"),
     "small": dict(grid=(32, 32, 4), cell=(2e-9, 2e-9, 2e-9), m="random", seed=1,
                   name="32x32x4 (padded 64x64x8), random unit m"),
+    "sweep": dict(grid=None, cell=(2.5e-9, 2.5e-9, 3e-9), m="random", seed=4,
+                  name="batched sweep: 64 uneven geometries (nx, ny in 48..384, nz in 1..8, Ms in 4e5..1.2e6), "
+                       "h_eff + RK4 LLG step of all in one graph replay"),
+    "grad": dict(grid=(256, 256, 8), cell=(2.5e-9, 2.5e-9, 3e-9), m="smooth", seed=5,
+                 name="differentiable 256x256x8: 200 RK4 steps, checkpoint every 20, gradient of mean m_z "
+                      "w.r.t. per-cell Ms through the adjoint"),
 }
 MS, A, ALPHA, GAMMA, DT = 8e5, 1.3e-11, 0.02, 2.211e5, 1e-13
 PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
@@ -166,6 +172,60 @@ def run_gpu(wname, prec, steps, warmup, m_host):
                 tiles=info["tiles"])
 
 
+def run_sweep(steps, warmup, prec="f32"):
+    """Aggregate cell-updates/s of the batched sweep (all geometries per graph replay)."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_01114_amd import Batch
+    geo = synth.batch_geometries(4)
+    grids = [g for g, _ in geo]
+    Ms = [ms for _, ms in geo]
+    dt = torch.float32 if prec == "f32" else torch.float64
+    t0 = time.perf_counter()
+    b = Batch(grids, [WORKLOADS["sweep"]["cell"]] * len(grids), prec)
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    ms = [torch.tensor(synth.random_unit(g, 100 + k), dtype=dt, device="cuda") for k, g in enumerate(grids)]
+    for _ in range(warmup):
+        b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    cells = int(sum(np.prod(g) for g in grids))
+    return {"cells": cells, "geometries": len(grids), "ms_per_step": wall * 1e3 / steps,
+            "Mcell_updates_per_s": cells * steps / wall / 1e6, "setup_s": setup, "prec": prec}
+
+
+def run_grad(prec="f32", steps=200, every=20):
+    """Forward + backward time of the checkpointed LLG run and its gradient."""
+    import torch
+    import synth
+    from paper_2606_01114_amd import DemagPlan, llg_run_checkpointed
+    w = WORKLOADS["grad"]
+    dt = torch.float32 if prec == "f32" else torch.float64
+    plan = DemagPlan(w["grid"], w["cell"], prec, autotune=True)
+    m0 = torch.tensor(synth.smooth_film(w["grid"], w["cell"], 5), dtype=dt, device="cuda")
+    Ms = torch.tensor(synth.ms_field(w["grid"], 5), dtype=dt, device="cuda")
+    out = {}
+    for rep in range(2):
+        Mst = Ms.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        mT = llg_run_checkpointed(plan, m0, Mst, A, ALPHA, GAMMA, DT, steps, every=every)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mT[..., 2].mean().backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        out = {"forward_s": t1 - t0, "backward_s": t2 - t1, "steps": steps, "checkpoint_every": every,
+               "cells": int(m0.numel() // 3), "prec": prec,
+               "grad_finite": bool(torch.isfinite(Mst.grad).all().item())}
+    return out
+
+
 def copy_bandwidth():
     import torch
     from paper_2606_01114_amd import _lib
@@ -286,6 +346,21 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "sweep":
+        r = run_sweep(args.steps, args.warmup, args.prec)
+        print(json.dumps({"metric": METRIC, "value": r["Mcell_updates_per_s"], "unit": "Mcell-updates/s",
+                          "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
+                          "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+                          "data": "synthetic", "config": {"workload": WORKLOADS["sweep"]["name"]}, "extra": r}))
+        return
+    if args.workload == "grad":
+        r = run_grad(args.prec)
+        print(json.dumps({"metric": "forward+backward seconds of the differentiable run", "value":
+                          r["forward_s"] + r["backward_s"], "unit": "s", "n_gpus": 1, "steps": r["steps"],
+                          "warmup": 1, "ms_per_step": (r["forward_s"] + r["backward_s"]) * 1e3 / r["steps"],
+                          "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
+                          "data": "synthetic", "config": {"workload": WORKLOADS["grad"]["name"]}, "extra": r}))
+        return
     w = WORKLOADS[args.workload]
     print("# generating inputs: %s" % w["name"], file=sys.stderr, flush=True)
     m_host = make_m(w)

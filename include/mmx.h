@@ -77,7 +77,10 @@ typedef struct mm_plan_opts {
     int autotune;       /* 0: default tile widths; 1: time the candidate tile
                            widths of every pass at plan creation and keep the
                            fastest. */
-    int reserved;
+    int pow2_padding;   /* for axes without an explicit L: 0 = the default
+                           above; 1 = the smallest power of two >= 2n-1
+                           (specialised power-of-two kernels; the default of
+                           mm_batch_create). */
 } mm_plan_opts;
 
 int mm_plan_opts_default(mm_plan_opts *opts);
@@ -177,9 +180,12 @@ int mm_demag_spectrum_get(mm_plan *plan, double *host_spectrum);
 
 /*
  * Batched parameter sweep: `count` independent geometries, each with its own
- * grid, padded lengths, tensor and scalar Ms, advanced together; every pass
- * is ONE grouped launch over a ragged table of tiles, and one step of all
- * geometries is captured in one HIP graph.
+ * grid, padded lengths, tensor and scalar Ms, advanced together.  Every pass
+ * is a grouped launch over a ragged table of tiles -- one launch per distinct
+ * padded length (geometries sharing a power-of-two length run the specialised
+ * kernels; all others share one runtime-planned launch) -- and one step of all
+ * geometries is captured in one HIP graph.  opts NULL selects power-of-two
+ * padding.
  *   grids[count][3], cells[count][3]: host arrays
  *   m_ptrs[count]: host array of device pointers, each (nx,ny,nz,3)
  *   h_ptrs[count]: host array of device pointers for mm_batch_h_eff

@@ -35,7 +35,7 @@ class MMError(RuntimeError):
 
 class PlanOpts(ctypes.Structure):
     _fields_ = [("far_radius", ctypes.c_double), ("L", ctypes.c_int64 * 3),
-                ("autotune", ctypes.c_int), ("reserved", ctypes.c_int)]
+                ("autotune", ctypes.c_int), ("pow2_padding", ctypes.c_int)]
 
 
 def _load():

@@ -153,7 +153,7 @@ class Batch:
     """Many independent geometries advanced by grouped launches (one HIP graph
     per step of all of them)."""
 
-    def __init__(self, grids, cells, precision="f32", far_radius=16.0):
+    def __init__(self, grids, cells, precision="f32", far_radius=16.0, pow2_padding=True):
         self.grids = [tuple(int(v) for v in g) for g in grids]
         self.cells = [tuple(float(v) for v in c) for c in cells]
         self.prec = _prec(precision)
@@ -164,6 +164,7 @@ class Batch:
         opts = PlanOpts()
         check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
         opts.far_radius = float(far_radius)
+        opts.pow2_padding = 1 if pow2_padding else 0
         self._h = ctypes.c_void_p()
         check(_lib.lib().mm_batch_create(ctypes.byref(self._h), n, G, C, self.prec, _stream(), ctypes.byref(opts)))
 

@@ -49,6 +49,13 @@ bool is_7smooth(int64_t v) {
     return v == 1;
 }
 
+int64_t pow2_L(int64_t n) {
+    if (n == 1) return 1;
+    int64_t L = 1;
+    while (L < 2 * n - 1) L <<= 1;
+    return L;
+}
+
 int64_t default_L(int64_t n) {
     if (n == 1) return 1;
     if (is_7smooth(n)) return 2 * n;
@@ -152,7 +159,6 @@ struct mm_plan {
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
     int x_var = 0;                                  // tile-width variant of the specialised x pass
-    int y_pipe = 0;                                 // fused-y kernel variant (0: one pencil per workgroup)
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -277,7 +283,6 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
     if (getenv("MMX_XVAR")) p->x_var = atoi(getenv("MMX_XVAR")) ? 1 : 0;
-    if (getenv("MMX_YPIPE")) p->y_pipe = atoi(getenv("MMX_YPIPE"));
     p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax && !getenv("MMX_NO_CT");
     if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
@@ -303,13 +308,13 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     for (int w : {8, 4, 2, 1}) {
         if (w <= std::max(1, npen) && (size_t)3 * w * py * csz <= kLdsTarget && fft_threads(p->fy.d, 3 * w, 3 * w * Ly) <= 1024) { Wp = w; break; }
     }
-    p->y_ct = fused_ct_threads(Ly) > 0 && fused_ct_lds(Ly, csz) <= kLdsMax && !getenv("MMX_NO_CT");
+    p->y_ct = fused_ct_threads(Ly, csz) > 0 && fused_ct_lds(Ly, csz) <= kLdsMax && !getenv("MMX_NO_CT");
     if (p->y_ct) Wp = 1;
     q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy;
     q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;
     q.npos = npen; q.W = Wp; q.tiles = (npen + Wp - 1) / Wp;
     q.pitch = p->y_ct ? Ly + 1 : py;
-    q.nthr = p->y_ct ? fused_ct_threads(Ly) : fft_threads(p->fy.d, 3 * Wp, 3 * Wp * Ly);
+    q.nthr = p->y_ct ? fused_ct_threads(Ly, csz) : fft_threads(p->fy.d, 3 * Wp, 3 * Wp * Ly);
     q.f = p->fy.d;
     p->lds_fp = p->y_ct ? fused_ct_lds(Ly, csz) : (size_t)3 * Wp * q.pitch * csz;
     if (p->lds_fp > kLdsMax) return fail(MM_ENOTSUP, "y length %d too long for one workgroup", Ly);
@@ -486,7 +491,7 @@ template <typename T>
 int run_xyx(mm_plan *p) {
     if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, p->lp_fwd.W, -1, p->stream));
     else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
-    if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->y_pipe, p->stream));
+    if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
     else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
     if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
     else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
@@ -679,7 +684,7 @@ int time_one(mm_plan *p, int k) {
         else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
         return MM_OK;
     case 2:
-        if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->y_pipe, p->stream));
+        if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
         else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
         return MM_OK;
     case 3:
@@ -729,12 +734,13 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     if (!std::isfinite(o.far_radius)) return fail(MM_EINVAL, "far_radius must be finite");
     int64_t L[3];
     for (int a = 0; a < 3; ++a) {
-        L[a] = o.L[a] > 0 ? o.L[a] : default_L(grid[a]);
+        L[a] = o.L[a] > 0 ? o.L[a] : (o.pow2_padding ? pow2_L(grid[a]) : default_L(grid[a]));
         if (L[a] < 2 * grid[a] - 1 || !is_7smooth(L[a]))
             return fail(MM_EINVAL, "L[%d]=%lld must be 7-smooth and >= 2n-1 = %lld", a, (long long)L[a], (long long)(2 * grid[a] - 1));
         if (L[a] > 16384) return fail(MM_ENOTSUP, "L[%d]=%lld exceeds 16384", a, (long long)L[a]);
     }
     if (o.autotune < 0 || o.autotune > 1) return fail(MM_EINVAL, "autotune must be 0 or 1");
+    if (o.pow2_padding < 0 || o.pow2_padding > 1) return fail(MM_EINVAL, "pow2_padding must be 0 or 1");
     const int64_t ncell = grid[0] * grid[1] * grid[2];
     if (grid[0] * grid[1] > 0x7fffffffLL / 2 || ncell > (1LL << 34)) return fail(MM_ENOTSUP, "grid too large");
     int dev = 0;
@@ -942,6 +948,17 @@ const char *mm_last_error(void) { return g_last.c_str(); }
 }  // extern "C"
 
 // =============================== batch ======================================
+// A launch group: geometries sharing one kernel for a pass (a specialised
+// power-of-two length, or the runtime-planned kernel for everything else).
+struct BGroup {
+    int L = 0;            // transform length of the group (specialised), 0 = runtime-planned
+    int W = 0;            // tile width of the specialised x pass
+    int tiles = 0;
+    int nthr = 64;
+    size_t lds = 0;
+    int2 *map = nullptr;  // device tile map (geometry, local tile)
+};
+
 struct mm_batch {
     int count = 0;
     int prec = MM_F32;
@@ -949,14 +966,11 @@ struct mm_batch {
     std::vector<mm_plan *> plans;
     std::vector<void *> allocs;
     size_t bytes = 0;
-    int2 *zmap = nullptr, *lmap = nullptr, *fmap = nullptr;
-    int zt = 0, lt = 0, ft = 0;
+    std::vector<BGroup> gx, gy, gz;
     LinePass *d_lpf = nullptr, *d_lpi = nullptr;
     FusedPass *d_fp = nullptr;
     ZFwdArgs *d_zf = nullptr;
     ZInvArgs *d_zi = nullptr;   // [5][count]: h_eff, stage 0..3
-    int nthr_z = 64, nthr_l = 64, nthr_f = 64;
-    size_t lds_z = 0, lds_l = 0, lds_f = 0;
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<unsigned char> gkey, akey;
@@ -1013,20 +1027,47 @@ int batch_args(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, dou
 }
 
 template <typename T>
+int batch_zfwd(mm_batch *b) {
+    for (const BGroup &g : b->gz) {
+        if (g.L) HIPCK(launch_zfwd_ct_b<T>(b->d_zf, g.map, g.tiles, g.L, SRC_MS_M, b->stream));
+        else HIPCK(launch_zfwd_batch<T>(b->d_zf, g.map, g.tiles, g.nthr, SRC_MS_M, g.lds, b->stream));
+    }
+    return MM_OK;
+}
+
+template <typename T>
+int batch_zinv(mm_batch *b, const ZInvArgs *d, int epi) {
+    for (const BGroup &g : b->gz) {
+        if (g.L) HIPCK(launch_zinv_ct_b<T>(d, g.map, g.tiles, g.L, epi, b->stream));
+        else HIPCK(launch_zinv_batch<T>(d, g.map, g.tiles, g.nthr, epi, g.lds, b->stream));
+    }
+    return MM_OK;
+}
+
+template <typename T>
 int batch_xyx(mm_batch *b) {
-    HIPCK(launch_line_pass<T>(b->d_lpf, b->lmap, b->lt, b->nthr_l, b->lds_l, -1, false, b->stream));
-    HIPCK(launch_fused_y<T>(b->d_fp, b->fmap, b->ft, b->nthr_f, b->lds_f, b->stream));
-    HIPCK(launch_line_pass<T>(b->d_lpi, b->lmap, b->lt, b->nthr_l, b->lds_l, +1, false, b->stream));
+    for (const BGroup &g : b->gx) {
+        if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpf, g.map, g.tiles, g.L, g.W, -1, b->stream));
+        else HIPCK(launch_line_pass<T>(b->d_lpf, g.map, g.tiles, g.nthr, g.lds, -1, false, b->stream));
+    }
+    for (const BGroup &g : b->gy) {
+        if (g.L) HIPCK(launch_fused_ct_b<T>(b->d_fp, g.map, g.tiles, g.L, b->stream));
+        else HIPCK(launch_fused_y<T>(b->d_fp, g.map, g.tiles, g.nthr, g.lds, b->stream));
+    }
+    for (const BGroup &g : b->gx) {
+        if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpi, g.map, g.tiles, g.L, g.W, +1, b->stream));
+        else HIPCK(launch_line_pass<T>(b->d_lpi, g.map, g.tiles, g.nthr, g.lds, +1, false, b->stream));
+    }
     return MM_OK;
 }
 
 template <typename T>
 int batch_step(mm_batch *b) {
     int rc;
-    HIPCK(launch_zfwd_batch<T>(b->d_zf, b->zmap, b->zt, b->nthr_z, SRC_MS_M, b->lds_z, b->stream));
+    if ((rc = batch_zfwd<T>(b))) return rc;
     for (int s = 0; s < 4; ++s) {
         if ((rc = batch_xyx<T>(b))) return rc;
-        HIPCK(launch_zinv_batch<T>(b->d_zi + (size_t)(1 + s) * b->count, b->zmap, b->zt, b->nthr_z, EPI_STAGE, b->lds_z, b->stream));
+        if ((rc = batch_zinv<T>(b, b->d_zi + (size_t)(1 + s) * b->count, EPI_STAGE))) return rc;
     }
     return MM_OK;
 }
@@ -1035,11 +1076,10 @@ template <typename T>
 int batch_heff(mm_batch *b, unsigned terms) {
     int rc;
     if (terms & MM_DEMAG) {
-        HIPCK(launch_zfwd_batch<T>(b->d_zf, b->zmap, b->zt, b->nthr_z, SRC_MS_M, b->lds_z, b->stream));
+        if ((rc = batch_zfwd<T>(b))) return rc;
         if ((rc = batch_xyx<T>(b))) return rc;
     }
-    HIPCK(launch_zinv_batch<T>(b->d_zi, b->zmap, b->zt, b->nthr_z, EPI_HEFF, b->lds_z, b->stream));
-    return MM_OK;
+    return batch_zinv<T>(b, b->d_zi, EPI_HEFF);
 }
 
 std::vector<unsigned char> batch_key(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, double alpha,
@@ -1057,6 +1097,34 @@ std::vector<unsigned char> batch_key(mm_batch *b, void *const *m_ptrs, const dou
     return k;
 }
 
+// Build the launch groups of one pass kind: key(plan) = specialised length or 0.
+template <class Key, class Tiles, class Shape>
+int build_groups(mm_batch *b, std::vector<BGroup> &out, Key key, Tiles tiles, Shape shape) {
+    std::vector<int> keys;
+    for (mm_plan *p : b->plans) {
+        const int k = key(p);
+        if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+    }
+    for (int k : keys) {
+        BGroup g;
+        g.L = k;
+        std::vector<int2> m;
+        for (int i = 0; i < b->count; ++i) {
+            mm_plan *p = b->plans[i];
+            if (key(p) != k) continue;
+            const int t = tiles(p);
+            for (int j = 0; j < t; ++j) m.push_back(make_int2(i, j));
+            shape(p, g);
+        }
+        g.tiles = (int)m.size();
+        int rc = balloc(b, (void **)&g.map, m.size() * sizeof(int2));
+        if (rc) return rc;
+        HIPCK(hipMemcpy(g.map, m.data(), m.size() * sizeof(int2), hipMemcpyHostToDevice));
+        out.push_back(g);
+    }
+    return MM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1072,46 +1140,40 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         int rc = validate_grid(grids[g], cells[g]);
         if (rc) return fail(rc, "geometry %d: %s", g, std::string(g_last).c_str());
     }
+    mm_plan_opts o;
+    mm_plan_opts_default(&o);
+    o.pow2_padding = 1;
+    if (opts) o = *opts;
     mm_batch *b = new (std::nothrow) mm_batch();
     if (!b) return fail(MM_ENOMEM, "batch allocation");
     b->count = count; b->prec = precision; b->stream = (hipStream_t)hip_stream;
     int rc = MM_OK;
     for (int g = 0; g < count && !rc; ++g) {
         mm_plan *p = nullptr;
-        rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, opts);
+        rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &o);
         if (!rc) b->plans.push_back(p);
     }
-    // grouped tile maps and descriptor tables
-    std::vector<int2> zm, lm, fm;
     std::vector<LinePass> lf, li;
     std::vector<FusedPass> fp;
     for (int g = 0; g < count && !rc; ++g) {
-        mm_plan *p = b->plans[g];
-        for (int t = 0; t < p->zg.tiles; ++t) zm.push_back(make_int2(g, t));
-        for (int t = 0; t < p->tiles_fwd; ++t) lm.push_back(make_int2(g, t));
-        for (int t = 0; t < p->fp.tiles; ++t) fm.push_back(make_int2(g, t));
-        lf.push_back(p->lp_fwd); li.push_back(p->lp_inv); fp.push_back(p->fp);
-        b->nthr_z = std::max(b->nthr_z, p->zg.nthr); b->lds_z = std::max(b->lds_z, p->lds_z);
-        b->nthr_l = std::max(b->nthr_l, p->lp_fwd.nthr); b->lds_l = std::max(b->lds_l, p->lds_fwd);
-        b->nthr_f = std::max(b->nthr_f, p->fp.nthr); b->lds_f = std::max(b->lds_f, p->lds_fp);
+        lf.push_back(b->plans[g]->lp_fwd); li.push_back(b->plans[g]->lp_inv); fp.push_back(b->plans[g]->fp);
     }
+    if (!rc) rc = build_groups(b, b->gx, [](mm_plan *p) { return p->x_ct ? (int)p->L[0] : 0; },
+                               [](mm_plan *p) { return p->tiles_fwd; },
+                               [](mm_plan *p, BGroup &g) { g.W = p->lp_fwd.W; g.nthr = std::max(g.nthr, p->lp_fwd.nthr); g.lds = std::max(g.lds, p->lds_fwd); });
+    if (!rc) rc = build_groups(b, b->gy, [](mm_plan *p) { return p->y_ct ? (int)p->L[1] : 0; },
+                               [](mm_plan *p) { return p->fp.tiles; },
+                               [](mm_plan *p, BGroup &g) { g.nthr = std::max(g.nthr, p->fp.nthr); g.lds = std::max(g.lds, p->lds_fp); });
+    if (!rc) rc = build_groups(b, b->gz, [](mm_plan *p) { return p->z_ct ? (int)p->L[2] : 0; },
+                               [](mm_plan *p) { return p->zg.tiles; },
+                               [](mm_plan *p, BGroup &g) { g.nthr = std::max(g.nthr, p->zg.nthr); g.lds = std::max(g.lds, p->lds_z); });
+    if (!rc) rc = balloc(b, (void **)&b->d_lpf, lf.size() * sizeof(LinePass));
+    if (!rc) rc = balloc(b, (void **)&b->d_lpi, li.size() * sizeof(LinePass));
+    if (!rc) rc = balloc(b, (void **)&b->d_fp, fp.size() * sizeof(FusedPass));
+    if (!rc) rc = balloc(b, (void **)&b->d_zf, (size_t)count * sizeof(ZFwdArgs));
+    if (!rc) rc = balloc(b, (void **)&b->d_zi, (size_t)5 * count * sizeof(ZInvArgs));
     if (!rc) {
-        b->zt = (int)zm.size(); b->lt = (int)lm.size(); b->ft = (int)fm.size();
-        if (!rc) rc = balloc(b, (void **)&b->zmap, zm.size() * sizeof(int2));
-        if (!rc) rc = balloc(b, (void **)&b->lmap, lm.size() * sizeof(int2));
-        if (!rc) rc = balloc(b, (void **)&b->fmap, fm.size() * sizeof(int2));
-        if (!rc) rc = balloc(b, (void **)&b->d_lpf, lf.size() * sizeof(LinePass));
-        if (!rc) rc = balloc(b, (void **)&b->d_lpi, li.size() * sizeof(LinePass));
-        if (!rc) rc = balloc(b, (void **)&b->d_fp, fp.size() * sizeof(FusedPass));
-        if (!rc) rc = balloc(b, (void **)&b->d_zf, (size_t)count * sizeof(ZFwdArgs));
-        if (!rc) rc = balloc(b, (void **)&b->d_zi, (size_t)5 * count * sizeof(ZInvArgs));
-    }
-    if (!rc) {
-        hipError_t e = hipSuccess;
-        if (e == hipSuccess) e = hipMemcpy(b->zmap, zm.data(), zm.size() * sizeof(int2), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(b->lmap, lm.data(), lm.size() * sizeof(int2), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(b->fmap, fm.data(), fm.size() * sizeof(int2), hipMemcpyHostToDevice);
-        if (e == hipSuccess) e = hipMemcpy(b->d_lpf, lf.data(), lf.size() * sizeof(LinePass), hipMemcpyHostToDevice);
+        hipError_t e = hipMemcpy(b->d_lpf, lf.data(), lf.size() * sizeof(LinePass), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(b->d_lpi, li.data(), li.size() * sizeof(LinePass), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(b->d_fp, fp.data(), fp.size() * sizeof(FusedPass), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = fail(MM_EHIP, "batch tables: %s", hipGetErrorString(e));

@@ -92,11 +92,10 @@ __global__ void __launch_bounds__(1024) k_line_pass(const LinePass *__restrict__
 // compile-time length L (power of two), W columns per tile, NT threads; the
 // first stage loads from global memory, the last stores to global memory
 template <typename T, int L, int DIR, int NT, int W>
-__global__ void __launch_bounds__(NT) k_line_ct(const LinePass a) {
+__device__ __forceinline__ void line_ct_body(const LinePass &a, int tile) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
-    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
     const int o = tile / a.tiles_inner;
     const int c0 = (tile - o * a.tiles_inner) * W;
     const int wc = min(W, a.inner - c0);
@@ -111,6 +110,18 @@ __global__ void __launch_bounds__(NT) k_line_ct(const LinePass a) {
         if (pos < n_out && line < wc) out[pos * orow + line] = v;
     };
     eng_fft<T, L, false, DIR, NT, W>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
+}
+
+template <typename T, int L, int DIR, int NT, int W>
+__global__ void __launch_bounds__(NT) k_line_ct(const LinePass a) {
+    line_ct_body<T, L, DIR, NT, W>(a, (int)xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// grouped launch over many geometries of the same length L
+template <typename T, int L, int DIR, int NT, int W>
+__global__ void __launch_bounds__(NT) k_line_ct_b(const LinePass *__restrict__ descs, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    line_ct_body<T, L, DIR, NT, W>(descs[e.x], e.y);
 }
 
 // ---------------- fused y pass -------------------------------------------
@@ -387,91 +398,16 @@ __device__ __forceinline__ PencilProduct<T, L> pencil_product(const FusedPass &a
     return pr;
 }
 
-// Persistent, software-pipelined fused pass: each workgroup walks a run of
-// consecutive pencils (so kx and Lx-kx, which share a tensor row, follow each
-// other) and issues the global loads of the next pencil's first radix stage
-// before computing the current one.
-template <typename T, int L, int NT, int MINW>
-__global__ void __launch_bounds__(NT, MINW) k_fused_y_pipe(const FusedPass a, int chunk) {
-    using C = cplx<T>;
-    extern __shared__ __align__(16) unsigned char smem[];
-    C *lds = reinterpret_cast<C *>(smem);
-    constexpr int NS = ct::nst(L);
-    constexpr int P = ct::lds_pitch(L, 3);
-    constexpr int R0 = ct::prad(L, false, 0);
-    constexpr int NB0 = L / R0;
-    constexpr int TOT0 = 3 * NB0;
-    constexpr int U0 = (TOT0 + NT - 1) / NT;
-    const int tid = threadIdx.x;
-    const int w = (int)xcd_tile(blockIdx.x, gridDim.x);
-    const int p_begin = w * chunk, p_end = min(a.npos, p_begin + chunk);
-    const int n = a.n;
-    const C *tw = reinterpret_cast<const C *>(a.tw);
-    const C *twr = tw + (L - 1);
-    // With L >= 2n-1 and L even, rows at or beyond L/2 are always zero: only
-    // the first half of each first-stage butterfly is loaded and kept.
-    constexpr int RH = R0 / 2;
-    C pre[U0][RH];
-    auto pencil_ptr = [&](int p) {
-        const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
-        return reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
-    };
-    auto prefetch = [&](int p) {
-        const C *pen = pencil_ptr(p);
-#pragma unroll
-        for (int u = 0; u < U0; ++u) {
-            const int b = tid + u * NT;
-            const int c = b % 3, j = b / 3;
-#pragma unroll
-            for (int r = 0; r < RH; ++r) {
-                const int pos = j + r * NB0;
-                pre[u][r] = (b < TOT0 && pos < n) ? pen[pos * 3 + c] : cmake<C>(T(0), T(0));
-            }
-        }
-    };
-    if (p_begin < p_end) prefetch(p_begin);
-    for (int p = p_begin; p < p_end; ++p) {
-        C *pen = pencil_ptr(p);
-        const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
-        __syncthreads();   // the previous pencil is done with LDS
-        // first radix stage (Ns = 1, no twiddles) from the prefetched registers
-#pragma unroll
-        for (int u = 0; u < U0; ++u) {
-            const int b = tid + u * NT;
-            if (b < TOT0) {
-                const int c = b % 3, j = b / 3;
-                C v[R0];
-#pragma unroll
-                for (int r = 0; r < R0; ++r) v[r] = r < RH ? pre[u][r] : cmake<C>(T(0), T(0));
-                Dft<R0, -1, C>::run(v);
-#pragma unroll
-                for (int r = 0; r < R0; ++r) lds[c * P + sw<L>(j * R0 + r)] = v[r];
-            }
-        }
-        __syncthreads();
-        if (p + 1 < p_end) prefetch(p + 1);
-        eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, tw, tid);
-        conv_middle<T, L, NT>(lds, tw, tid, pencil_product<T, L>(a, kz, kx));
-        eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
-        auto st = [&](int c, int pos, C v) {
-            if (pos < n) pen[pos * 3 + c] = v;
-        };
-        auto nold = [](int, int) { return C(); };
-        eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
-    }
-}
-
 // compile-time Ly; one (kz, kx) pencil of three components per tile.  The
 // tensor row is fetched into registers together with the pencil's first
 // radix-stage inputs.
 template <typename T, int L, int NT>
-__global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
+__device__ __forceinline__ void fused_ct_body(const FusedPass &a, int p) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
     constexpr int NS = ct::nst(L);
     static_assert(NS >= 2, "fused pencil needs two or more radix stages");
-    const int p = (int)xcd_tile(blockIdx.x, gridDim.x);
     const int tid = threadIdx.x;
     const int n = a.n;
     const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
@@ -504,6 +440,17 @@ __global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
     }
     eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
     eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
+}
+
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
+    fused_ct_body<T, L, NT>(a, (int)xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_ct_b(const FusedPass *__restrict__ descs, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    fused_ct_body<T, L, NT>(descs[e.x], e.y);
 }
 
 // ---------------- launchers -------------------------------------------------
@@ -580,61 +527,86 @@ hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStrea
 size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W) * csz; }
 size_t fused_ct_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L, 3) * csz; }
 
-int fused_ct_threads(int L) {
+int fused_ct_threads(int L, size_t csz) {
     switch (L) {
     case 64: return 64;
     case 128: return 64;
     case 256: return 64;
     case 512: return 128;
     case 1024: return 256;
-    case 2048: return 384;   // FP64; FP32 launches 256 (fused_ct_nt)
+    case 2048: return csz == 8 ? 256 : 384;
     case 4096: return 768;
     default: return 0;
     }
 }
 
 template <typename T>
-hipError_t launch_fused_ct(const FusedPass &a, int pipe, hipStream_t s) {
+hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
     if (a.npos <= 0) return hipSuccess;
     const size_t lds = fused_ct_lds(a.f.L, sizeof(cplx<T>));
-    // pipe = 0: one pencil per workgroup; pipe = 1, 2, 3: persistent,
-    // prefetching kernel with 2 or 3 workgroups per CU and 256 / 384 threads
-    const int per_cu = pipe == 1 ? 2 : 3;
-    const int groups = std::min(a.npos, 256 * per_cu * 2);
-    const int chunk = (a.npos + groups - 1) / groups;
-    const int G = (a.npos + chunk - 1) / chunk;
 #define FCASE(LL, NTT)                                                                                                \
     case LL:                                                                                                          \
         hipLaunchKernelGGL((k_fused_y_ct<T, LL, NTT>), dim3(a.npos), dim3(NTT), lds, s, a);                         \
         break;
-    if (a.f.L == 2048 && pipe >= 4) {
-        // thread-count variants of the 2048-point pencil (measurement)
-        if (pipe == 4) hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 128>), dim3(a.npos), dim3(128), lds, s, a);
-        else if (pipe == 5) hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 256>), dim3(a.npos), dim3(256), lds, s, a);
-        else hipLaunchKernelGGL((k_fused_y_ct<T, 2048, 384>), dim3(a.npos), dim3(384), lds, s, a);
-    } else if (pipe == 0 || a.f.L != 2048) {
-        switch (a.f.L) {
-            FCASE(64, 64) FCASE(128, 64) FCASE(256, 64) FCASE(512, 128) FCASE(1024, 256) FCASE(2048, (sizeof(T) == 4 ? 256 : 384)) FCASE(4096, 768)
-        default: return hipErrorInvalidValue;
-        }
-    } else if (pipe == 1) {
-        hipLaunchKernelGGL((k_fused_y_pipe<T, 2048, 256, 2>), dim3(G), dim3(256), lds, s, a, chunk);
-    } else if (pipe == 2) {
-        hipLaunchKernelGGL((k_fused_y_pipe<T, 2048, 256, 3>), dim3(G), dim3(256), lds, s, a, chunk);
-    } else {
-        hipLaunchKernelGGL((k_fused_y_pipe<T, 2048, 384, 3>), dim3(G), dim3(384), lds, s, a, chunk);
+    // one pencil per workgroup; 2048 points: 256 threads in FP32 (three
+    // workgroups per CU fill the LDS), 384 in FP64 (one per CU)
+    switch (a.f.L) {
+        FCASE(64, 64) FCASE(128, 64) FCASE(256, 64) FCASE(512, 128) FCASE(1024, 256)
+        FCASE(2048, (sizeof(T) == 4 ? 256 : 384)) FCASE(4096, 768)
+    default: return hipErrorInvalidValue;
     }
 #undef FCASE
     return hipGetLastError();
 }
 
+// grouped launches of the specialised kernels (descriptor table + tile map;
+// every geometry in the group has the same transform length)
+template <typename T>
+hipError_t launch_line_ct_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    const size_t lds = line_ct_lds(L, W, sizeof(cplx<T>));
+#define LINE_B(LL, WW)                                                                                                \
+    if (L == LL && W == WW) {                                                                                         \
+        if (dir < 0) hipLaunchKernelGGL((k_line_ct_b<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, d, map); \
+        else hipLaunchKernelGGL((k_line_ct_b<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, d, map);       \
+        return hipGetLastError();                                                                                     \
+    }
+    if constexpr (sizeof(T) == 4) {
+        LINE_B(64, 16) LINE_B(128, 16) LINE_B(256, 16) LINE_B(512, 16) LINE_B(1024, 8) LINE_B(2048, 4) LINE_B(4096, 2)
+    } else {
+        LINE_B(64, 16) LINE_B(128, 16) LINE_B(256, 16) LINE_B(512, 8) LINE_B(1024, 4) LINE_B(2048, 2) LINE_B(4096, 1)
+    }
+#undef LINE_B
+    return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int L, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    const size_t lds = fused_ct_lds(L, sizeof(cplx<T>));
+#define FB(LL, NTT)                                                                                                   \
+    case LL:                                                                                                          \
+        hipLaunchKernelGGL((k_fused_y_ct_b<T, LL, NTT>), dim3(tiles), dim3(NTT), lds, s, d, map);                   \
+        break;
+    switch (L) {
+        FB(64, 64) FB(128, 64) FB(256, 64) FB(512, 128) FB(1024, 256) FB(2048, (sizeof(T) == 4 ? 256 : 384)) FB(4096, 768)
+    default: return hipErrorInvalidValue;
+    }
+#undef FB
+    return hipGetLastError();
+}
+
+template hipError_t launch_line_ct_b<float>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
+template hipError_t launch_line_ct_b<double>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
+template hipError_t launch_fused_ct_b<float>(const FusedPass *, const int2 *, int, int, hipStream_t);
+template hipError_t launch_fused_ct_b<double>(const FusedPass *, const int2 *, int, int, hipStream_t);
 template hipError_t launch_line_pass<float>(const LinePass *, const int2 *, int, int, size_t, int, bool, hipStream_t);
 template hipError_t launch_line_pass<double>(const LinePass *, const int2 *, int, int, size_t, int, bool, hipStream_t);
 template hipError_t launch_fused_y<float>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
 template hipError_t launch_fused_y<double>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
 template hipError_t launch_line_ct<float>(const LinePass &, int, int, int, hipStream_t);
 template hipError_t launch_line_ct<double>(const LinePass &, int, int, int, hipStream_t);
-template hipError_t launch_fused_ct<float>(const FusedPass &, int, hipStream_t);
-template hipError_t launch_fused_ct<double>(const FusedPass &, int, hipStream_t);
+template hipError_t launch_fused_ct<float>(const FusedPass &, hipStream_t);
+template hipError_t launch_fused_ct<double>(const FusedPass &, hipStream_t);
 
 }  // namespace mmx

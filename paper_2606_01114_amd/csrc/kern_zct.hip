@@ -38,7 +38,7 @@ __device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g
 }
 
 template <typename T, int N, int SRC>
-__global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct(const ZFwdArgs a) {
+__device__ __forceinline__ void zfwd_ct_body(const ZFwdArgs &a, uint32_t tile) {
     using C = cplx<T>;
     constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct(const ZFwdArgs a) {
     const ZGeom &g = a.g;
     const int tid = threadIdx.x;
     const int64_t npos = (int64_t)g.nx * g.ny;
-    const int64_t pos0 = (int64_t)xcd_tile(blockIdx.x, gridDim.x) * P;
+    const int64_t pos0 = (int64_t)tile * P;
     const int wp = (int)min((int64_t)P, npos - pos0);
     const int nz = g.nz;
     const T *src = reinterpret_cast<const T *>(a.src);
@@ -72,7 +72,7 @@ __global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct(const ZFwdArgs a) {
 }
 
 template <typename T, int N, int EPI>
-__global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
+__device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     using C = cplx<T>;
     constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
     extern __shared__ __align__(16) unsigned char smem[];
@@ -80,7 +80,6 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
     const ZGeom &g = a.g;
     const int tid = threadIdx.x;
     const int64_t npos = (int64_t)g.nx * g.ny;
-    const uint32_t blk = xcd_tile(blockIdx.x, gridDim.x);
     const int64_t pos0 = (int64_t)blk * P;
     const int wp = (int)min((int64_t)P, npos - pos0);
     const int w3 = 3 * wp;
@@ -185,6 +184,28 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
     }
 }
 
+template <typename T, int N, int SRC>
+__global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct(const ZFwdArgs a) {
+    zfwd_ct_body<T, N, SRC>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int N, int SRC>
+__global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct_b(const ZFwdArgs *__restrict__ d, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    zfwd_ct_body<T, N, SRC>(d[e.x], (uint32_t)e.y);
+}
+
+template <typename T, int N, int EPI>
+__global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
+    zinv_ct_body<T, N, EPI>(a, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+template <typename T, int N, int EPI>
+__global__ void __launch_bounds__(zthreads(N)) k_zinv_ct_b(const ZInvArgs *__restrict__ d, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    zinv_ct_body<T, N, EPI>(d[e.x], (uint32_t)e.y);
+}
+
 // ---------------- launchers -------------------------------------------------
 int zct_cols(int Lz) {
     if (Lz < 2 || Lz > 2048 || (Lz & (Lz - 1))) return 0;
@@ -236,6 +257,47 @@ hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_zfwd_ct_b(const ZFwdArgs *d, const int2 *map, int tiles, int Lz, int src_mode, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    const int N = Lz / 2;
+    const size_t lds = zct_lds(Lz, sizeof(cplx<T>));
+    switch (N) {
+#define ZF(NN)                                                                                                        \
+    case NN:                                                                                                          \
+        if (src_mode == SRC_MS_M) hipLaunchKernelGGL((k_zfwd_ct_b<T, NN, SRC_MS_M>), dim3(tiles), dim3(zthreads(NN)), lds, s, d, map); \
+        else hipLaunchKernelGGL((k_zfwd_ct_b<T, NN, SRC_RAW>), dim3(tiles), dim3(zthreads(NN)), lds, s, d, map);   \
+        break;
+        ZN_CASES(ZF)
+#undef ZF
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zinv_ct_b(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    const int N = Lz / 2;
+    const size_t lds = zct_lds(Lz, sizeof(cplx<T>));
+    switch (N) {
+#define ZI(NN)                                                                                                        \
+    case NN:                                                                                                          \
+        if (epi == EPI_HEFF) hipLaunchKernelGGL((k_zinv_ct_b<T, NN, EPI_HEFF>), dim3(tiles), dim3(zthreads(NN)), lds, s, d, map); \
+        else if (epi == EPI_STAGE) hipLaunchKernelGGL((k_zinv_ct_b<T, NN, EPI_STAGE>), dim3(tiles), dim3(zthreads(NN)), lds, s, d, map); \
+        else hipLaunchKernelGGL((k_zinv_ct_b<T, NN, EPI_ADJ>), dim3(tiles), dim3(zthreads(NN)), lds, s, d, map);   \
+        break;
+        ZN_CASES(ZI)
+#undef ZI
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template hipError_t launch_zfwd_ct_b<float>(const ZFwdArgs *, const int2 *, int, int, int, hipStream_t);
+template hipError_t launch_zfwd_ct_b<double>(const ZFwdArgs *, const int2 *, int, int, int, hipStream_t);
+template hipError_t launch_zinv_ct_b<float>(const ZInvArgs *, const int2 *, int, int, int, hipStream_t);
+template hipError_t launch_zinv_ct_b<double>(const ZInvArgs *, const int2 *, int, int, int, hipStream_t);
 template hipError_t launch_zfwd_ct<float>(const ZFwdArgs &, int, hipStream_t);
 template hipError_t launch_zfwd_ct<double>(const ZFwdArgs &, int, hipStream_t);
 template hipError_t launch_zinv_ct<float>(const ZInvArgs &, int, hipStream_t);

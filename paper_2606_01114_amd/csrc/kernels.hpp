@@ -15,11 +15,11 @@ hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles
 // power-of-two specialisations; line_ct_shape / fused_ct_threads report
 // whether one exists for a length (and its tile width / thread count)
 int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT);
-int fused_ct_threads(int L);
+int fused_ct_threads(int L, size_t csz);
 size_t line_ct_lds(int L, int W, size_t csz);
 size_t fused_ct_lds(int L, size_t csz);
 template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s);
-template <typename T> hipError_t launch_fused_ct(const FusedPass &a, int pipe, hipStream_t s);
+template <typename T> hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s);
 template <typename T> hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s);
 template <typename T> hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s);
 template <typename T>
@@ -35,6 +35,13 @@ int zct_cols(int Lz);
 size_t zct_lds(int Lz, size_t csz);
 template <typename T> hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s);
 template <typename T> hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s);
+template <typename T>
+hipError_t launch_line_ct_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s);
+template <typename T> hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int L, hipStream_t s);
+template <typename T>
+hipError_t launch_zfwd_ct_b(const ZFwdArgs *d, const int2 *map, int tiles, int Lz, int src_mode, hipStream_t s);
+template <typename T>
+hipError_t launch_zinv_ct_b(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, hipStream_t s);
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s);
 hipError_t launch_tensor_octant(double *out, int nx, int ny, int nz, double dx, double dy, double dz, double P,
                                 hipStream_t s);

@@ -102,24 +102,34 @@ def test_large_grid_fp32_vs_fp64_and_sampled():
 GEOMS = [((53, 20, 3), 6e5), ((48, 61, 1), 1.1e6), ((7, 9, 5), 4e5), ((32, 16, 8), 9e5), ((1, 24, 2), 7e5)]
 
 
-@pytest.mark.parametrize("prec", ["f32", "f64"])
-def test_batch_against_oracle_and_plans(prec):
+def _pow2_L(n):
+    """Smallest power of two >= 2n-1 (1 for a single cell)."""
+    if n == 1:
+        return 1
+    L = 1
+    while L < 2 * n - 1:
+        L *= 2
+    return L
+
+
+@pytest.mark.parametrize("prec,pow2", [("f32", True), ("f64", True), ("f32", False), ("f64", False)])
+def test_batch_against_oracle_and_plans(prec, pow2):
     import torch
     from paper_2606_01114_amd import Batch, DemagPlan
     dt = torch.float32 if prec == "f32" else torch.float64
     grids = [g for g, _ in GEOMS]
     Ms = [ms for _, ms in GEOMS]
-    b = Batch(grids, [D] * len(grids), prec)
+    b = Batch(grids, [D] * len(grids), prec, pow2_padding=pow2)
     m0 = [rounded(synth.random_unit(g, 40 + k), dt) for k, g in enumerate(grids)]
     ms = [to_dev(x, dt) for x in m0]
     hs = b.h_eff(ms, Ms, A)
     for k, g in enumerate(grids):
         oct_ = oracle.tensor_octant(g, D)
-        L = tuple(oracle.default_L(v) for v in g)
+        L = tuple((_pow2_L if pow2 else oracle.default_L)(v) for v in g)
         ref = oracle.h_eff(m0[k], Ms[k], A, D, oct_, L)
         e = rel_l2(hs[k].cpu().numpy(), ref)
         assert e <= (1e-9 if prec == "f64" else 1e-5), (g, e)
-        pl = DemagPlan(g, D, prec)
+        pl = DemagPlan(g, D, prec, L=L)
         single = pl.h_eff(ms[k], Ms[k], A)
         assert rel_l2(hs[k].cpu().numpy(), single.cpu().numpy()) <= (1e-14 if prec == "f64" else 1e-6)
     # one and two RK4 steps, graph and direct, against the oracle
@@ -129,7 +139,7 @@ def test_batch_against_oracle_and_plans(prec):
     for k, g in enumerate(grids):
         assert torch.equal(ms[k], ms2[k])
         oct_ = oracle.tensor_octant(g, D)
-        L = tuple(oracle.default_L(v) for v in g)
+        L = tuple((_pow2_L if pow2 else oracle.default_L)(v) for v in g)
         ref = oracle.rk4_step(m0[k], Ms[k], A, D, oct_, L, ALPHA, GAMMA, DT)
         e = rel_l2(ms[k].cpu().numpy() - m0[k], ref - m0[k])
         assert e <= (1e-9 if prec == "f64" else 1e-5), (g, e)
