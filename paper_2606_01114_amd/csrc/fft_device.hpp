@@ -28,6 +28,33 @@ template <int DIR, typename C> __device__ __forceinline__ C crot(C a, decltype(C
     return cmake<C>(a.x * c - a.y * ss, a.x * ss + a.y * c);
 }
 
+// ---- raw buffer access with hardware range checking ------------------------
+// A resource covers `bytes` bytes from a wave-uniform base.  A load at a byte
+// offset at or beyond that size returns zero and a store there is dropped, so
+// zero padding and ragged line ends need no per-element branches.  Sizes are
+// below 2^31 (checked by the host planner), so an offset of 2^31 plus any
+// in-range offset is always out of range.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+constexpr uint32_t kBufOff = 0x80000000u;   // an offset that is always out of range
+using BufRsrc = __amdgpu_buffer_rsrc_t;
+__device__ __forceinline__ BufRsrc make_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename C> __device__ __forceinline__ C buf_load(BufRsrc r, uint32_t off);
+template <> __device__ __forceinline__ float2 buf_load<float2>(BufRsrc r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+template <> __device__ __forceinline__ double2 buf_load<double2>(BufRsrc r, uint32_t off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(BufRsrc r, uint32_t off, float2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(BufRsrc r, uint32_t off, double2 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, 0);
+}
+
 // ---- small DFTs: X_k = sum_n x_n exp(DIR 2 pi i n k / R), in place -------
 template <int R, int DIR, typename C> struct Dft;
 
@@ -90,6 +117,107 @@ template <int DIR, typename C> struct Dft<16, DIR, C> {
             Dft<4, DIR, C>::run(t);
 #pragma unroll
             for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+        }
+    }
+};
+
+// ---- pruned DFTs for zero-padded lines -------------------------------------
+// MODE 1: inputs R/2..R-1 are zero and are not read (first stage of a
+// transform whose input occupies the lower half of the line); MODE 2: only
+// outputs 0..R/2-1 are produced (last stage of a transform of which only the
+// lower half is kept).  MODE 0 is the full DFT.
+template <int R, int DIR, int MODE, typename C> struct PDft {
+    static __device__ __forceinline__ void run(C *v) {
+        if constexpr (MODE == 1) {
+#pragma unroll
+            for (int r = R / 2; r < R; ++r) v[r] = cmake<C>(0, 0);
+        }
+        Dft<R, DIR, C>::run(v);
+    }
+};
+
+template <int DIR, typename C> struct PDft<2, DIR, 1, C> {
+    static __device__ __forceinline__ void run(C *v) { v[1] = v[0]; }
+};
+template <int DIR, typename C> struct PDft<2, DIR, 2, C> {
+    static __device__ __forceinline__ void run(C *v) { v[0] = cadd(v[0], v[1]); }
+};
+
+template <int DIR, typename C> struct PDft<4, DIR, 1, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        const C a = v[0], b = v[1], t = cmul_i<DIR>(b);
+        v[0] = cadd(a, b); v[2] = csub(a, b);
+        v[1] = cadd(a, t); v[3] = csub(a, t);
+    }
+};
+template <int DIR, typename C> struct PDft<4, DIR, 2, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        C t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+        C t2 = cadd(v[1], v[3]), t3 = cmul_i<DIR>(csub(v[1], v[3]));
+        v[0] = cadd(t0, t2); v[1] = cadd(t1, t3);
+    }
+};
+
+template <int DIR, int MODE, typename C> struct PDft<8, DIR, MODE, C> {
+    static __device__ __forceinline__ void run(C *v) {
+        if constexpr (MODE == 0) {
+            Dft<8, DIR, C>::run(v);
+        } else {
+            using R = decltype(C().x);
+            const R h = R(0.70710678118654752440084436210484904);
+            C e[4] = {v[0], v[2], v[4], v[6]};
+            C o[4] = {v[1], v[3], v[5], v[7]};
+            // inputs 4..7 are the upper halves of the even and odd sub-DFTs
+            PDft<4, DIR, MODE == 1 ? 1 : 0, C>::run(e);
+            PDft<4, DIR, MODE == 1 ? 1 : 0, C>::run(o);
+            o[1] = crot<DIR>(o[1], h, h);
+            o[2] = cmul_i<DIR>(o[2]);
+            o[3] = crot<DIR>(o[3], -h, h);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                v[k] = cadd(e[k], o[k]);
+                if (MODE == 1) v[k + 4] = csub(e[k], o[k]);
+            }
+        }
+    }
+};
+
+template <int DIR, int MODE, typename C> struct PDft<16, DIR, MODE, C> {
+    // 16 = 4 x 4: n = 4 n1 + n2, k = k1 + 4 k2.  Inputs 8..15 are n1 = 2, 3
+    // (the upper half of every first-layer DFT); outputs 0..7 are k2 = 0, 1
+    // (the lower half of every second-layer DFT).
+    static __device__ __forceinline__ void run(C *v) {
+        if constexpr (MODE == 0) {
+            Dft<16, DIR, C>::run(v);
+        } else {
+            using R = decltype(C().x);
+            const R c1 = R(0.92387953251128675612818318939678829), s1 = R(0.38268343236508977172845998403039887);
+            const R h = R(0.70710678118654752440084436210484904);
+            C y[4][4];
+#pragma unroll
+            for (int n2 = 0; n2 < 4; ++n2) {
+                C t[4] = {v[n2], v[4 + n2], MODE == 1 ? C() : v[8 + n2], MODE == 1 ? C() : v[12 + n2]};
+                PDft<4, DIR, MODE == 1 ? 1 : 0, C>::run(t);
+#pragma unroll
+                for (int k1 = 0; k1 < 4; ++k1) y[n2][k1] = t[k1];
+            }
+            y[1][1] = crot<DIR>(y[1][1], c1, s1);
+            y[1][2] = crot<DIR>(y[1][2], h, h);
+            y[1][3] = crot<DIR>(y[1][3], s1, c1);
+            y[2][1] = crot<DIR>(y[2][1], h, h);
+            y[2][2] = cmul_i<DIR>(y[2][2]);
+            y[2][3] = crot<DIR>(y[2][3], -h, h);
+            y[3][1] = crot<DIR>(y[3][1], s1, c1);
+            y[3][2] = crot<DIR>(y[3][2], -h, h);
+            y[3][3] = crot<DIR>(y[3][3], -c1, -s1);
+#pragma unroll
+            for (int k1 = 0; k1 < 4; ++k1) {
+                C t[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+                PDft<4, DIR, MODE == 2 ? 2 : 0, C>::run(t);
+                v[k1] = t[0];
+                v[k1 + 4] = t[1];
+                if (MODE == 1) { v[k1 + 8] = t[2]; v[k1 + 12] = t[3]; }
+            }
         }
     }
 };
@@ -325,7 +453,8 @@ __device__ __forceinline__ void fft_stage_ct(cplx<T> *buf, int nlines, int pitch
 template <typename T, int L, int S, int DIR, int NT, int NLMAX>
 __device__ __forceinline__ void fft_ct_from(cplx<T> *buf, int nlines, int pitch, const cplx<T> *__restrict__ tw, int tid) {
     if constexpr (S < ct::nst(L)) {
-        fft_stage_ct<T, L, ct::rad(L, S), ct::ns_before(L, S), DIR, NT, NLMAX>(buf, nlines, pitch, tw + ct::twoff(L, S), tid);
+        constexpr int TWO = ct::twoff(L, S);
+        fft_stage_ct<T, L, ct::rad(L, S), ct::ns_before(L, S), DIR, NT, NLMAX>(buf, nlines, pitch, tw + TWO, tid);
         fft_ct_from<T, L, S + 1, DIR, NT, NLMAX>(buf, nlines, pitch, tw, tid);
     }
 }

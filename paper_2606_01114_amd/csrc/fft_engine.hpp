@@ -28,12 +28,23 @@ constexpr int lds_pitch(int L, int NL) {
 
 template <int L> __device__ __forceinline__ int sw(int p) { return L >= 32 ? p + (p >> 4) : p; }
 
+// Offset form of the swizzle: sw(a + b) = sw(a) + swc(b) whenever
+// (a mod 16) + (b mod 16) < 16.  Every access of a power-of-two Stockham stage
+// has that form (a = j or the butterfly's output base, b = a multiple of the
+// stride that stays within the 16-block), so per-element addresses become
+// compile-time offsets from one per-butterfly base.
+template <int L> __device__ __forceinline__ constexpr int swc(int b) { return L >= 32 ? b + (b >> 4) : b; }
+
 // One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
 // 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
 // line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB: groups of LA lines
 // are interleaved (LA = NL: all lines; LA = 3: the components of one cell
-// column).  P = LDS pitch of a line.
-template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int LA, int P, class Ld, class St>
+// column).  P = LDS pitch of a line.  PR = 1: the line's upper half
+// (positions >= L/2, i.e. inputs r >= R/2 of a first stage) is zero and not
+// loaded; PR = 2: only the lower half of the output is stored (outputs
+// r < R/2 of a last stage).
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int LA, int P, int PR = 0,
+          class Ld, class St>
 __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     using C = cplx<T>;
     constexpr int R = ct::prad(L, REV, S);
@@ -41,15 +52,21 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
     constexpr int NB = L / R;
     constexpr int TOT = NL * NB;
     constexpr int U = (TOT + NT - 1) / NT;
-    const C *t = tw + ct::ptw(L, REV, S);
+    constexpr int TWO = ct::ptw(L, REV, S);
+    constexpr int RI = PR == 1 ? R / 2 : R;   // inputs read
+    constexpr int RO = PR == 2 ? R / 2 : R;   // outputs written
+    static_assert(PR != 1 || (Ns == 1 && IN == 0), "zero upper half applies to a first stage fed by the loader");
+    static_assert(PR != 2 || (Ns * R == L && OUT == 0), "half output applies to a last stage feeding the storer");
+    const C *t = tw + TWO;
     C v[U][R];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int b = tid + u * NT;
         if (b < TOT) {
             const int line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB;
+            const int sj = line * P + sw<L>(j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[u][r] = IN ? lds[line * P + sw<L>(j + r * NB)] : ld(line, j + r * NB);
+            for (int r = 0; r < RI; ++r) v[u][r] = IN ? lds[sj + swc<L>(r * NB)] : ld(line, j + r * NB);
             if (Ns > 1) {
                 const C *tt = t + (j % Ns) * (R - 1);
 #pragma unroll
@@ -59,7 +76,7 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
                     v[u][r] = cmul(v[u][r], w);
                 }
             }
-            Dft<R, DIR, C>::run(v[u]);
+            PDft<R, DIR, PR, C>::run(v[u]);
         }
     }
     if (IN && OUT) __syncthreads();
@@ -69,9 +86,10 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
         if (b < TOT) {
             const int line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB;
             const int d = (j / Ns) * Ns * R + (j % Ns);
+            const int sd = line * P + sw<L>(d);
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                if (OUT) lds[line * P + sw<L>(d + r * Ns)] = v[u][r];
+            for (int r = 0; r < RO; ++r) {
+                if (OUT) lds[sd + swc<L>(r * Ns)] = v[u][r];
                 else st(line, d + r * Ns, v[u][r]);
             }
         }
@@ -79,9 +97,9 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
     if (OUT) __syncthreads();
 }
 
-template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, class Ld, class St>
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int PR = 0, class Ld, class St>
 __device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
-    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL)>(lds, tw, tid, ld, st);
+    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL), PR>(lds, tw, tid, ld, st);
 }
 
 // stages [S, E) LDS -> LDS with interleave LA and pitch P
@@ -99,7 +117,7 @@ __device__ __forceinline__ void eng_mid_la(cplx<T> *lds, const cplx<T> *__restri
 // last stage to the storer (OUTL = 0) or LDS (OUTL = 1).  With IN0 = 1 the
 // caller must have synchronised after filling LDS; with OUTL = 1 the call
 // ends with a barrier.
-template <typename T, int L, int DIR, int NT, int NL, int LA, int P, int IN0, int OUTL, class Ld, class St>
+template <typename T, int L, int DIR, int NT, int NL, int LA, int P, int IN0, int OUTL, int PRUNE = 0, class Ld, class St>
 __device__ __forceinline__ void eng_fft_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     constexpr int NS = ct::nst(L);
     if constexpr (NS == 0) {
@@ -117,9 +135,10 @@ __device__ __forceinline__ void eng_fft_la(cplx<T> *lds, const cplx<T> *__restri
     } else {
         auto nold = [](int, int) { return cplx<T>(); };
         auto nost = [](int, int, cplx<T>) {};
-        eng_stage_la<T, L, false, 0, DIR, NT, NL, IN0, 1, LA, P>(lds, tw, tid, ld, nost);
+        constexpr int P0 = (IN0 == 0 && (PRUNE & 1)) ? 1 : 0, PL = (OUTL == 0 && (PRUNE & 2)) ? 2 : 0;
+        eng_stage_la<T, L, false, 0, DIR, NT, NL, IN0, 1, LA, P, P0>(lds, tw, tid, ld, nost);
         eng_mid_la<T, L, false, 1, NS - 1, DIR, NT, NL, LA, P>(lds, tw, tid);
-        eng_stage_la<T, L, false, NS - 1, DIR, NT, NL, 1, OUTL, LA, P>(lds, tw, tid, nold, st);
+        eng_stage_la<T, L, false, NS - 1, DIR, NT, NL, 1, OUTL, LA, P, PL>(lds, tw, tid, nold, st);
     }
 }
 
@@ -134,8 +153,11 @@ __device__ __forceinline__ void eng_mid(cplx<T> *lds, const cplx<T> *__restrict_
     }
 }
 
-// Full transform: loader -> [LDS stages] -> storer.
-template <typename T, int L, bool REV, int DIR, int NT, int NL, class Ld, class St>
+// Full transform: loader -> [LDS stages] -> storer.  PRUNE bit 0: the input
+// occupies the lower half of each line (upper half zero, not loaded); bit 1:
+// only the lower half of each output line is stored.  Transforms of two or
+// more stages only.
+template <typename T, int L, bool REV, int DIR, int NT, int NL, int PRUNE = 0, class Ld, class St>
 __device__ __forceinline__ void eng_fft(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     constexpr int NS = ct::nst(L);
     if constexpr (NS == 0) {
@@ -144,9 +166,9 @@ __device__ __forceinline__ void eng_fft(cplx<T> *lds, const cplx<T> *__restrict_
     } else if constexpr (NS == 1) {
         eng_stage<T, L, REV, 0, DIR, NT, NL, 0, 0>(lds, tw, tid, ld, st);
     } else {
-        eng_stage<T, L, REV, 0, DIR, NT, NL, 0, 1>(lds, tw, tid, ld, st);
+        eng_stage<T, L, REV, 0, DIR, NT, NL, 0, 1, (PRUNE & 1) ? 1 : 0>(lds, tw, tid, ld, st);
         eng_mid<T, L, REV, 1, NS - 1, DIR, NT, NL>(lds, tw, tid);
-        eng_stage<T, L, REV, NS - 1, DIR, NT, NL, 1, 0>(lds, tw, tid, ld, st);
+        eng_stage<T, L, REV, NS - 1, DIR, NT, NL, 1, 0, (PRUNE & 2) ? 2 : 0>(lds, tw, tid, ld, st);
     }
 }
 

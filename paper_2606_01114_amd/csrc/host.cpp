@@ -283,7 +283,10 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
     if (getenv("MMX_XVAR")) p->x_var = atoi(getenv("MMX_XVAR")) ? 1 : 0;
-    p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax && !getenv("MMX_NO_CT");
+    // the specialised kernels address one kz plane (Lx rows) through a buffer
+    // resource, whose size is a 31-bit byte count
+    p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax &&
+              (int64_t)Lx * ny3 * (int64_t)csz < (int64_t(1) << 31) && !getenv("MMX_NO_CT");
     if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);

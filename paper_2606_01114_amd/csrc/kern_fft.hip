@@ -100,16 +100,21 @@ __device__ __forceinline__ void line_ct_body(const LinePass &a, int tile) {
     const int c0 = (tile - o * a.tiles_inner) * W;
     const int wc = min(W, a.inner - c0);
     const int n_in = a.n_in, n_out = a.n_out;
-    const int64_t ir = a.in_row, orow = a.out_row;
+    const uint32_t ir = (uint32_t)a.in_row * sizeof(C), orow = (uint32_t)a.out_row * sizeof(C);
     const C *in = reinterpret_cast<const C *>(a.in) + (int64_t)o * a.in_outer + c0;
     C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
-    auto ld = [&](int line, int pos) -> C {
-        return (pos < n_in && line < wc) ? in[pos * ir + line] : cmake<C>(T(0), T(0));
-    };
+    // each resource ends at the tile's last valid element: rows past n_in read
+    // as zero, rows past n_out are not written
+    const BufRsrc ri = make_rsrc(in, (uint32_t)(n_in - 1) * ir + (uint32_t)(a.inner - c0) * sizeof(C));
+    const BufRsrc ro = make_rsrc(out, (uint32_t)(n_out - 1) * orow + (uint32_t)(a.inner - c0) * sizeof(C));
+    // columns past the tile's width (last tile of a row) are loaded from the
+    // next row or as zero and never stored
+    auto ld = [&](int line, int pos) -> C { return buf_load<C>(ri, (uint32_t)pos * ir + (uint32_t)line * sizeof(C)); };
     auto st = [&](int line, int pos, C v) {
-        if (pos < n_out && line < wc) out[pos * orow + line] = v;
+        buf_store(ro, (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff), v);
     };
-    eng_fft<T, L, false, DIR, NT, W>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
+    // forward: input rows n_in <= L/2; inverse: output rows n_out <= L/2
+    eng_fft<T, L, false, DIR, NT, W, DIR < 0 ? 1 : 2>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
 }
 
 template <typename T, int L, int DIR, int NT, int W>
@@ -227,18 +232,20 @@ __device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restr
     constexpr int R = ct::prad(L, false, NS - 1);
     constexpr int NB = L / R;
     constexpr int Nsf = ct::pns(L, false, NS - 1);
+    constexpr int TWM = ct::ptw(L, false, NS - 1);
     constexpr int UJ = (NB + NT - 1) / NT;
     C v[UJ][3][R];
 #pragma unroll
     for (int u = 0; u < UJ; ++u) {
         const int j = tid + u * NT;
         if (j < NB) {
+            const int sj = sw<L>(j);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sw<L>(j + r * NB)];
+                for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sj + swc<L>(r * NB)];
                 if (Nsf > 1) {
-                    const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
+                    const C *tt = twf + TWM + (j % Nsf) * (R - 1);
 #pragma unroll
                     for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
                 }
@@ -255,10 +262,11 @@ __device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restr
     for (int u = 0; u < UJ; ++u) {
         const int j = tid + u * NT;
         if (j < NB) {
+            const int sj = sw<L>(j * R);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[c * P + sw<L>(j * R + r)] = v[u][c][r];
+                for (int r = 0; r < R; ++r) lds[c * P + sj + swc<L>(r)] = v[u][c][r];
         }
     }
     __syncthreads();
@@ -307,18 +315,20 @@ __device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__r
     constexpr int R = ct::prad(L, false, NS - 1);
     constexpr int NB = L / R;
     constexpr int Nsf = ct::pns(L, false, NS - 1);
+    constexpr int TWM = ct::ptw(L, false, NS - 1);
     constexpr int UJ = (NB + NT - 1) / NT;
     C v[UJ][3][R];
 #pragma unroll
     for (int u = 0; u < UJ; ++u) {
         const int j = tid + u * NT;
         if (j < NB) {
+            const int sj = sw<L>(j);
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sw<L>(j + r * NB)];
+                for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sj + swc<L>(r * NB)];
                 if (Nsf > 1) {
-                    const C *tt = twf + ct::ptw(L, false, NS - 1) + (j % Nsf) * (R - 1);
+                    const C *tt = twf + TWM + (j % Nsf) * (R - 1);
 #pragma unroll
                     for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
                 }
@@ -341,31 +351,14 @@ __device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__r
     for (int u = 0; u < UJ; ++u) {
         const int j = tid + u * NT;
         if (j < NB) {
+            const int sj = sw<L>(j * R);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[c * P + sw<L>(j * R + r)] = v[u][c][r];
+                for (int r = 0; r < R; ++r) lds[c * P + sj + swc<L>(r)] = v[u][c][r];
         }
     }
     __syncthreads();
-}
-
-// Convolution core of one three-line pencil: forward stages, conv_middle,
-// then the remaining inverse stages.  twf / twr: forward / reversed-order
-// tables.  Needs at least two radix stages.
-template <typename T, int L, int NT, class Ld, class St, class Pr>
-__device__ __forceinline__ void conv_pencil(cplx<T> *lds, const cplx<T> *__restrict__ twf, const cplx<T> *__restrict__ twr,
-                                            int tid, const Ld &ld, const St &st, const Pr &prod) {
-    using C = cplx<T>;
-    constexpr int NS = ct::nst(L);
-    static_assert(NS >= 2, "conv_pencil needs two or more radix stages");
-    auto nost = [](int, int, C) {};
-    eng_stage<T, L, false, 0, -1, NT, 3, 0, 1>(lds, twf, tid, ld, nost);
-    eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, twf, tid);
-    conv_middle<T, L, NT>(lds, twf, tid, prod);
-    eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
-    auto nold = [](int, int) { return C(); };
-    eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
 }
 
 // tensor product of one (kz, kx) pencil: the tensor row (kz, |kx|) with the
@@ -420,15 +413,15 @@ __device__ __forceinline__ void fused_ct_body(const FusedPass &a, int p) {
     constexpr bool early = sizeof(T) == 4;
     PencilTensor<T, L, (early ? NT : 1)> pt;
     if constexpr (early) pt.load(Trow, sx, tid);
-    auto ld = [&](int c, int pos) -> C { return pos < n ? pen[pos * 3 + c] : cmake<C>(T(0), T(0)); };
-    auto st = [&](int c, int pos, C v) {
-        if (pos < n) pen[pos * 3 + c] = v;
-    };
+    // rows past n (the zero padding) read as zero and are not written
+    const BufRsrc rp = make_rsrc(pen, (uint32_t)(3 * n) * sizeof(C));
+    auto ld = [&](int c, int pos) -> C { return buf_load<C>(rp, (uint32_t)(pos * 3 + c) * sizeof(C)); };
+    auto st = [&](int c, int pos, C v) { buf_store(rp, (uint32_t)(pos * 3 + c) * sizeof(C), v); };
     const C *tw = reinterpret_cast<const C *>(a.tw);
     const C *twr = tw + (L - 1);
     auto nost = [](int, int, C) {};
     auto nold = [](int, int) { return C(); };
-    eng_stage<T, L, false, 0, -1, NT, 3, 0, 1>(lds, tw, tid, ld, nost);
+    eng_stage<T, L, false, 0, -1, NT, 3, 0, 1, 1>(lds, tw, tid, ld, nost);
     eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, tw, tid);
     if constexpr (early) {
         conv_middle_pre<T, L, NT>(lds, tw, tid, pt);
@@ -439,7 +432,7 @@ __device__ __forceinline__ void fused_ct_body(const FusedPass &a, int p) {
         conv_middle<T, L, NT>(lds, tw, tid, pr);
     }
     eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
-    eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0>(lds, twr, tid, nold, st);
+    eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0, 2>(lds, twr, tid, nold, st);
 }
 
 template <typename T, int L, int NT>
