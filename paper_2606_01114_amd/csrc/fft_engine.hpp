@@ -55,8 +55,8 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
     constexpr int TWO = ct::ptw(L, REV, S);
     constexpr int RI = PR == 1 ? R / 2 : R;   // inputs read
     constexpr int RO = PR == 2 ? R / 2 : R;   // outputs written
-    static_assert(PR != 1 || (Ns == 1 && IN == 0), "zero upper half applies to a first stage fed by the loader");
-    static_assert(PR != 2 || (Ns * R == L && OUT == 0), "half output applies to a last stage feeding the storer");
+    static_assert(PR != 1 || Ns == 1, "a zero upper half applies to a first stage");
+    static_assert(PR != 2 || Ns * R == L, "a half output applies to a last stage");
     const C *t = tw + TWO;
     C v[U][R];
 #pragma unroll
@@ -116,7 +116,8 @@ __device__ __forceinline__ void eng_mid_la(cplx<T> *lds, const cplx<T> *__restri
 // General transform: stage 0 from the loader (IN0 = 0) or LDS (IN0 = 1), the
 // last stage to the storer (OUTL = 0) or LDS (OUTL = 1).  With IN0 = 1 the
 // caller must have synchronised after filling LDS; with OUTL = 1 the call
-// ends with a barrier.
+// ends with a barrier.  PRUNE as for eng_fft (two or more stages only; the
+// skipped upper half is neither read nor written in LDS either).
 template <typename T, int L, int DIR, int NT, int NL, int LA, int P, int IN0, int OUTL, int PRUNE = 0, class Ld, class St>
 __device__ __forceinline__ void eng_fft_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     constexpr int NS = ct::nst(L);
@@ -135,7 +136,7 @@ __device__ __forceinline__ void eng_fft_la(cplx<T> *lds, const cplx<T> *__restri
     } else {
         auto nold = [](int, int) { return cplx<T>(); };
         auto nost = [](int, int, cplx<T>) {};
-        constexpr int P0 = (IN0 == 0 && (PRUNE & 1)) ? 1 : 0, PL = (OUTL == 0 && (PRUNE & 2)) ? 2 : 0;
+        constexpr int P0 = (PRUNE & 1) ? 1 : 0, PL = (PRUNE & 2) ? 2 : 0;
         eng_stage_la<T, L, false, 0, DIR, NT, NL, IN0, 1, LA, P, P0>(lds, tw, tid, ld, nost);
         eng_mid_la<T, L, false, 1, NS - 1, DIR, NT, NL, LA, P>(lds, tw, tid);
         eng_stage_la<T, L, false, NS - 1, DIR, NT, NL, 1, OUTL, LA, P, PL>(lds, tw, tid, nold, st);

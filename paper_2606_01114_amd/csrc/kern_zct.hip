@@ -15,25 +15,31 @@ constexpr int zcols(int N) { return N >= 1024 ? 1 : 1024 / N; }   // P: ~3072 co
 constexpr int zthreads(int N) { return 256; }
 }  // namespace
 
+// Lines of a tile past its last cell column (the grid's last tile) are
+// transformed like the others but never stored.
+//
 // unfold: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[N-k])/2, O = (Z[k] - conj Z[N-k])/(2i),
-// W = exp(-2 pi i / 2N); written to S1 [kz][pos][c] for the tile's lines
+// W = exp(-2 pi i / 2N); since E[N-k] = conj E[k] and O[N-k] = conj O[k], one
+// pair (Z[k], Z[N-k]) gives X[k] and X[N-k].  Written to S1 [kz][pos][c].
 template <typename T, int N, int NT, int NL, int PT>
-__device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g, int64_t pos0, int wp,
+__device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g, int64_t pos0, int w3,
                                               const cplx<T> *__restrict__ wt, int tid) {
     using C = cplx<T>;
-    const int w3 = 3 * wp;
     const int64_t npos3 = (int64_t)g.nx * g.ny * 3;
     C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * 3;
-    const FastDiv dw = make_fastdiv((uint32_t)w3);
     const T h = T(0.5);
-    for (int e = tid; e < (N + 1) * w3; e += NT) {
-        const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
+    for (int e = tid; e < (N / 2 + 1) * NL; e += NT) {
+        const int k = e / NL, l = e - k * NL;
         const C za = lds[l * PT + sw<N>(k % N)];
         const C zb = lds[l * PT + sw<N>((N - k) % N)];
         const C E = cmake<C>(h * (za.x + zb.x), h * (za.y - zb.y));
         const C O = cmake<C>(h * (za.y + zb.y), -h * (za.x - zb.x));
-        const C w = wt[k];
-        S1[k * npos3 + l] = cmake<C>(E.x + w.x * O.x - w.y * O.y, E.y + w.x * O.y + w.y * O.x);
+        const C w = wt[k], wm = wt[N - k];
+        if (l < w3) {
+            S1[k * npos3 + l] = cmake<C>(E.x + w.x * O.x - w.y * O.y, E.y + w.x * O.y + w.y * O.x);
+            if (2 * k != N)
+                S1[(N - k) * npos3 + l] = cmake<C>(E.x + wm.x * O.x + wm.y * O.y, -E.y - wm.x * O.y + wm.y * O.x);
+        }
     }
 }
 
@@ -67,14 +73,19 @@ __device__ __forceinline__ void zfwd_ct_body(const ZFwdArgs &a, uint32_t tile) {
     };
     auto nost = [](int, int, C) {};
     const C *tw = reinterpret_cast<const C *>(g.twh);
-    eng_fft_la<T, N, -1, NT, NL, 3, PT, 0, 1>(lds, tw, tid, ld, nost);
-    zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, wp, tw + (N > 1 ? N - 1 : 0), tid);
+    // folded samples occupy slots < ceil(nz/2) <= N/2
+    eng_fft_la<T, N, -1, NT, NL, 3, PT, 0, 1, 1>(lds, tw, tid, ld, nost);
+    zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, 3 * wp, tw + (N > 1 ? N - 1 : 0), tid);
 }
 
 template <typename T, int N, int EPI>
 __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     using C = cplx<T>;
     constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
+    // slots of the folded line that can hold cells: ceil(nz/2) <= N/2; the
+    // transforms skip the upper half when they have two or more stages
+    constexpr bool HALF = ct::nst(N) >= 2;
+    constexpr int NH = HALF ? N / 2 : N;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
     const ZGeom &g = a.g;
@@ -87,37 +98,24 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     const bool demag = (a.terms & 1u) != 0;
     const C *tw = reinterpret_cast<const C *>(g.twh);
     const C *wt = tw + (N > 1 ? N - 1 : 0);
-    const FastDiv dw = make_fastdiv((uint32_t)w3);
-    // 0. each thread's first KPRE cells: own inputs fetched now, used after the transform
-    constexpr int KPRE = 0;   // prefetching own inputs costs occupancy more than it hides latency
-    OwnCell<T> own[KPRE > 0 ? KPRE : 1];
-    const int ncells = wp * nz;
-#pragma unroll
-    for (int k = 0; k < KPRE; ++k) {
-        const int e = tid + k * NT;
-        if (e < ncells) load_own<T, EPI>(a, pos0 * nz + e, own[k]);
-    }
     if (demag) {
-        // 1. half spectra X[0..N] of the tile's lines (DC and Nyquist real)
+        // 1. half spectra X[k], X[N-k] of the tile's lines (DC and Nyquist
+        //    real), folded at once:
+        //    Z[k] = (X[k] + conj X[N-k]) + i conj(W^k) (X[k] - conj X[N-k])
         const int64_t npos3 = npos * 3;
         const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * 3;
-        for (int e = tid; e < (N + 1) * w3; e += NT) {
-            const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
-            C X = S1[k * npos3 + l];
-            if (k == 0 || k == N) X.y = T(0);
-            lds[l * PT + sw<N>(k)] = X;
-        }
-        __syncthreads();
-        // 2. fold: Z[k] = (X[k] + conj X[N-k]) + i conj(W^k) (X[k] - conj X[N-k]), k < N
-        for (int e = tid; e < (N / 2 + 1) * w3; e += NT) {
-            const int k = (int)fdiv((uint32_t)e, dw), l = e - k * w3;
+        for (int e = tid; e < (N / 2 + 1) * NL; e += NT) {
+            const int k = e / NL, l = e - k * NL;
+            const int lc = min(l, w3 - 1);
+            C xk = S1[k * npos3 + lc];
+            C xm = S1[(N - k) * npos3 + lc];
             C *b = lds + l * PT;
             if (k == 0) {
-                const C x0 = b[0], xn = b[sw<N>(N)];
-                const C s = cmake<C>(x0.x + xn.x, x0.y - xn.y), d = cmake<C>(x0.x - xn.x, x0.y + xn.y);
+                xk.y = T(0);
+                xm.y = T(0);
+                const C s = cmake<C>(xk.x + xm.x, xk.y - xm.y), d = cmake<C>(xk.x - xm.x, xk.y + xm.y);
                 b[0] = cmake<C>(s.x - d.y, s.y + d.x);
             } else {
-                const C xk = b[sw<N>(k)], xm = b[sw<N>(N - k)];
                 const C wk = wt[k];
                 {
                     const C s = cmake<C>(xk.x + xm.x, xk.y - xm.y), d = cmake<C>(xk.x - xm.x, xk.y + xm.y);
@@ -136,12 +134,13 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
         __syncthreads();
         auto nold = [](int, int) { return C(); };
         auto nost = [](int, int, C) {};
-        eng_fft_la<T, N, +1, NT, NL, 3, PT, 1, 1>(lds, tw, tid, nold, nost);
+        eng_fft_la<T, N, +1, NT, NL, 3, PT, 1, 1, HALF ? 2 : 0>(lds, tw, tid, nold, nost);
     }
-    // 3. epilogue per cell; demag field sample z of component c sits in line
+    // 2. epilogue per cell; demag field sample z of component c sits in line
     //    3 pl + c, slot z/2, real part for even z
     double ed = 0.0, ex = 0.0;
-    auto do_cell = [&](int e, const OwnCell<T> *pre) {
+    const int ncells = wp * nz;
+    for (int e = tid; e < ncells; e += NT) {
         const int pl = (int)fdiv((uint32_t)e, g.dnz), z = e - pl * nz;
         const int64_t pos = pos0 + pl;
         const int i = (int)fdiv((uint32_t)pos, g.dny), j = (int)(pos - (int64_t)i * ny);
@@ -152,25 +151,20 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
             for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
         }
         T srcn[3];
-        cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn, pre);
+        cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn);
         if (EPI == EPI_STAGE && a.next_r2c) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
         }
-    };
-#pragma unroll
-    for (int k = 0; k < KPRE; ++k) {
-        const int e = tid + k * NT;
-        if (e < ncells) do_cell(e, &own[k]);
     }
-    for (int e = tid + KPRE * NT; e < ncells; e += NT) do_cell(e, nullptr);
     if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_STAGE && a.next_r2c) {
-        // 4. the next stage's source, already folded in LDS: clear the padding
-        //    and transform it forward
+        // 3. the next stage's source, already folded in LDS: clear the slots
+        //    between the last cell and the transform's input half, then
+        //    transform forward
         const int n0 = (nz + 1) / 2;
-        for (int e = tid; e < (N - n0) * w3; e += NT) {
-            const int k = n0 + (int)fdiv((uint32_t)e, dw), l = e - (k - n0) * w3;
+        for (int e = tid; e < (NH - n0) * w3; e += NT) {
+            const int k = n0 + e / w3, l = e - (k - n0) * w3;
             lds[l * PT + sw<N>(k)] = cmake<C>(T(0), T(0));
         }
         if (nz & 1) {
@@ -179,8 +173,8 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
         __syncthreads();
         auto nold = [](int, int) { return C(); };
         auto nost = [](int, int, C) {};
-        eng_fft_la<T, N, -1, NT, NL, 3, PT, 1, 1>(lds, tw, tid, nold, nost);
-        zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, wp, wt, tid);
+        eng_fft_la<T, N, -1, NT, NL, 3, PT, 1, 1, HALF ? 1 : 0>(lds, tw, tid, nold, nost);
+        zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, w3, wt, tid);
     }
 }
 

@@ -18,68 +18,85 @@ __device__ __forceinline__ void cross3(const T a[3], const T b[3], T o[3]) {
 template <typename T>
 __device__ __forceinline__ T ms_at(const T *Ms, T Ms_s, int64_t cell) { return Ms ? Ms[cell] : Ms_s; }
 
-// The cell's own inputs, fetched ahead of the z transform so their latency
-// overlaps it: m (stage input or h_eff input), m_n, the RK4 accumulator, Ms.
-template <typename T>
-struct OwnCell {
-    T mi[3], mn[3], acc[3], ms;
-};
-
-template <typename T, int EPI>
-__device__ __forceinline__ void load_own(const ZInvArgs &a, int64_t cell, OwnCell<T> &o) {
-    const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
-    const T *Ms = reinterpret_cast<const T *>(a.Ms);
-    o.ms = Ms ? Ms[cell] : T(a.Ms_scalar);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) o.mi[c] = mfield[cell * 3 + c];
-    if (EPI == EPI_STAGE) {
-        const T *mn = reinterpret_cast<const T *>(a.m_n);
-#pragma unroll
-        for (int c = 0; c < 3; ++c) o.mn[c] = mn[cell * 3 + c];
-        if (a.stage > 0) {
-            const T *acc = reinterpret_cast<const T *>(a.acc);
-#pragma unroll
-            for (int c = 0; c < 3; ++c) o.acc[c] = acc[cell * 3 + c];
-        }
-    }
-}
+// Reciprocal and reciprocal square root: the hardware approximations (about
+// one ulp) in FP32, correctly rounded division in FP64.
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rnorm(float n2) { return __builtin_amdgcn_rsqf(n2); }
+__device__ __forceinline__ double rnorm(double n2) { return 1.0 / sqrt(n2); }
 
 // cell (i, j, z) with flat index `cell`; hd = demag field there (0 if not
 // requested).  Returns in src_next the next stage's z-transform source
-// Ms * m_next (EPI_STAGE with next_r2c only).  `pre` (nullable) holds the
-// cell's own inputs already loaded.
-template <typename T, int EPI>
-__device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
-                                              double &ed, double &ex, T src_next[3], const OwnCell<T> *pre = nullptr) {
+// Ms * m_next (EPI_STAGE with next_r2c only).  MSV: Ms is a per-cell field
+// (else the scalar).  All loads are issued before any arithmetic: a neighbour
+// outside the domain is replaced by the cell itself (its difference term is
+// exactly zero, the Neumann condition) and a vacuum neighbour gets weight 0.
+template <typename T, int EPI, bool MSV>
+__device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
+                                                double &ed, double &ex, T src_next[3]) {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int64_t sx = (int64_t)ny * nz, sy = nz;
     const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
     const T *Ms = reinterpret_cast<const T *>(a.Ms);
-    const T Ms_s = T(a.Ms_scalar);
     const T exp_ = T(a.ex_pref);
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
-    const T msi = pre ? pre->ms : ms_at(Ms, Ms_s, cell);
-    const bool magi = msi > T(0);
-    T mi[3];
+    int64_t nc[6];
+    nc[0] = i > 0 ? cell - sx : cell;
+    nc[1] = i < nx - 1 ? cell + sx : cell;
+    nc[2] = j > 0 ? cell - sy : cell;
+    nc[3] = j < ny - 1 ? cell + sy : cell;
+    nc[4] = z > 0 ? cell - 1 : cell;
+    nc[5] = z < nz - 1 ? cell + 1 : cell;
+    // ---- loads
+    const T msi = MSV ? Ms[cell] : T(a.Ms_scalar);
+    T mi[3], mnb[6][3], msn[6];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mi[c] = pre ? pre->mi[c] : mfield[cell * 3 + c];
-    const int64_t noff[6] = {-sx, sx, -sy, sy, -1, 1};
-    const bool nin[6] = {i > 0, i < nx - 1, j > 0, j < ny - 1, z > 0, z < nz - 1};
-    T hex[3] = {T(0), T(0), T(0)};
-    if (exch && magi) {
-        T lap[3] = {T(0), T(0), T(0)};
+    for (int c = 0; c < 3; ++c) mi[c] = mfield[cell * 3 + c];
+    if (exch) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
-            if (!nin[q]) continue;
-            const int64_t nc = cell + noff[q];
-            if (!(ms_at(Ms, Ms_s, nc) > T(0))) continue;
-            const T w = T(a.inv_d2[q >> 1]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) lap[c] += (mfield[nc * 3 + c] - mi[c]) * w;
+            for (int c = 0; c < 3; ++c) mnb[q][c] = mfield[nc[q] * 3 + c];
+            msn[q] = MSV ? Ms[nc[q]] : msi;
         }
-        const T ci = exp_ / msi;
+    }
+    T mn[3], ac[3], gi[3], gnb[6][3];
+    if (EPI == EPI_STAGE) {
+        const T *mnp = reinterpret_cast<const T *>(a.m_n) + cell * 3;
+        const T *accp = reinterpret_cast<const T *>(a.acc) + cell * 3;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) hex[c] = ci * lap[c];
+        for (int c = 0; c < 3; ++c) mn[c] = mnp[c];
+        if (a.stage > 0) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) ac[c] = accp[c];
+        }
+    }
+    if (EPI == EPI_ADJ) {
+        const T *gh = reinterpret_cast<const T *>(a.g_h);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) gi[c] = gh[cell * 3 + c];
+        if (exch) {
+#pragma unroll
+            for (int q = 0; q < 6; ++q)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) gnb[q][c] = gh[nc[q] * 3 + c];
+        }
+    }
+    // ---- exchange field
+    const bool magi = msi > T(0);
+    T hex[3] = {T(0), T(0), T(0)};
+    T wq[6];
+    if (exch) {
+#pragma unroll
+        for (int q = 0; q < 6; ++q) wq[q] = (MSV && !(msn[q] > T(0))) ? T(0) : T(a.inv_d2[q >> 1]);
+        T lap[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int q = 0; q < 6; ++q)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) lap[c] += (mnb[q][c] - mi[c]) * wq[q];
+        const T ci = exp_ * recip(msi);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hex[c] = magi ? ci * lap[c] : T(0);
     }
     if (EPI == EPI_HEFF) {
         T *ho = reinterpret_cast<T *>(a.h_out) + cell * 3;
@@ -104,15 +121,7 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
         const T gp = T(a.gp), al = T(a.alpha), dt = T(a.dt);
 #pragma unroll
         for (int c = 0; c < 3; ++c) f[c] = -gp * (mxh[c] + al * mxmxh[c]);
-        const T *mnp = reinterpret_cast<const T *>(a.m_n) + cell * 3;
         T *acc = reinterpret_cast<T *>(a.acc) + cell * 3;
-        T mn[3], ac[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) mn[c] = pre ? pre->mn[c] : mnp[c];
-        if (a.stage > 0) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) ac[c] = pre ? pre->acc[c] : acc[c];
-        }
         T nxt[3];
         if (a.stage == 0) {
 #pragma unroll
@@ -133,27 +142,19 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
                 for (int c = 0; c < 3; ++c) ur[c] = nxt[c];
             }
             if (a.renorm) {
-                const T nn = sqrt(nxt[0] * nxt[0] + nxt[1] * nxt[1] + nxt[2] * nxt[2]);
+                const T r = rnorm(nxt[0] * nxt[0] + nxt[1] * nxt[1] + nxt[2] * nxt[2]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) nxt[c] = nxt[c] / nn;
+                for (int c = 0; c < 3; ++c) nxt[c] *= r;
             }
         }
-        if (a.stage < 3) {
-            T *mo = reinterpret_cast<T *>(a.ms_out) + cell * 3;
+        T *mo = reinterpret_cast<T *>(a.stage < 3 ? a.ms_out : a.m_out);
+        if (mo) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) mo[c] = nxt[c];
-        } else if (a.m_out) {
-            T *mo = reinterpret_cast<T *>(a.m_out) + cell * 3;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) mo[c] = nxt[c];
+            for (int c = 0; c < 3; ++c) mo[cell * 3 + c] = nxt[c];
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) src_next[c] = msi * nxt[c];
     } else {  // EPI_ADJ
-        const T *gh = reinterpret_cast<const T *>(a.g_h);
-        T gi[3];
-#pragma unroll
-        for (int c = 0; c < 3; ++c) gi[c] = gh[cell * 3 + c];
         T gm[3] = {T(0), T(0), T(0)};
         T gms = T(0);
         if (demag) {
@@ -162,22 +163,18 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
             gms = mi[0] * hd[0] + mi[1] * hd[1] + mi[2] * hd[2];
         }
         if (exch && magi) {
-            const T ci = exp_ / msi;
+            const T ci = exp_ * recip(msi);
             T lg[3] = {T(0), T(0), T(0)};
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
-                if (!nin[q]) continue;
-                const int64_t nc = cell + noff[q];
-                const T msn = ms_at(Ms, Ms_s, nc);
-                if (!(msn > T(0))) continue;
-                const T cn = exp_ / msn;
-                const T w = T(a.inv_d2[q >> 1]);
+                // a vacuum neighbour has weight 0 (and would divide by Ms = 0)
+                const T cn = wq[q] != T(0) ? exp_ * recip(msn[q]) : T(0);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) lg[c] += (cn * gh[nc * 3 + c] - ci * gi[c]) * w;
+                for (int c = 0; c < 3; ++c) lg[c] += (cn * gnb[q][c] - ci * gi[c]) * wq[q];
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) gm[c] += lg[c];
-            gms -= (gi[0] * hex[0] + gi[1] * hex[1] + gi[2] * hex[2]) / msi;
+            gms -= (gi[0] * hex[0] + gi[1] * hex[1] + gi[2] * hex[2]) * recip(msi);
         }
         T *go = reinterpret_cast<T *>(a.g_m) + cell * 3;
 #pragma unroll
@@ -187,6 +184,13 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
             gM[0] = a.acc_gMs ? gM[0] + gms : gms;
         }
     }
+}
+
+template <typename T, int EPI>
+__device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
+                                              double &ed, double &ex, T src_next[3]) {
+    if (a.Ms) cell_epilogue_t<T, EPI, true>(a, cell, i, j, z, hd, ed, ex, src_next);
+    else cell_epilogue_t<T, EPI, false>(a, cell, i, j, z, hd, ed, ex, src_next);
 }
 
 // fixed-order block reduction of the two FP64 energy partial sums
