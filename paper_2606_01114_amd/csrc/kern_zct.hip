@@ -28,17 +28,35 @@ __device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g
     const int64_t npos3 = (int64_t)g.nx * g.ny * 3;
     C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * 3;
     const T h = T(0.5);
-    for (int e = tid; e < (N / 2 + 1) * NL; e += NT) {
-        const int k = e / NL, l = e - k * NL;
-        const C za = lds[l * PT + sw<N>(k % N)];
-        const C zb = lds[l * PT + sw<N>((N - k) % N)];
-        const C E = cmake<C>(h * (za.x + zb.x), h * (za.y - zb.y));
-        const C O = cmake<C>(h * (za.y + zb.y), -h * (za.x - zb.x));
-        const C w = wt[k], wm = wt[N - k];
-        if (l < w3) {
-            S1[k * npos3 + l] = cmake<C>(E.x + w.x * O.x - w.y * O.y, E.y + w.x * O.y + w.y * O.x);
-            if (2 * k != N)
-                S1[(N - k) * npos3 + l] = cmake<C>(E.x + wm.x * O.x + wm.y * O.y, -E.y - wm.x * O.y + wm.y * O.x);
+    constexpr int NE = (N / 2 + 1) * NL;
+    constexpr int CH = sizeof(T) == 4 ? 8 : 4;
+    for (int e0 = 0; e0 < NE; e0 += CH * NT) {
+        C w[CH], wm[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < NE) {
+                const int k = e / NL;
+                w[u] = wt[k];
+                wm[u] = wt[N - k];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < NE) {
+                const int k = e / NL, l = e - k * NL;
+                const C za = lds[l * PT + sw<N>(k % N)];
+                const C zb = lds[l * PT + sw<N>((N - k) % N)];
+                const C E = cmake<C>(h * (za.x + zb.x), h * (za.y - zb.y));
+                const C O = cmake<C>(h * (za.y + zb.y), -h * (za.x - zb.x));
+                if (l < w3) {
+                    S1[k * npos3 + l] = cmake<C>(E.x + w[u].x * O.x - w[u].y * O.y, E.y + w[u].x * O.y + w[u].y * O.x);
+                    if (2 * k != N)
+                        S1[(N - k) * npos3 + l] = cmake<C>(E.x + wm[u].x * O.x + wm[u].y * O.y,
+                                                           -E.y - wm[u].x * O.y + wm[u].y * O.x);
+                }
+            }
         }
     }
 }
@@ -78,6 +96,54 @@ __device__ __forceinline__ void zfwd_ct_body(const ZFwdArgs &a, uint32_t tile) {
     zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, 3 * wp, tw + (N > 1 ? N - 1 : 0), tid);
 }
 
+// Epilogue over the tile's cells, two cells per thread at a time: both cells'
+// loads are issued before either's arithmetic.  The demag field sample z of
+// component c sits in line 3 pl + c, slot z/2, real part for even z; the next
+// stage's source is written back to the same place.
+template <typename T, int N, int EPI, bool MSV>
+__device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int64_t pos0, int ncells, bool demag,
+                                           double &ed, double &ex, int tid) {
+    constexpr int NT = zthreads(N), PT = zpitch(N);
+    const ZGeom &g = a.g;
+    const int nz = g.nz, ny = g.ny;
+    auto where = [&](int e, int &pl, int &z, int64_t &cell, int &i, int &j) {
+        pl = (int)fdiv((uint32_t)e, g.dnz);
+        z = e - pl * nz;
+        const int64_t pos = pos0 + pl;
+        i = (int)fdiv((uint32_t)pos, g.dny);
+        j = (int)(pos - (int64_t)i * ny);
+        cell = pos * nz + z;
+    };
+    auto finish = [&](int pl, int z, const CellIn<T> &in) {
+        T hd[3] = {T(0), T(0), T(0)};
+        if (demag) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
+        }
+        T srcn[3];
+        cell_compute<T, EPI, MSV>(a, in, hd, ed, ex, srcn);
+        if (EPI == EPI_STAGE && a.next_r2c) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
+        }
+    };
+    for (int e0 = tid; e0 < ncells; e0 += 2 * NT) {
+        const int e1 = e0 + NT;
+        const bool two = e1 < ncells;
+        int pl0, z0, i0, j0, pl1 = 0, z1 = 0, i1 = 0, j1 = 0;
+        int64_t c0, c1 = 0;
+        where(e0, pl0, z0, c0, i0, j0);
+        CellIn<T> in0, in1;
+        cell_load<T, EPI, MSV>(a, c0, i0, j0, z0, in0);
+        if (two) {
+            where(e1, pl1, z1, c1, i1, j1);
+            cell_load<T, EPI, MSV>(a, c1, i1, j1, z1, in1);
+        }
+        finish(pl0, z0, in0);
+        if (two) finish(pl1, z1, in1);
+    }
+}
+
 template <typename T, int N, int EPI>
 __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     using C = cplx<T>;
@@ -102,32 +168,51 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
         // 1. half spectra X[k], X[N-k] of the tile's lines (DC and Nyquist
         //    real), folded at once:
         //    Z[k] = (X[k] + conj X[N-k]) + i conj(W^k) (X[k] - conj X[N-k])
+        //    Loads of CH iterations are issued before their arithmetic.
         const int64_t npos3 = npos * 3;
         const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * 3;
-        for (int e = tid; e < (N / 2 + 1) * NL; e += NT) {
-            const int k = e / NL, l = e - k * NL;
-            const int lc = min(l, w3 - 1);
-            C xk = S1[k * npos3 + lc];
-            C xm = S1[(N - k) * npos3 + lc];
-            C *b = lds + l * PT;
-            if (k == 0) {
-                xk.y = T(0);
-                xm.y = T(0);
-                const C s = cmake<C>(xk.x + xm.x, xk.y - xm.y), d = cmake<C>(xk.x - xm.x, xk.y + xm.y);
-                b[0] = cmake<C>(s.x - d.y, s.y + d.x);
-            } else {
-                const C wk = wt[k];
-                {
-                    const C s = cmake<C>(xk.x + xm.x, xk.y - xm.y), d = cmake<C>(xk.x - xm.x, xk.y + xm.y);
-                    // i conj(w) d
-                    const C cd = cmake<C>(wk.x * d.x + wk.y * d.y, wk.x * d.y - wk.y * d.x);
-                    b[sw<N>(k)] = cmake<C>(s.x - cd.y, s.y + cd.x);
+        constexpr int NE = (N / 2 + 1) * NL;
+        constexpr int CH = sizeof(T) == 4 ? 8 : 4;
+        for (int e0 = 0; e0 < NE; e0 += CH * NT) {
+            C xk[CH], xm[CH], wk[CH], wm[CH];
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int e = e0 + tid + u * NT;
+                if (e < NE) {
+                    const int k = e / NL, l = e - k * NL;
+                    const int lc = min(l, w3 - 1);
+                    xk[u] = S1[k * npos3 + lc];
+                    xm[u] = S1[(N - k) * npos3 + lc];
+                    wk[u] = wt[k];
+                    wm[u] = wt[N - k];
                 }
-                if (2 * k != N) {
-                    const C wm = wt[N - k];
-                    const C s = cmake<C>(xm.x + xk.x, xm.y - xk.y), d = cmake<C>(xm.x - xk.x, xm.y + xk.y);
-                    const C cd = cmake<C>(wm.x * d.x + wm.y * d.y, wm.x * d.y - wm.y * d.x);
-                    b[sw<N>(N - k)] = cmake<C>(s.x - cd.y, s.y + cd.x);
+            }
+#pragma unroll
+            for (int u = 0; u < CH; ++u) {
+                const int e = e0 + tid + u * NT;
+                if (e < NE) {
+                    const int k = e / NL, l = e - k * NL;
+                    C *b = lds + l * PT;
+                    if (k == 0) {
+                        const C x0 = cmake<C>(xk[u].x, T(0)), xn = cmake<C>(xm[u].x, T(0));
+                        const C s = cmake<C>(x0.x + xn.x, x0.y - xn.y), d = cmake<C>(x0.x - xn.x, x0.y + xn.y);
+                        b[0] = cmake<C>(s.x - d.y, s.y + d.x);
+                    } else {
+                        const C xa = xk[u], xb = xm[u];
+                        {
+                            const C s = cmake<C>(xa.x + xb.x, xa.y - xb.y), d = cmake<C>(xa.x - xb.x, xa.y + xb.y);
+                            // i conj(w) d
+                            const C w = wk[u];
+                            const C cd = cmake<C>(w.x * d.x + w.y * d.y, w.x * d.y - w.y * d.x);
+                            b[sw<N>(k)] = cmake<C>(s.x - cd.y, s.y + cd.x);
+                        }
+                        if (2 * k != N) {
+                            const C s = cmake<C>(xb.x + xa.x, xb.y - xa.y), d = cmake<C>(xb.x - xa.x, xb.y + xa.y);
+                            const C w = wm[u];
+                            const C cd = cmake<C>(w.x * d.x + w.y * d.y, w.x * d.y - w.y * d.x);
+                            b[sw<N>(N - k)] = cmake<C>(s.x - cd.y, s.y + cd.x);
+                        }
+                    }
                 }
             }
         }
@@ -140,23 +225,8 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     //    3 pl + c, slot z/2, real part for even z
     double ed = 0.0, ex = 0.0;
     const int ncells = wp * nz;
-    for (int e = tid; e < ncells; e += NT) {
-        const int pl = (int)fdiv((uint32_t)e, g.dnz), z = e - pl * nz;
-        const int64_t pos = pos0 + pl;
-        const int i = (int)fdiv((uint32_t)pos, g.dny), j = (int)(pos - (int64_t)i * ny);
-        const int64_t cell = pos * nz + z;
-        T hd[3] = {T(0), T(0), T(0)};
-        if (demag) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
-        }
-        T srcn[3];
-        cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, srcn);
-        if (EPI == EPI_STAGE && a.next_r2c) {
-#pragma unroll
-            for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
-        }
-    }
+    if (a.Ms) zepi_cells<T, N, EPI, true>(a, lds, pos0, ncells, demag, ed, ex, tid);
+    else zepi_cells<T, N, EPI, false>(a, lds, pos0, ncells, demag, ed, ex, tid);
     if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_STAGE && a.next_r2c) {
         // 3. the next stage's source, already folded in LDS: clear the slots

@@ -25,20 +25,23 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rnorm(float n2) { return __builtin_amdgcn_rsqf(n2); }
 __device__ __forceinline__ double rnorm(double n2) { return 1.0 / sqrt(n2); }
 
-// cell (i, j, z) with flat index `cell`; hd = demag field there (0 if not
-// requested).  Returns in src_next the next stage's z-transform source
-// Ms * m_next (EPI_STAGE with next_r2c only).  MSV: Ms is a per-cell field
-// (else the scalar).  All loads are issued before any arithmetic: a neighbour
-// outside the domain is replaced by the cell itself (its difference term is
-// exactly zero, the Neumann condition) and a vacuum neighbour gets weight 0.
+// Inputs of one cell's epilogue, loaded before any arithmetic so that the
+// loads of several cells can be in flight together.  MSV: Ms is a per-cell
+// field (else the scalar).  A neighbour outside the domain is replaced by the
+// cell itself (its difference term is exactly zero: the Neumann condition);
+// a vacuum neighbour gets weight 0.
+template <typename T>
+struct CellIn {
+    int64_t cell;
+    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3];
+};
+
 template <typename T, int EPI, bool MSV>
-__device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
-                                                double &ed, double &ex, T src_next[3]) {
+__device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i, int j, int z, CellIn<T> &in) {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int64_t sx = (int64_t)ny * nz, sy = nz;
-    const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
+    const bool exch = (a.terms & 2u) != 0;
     const T *Ms = reinterpret_cast<const T *>(a.Ms);
-    const T exp_ = T(a.ex_pref);
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
     int64_t nc[6];
     nc[0] = i > 0 ? cell - sx : cell;
@@ -47,53 +50,63 @@ __device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell,
     nc[3] = j < ny - 1 ? cell + sy : cell;
     nc[4] = z > 0 ? cell - 1 : cell;
     nc[5] = z < nz - 1 ? cell + 1 : cell;
-    // ---- loads
-    const T msi = MSV ? Ms[cell] : T(a.Ms_scalar);
-    T mi[3], mnb[6][3], msn[6];
+    in.cell = cell;
+    in.msi = MSV ? Ms[cell] : T(a.Ms_scalar);
 #pragma unroll
-    for (int c = 0; c < 3; ++c) mi[c] = mfield[cell * 3 + c];
+    for (int c = 0; c < 3; ++c) in.mi[c] = mfield[cell * 3 + c];
     if (exch) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) mnb[q][c] = mfield[nc[q] * 3 + c];
-            msn[q] = MSV ? Ms[nc[q]] : msi;
+            for (int c = 0; c < 3; ++c) in.mnb[q][c] = mfield[nc[q] * 3 + c];
+            in.msn[q] = MSV ? Ms[nc[q]] : in.msi;
         }
     }
-    T mn[3], ac[3], gi[3], gnb[6][3];
     if (EPI == EPI_STAGE) {
         const T *mnp = reinterpret_cast<const T *>(a.m_n) + cell * 3;
         const T *accp = reinterpret_cast<const T *>(a.acc) + cell * 3;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) mn[c] = mnp[c];
+        for (int c = 0; c < 3; ++c) in.mn[c] = mnp[c];
         if (a.stage > 0) {
 #pragma unroll
-            for (int c = 0; c < 3; ++c) ac[c] = accp[c];
+            for (int c = 0; c < 3; ++c) in.ac[c] = accp[c];
         }
     }
     if (EPI == EPI_ADJ) {
         const T *gh = reinterpret_cast<const T *>(a.g_h);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) gi[c] = gh[cell * 3 + c];
+        for (int c = 0; c < 3; ++c) in.gi[c] = gh[cell * 3 + c];
         if (exch) {
 #pragma unroll
             for (int q = 0; q < 6; ++q)
 #pragma unroll
-                for (int c = 0; c < 3; ++c) gnb[q][c] = gh[nc[q] * 3 + c];
+                for (int c = 0; c < 3; ++c) in.gnb[q][c] = gh[nc[q] * 3 + c];
         }
     }
+}
+
+// hd = demag field at the cell (0 if not requested).  Returns in src_next the
+// next stage's z-transform source Ms * m_next (EPI_STAGE only).
+template <typename T, int EPI, bool MSV>
+__device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> &in, const T hd[3], double &ed,
+                                             double &ex, T src_next[3]) {
+    const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
+    const T exp_ = T(a.ex_pref);
+    const int64_t cell = in.cell;
+    const T msi = in.msi;
+    const T *mi = in.mi;
     // ---- exchange field
     const bool magi = msi > T(0);
     T hex[3] = {T(0), T(0), T(0)};
     T wq[6];
     if (exch) {
 #pragma unroll
-        for (int q = 0; q < 6; ++q) wq[q] = (MSV && !(msn[q] > T(0))) ? T(0) : T(a.inv_d2[q >> 1]);
+        for (int q = 0; q < 6; ++q) wq[q] = (MSV && !(in.msn[q] > T(0))) ? T(0) : T(a.inv_d2[q >> 1]);
         T lap[3] = {T(0), T(0), T(0)};
 #pragma unroll
         for (int q = 0; q < 6; ++q)
 #pragma unroll
-            for (int c = 0; c < 3; ++c) lap[c] += (mnb[q][c] - mi[c]) * wq[q];
+            for (int c = 0; c < 3; ++c) lap[c] += (in.mnb[q][c] - mi[c]) * wq[q];
         const T ci = exp_ * recip(msi);
 #pragma unroll
         for (int c = 0; c < 3; ++c) hex[c] = magi ? ci * lap[c] : T(0);
@@ -122,6 +135,7 @@ __device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell,
 #pragma unroll
         for (int c = 0; c < 3; ++c) f[c] = -gp * (mxh[c] + al * mxmxh[c]);
         T *acc = reinterpret_cast<T *>(a.acc) + cell * 3;
+        const T *mn = in.mn, *ac = in.ac;
         T nxt[3];
         if (a.stage == 0) {
 #pragma unroll
@@ -157,6 +171,7 @@ __device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell,
     } else {  // EPI_ADJ
         T gm[3] = {T(0), T(0), T(0)};
         T gms = T(0);
+        const T *gi = in.gi;
         if (demag) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) gm[c] = msi * hd[c];
@@ -168,9 +183,9 @@ __device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell,
 #pragma unroll
             for (int q = 0; q < 6; ++q) {
                 // a vacuum neighbour has weight 0 (and would divide by Ms = 0)
-                const T cn = wq[q] != T(0) ? exp_ * recip(msn[q]) : T(0);
+                const T cn = wq[q] != T(0) ? exp_ * recip(in.msn[q]) : T(0);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) lg[c] += (cn * gnb[q][c] - ci * gi[c]) * wq[q];
+                for (int c = 0; c < 3; ++c) lg[c] += (cn * in.gnb[q][c] - ci * gi[c]) * wq[q];
             }
 #pragma unroll
             for (int c = 0; c < 3; ++c) gm[c] += lg[c];
@@ -186,11 +201,18 @@ __device__ __forceinline__ void cell_epilogue_t(const ZInvArgs &a, int64_t cell,
     }
 }
 
+// one cell, loads then arithmetic
 template <typename T, int EPI>
 __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
                                               double &ed, double &ex, T src_next[3]) {
-    if (a.Ms) cell_epilogue_t<T, EPI, true>(a, cell, i, j, z, hd, ed, ex, src_next);
-    else cell_epilogue_t<T, EPI, false>(a, cell, i, j, z, hd, ed, ex, src_next);
+    CellIn<T> in;
+    if (a.Ms) {
+        cell_load<T, EPI, true>(a, cell, i, j, z, in);
+        cell_compute<T, EPI, true>(a, in, hd, ed, ex, src_next);
+    } else {
+        cell_load<T, EPI, false>(a, cell, i, j, z, in);
+        cell_compute<T, EPI, false>(a, in, hd, ed, ex, src_next);
+    }
 }
 
 // fixed-order block reduction of the two FP64 energy partial sums
