@@ -105,7 +105,10 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
 int mm_plan_destroy(mm_plan *plan);
 int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
 
-/* Padded lengths, device bytes held, and tile widths in use (each nullable). */
+/* Padded lengths, device bytes held, and the launch shapes in use (each
+ * nullable): tiles = {z cell columns per tile, x columns per tile, y pencils
+ * per tile, x pass variant (0 and 1: two tile widths, 2: persistent kernel),
+ * z cell columns per tile}. */
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 
 /*

@@ -42,6 +42,10 @@ def _load():
     if not os.path.exists(LIBPATH):
         raise ImportError("libmmx.so is not built (%s); run __graft_entry__.build() or "
                           "python paper_2606_01114_amd/build.py" % LIBPATH)
+    # The library and torch must share one HIP runtime (device pointers and
+    # streams cross between them): load torch's first so that the library's
+    # libamdhip64 dependency resolves to it.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIBPATH)
     vp, i64p, dp, ci, cu, cd = (ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double),
                                 ctypes.c_int, ctypes.c_uint, ctypes.c_double)

@@ -97,6 +97,52 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
     if (OUT) __syncthreads();
 }
 
+// The first stage split in two, so that a tile's first-stage inputs can be
+// loaded (eng_load0) while the previous tile is still being transformed, and
+// transformed later (eng_stage0_regs: registers -> LDS, ends with a barrier).
+template <typename T, int L, int NT, int NL>
+struct Stage0Regs {
+    static constexpr int R = ct::prad(L, false, 0);
+    static constexpr int NB = L / R;
+    static constexpr int TOT = NL * NB;
+    static constexpr int U = (TOT + NT - 1) / NT;
+    cplx<T> v[U][R];
+};
+
+template <typename T, int L, int NT, int NL, int PR, class Ld>
+__device__ __forceinline__ void eng_load0(Stage0Regs<T, L, NT, NL> &s, int tid, const Ld &ld) {
+    using S = Stage0Regs<T, L, NT, NL>;
+    constexpr int RI = PR == 1 ? S::R / 2 : S::R;
+#pragma unroll
+    for (int u = 0; u < S::U; ++u) {
+        const int b = tid + u * NT;
+        if (b < S::TOT) {
+            const int line = b % NL, j = b / NL;
+#pragma unroll
+            for (int r = 0; r < RI; ++r) s.v[u][r] = ld(line, j + r * S::NB);
+        }
+    }
+}
+
+template <typename T, int L, int DIR, int NT, int NL, int PR>
+__device__ __forceinline__ void eng_stage0_regs(cplx<T> *lds, Stage0Regs<T, L, NT, NL> &s, int tid) {
+    using S = Stage0Regs<T, L, NT, NL>;
+    constexpr int P = ct::lds_pitch(L, NL);
+    static_assert(ct::nst(L) >= 2, "the split first stage needs a later stage");
+#pragma unroll
+    for (int u = 0; u < S::U; ++u) {
+        const int b = tid + u * NT;
+        if (b < S::TOT) {
+            const int line = b % NL, j = b / NL;
+            PDft<S::R, DIR, PR, cplx<T>>::run(s.v[u]);
+            const int sd = line * P + sw<L>(j * S::R);
+#pragma unroll
+            for (int r = 0; r < S::R; ++r) lds[sd + swc<L>(r)] = s.v[u][r];
+        }
+    }
+    __syncthreads();
+}
+
 template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int PR = 0, class Ld, class St>
 __device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL), PR>(lds, tw, tid, ld, st);

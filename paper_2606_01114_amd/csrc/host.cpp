@@ -158,7 +158,8 @@ struct mm_plan {
     ZGeom zg{};
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
-    int x_var = 0;                                  // tile-width variant of the specialised x pass
+    int x_var = 0;                                  // variant of the specialised x pass (0, 1: tile widths; 2: persistent)
+    int x_grid = 0;                                 // workgroups of the persistent x pass
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -282,12 +283,19 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     size_t lds;
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
-    if (getenv("MMX_XVAR")) p->x_var = atoi(getenv("MMX_XVAR")) ? 1 : 0;
+    if (getenv("MMX_XVAR")) p->x_var = std::min(2, std::max(0, atoi(getenv("MMX_XVAR"))));
     // the specialised kernels address one kz plane (Lx rows) through a buffer
     // resource, whose size is a 31-bit byte count
     p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax &&
               (int64_t)Lx * ny3 * (int64_t)csz < (int64_t(1) << 31) && !getenv("MMX_NO_CT");
-    if (p->x_ct) { W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz); }
+    if (p->x_ct) {
+        W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz);
+        int ncu = 0;
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
+        p->x_grid = ncu * (int)std::max<size_t>(1, std::min<size_t>(2, kLdsMax / std::max<size_t>(lds, 1)));
+    }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);
     f.in = p->S1; f.out = p->S2; f.tw = twc + ox;
@@ -411,12 +419,26 @@ int build_spectrum(mm_plan *p, const double *d_oct) {
     return rc;
 }
 
-// Switch the specialised x pass to tile-width variant v (descriptors, LDS).
+// one specialised x pass (dir -1 forward, +1 inverse) in the plan's variant
+template <typename T>
+hipError_t launch_x(mm_plan *p, int dir) {
+    const LinePass &a = dir < 0 ? p->lp_fwd : p->lp_inv;
+    return launch_line_ct<T>(a, dir < 0 ? p->tiles_fwd : p->tiles_inv, a.W, dir, p->stream, p->x_var == 2 ? p->x_grid : 0);
+}
+
+// Switch the specialised x pass to variant v (descriptors, LDS, persistent grid).
 int configure_x(mm_plan *p, int v) {
     const size_t csz = p->prec == MM_F32 ? sizeof(float2) : sizeof(double2);
     int W = 0, NT = 0;
     if (!p->x_ct || !line_ct_shape((int)p->L[0], csz, v, &W, &NT)) return MM_OK;
     p->x_var = v;
+    {
+        int dev = 0, cu = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
+        const size_t l = line_ct_lds((int)p->L[0], W, csz);
+        p->x_grid = cu * (int)std::max<size_t>(1, std::min<size_t>(2, kLdsMax / std::max<size_t>(l, 1)));
+    }
     for (LinePass *f : {&p->lp_fwd, &p->lp_inv}) {
         f->W = W;
         f->nthr = NT;
@@ -439,7 +461,7 @@ int autotune_x(mm_plan *p) {
     HIPCK(hipEventCreate(&e1));
     double best = 1e300;
     int bestv = p->x_var, rc = MM_OK;
-    for (int v = 0; v < 2 && !rc; ++v) {
+    for (int v = 0; v < 3 && !rc; ++v) {
         const size_t csz = sizeof(cplx<T>);
         int W = 0, NT = 0;
         if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT) || line_ct_lds((int)p->L[0], W, csz) > kLdsMax) continue;
@@ -448,8 +470,8 @@ int autotune_x(mm_plan *p) {
         for (int rep = 0; rep < 2 && !rc; ++rep) {
             (void)hipEventRecord(e0, p->stream);
             for (int k = 0; k < 3; ++k) {
-                hipError_t e = launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, W, -1, p->stream);
-                if (e == hipSuccess) e = launch_line_ct<T>(p->lp_inv, p->tiles_inv, W, +1, p->stream);
+                hipError_t e = launch_x<T>(p, -1);
+                if (e == hipSuccess) e = launch_x<T>(p, +1);
                 if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
             }
             (void)hipEventRecord(e1, p->stream);
@@ -492,11 +514,11 @@ int run_zfwd(mm_plan *p, int src, const void *srcp, const void *Ms, double Ms_s,
 
 template <typename T>
 int run_xyx(mm_plan *p) {
-    if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, p->lp_fwd.W, -1, p->stream));
+    if (p->x_ct) HIPCK(launch_x<T>(p, -1));
     else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
     if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
     else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
-    if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
+    if (p->x_ct) HIPCK(launch_x<T>(p, +1));
     else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
     return MM_OK;
 }
@@ -683,7 +705,7 @@ int time_one(mm_plan *p, int k) {
     switch (k) {
     case 0: return run_zfwd<T>(p, SRC_MS_M, p->ms[0], nullptr, 8e5);
     case 1:
-        if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_fwd, p->tiles_fwd, p->lp_fwd.W, -1, p->stream));
+        if (p->x_ct) HIPCK(launch_x<T>(p, -1));
         else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
         return MM_OK;
     case 2:
@@ -691,7 +713,7 @@ int time_one(mm_plan *p, int k) {
         else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
         return MM_OK;
     case 3:
-        if (p->x_ct) HIPCK(launch_line_ct<T>(p->lp_inv, p->tiles_inv, p->lp_inv.W, +1, p->stream));
+        if (p->x_ct) HIPCK(launch_x<T>(p, +1));
         else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
         return MM_OK;
     case 4: {
@@ -788,7 +810,7 @@ int mm_plan_info(const mm_plan *p, int64_t L[3], size_t *bytes, int tiles[5]) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     if (L) for (int a = 0; a < 3; ++a) L[a] = p->L[a];
     if (bytes) *bytes = p->bytes;
-    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->fp.W; tiles[3] = p->lp_inv.W; tiles[4] = p->zg.P; }
+    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->fp.W; tiles[3] = p->x_var; tiles[4] = p->zg.P; }
     return MM_OK;
 }
 
@@ -1155,6 +1177,8 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         mm_plan *p = nullptr;
         rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &o);
         if (!rc) b->plans.push_back(p);
+        // grouped launches use the narrow-tile x kernels
+        if (!rc && p->x_var != 0) rc = configure_x(p, 0);
     }
     std::vector<LinePass> lf, li;
     std::vector<FusedPass> fp;

@@ -230,3 +230,36 @@ def test_gradient_c5_against_fd():
         err = np.abs(g - fd).max() / scale
         _say("c5", prec, "max err / max|g| = %.3e" % err)
         assert err <= tol, (prec, err)
+
+
+def test_x_pass_variants_against_oracle():
+    """Every variant of the specialised x pass (two tile widths and the
+    persistent kernel, selected with MMX_XVAR at plan creation) on a grid with
+    more x tiles than the persistent grid holds and a ragged last tile, FP32
+    and FP64, against the oracle's h_eff and one RK4 step."""
+    import os
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    n = (64, 500, 16)
+    oct_ = oracle.tensor_octant(n, D)
+    L = tuple(oracle.default_L(v) for v in n)
+    m0 = synth.random_unit(n, 17)
+    _say("x variants: oracle h_eff", n, L)
+    ref = oracle.h_eff(m0, MS, A, D, oct_, L)
+    old = os.environ.get("MMX_XVAR")
+    try:
+        for prec, var, tol in (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-9)):
+            _say("x variant", prec, var)
+            os.environ["MMX_XVAR"] = str(var)
+            dt = torch.float32 if prec == "f32" else torch.float64
+            plan = DemagPlan(n, D, prec)
+            h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
+            e = rel_l2(h.cpu().numpy(), ref)
+            _say("  rel-L2", e)
+            assert e <= tol, (prec, var, e)
+            plan.close()
+    finally:
+        if old is None:
+            os.environ.pop("MMX_XVAR", None)
+        else:
+            os.environ["MMX_XVAR"] = old
