@@ -42,9 +42,9 @@ PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
 # kernel-name patterns of each pass (specialised first, runtime-planned second)
 KERNEL_PATTERNS = {
     "z_fwd": [r"k_zfwd_ct<float", r"k_zfwd<float"],
-    "x_fwd": [r"k_line_ct<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
+    "x_fwd": [r"k_line_(ct|pp)<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
     "y_fused": [r"k_fused_y_ct<float", r"k_fused_y<float"],
-    "x_inv": [r"k_line_ct<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
+    "x_inv": [r"k_line_(ct|pp)<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
     "z_inv_stage": [r"k_zinv_ct<float, \d+, 1>", r"k_zinv<float, 1>"],
     "z_inv_heff": [r"k_zinv_ct<float, \d+, 0>", r"k_zinv<float, 0>"],
 }
