@@ -389,7 +389,7 @@ def main():
         "pass_GBps": {k: pb[k] / (res["passes"][k] * 1e-3) / 1e9 for k in pb},
         "padded_L": list(res["L"]),
         "tiles": {"z_cols": res["tiles"][0], "x_cols": res["tiles"][1], "y_pencils": res["tiles"][2],
-                  "x_variant": res["tiles"][3]},
+                  "x_variant_fwd": res["tiles"][3], "x_variant_inv": res["tiles"][4]},
         "finite": res["finite"],
     }
     try:

@@ -97,50 +97,150 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
     if (OUT) __syncthreads();
 }
 
-// The first stage split in two, so that a tile's first-stage inputs can be
-// loaded (eng_load0) while the previous tile is still being transformed, and
-// transformed later (eng_stage0_regs: registers -> LDS, ends with a barrier).
-template <typename T, int L, int NT, int NL>
-struct Stage0Regs {
-    static constexpr int R = ct::prad(L, false, 0);
+// ---- register-resident transform with half-line LDS exchanges -------------
+// Every thread keeps its values in registers from the first stage to the
+// last; between two stages the values cross through an LDS buffer that holds
+// only half of each line: first the positions in the lower half of the line
+// (written by the butterflies that produce them, read by every butterfly of
+// the next stage for its inputs r < R/2), then the upper half.  The tile
+// needs half the LDS of eng_fft, at the price of two more barriers per
+// exchange.  Butterfly b maps to line = b % NL, j = b / NL.
+template <int L, int S> struct HxStage {
+    static constexpr int R = ct::prad(L, false, S);
+    static constexpr int Ns = ct::pns(L, false, S);
     static constexpr int NB = L / R;
-    static constexpr int TOT = NL * NB;
-    static constexpr int U = (TOT + NT - 1) / NT;
-    cplx<T> v[U][R];
+    static constexpr int TWO = ct::ptw(L, false, S);
 };
 
-template <typename T, int L, int NT, int NL, int PR, class Ld>
-__device__ __forceinline__ void eng_load0(Stage0Regs<T, L, NT, NL> &s, int tid, const Ld &ld) {
-    using S = Stage0Regs<T, L, NT, NL>;
-    constexpr int RI = PR == 1 ? S::R / 2 : S::R;
+template <int L, int NL> constexpr int hx_pitch() { return ct::lds_pitch(L / 2, NL); }
+
+// twiddles and the radix-R DFT of stage S on registers
+template <typename T, int L, int S, int DIR, int NT, int NL, int PR, int U, int R>
+__device__ __forceinline__ void hx_compute(cplx<T> (&v)[U][R], const cplx<T> *__restrict__ tw, int tid) {
+    using C = cplx<T>;
+    using St = HxStage<L, S>;
+    static_assert(St::R == R, "stage shape");
 #pragma unroll
-    for (int u = 0; u < S::U; ++u) {
+    for (int u = 0; u < U; ++u) {
         const int b = tid + u * NT;
-        if (b < S::TOT) {
-            const int line = b % NL, j = b / NL;
+        if (b < NL * St::NB) {
+            const int j = b / NL;
+            if (St::Ns > 1) {
+                const C *tt = tw + St::TWO + (j % St::Ns) * (R - 1);
 #pragma unroll
-            for (int r = 0; r < RI; ++r) s.v[u][r] = ld(line, j + r * S::NB);
+                for (int r = 1; r < R; ++r) {
+                    C w = tt[r - 1];
+                    if (DIR > 0) w = cconj(w);
+                    v[u][r] = cmul(v[u][r], w);
+                }
+            }
+            PDft<R, DIR, PR, C>::run(v[u]);
         }
     }
 }
 
-template <typename T, int L, int DIR, int NT, int NL, int PR>
-__device__ __forceinline__ void eng_stage0_regs(cplx<T> *lds, Stage0Regs<T, L, NT, NL> &s, int tid) {
-    using S = Stage0Regs<T, L, NT, NL>;
-    constexpr int P = ct::lds_pitch(L, NL);
-    static_assert(ct::nst(L) >= 2, "the split first stage needs a later stage");
+// outputs o of stage S (not the last) -> inputs v of stage S+1
+template <typename T, int L, int S, int NT, int NL, int UO, int RO, int UI, int RI>
+__device__ __forceinline__ void hx_exchange(cplx<T> *lds, const cplx<T> (&o)[UO][RO], cplx<T> (&v)[UI][RI], int tid) {
+    using A = HxStage<L, S>;
+    using B = HxStage<L, S + 1>;
+    constexpr int PH = hx_pitch<L, NL>();
+    static_assert(A::Ns * A::R <= L / 2, "a stage before the last writes whole blocks of one half");
 #pragma unroll
-    for (int u = 0; u < S::U; ++u) {
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int u = 0; u < UO; ++u) {
+            const int b = tid + u * NT;
+            if (b < NL * A::NB) {
+                const int line = b % NL, j = b / NL;
+                if ((j >= A::NB / 2) == (h == 1)) {
+                    const int d = (j / A::Ns) * A::Ns * A::R + (j % A::Ns) - h * (L / 2);
+                    const int base = line * PH + sw<L>(d);
+#pragma unroll
+                    for (int r = 0; r < RO; ++r) lds[base + swc<L>(r * A::Ns)] = o[u][r];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < UI; ++u) {
+            const int b = tid + u * NT;
+            if (b < NL * B::NB) {
+                const int line = b % NL, j = b / NL;
+                const int base = line * PH + sw<L>(j);
+#pragma unroll
+                for (int r = 0; r < RI / 2; ++r) v[u][h * (RI / 2) + r] = lds[base + swc<L>(r * B::NB)];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// stages S .. NS-1 on registers v (stage S's inputs); the last stage hands
+// its outputs to the storer.  PRL: pruning of the last stage.
+template <typename T, int L, int S, int DIR, int NT, int NL, int PRL, int U, int R, class St>
+__device__ __forceinline__ void hx_run(cplx<T> *lds, cplx<T> (&v)[U][R], const cplx<T> *__restrict__ tw, int tid,
+                                       const St &st) {
+    constexpr int NS = ct::nst(L);
+    using A = HxStage<L, S>;
+    hx_compute<T, L, S, DIR, NT, NL, S == NS - 1 ? PRL : 0>(v, tw, tid);
+    if constexpr (S == NS - 1) {
+        constexpr int RO = PRL == 2 ? R / 2 : R;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = tid + u * NT;
+            if (b < NL * A::NB) {
+                const int line = b % NL, j = b / NL;
+                const int d = (j / A::Ns) * A::Ns * R + (j % A::Ns);
+#pragma unroll
+                for (int r = 0; r < RO; ++r) st(line, d + r * A::Ns, v[u][r]);
+            }
+        }
+    } else {
+        using B = HxStage<L, S + 1>;
+        constexpr int UI = (NL * B::NB + NT - 1) / NT;
+        cplx<T> w[UI][B::R];
+        hx_exchange<T, L, S, NT, NL>(lds, v, w, tid);
+        hx_run<T, L, S + 1, DIR, NT, NL, PRL>(lds, w, tw, tid, st);
+    }
+}
+
+// Full transform: loader -> registers -> (half-line LDS exchanges) -> storer.
+// PRUNE as for eng_fft.  Needs two or more stages.
+template <typename T, int L, int DIR, int NT, int NL, int PRUNE, class Ld, class St>
+__device__ __forceinline__ void eng_fft_hx(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld,
+                                           const St &st) {
+    static_assert(ct::nst(L) >= 2, "two or more stages");
+    using A = HxStage<L, 0>;
+    constexpr int U = (NL * A::NB + NT - 1) / NT;
+    constexpr int RI = (PRUNE & 1) ? A::R / 2 : A::R;
+    cplx<T> v[U][A::R];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
         const int b = tid + u * NT;
-        if (b < S::TOT) {
+        if (b < NL * A::NB) {
             const int line = b % NL, j = b / NL;
-            PDft<S::R, DIR, PR, cplx<T>>::run(s.v[u]);
-            const int sd = line * P + sw<L>(j * S::R);
 #pragma unroll
-            for (int r = 0; r < S::R; ++r) lds[sd + swc<L>(r)] = s.v[u][r];
+            for (int r = 0; r < RI; ++r) v[u][r] = ld(line, j + r * A::NB);
         }
     }
-    __syncthreads();
+    // the first stage's pruning is applied in hx_compute through PR below
+    using C = cplx<T>;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int b = tid + u * NT;
+        if (b < NL * A::NB) PDft<A::R, DIR, (PRUNE & 1) ? 1 : 0, C>::run(v[u]);
+    }
+    constexpr int NS = ct::nst(L);
+    if constexpr (NS == 1) {
+        static_assert(NS >= 2, "two or more stages");
+    } else {
+        using B = HxStage<L, 1>;
+        constexpr int UI = (NL * B::NB + NT - 1) / NT;
+        C w[UI][B::R];
+        hx_exchange<T, L, 0, NT, NL>(lds, v, w, tid);
+        hx_run<T, L, 1, DIR, NT, NL, (PRUNE & 2) ? 2 : 0>(lds, w, tw, tid, st);
+    }
 }
 
 template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int PR = 0, class Ld, class St>

@@ -158,8 +158,7 @@ struct mm_plan {
     ZGeom zg{};
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
-    int x_var = 0;                                  // variant of the specialised x pass (0, 1: tile widths; 2: persistent)
-    int x_grid = 0;                                 // workgroups of the persistent x pass
+    int x_var[2] = {0, 0};                          // variants of the forward / inverse x pass (0, 1: tile widths; 2: half-LDS)
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -283,19 +282,12 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     size_t lds;
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
-    if (getenv("MMX_XVAR")) p->x_var = std::min(2, std::max(0, atoi(getenv("MMX_XVAR"))));
+    if (getenv("MMX_XVAR")) p->x_var[0] = p->x_var[1] = std::min(2, std::max(0, atoi(getenv("MMX_XVAR"))));
     // the specialised kernels address one kz plane (Lx rows) through a buffer
     // resource, whose size is a 31-bit byte count
-    p->x_ct = line_ct_shape(Lx, csz, p->x_var, &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax &&
+    p->x_ct = line_ct_shape(Lx, csz, p->x_var[0], &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax &&
               (int64_t)Lx * ny3 * (int64_t)csz < (int64_t(1) << 31) && !getenv("MMX_NO_CT");
-    if (p->x_ct) {
-        W = Wct; nthr = NTct; lds = line_ct_lds(Lx, W, csz);
-        int ncu = 0;
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0) ncu = 256;
-        p->x_grid = ncu * (int)std::max<size_t>(1, std::min<size_t>(2, kLdsMax / std::max<size_t>(lds, 1)));
-    }
+    if (p->x_ct) { W = Wct; nthr = NTct; lds = p->x_var[0] == 2 ? line_hx_lds(Lx, W, csz) : line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);
     f.in = p->S1; f.out = p->S2; f.tw = twc + ox;
@@ -423,66 +415,69 @@ int build_spectrum(mm_plan *p, const double *d_oct) {
 template <typename T>
 hipError_t launch_x(mm_plan *p, int dir) {
     const LinePass &a = dir < 0 ? p->lp_fwd : p->lp_inv;
-    return launch_line_ct<T>(a, dir < 0 ? p->tiles_fwd : p->tiles_inv, a.W, dir, p->stream, p->x_var == 2 ? p->x_grid : 0);
+    const int v = p->x_var[dir < 0 ? 0 : 1];
+    return launch_line_ct<T>(a, dir < 0 ? p->tiles_fwd : p->tiles_inv, a.W, dir, p->stream, v == 2 ? 1 : 0);
 }
 
-// Switch the specialised x pass to variant v (descriptors, LDS, persistent grid).
-int configure_x(mm_plan *p, int v) {
+// Switch the forward (d = 0) or inverse (d = 1) specialised x pass to
+// variant v (descriptor, LDS).
+int configure_x(mm_plan *p, int d, int v) {
     const size_t csz = p->prec == MM_F32 ? sizeof(float2) : sizeof(double2);
     int W = 0, NT = 0;
     if (!p->x_ct || !line_ct_shape((int)p->L[0], csz, v, &W, &NT)) return MM_OK;
-    p->x_var = v;
-    {
-        int dev = 0, cu = 0;
-        (void)hipGetDevice(&dev);
-        if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu <= 0) cu = 256;
-        const size_t l = line_ct_lds((int)p->L[0], W, csz);
-        p->x_grid = cu * (int)std::max<size_t>(1, std::min<size_t>(2, kLdsMax / std::max<size_t>(l, 1)));
-    }
-    for (LinePass *f : {&p->lp_fwd, &p->lp_inv}) {
-        f->W = W;
-        f->nthr = NT;
-        f->tiles_inner = (f->inner + W - 1) / W;
-    }
-    p->lds_fwd = p->lds_inv = line_ct_lds((int)p->L[0], W, csz);
-    p->tiles_fwd = p->tiles_inv = p->lp_fwd.tiles_inner * p->lp_fwd.outer;
+    p->x_var[d] = v;
+    LinePass *f = d == 0 ? &p->lp_fwd : &p->lp_inv;
+    f->W = W;
+    f->nthr = NT;
+    f->tiles_inner = (f->inner + W - 1) / W;
+    const size_t lds = v == 2 ? line_hx_lds((int)p->L[0], W, csz) : line_ct_lds((int)p->L[0], W, csz);
+    (d == 0 ? p->lds_fwd : p->lds_inv) = lds;
+    (d == 0 ? p->tiles_fwd : p->tiles_inv) = f->tiles_inner * f->outer;
     LinePass two[2] = {p->lp_fwd, p->lp_inv};
     HIPCK(hipMemcpy(p->d_lp, two, sizeof two, hipMemcpyHostToDevice));
     return MM_OK;
 }
 
-// Autotuner: time each tile-width variant of the x passes on this plan's own
-// buffers and keep the fastest.
+int configure_x(mm_plan *p, int v) {
+    int rc = configure_x(p, 0, v);
+    return rc ? rc : configure_x(p, 1, v);
+}
+
+// Autotuner: time each variant of the forward and of the inverse x pass on
+// this plan's own buffers and keep the fastest of each.
 template <typename T>
 int autotune_x(mm_plan *p) {
     if (!p->x_ct) return MM_OK;
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
-    double best = 1e300;
-    int bestv = p->x_var, rc = MM_OK;
-    for (int v = 0; v < 3 && !rc; ++v) {
-        const size_t csz = sizeof(cplx<T>);
-        int W = 0, NT = 0;
-        if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT) || line_ct_lds((int)p->L[0], W, csz) > kLdsMax) continue;
-        if ((rc = configure_x(p, v))) break;
-        float ms = 0.f;
-        for (int rep = 0; rep < 2 && !rc; ++rep) {
-            (void)hipEventRecord(e0, p->stream);
-            for (int k = 0; k < 3; ++k) {
-                hipError_t e = launch_x<T>(p, -1);
-                if (e == hipSuccess) e = launch_x<T>(p, +1);
-                if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
+    int rc = MM_OK;
+    for (int d = 0; d < 2 && !rc; ++d) {
+        const int dir = d == 0 ? -1 : +1;
+        double best = 1e300;
+        int bestv = p->x_var[d];
+        for (int v = 0; v < 3 && !rc; ++v) {
+            const size_t csz = sizeof(cplx<T>);
+            int W = 0, NT = 0;
+            if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT) || line_ct_lds((int)p->L[0], W, csz) > kLdsMax) continue;
+            if ((rc = configure_x(p, d, v))) break;
+            float ms = 0.f;
+            for (int rep = 0; rep < 2 && !rc; ++rep) {
+                (void)hipEventRecord(e0, p->stream);
+                for (int k = 0; k < 3; ++k) {
+                    hipError_t e = launch_x<T>(p, dir);
+                    if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
+                }
+                (void)hipEventRecord(e1, p->stream);
+                (void)hipEventSynchronize(e1);
+                (void)hipEventElapsedTime(&ms, e0, e1);
             }
-            (void)hipEventRecord(e1, p->stream);
-            (void)hipEventSynchronize(e1);
-            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (!rc && ms < best) { best = ms; bestv = v; }
         }
-        if (!rc && ms < best) { best = ms; bestv = v; }
+        if (!rc) rc = configure_x(p, d, bestv);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (!rc) rc = configure_x(p, bestv);
     return rc;
 }
 
@@ -810,7 +805,7 @@ int mm_plan_info(const mm_plan *p, int64_t L[3], size_t *bytes, int tiles[5]) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     if (L) for (int a = 0; a < 3; ++a) L[a] = p->L[a];
     if (bytes) *bytes = p->bytes;
-    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->fp.W; tiles[3] = p->x_var; tiles[4] = p->zg.P; }
+    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->fp.W; tiles[3] = p->x_var[0]; tiles[4] = p->x_var[1]; }
     return MM_OK;
 }
 
@@ -1178,7 +1173,7 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &o);
         if (!rc) b->plans.push_back(p);
         // grouped launches use the narrow-tile x kernels
-        if (!rc && p->x_var != 0) rc = configure_x(p, 0);
+        if (!rc && (p->x_var[0] != 0 || p->x_var[1] != 0)) rc = configure_x(p, 0);
     }
     std::vector<LinePass> lf, li;
     std::vector<FusedPass> fp;

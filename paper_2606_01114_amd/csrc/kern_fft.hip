@@ -129,61 +129,28 @@ __global__ void __launch_bounds__(NT) k_line_ct_b(const LinePass *__restrict__ d
     line_ct_body<T, L, DIR, NT, W>(descs[e.x], e.y);
 }
 
-// Persistent x pass: a few workgroups per CU walk the tiles of their XCD's
-// contiguous share of the grid (so the two tiles that share a cache line run
-// on one XCD at about the same time).  While a tile's later stages run, the
-// first-stage inputs of the workgroup's next tile are already in flight.
+// x pass with register-resident lines and half-line LDS exchanges: the same
+// tiles as k_line_ct at half the LDS, so two workgroups share a CU and one's
+// global loads and stores overlap the other's exchanges and arithmetic.
 template <typename T, int L, int DIR, int NT, int W>
-__global__ void __launch_bounds__(NT) k_line_pp(const LinePass a, int tiles) {
+__global__ void __launch_bounds__(NT) k_line_hx(const LinePass a) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
-    constexpr int NS = ct::nst(L);
-    constexpr int PR0 = DIR < 0 ? 1 : 0;   // forward: input rows n_in <= L/2
-    constexpr int PRL = DIR < 0 ? 0 : 2;   // inverse: output rows n_out <= L/2
-    const int tid = threadIdx.x;
-    // X groups of workgroups (one per XCD when there are at least 8); group x
-    // owns a contiguous run of tiles and its gq workgroups stride through it
-    const int G = gridDim.x, b = blockIdx.x;
-    const int X = G < 8 ? G : 8;
-    const int x = b % X, q = b / X, gq = (G - x + X - 1) / X;
-    const int qX = tiles / X, rX = tiles % X;
-    const int start = x * qX + min(x, rX), size = qX + (x < rX ? 1 : 0);
+    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int o = tile / a.tiles_inner;
+    const int c0 = (tile - o * a.tiles_inner) * W;
+    const int wc = min(W, a.inner - c0);
     const uint32_t ir = (uint32_t)a.in_row * sizeof(C), orow = (uint32_t)a.out_row * sizeof(C);
-    const C *tw = reinterpret_cast<const C *>(a.tw);
-    auto in_rsrc = [&](int tile) {
-        const int o = tile / a.tiles_inner, c0 = (tile - o * a.tiles_inner) * W;
-        const C *in = reinterpret_cast<const C *>(a.in) + (int64_t)o * a.in_outer + c0;
-        return make_rsrc(in, (uint32_t)(a.n_in - 1) * ir + (uint32_t)(a.inner - c0) * sizeof(C));
+    const C *in = reinterpret_cast<const C *>(a.in) + (int64_t)o * a.in_outer + c0;
+    C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
+    const BufRsrc ri = make_rsrc(in, (uint32_t)(a.n_in - 1) * ir + (uint32_t)(a.inner - c0) * sizeof(C));
+    const BufRsrc ro = make_rsrc(out, (uint32_t)(a.n_out - 1) * orow + (uint32_t)(a.inner - c0) * sizeof(C));
+    auto ld = [&](int line, int pos) -> C { return buf_load<C>(ri, (uint32_t)pos * ir + (uint32_t)line * sizeof(C)); };
+    auto st = [&](int line, int pos, C v) {
+        buf_store(ro, (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff), v);
     };
-    Stage0Regs<T, L, NT, W> s0;
-    if (q < size) {
-        const BufRsrc ri = in_rsrc(start + q);
-        eng_load0<T, L, NT, W, PR0>(s0, tid, [&](int line, int pos) -> C {
-            return buf_load<C>(ri, (uint32_t)pos * ir + (uint32_t)line * sizeof(C));
-        });
-    }
-    for (int li = q; li < size; li += gq) {
-        const int tile = start + li;
-        const int o = tile / a.tiles_inner, c0 = (tile - o * a.tiles_inner) * W;
-        const int wc = min(W, a.inner - c0);
-        C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
-        const BufRsrc ro = make_rsrc(out, (uint32_t)(a.n_out - 1) * orow + (uint32_t)(a.inner - c0) * sizeof(C));
-        if (li != q) __syncthreads();   // the previous tile's last stage has read LDS
-        eng_stage0_regs<T, L, DIR, NT, W, PR0>(lds, s0, tid);
-        if (li + gq < size) {
-            const BufRsrc ri = in_rsrc(tile + gq);
-            eng_load0<T, L, NT, W, PR0>(s0, tid, [&](int line, int pos) -> C {
-                return buf_load<C>(ri, (uint32_t)pos * ir + (uint32_t)line * sizeof(C));
-            });
-        }
-        eng_mid<T, L, false, 1, NS - 1, DIR, NT, W>(lds, tw, tid);
-        auto nold = [](int, int) { return C(); };
-        auto st = [&](int line, int pos, C v) {
-            buf_store(ro, (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff), v);
-        };
-        eng_stage<T, L, false, NS - 1, DIR, NT, W, 1, 0, PRL>(lds, tw, tid, nold, st);
-    }
+    eng_fft_hx<T, L, DIR, NT, W, DIR < 0 ? 1 : 2>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
 }
 
 // ---------------- fused y pass -------------------------------------------
@@ -539,7 +506,7 @@ static int line_ct_w(int L, bool f32, int variant) {
     case 4096: w = f32 ? 2 : 1; break;
     default: return 0;
     }
-    return variant ? 2 * w : w;   // variant 2 (persistent) has variant 1's tiles
+    return variant ? 2 * w : w;   // variant 2 (half-LDS kernel) has variant 1's tiles
 }
 
 int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT) {
@@ -552,18 +519,18 @@ int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT) {
 
 #define LINE_CASE(LL, WW)                                                                                             \
     if (a.f.L == LL && W == WW) {                                                                                     \
-        if (grid > 0 && ct::nst(LL) >= 2) {                                                                           \
-            const int g = grid < tiles ? grid : tiles;                                                                \
-            if (dir < 0) hipLaunchKernelGGL((k_line_pp<T, LL, -1, (WW * LL / 16), WW>), dim3(g), dim3(WW * LL / 16), lds, s, a, tiles); \
-            else hipLaunchKernelGGL((k_line_pp<T, LL, +1, (WW * LL / 16), WW>), dim3(g), dim3(WW * LL / 16), lds, s, a, tiles);       \
+        if (half && ct::nst(LL) >= 2) {                                                                               \
+            const size_t lh = line_hx_lds(LL, WW, sizeof(cplx<T>));                                                   \
+            if (dir < 0) hipLaunchKernelGGL((k_line_hx<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lh, s, a); \
+            else hipLaunchKernelGGL((k_line_hx<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lh, s, a);       \
         } else if (dir < 0) hipLaunchKernelGGL((k_line_ct<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a); \
         else hipLaunchKernelGGL((k_line_ct<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a);       \
         return hipGetLastError();                                                                                     \
     }
 
-// grid > 0: the persistent kernel with that many workgroups
+// half != 0: the half-LDS kernel (k_line_hx)
 template <typename T>
-hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int grid) {
+hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int half) {
     if (tiles <= 0) return hipSuccess;
     const size_t lds = line_ct_lds(a.f.L, W, sizeof(cplx<T>));
     if constexpr (sizeof(T) == 4) {
@@ -580,6 +547,7 @@ hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStrea
 #undef LINE_CASE
 
 size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W) * csz; }
+size_t line_hx_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L / 2, W) * csz; }
 size_t fused_ct_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L, 3) * csz; }
 
 int fused_ct_threads(int L, size_t csz) {

@@ -17,9 +17,10 @@ hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles
 int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT);
 int fused_ct_threads(int L, size_t csz);
 size_t line_ct_lds(int L, int W, size_t csz);
+size_t line_hx_lds(int L, int W, size_t csz);
 size_t fused_ct_lds(int L, size_t csz);
-// grid > 0 launches the persistent variant with that many workgroups
-template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int grid = 0);
+// half != 0 launches the half-LDS variant (k_line_hx)
+template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int half = 0);
 template <typename T> hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s);
 template <typename T> hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s);
 template <typename T> hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s);
