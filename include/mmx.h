@@ -98,6 +98,10 @@ int mm_plan_opts_default(mm_plan_opts *opts);
  *   opts       nullable
  * Synchronises the stream before returning.  The plan owns its device memory
  * (tensor spectrum, FFT workspace, twiddles) until mm_plan_destroy.
+ * Returns MM_ENOTSUP when one padded y line of three components does not fit
+ * a workgroup's 160 KiB of LDS: Ly <= 4096 for power-of-two Ly and
+ * 3 (Ly+1) complex values otherwise, i.e. at most 6826 (FP32) or 3412 (FP64)
+ * for other 7-smooth lengths, and at most 2048 for power-of-two Ly in FP64.
  */
 int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3], int precision,
                       void *hip_stream, const mm_plan_opts *opts);

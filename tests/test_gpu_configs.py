@@ -263,3 +263,43 @@ def test_x_pass_variants_against_oracle():
             os.environ.pop("MMX_XVAR", None)
         else:
             os.environ["MMX_XVAR"] = old
+
+
+@pytest.mark.parametrize("n", [(2048, 6, 2), (6, 2048, 2), (3, 4, 1024), (1000, 5, 3)])
+def test_longest_specialised_lengths(n):
+    """The longest compile-time transforms (x and y length 4096, z length
+    2048: x tiles of one or two columns, the 768-thread fused y pencil, the
+    1024-point folded z line) and a long non-power-of-two x line (runtime
+    planned), FP32 and FP64, h_eff and one RK4 step against the oracle."""
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    oct_ = oracle.tensor_octant(n, D)
+    L = tuple(oracle.default_L(v) for v in n)
+    m0 = synth.random_unit(n, 23)
+    Ms = synth.ms_field(n, 24)
+    _say("long lengths", n, L)
+    ref_h = oracle.h_eff(m0, Ms, A, D, oct_, L)
+    ref_s = oracle.rk4_step(m0, Ms, A, D, oct_, L, ALPHA, GAMMA, DT)
+    for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        if prec == "f64" and L[1] == 4096:
+            # a 4096-long FP64 pencil of three components exceeds the LDS
+            from paper_2606_01114_amd._lib import MM_ENOTSUP, MMError
+            with pytest.raises(MMError) as ei:
+                DemagPlan(n, D, prec)
+            assert ei.value.code == MM_ENOTSUP
+            continue
+        plan = DemagPlan(n, D, prec)
+        assert tuple(plan.info()["L"]) == L
+        mr = rounded(m0, dt)
+        Msr = to_dev(rounded(Ms, dt), dt)
+        h = plan.h_eff(to_dev(mr, dt), Msr, A)
+        e = rel_l2(h.cpu().numpy(), ref_h)
+        _say("  ", prec, "h_eff rel-L2", e)
+        assert e <= tol, (prec, e)
+        m = to_dev(mr, dt)
+        plan.llg_step(m, Msr, A, ALPHA, GAMMA, DT)
+        e = rel_l2(m.cpu().numpy() - m0, ref_s - m0)
+        _say("  ", prec, "step rel-L2", e)
+        assert e <= tol, (prec, e)
+        plan.close()
