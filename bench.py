@@ -43,7 +43,7 @@ PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
 KERNEL_PATTERNS = {
     "z_fwd": [r"k_zfwd_ct<float", r"k_zfwd<float"],
     "x_fwd": [r"k_line_(ct|pp)<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
-    "y_fused": [r"k_fused_y_ct<float", r"k_fused_y<float"],
+    "y_fused": [r"k_fused_y_(ct|hx)<float", r"k_fused_y<float"],
     "x_inv": [r"k_line_(ct|pp)<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
     "z_inv_stage": [r"k_zinv_ct<float, \d+, 1>", r"k_zinv<float, 1>"],
     "z_inv_heff": [r"k_zinv_ct<float, \d+, 0>", r"k_zinv<float, 0>"],
@@ -388,7 +388,8 @@ def main():
         "pass_ms": res["passes"],
         "pass_GBps": {k: pb[k] / (res["passes"][k] * 1e-3) / 1e9 for k in pb},
         "padded_L": list(res["L"]),
-        "tiles": {"z_cols": res["tiles"][0], "x_cols": res["tiles"][1], "y_pencils": res["tiles"][2],
+        "tiles": {"z_cols": res["tiles"][0], "x_cols": res["tiles"][1], "y_pencils": abs(res["tiles"][2]),
+                  "y_register_resident": res["tiles"][2] < 0,
                   "x_variant_fwd": res["tiles"][3], "x_variant_inv": res["tiles"][4]},
         "finite": res["finite"],
     }

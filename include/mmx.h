@@ -111,8 +111,9 @@ int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
 
 /* Padded lengths, device bytes held, and the launch shapes in use (each
  * nullable): tiles = {z cell columns per tile, forward x columns per tile,
- * y pencils per tile, forward x variant, inverse x variant}; x variants
- * 0 and 1 are two tile widths, 2 the half-LDS kernel with variant 1's tiles. */
+ * y pencils per tile (negated when the register-resident pencil kernel runs
+ * the y pass), forward x variant, inverse x variant}; x variants 0 and 1 are
+ * two tile widths, 2 the half-LDS kernel with variant 1's tiles. */
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 
 /*

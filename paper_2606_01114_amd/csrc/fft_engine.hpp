@@ -105,20 +105,20 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
 // the next stage for its inputs r < R/2), then the upper half.  The tile
 // needs half the LDS of eng_fft, at the price of two more barriers per
 // exchange.  Butterfly b maps to line = b % NL, j = b / NL.
-template <int L, int S> struct HxStage {
-    static constexpr int R = ct::prad(L, false, S);
-    static constexpr int Ns = ct::pns(L, false, S);
+template <int L, bool REV, int S> struct HxStage {
+    static constexpr int R = ct::prad(L, REV, S);
+    static constexpr int Ns = ct::pns(L, REV, S);
     static constexpr int NB = L / R;
-    static constexpr int TWO = ct::ptw(L, false, S);
+    static constexpr int TWO = ct::ptw(L, REV, S);
 };
 
 template <int L, int NL> constexpr int hx_pitch() { return ct::lds_pitch(L / 2, NL); }
 
-// twiddles and the radix-R DFT of stage S on registers
-template <typename T, int L, int S, int DIR, int NT, int NL, int PR, int U, int R>
+// twiddles and the radix-R DFT of stage S (order REV, table tw) on registers
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int PR, int U, int R>
 __device__ __forceinline__ void hx_compute(cplx<T> (&v)[U][R], const cplx<T> *__restrict__ tw, int tid) {
     using C = cplx<T>;
-    using St = HxStage<L, S>;
+    using St = HxStage<L, REV, S>;
     static_assert(St::R == R, "stage shape");
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -139,39 +139,54 @@ __device__ __forceinline__ void hx_compute(cplx<T> (&v)[U][R], const cplx<T> *__
     }
 }
 
-// outputs o of stage S (not the last) -> inputs v of stage S+1
-template <typename T, int L, int S, int NT, int NL, int UO, int RO, int UI, int RI>
-__device__ __forceinline__ void hx_exchange(cplx<T> *lds, const cplx<T> (&o)[UO][RO], cplx<T> (&v)[UI][RI], int tid) {
-    using A = HxStage<L, S>;
-    using B = HxStage<L, S + 1>;
+// Half-line exchange, writer side: the outputs o of stage S (order REV, not
+// the last stage) whose block lies in half h.
+template <typename T, int L, bool REV, int S, int NT, int NL, int UO, int RO>
+__device__ __forceinline__ void hx_put(cplx<T> *lds, const cplx<T> (&o)[UO][RO], int h, int tid) {
+    using A = HxStage<L, REV, S>;
     constexpr int PH = hx_pitch<L, NL>();
     static_assert(A::Ns * A::R <= L / 2, "a stage before the last writes whole blocks of one half");
 #pragma unroll
+    for (int u = 0; u < UO; ++u) {
+        const int b = tid + u * NT;
+        if (b < NL * A::NB) {
+            const int line = b % NL, j = b / NL;
+            if ((j >= A::NB / 2) == (h == 1)) {
+                const int d = (j / A::Ns) * A::Ns * A::R + (j % A::Ns) - h * (L / 2);
+                const int base = line * PH + sw<L>(d);
+#pragma unroll
+                for (int r = 0; r < RO; ++r) lds[base + swc<L>(r * A::Ns)] = o[u][r];
+            }
+        }
+    }
+}
+
+// Half-line exchange, reader side: the inputs r of half h of stage S
+// (order REV) for every butterfly of this thread.
+template <typename T, int L, bool REV, int S, int NT, int NL, int UI, int RI>
+__device__ __forceinline__ void hx_get(const cplx<T> *lds, cplx<T> (&v)[UI][RI], int h, int tid) {
+    using B = HxStage<L, REV, S>;
+    constexpr int PH = hx_pitch<L, NL>();
+#pragma unroll
+    for (int u = 0; u < UI; ++u) {
+        const int b = tid + u * NT;
+        if (b < NL * B::NB) {
+            const int line = b % NL, j = b / NL;
+            const int base = line * PH + sw<L>(j);
+#pragma unroll
+            for (int r = 0; r < RI / 2; ++r) v[u][h * (RI / 2) + r] = lds[base + swc<L>(r * B::NB)];
+        }
+    }
+}
+
+// outputs o of stage S (not the last) -> inputs v of stage S+1, same order
+template <typename T, int L, bool REV, int S, int NT, int NL, int UO, int RO, int UI, int RI>
+__device__ __forceinline__ void hx_exchange(cplx<T> *lds, const cplx<T> (&o)[UO][RO], cplx<T> (&v)[UI][RI], int tid) {
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
-#pragma unroll
-        for (int u = 0; u < UO; ++u) {
-            const int b = tid + u * NT;
-            if (b < NL * A::NB) {
-                const int line = b % NL, j = b / NL;
-                if ((j >= A::NB / 2) == (h == 1)) {
-                    const int d = (j / A::Ns) * A::Ns * A::R + (j % A::Ns) - h * (L / 2);
-                    const int base = line * PH + sw<L>(d);
-#pragma unroll
-                    for (int r = 0; r < RO; ++r) lds[base + swc<L>(r * A::Ns)] = o[u][r];
-                }
-            }
-        }
+        hx_put<T, L, REV, S, NT, NL>(lds, o, h, tid);
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < UI; ++u) {
-            const int b = tid + u * NT;
-            if (b < NL * B::NB) {
-                const int line = b % NL, j = b / NL;
-                const int base = line * PH + sw<L>(j);
-#pragma unroll
-                for (int r = 0; r < RI / 2; ++r) v[u][h * (RI / 2) + r] = lds[base + swc<L>(r * B::NB)];
-            }
-        }
+        hx_get<T, L, REV, S + 1, NT, NL>(lds, v, h, tid);
         __syncthreads();
     }
 }
@@ -182,8 +197,8 @@ template <typename T, int L, int S, int DIR, int NT, int NL, int PRL, int U, int
 __device__ __forceinline__ void hx_run(cplx<T> *lds, cplx<T> (&v)[U][R], const cplx<T> *__restrict__ tw, int tid,
                                        const St &st) {
     constexpr int NS = ct::nst(L);
-    using A = HxStage<L, S>;
-    hx_compute<T, L, S, DIR, NT, NL, S == NS - 1 ? PRL : 0>(v, tw, tid);
+    using A = HxStage<L, false, S>;
+    hx_compute<T, L, false, S, DIR, NT, NL, S == NS - 1 ? PRL : 0>(v, tw, tid);
     if constexpr (S == NS - 1) {
         constexpr int RO = PRL == 2 ? R / 2 : R;
 #pragma unroll
@@ -197,10 +212,10 @@ __device__ __forceinline__ void hx_run(cplx<T> *lds, cplx<T> (&v)[U][R], const c
             }
         }
     } else {
-        using B = HxStage<L, S + 1>;
+        using B = HxStage<L, false, S + 1>;
         constexpr int UI = (NL * B::NB + NT - 1) / NT;
         cplx<T> w[UI][B::R];
-        hx_exchange<T, L, S, NT, NL>(lds, v, w, tid);
+        hx_exchange<T, L, false, S, NT, NL>(lds, v, w, tid);
         hx_run<T, L, S + 1, DIR, NT, NL, PRL>(lds, w, tw, tid, st);
     }
 }
@@ -211,7 +226,7 @@ template <typename T, int L, int DIR, int NT, int NL, int PRUNE, class Ld, class
 __device__ __forceinline__ void eng_fft_hx(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld,
                                            const St &st) {
     static_assert(ct::nst(L) >= 2, "two or more stages");
-    using A = HxStage<L, 0>;
+    using A = HxStage<L, false, 0>;
     constexpr int U = (NL * A::NB + NT - 1) / NT;
     constexpr int RI = (PRUNE & 1) ? A::R / 2 : A::R;
     cplx<T> v[U][A::R];
@@ -235,10 +250,10 @@ __device__ __forceinline__ void eng_fft_hx(cplx<T> *lds, const cplx<T> *__restri
     if constexpr (NS == 1) {
         static_assert(NS >= 2, "two or more stages");
     } else {
-        using B = HxStage<L, 1>;
+        using B = HxStage<L, false, 1>;
         constexpr int UI = (NL * B::NB + NT - 1) / NT;
         C w[UI][B::R];
-        hx_exchange<T, L, 0, NT, NL>(lds, v, w, tid);
+        hx_exchange<T, L, false, 0, NT, NL>(lds, v, w, tid);
         hx_run<T, L, 1, DIR, NT, NL, (PRUNE & 2) ? 2 : 0>(lds, w, tw, tid, st);
     }
 }

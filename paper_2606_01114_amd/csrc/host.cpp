@@ -158,6 +158,7 @@ struct mm_plan {
     ZGeom zg{};
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
+    int y_var = 0;                                   // specialised y pass: 0 LDS-resident pencil, 1 register-resident
     int x_var[2] = {0, 0};                          // variants of the forward / inverse x pass (0, 1: tile widths; 2: half-LDS)
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
@@ -312,6 +313,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
         if (w <= std::max(1, npen) && (size_t)3 * w * py * csz <= kLdsTarget && fft_threads(p->fy.d, 3 * w, 3 * w * Ly) <= 1024) { Wp = w; break; }
     }
     p->y_ct = fused_ct_threads(Ly, csz) > 0 && fused_ct_lds(Ly, csz) <= kLdsMax && !getenv("MMX_NO_CT");
+    if (p->y_ct && getenv("MMX_YVAR") && atoi(getenv("MMX_YVAR")) == 1 && fused_hx_threads(Ly) > 0) p->y_var = 1;
     if (p->y_ct) Wp = 1;
     q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy;
     q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;
@@ -419,6 +421,43 @@ hipError_t launch_x(mm_plan *p, int dir) {
     return launch_line_ct<T>(a, dir < 0 ? p->tiles_fwd : p->tiles_inv, a.W, dir, p->stream, v == 2 ? 1 : 0);
 }
 
+// the specialised fused y pass in the plan's variant
+template <typename T>
+hipError_t launch_y(mm_plan *p) {
+    return p->y_var == 1 ? launch_fused_hx<T>(p->fp, p->stream) : launch_fused_ct<T>(p->fp, p->stream);
+}
+
+// Autotuner for the fused y pass: the LDS-resident and the register-resident
+// pencil kernels, timed on this plan's buffers.
+template <typename T>
+int autotune_y(mm_plan *p) {
+    if (!p->y_ct || fused_hx_threads((int)p->L[1]) <= 0) return MM_OK;
+    hipEvent_t e0, e1;
+    HIPCK(hipEventCreate(&e0));
+    HIPCK(hipEventCreate(&e1));
+    int rc = MM_OK, best_v = p->y_var;
+    double best = 1e300;
+    for (int v = 0; v < 2 && !rc; ++v) {
+        p->y_var = v;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && !rc; ++rep) {
+            (void)hipEventRecord(e0, p->stream);
+            for (int k = 0; k < 3; ++k) {
+                hipError_t e = launch_y<T>(p);
+                if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
+            }
+            (void)hipEventRecord(e1, p->stream);
+            (void)hipEventSynchronize(e1);
+            (void)hipEventElapsedTime(&ms, e0, e1);
+        }
+        if (!rc && ms < best) { best = ms; best_v = v; }
+    }
+    p->y_var = best_v;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 // Switch the forward (d = 0) or inverse (d = 1) specialised x pass to
 // variant v (descriptor, LDS).
 int configure_x(mm_plan *p, int d, int v) {
@@ -511,7 +550,7 @@ template <typename T>
 int run_xyx(mm_plan *p) {
     if (p->x_ct) HIPCK(launch_x<T>(p, -1));
     else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
-    if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
+    if (p->y_ct) HIPCK(launch_y<T>(p));
     else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
     if (p->x_ct) HIPCK(launch_x<T>(p, +1));
     else HIPCK(launch_line_pass<T>(p->d_lp + 1, nullptr, p->tiles_inv, p->lp_inv.nthr, p->lds_inv, +1, false, p->stream));
@@ -704,7 +743,7 @@ int time_one(mm_plan *p, int k) {
         else HIPCK(launch_line_pass<T>(p->d_lp, nullptr, p->tiles_fwd, p->lp_fwd.nthr, p->lds_fwd, -1, false, p->stream));
         return MM_OK;
     case 2:
-        if (p->y_ct) HIPCK(launch_fused_ct<T>(p->fp, p->stream));
+        if (p->y_ct) HIPCK(launch_y<T>(p));
         else HIPCK(launch_fused_y<T>(p->d_fp, nullptr, p->fp.tiles, p->fp.nthr, p->lds_fp, p->stream));
         return MM_OK;
     case 3:
@@ -776,6 +815,7 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     rc = precision == MM_F32 ? setup_plan<float>(p, &o) : setup_plan<double>(p, &o);
     if (!rc) rc = compute_tensor(p);
     if (!rc && o.autotune) rc = precision == MM_F32 ? autotune_x<float>(p) : autotune_x<double>(p);
+    if (!rc && o.autotune) rc = precision == MM_F32 ? autotune_y<float>(p) : autotune_y<double>(p);
     if (rc) {
         std::string keep = g_last;
         free_all(p);
@@ -805,7 +845,7 @@ int mm_plan_info(const mm_plan *p, int64_t L[3], size_t *bytes, int tiles[5]) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     if (L) for (int a = 0; a < 3; ++a) L[a] = p->L[a];
     if (bytes) *bytes = p->bytes;
-    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->fp.W; tiles[3] = p->x_var[0]; tiles[4] = p->x_var[1]; }
+    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->y_var == 1 ? -p->fp.W : p->fp.W; tiles[3] = p->x_var[0]; tiles[4] = p->x_var[1]; }
     return MM_OK;
 }
 
@@ -1174,6 +1214,7 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         if (!rc) b->plans.push_back(p);
         // grouped launches use the narrow-tile x kernels
         if (!rc && (p->x_var[0] != 0 || p->x_var[1] != 0)) rc = configure_x(p, 0);
+        if (!rc) p->y_var = 0;
     }
     std::vector<LinePass> lf, li;
     std::vector<FusedPass> fp;

@@ -459,6 +459,170 @@ __device__ __forceinline__ void fused_ct_body(const FusedPass &a, int p) {
     eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0, 2>(lds, twr, tid, nold, st);
 }
 
+// ---- fused y pass with register-resident pencils ---------------------------
+// The pencil's values stay in registers from the first forward stage to the
+// last inverse stage; the stages exchange them through an LDS buffer of half
+// a line per component (lower half of the positions first, then the upper
+// half), so a workgroup needs half the LDS of k_fused_y_ct and more pencils
+// share a CU.  The middle (last forward stage, tensor product, first inverse
+// stage) runs on triples: one thread holds all three components of its ky.
+template <int L, int NT> struct FusedHx {
+    static constexpr int NS = ct::nst(L);
+    static constexpr int RC = ct::prad(L, false, NS - 1);
+    static constexpr int NBC = L / RC;
+    static constexpr int UC = (NBC + NT - 1) / NT;
+    static constexpr int PH = hx_pitch<L, 3>();
+};
+
+// forward stage S's outputs v -> ... -> the middle's inputs vc
+template <typename T, int L, int NT, int S, int U, int R>
+__device__ __forceinline__ void fhx_forward(cplx<T> *lds, cplx<T> (&v)[U][R],
+                                            cplx<T> (&vc)[FusedHx<L, NT>::UC][3][FusedHx<L, NT>::RC],
+                                            const cplx<T> *__restrict__ tw, int tid) {
+    using F = FusedHx<L, NT>;
+    if constexpr (S + 1 == F::NS - 1) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            hx_put<T, L, false, S, NT, 3>(lds, v, h, tid);
+            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < F::UC; ++u) {
+                const int j = tid + u * NT;
+                if (j < F::NBC) {
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        const int base = c * F::PH + sw<L>(j);
+#pragma unroll
+                        for (int r = 0; r < F::RC / 2; ++r) vc[u][c][h * (F::RC / 2) + r] = lds[base + swc<L>(r * F::NBC)];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        using B = HxStage<L, false, S + 1>;
+        constexpr int UI = (3 * B::NB + NT - 1) / NT;
+        cplx<T> w[UI][B::R];
+        hx_exchange<T, L, false, S, NT, 3>(lds, v, w, tid);
+        hx_compute<T, L, false, S + 1, -1, NT, 3, 0>(w, tw, tid);
+        fhx_forward<T, L, NT, S + 1>(lds, w, vc, tw, tid);
+    }
+}
+
+// inverse stage S (reversed order) from its inputs v; the last stage stores
+// the rows below L/2 (rows at or past n are dropped by the resource)
+template <typename T, int L, int NT, int S, int U, int R>
+__device__ __forceinline__ void fhx_inverse(cplx<T> *lds, cplx<T> (&v)[U][R], const cplx<T> *__restrict__ twr,
+                                            int tid, BufRsrc rp) {
+    using C = cplx<T>;
+    constexpr int NS = ct::nst(L);
+    constexpr bool LAST = S == NS - 1;
+    hx_compute<T, L, true, S, +1, NT, 3, LAST ? 2 : 0>(v, twr, tid);
+    if constexpr (LAST) {
+        using A = HxStage<L, true, S>;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = tid + u * NT;
+            if (b < 3 * A::NB) {
+                const int line = b % 3, j = b / 3;
+                const int d = (j / A::Ns) * A::Ns * R + (j % A::Ns);
+#pragma unroll
+                for (int r = 0; r < R / 2; ++r) buf_store(rp, (uint32_t)((d + r * A::Ns) * 3 + line) * sizeof(C), v[u][r]);
+            }
+        }
+    } else {
+        using B = HxStage<L, true, S + 1>;
+        constexpr int UI = (3 * B::NB + NT - 1) / NT;
+        C w[UI][B::R];
+        hx_exchange<T, L, true, S, NT, 3>(lds, v, w, tid);
+        fhx_inverse<T, L, NT, S + 1>(lds, w, twr, tid, rp);
+    }
+}
+
+template <typename T, int L, int NT>
+__device__ __forceinline__ void fused_hx_body(const FusedPass &a, int p) {
+    using C = cplx<T>;
+    using F = FusedHx<L, NT>;
+    static_assert(F::NS >= 2, "fused pencil needs two or more radix stages");
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int tid = threadIdx.x;
+    const int n = a.n;
+    const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+    C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
+    const BufRsrc rp = make_rsrc(pen, (uint32_t)(3 * n) * sizeof(C));
+    const PencilProduct<T, L> pr = pencil_product<T, L>(a, kz, kx);
+    const C *tw = reinterpret_cast<const C *>(a.tw);
+    const C *twr = tw + (L - 1);
+    // forward stage 0 straight from the pencil (rows past L/2 are padding)
+    using A0 = HxStage<L, false, 0>;
+    constexpr int U0 = (3 * A0::NB + NT - 1) / NT;
+    C v0[U0][A0::R];
+#pragma unroll
+    for (int u = 0; u < U0; ++u) {
+        const int b = tid + u * NT;
+        if (b < 3 * A0::NB) {
+            const int line = b % 3, j = b / 3;
+#pragma unroll
+            for (int r = 0; r < A0::R / 2; ++r) v0[u][r] = buf_load<C>(rp, (uint32_t)((j + r * A0::NB) * 3 + line) * sizeof(C));
+            PDft<A0::R, -1, 1, C>::run(v0[u]);
+        }
+    }
+    C vc[F::UC][3][F::RC];
+    fhx_forward<T, L, NT, 0>(lds, v0, vc, tw, tid);
+    // middle: last forward stage, 3x3 product, first inverse stage
+    constexpr int Nsf = ct::pns(L, false, F::NS - 1);
+    constexpr int TWM = ct::ptw(L, false, F::NS - 1);
+#pragma unroll
+    for (int u = 0; u < F::UC; ++u) {
+        const int j = tid + u * NT;
+        if (j < F::NBC) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                if (Nsf > 1) {
+                    const C *tt = tw + TWM + (j % Nsf) * (F::RC - 1);
+#pragma unroll
+                    for (int r = 1; r < F::RC; ++r) vc[u][c][r] = cmul(vc[u][c][r], tt[r - 1]);
+                }
+                Dft<F::RC, -1, C>::run(vc[u][c]);
+            }
+#pragma unroll
+            for (int r = 0; r < F::RC; ++r) pr(j + r * F::NBC, vc[u][0][r], vc[u][1][r], vc[u][2][r]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Dft<F::RC, +1, C>::run(vc[u][c]);
+        }
+    }
+    // middle -> inverse stage 1 (outputs of the first inverse stage sit at
+    // j RC + r: one block of RC per triple, in one half of the line)
+    using B1 = HxStage<L, true, 1>;
+    constexpr int U1 = (3 * B1::NB + NT - 1) / NT;
+    C w1[U1][B1::R];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int u = 0; u < F::UC; ++u) {
+            const int j = tid + u * NT;
+            if (j < F::NBC && (j >= F::NBC / 2) == (h == 1)) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const int base = c * F::PH + sw<L>(j * F::RC - h * (L / 2));
+#pragma unroll
+                    for (int r = 0; r < F::RC; ++r) lds[base + swc<L>(r)] = vc[u][c][r];
+                }
+            }
+        }
+        __syncthreads();
+        hx_get<T, L, true, 1, NT, 3>(lds, w1, h, tid);
+        __syncthreads();
+    }
+    fhx_inverse<T, L, NT, 1>(lds, w1, twr, tid, rp);
+}
+
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_hx(const FusedPass a) {
+    fused_hx_body<T, L, NT>(a, (int)xcd_tile(blockIdx.x, gridDim.x));
+}
+
 template <typename T, int L, int NT>
 __global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
     fused_ct_body<T, L, NT>(a, (int)xcd_tile(blockIdx.x, gridDim.x));
@@ -581,6 +745,37 @@ hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
 #undef FCASE
     return hipGetLastError();
 }
+
+// threads of the register-resident fused pass: one radix-16 butterfly per
+// thread and stage, rounded up to whole waves
+int fused_hx_threads(int L) {
+    switch (L) {
+    case 256: return 64;
+    case 512: return 128;
+    case 1024: return 192;
+    case 2048: return 384;
+    default: return 0;
+    }
+}
+size_t fused_hx_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L / 2, 3) * csz; }
+
+template <typename T>
+hipError_t launch_fused_hx(const FusedPass &a, hipStream_t s) {
+    if (a.npos <= 0) return hipSuccess;
+    const size_t lds = fused_hx_lds(a.f.L, sizeof(cplx<T>));
+#define HCASE(LL, NTT)                                                                                                \
+    case LL:                                                                                                          \
+        hipLaunchKernelGGL((k_fused_y_hx<T, LL, NTT>), dim3(a.npos), dim3(NTT), lds, s, a);                         \
+        break;
+    switch (a.f.L) {
+        HCASE(256, 64) HCASE(512, 128) HCASE(1024, 192) HCASE(2048, 384)
+    default: return hipErrorInvalidValue;
+    }
+#undef HCASE
+    return hipGetLastError();
+}
+template hipError_t launch_fused_hx<float>(const FusedPass &, hipStream_t);
+template hipError_t launch_fused_hx<double>(const FusedPass &, hipStream_t);
 
 // grouped launches of the specialised kernels (descriptor table + tile map;
 // every geometry in the group has the same transform length)

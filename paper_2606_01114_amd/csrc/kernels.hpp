@@ -18,6 +18,10 @@ int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT);
 int fused_ct_threads(int L, size_t csz);
 size_t line_ct_lds(int L, int W, size_t csz);
 size_t line_hx_lds(int L, int W, size_t csz);
+// register-resident fused y pass: threads (0 = no such kernel) and LDS bytes
+int fused_hx_threads(int L);
+size_t fused_hx_lds(int L, size_t csz);
+template <typename T> hipError_t launch_fused_hx(const FusedPass &a, hipStream_t s);
 size_t fused_ct_lds(int L, size_t csz);
 // half != 0 launches the half-LDS variant (k_line_hx)
 template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int half = 0);

@@ -303,3 +303,36 @@ def test_longest_specialised_lengths(n):
         _say("  ", prec, "step rel-L2", e)
         assert e <= tol, (prec, e)
         plan.close()
+
+
+@pytest.mark.parametrize("n", [(6, 128, 3), (5, 256, 2), (4, 512, 2), (3, 1024, 2)])
+def test_y_pass_variants_against_oracle(n):
+    """Both specialised y passes (the LDS-resident pencil and the
+    register-resident one with half-line exchanges, selected with MMX_YVAR at
+    plan creation) for every length the register-resident kernel has, FP32 and
+    FP64, against the oracle's h_eff."""
+    import os
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    oct_ = oracle.tensor_octant(n, D)
+    L = tuple(oracle.default_L(v) for v in n)
+    m0 = synth.random_unit(n, 29)
+    ref = oracle.h_eff(m0, MS, A, D, oct_, L)
+    old = os.environ.get("MMX_YVAR")
+    try:
+        for var in (0, 1):
+            os.environ["MMX_YVAR"] = str(var)
+            for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+                dt = torch.float32 if prec == "f32" else torch.float64
+                plan = DemagPlan(n, D, prec)
+                assert (plan.info()["tiles"][2] < 0) == (var == 1)
+                h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
+                e = rel_l2(h.cpu().numpy(), ref)
+                _say("y variant", var, prec, n, e)
+                assert e <= tol, (var, prec, e)
+                plan.close()
+    finally:
+        if old is None:
+            os.environ.pop("MMX_YVAR", None)
+        else:
+            os.environ["MMX_YVAR"] = old
