@@ -47,6 +47,7 @@ extern "C" {
 #define MM_EHIP (-3)        /* HIP runtime error (includes "no GPU")         */
 #define MM_ESTATE (-4)      /* call not valid in the plan's current state    */
 #define MM_ENOTSUP (-5)     /* valid request this build does not support     */
+#define MM_ENONFINITE (-6)  /* a synchronous result is not finite (NaN/Inf)  */
 
 /* precision of a plan: the type of m, h, Ms and of the FFT arithmetic */
 #define MM_F32 1
@@ -107,6 +108,42 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
                       void *hip_stream, const mm_plan_opts *opts);
 
 int mm_plan_destroy(mm_plan *plan);
+
+/*
+ * mm_plan_bytes -- device memory a plan for this grid needs (host only; no
+ * GPU call), so that the caller can own it (mm_plan_attach_memory).
+ *   grid[3], precision, opts  as for demag_tensor_init (the cell size does not
+ *              change the sizes)
+ *   tensor_bytes    receives the size of the tensor spectrum (real octant,
+ *              6 components, plan precision)
+ *   workspace_bytes receives the size of everything else the forward path
+ *              keeps: the two spectrum workspaces, the RK4 stage and
+ *              accumulator fields, twiddle tables, descriptors and energy
+ *              partials (sub-buffers start on 256-byte boundaries).
+ * The adjoint entry points' scratch (14 three-component fields) is not part
+ * of it: they allocate it on first use.
+ */
+int mm_plan_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts, size_t *tensor_bytes,
+                  size_t *workspace_bytes);
+
+/*
+ * mm_plan_attach_memory -- move the plan onto caller-owned device memory.
+ *   tensor_buf     device buffer of at least tensor_bytes (mm_plan_bytes for
+ *                  the plan's grid, precision and options), 256-byte aligned;
+ *                  receives the tensor spectrum
+ *   workspace_buf  device buffer of at least workspace_bytes, 256-byte aligned
+ * Synchronises the plan's stream, copies the spectrum into tensor_buf, frees
+ * the plan's own buffers (and any captured graph or adjoint scratch) and
+ * rebuilds the plan's tables in workspace_buf; the autotuned launch shapes
+ * are kept.  From then on the plan uses only these buffers (plus adjoint
+ * scratch, allocated on first use); the caller keeps them alive and
+ * untouched until mm_plan_destroy, which does not free them.  At most once
+ * per plan (MM_ESTATE otherwise).  The sizes cannot be checked: smaller
+ * buffers than mm_plan_bytes reports are undefined behaviour.  On an error
+ * after the copy the plan is left without a tensor and every later call
+ * returns MM_ESTATE.
+ */
+int mm_plan_attach_memory(mm_plan *plan, void *tensor_buf, void *workspace_buf);
 int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
 
 /* Padded lengths, device bytes held, and the launch shapes in use (each
@@ -126,7 +163,9 @@ int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int ti
  *   terms      MM_DEMAG | MM_EXCHANGE (non-zero)
  *   energy_out host double[2] or NULL: receives (E_demag, E_exchange) in J,
  *              E = -(mu0/2) V sum Ms m.h per term, accumulated in FP64 with a
- *              fixed-order reduction; non-NULL makes the call synchronous.
+ *              fixed-order reduction; non-NULL makes the call synchronous,
+ *              and a non-finite energy (from non-finite inputs) returns
+ *              MM_ENONFINITE after h_out and energy_out are written.
  */
 int h_eff(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A, void *h_out,
           unsigned terms, double *energy_out);

@@ -11,7 +11,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libmmx.so")
 
-MM_OK, MM_EINVAL, MM_ENOMEM, MM_EHIP, MM_ESTATE, MM_ENOTSUP = 0, -1, -2, -3, -4, -5
+MM_OK, MM_EINVAL, MM_ENOMEM, MM_EHIP, MM_ESTATE, MM_ENOTSUP, MM_ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 MM_F32, MM_F64 = 1, 2
 MM_DEMAG, MM_EXCHANGE = 1, 2
 MM_NO_RENORM, MM_NO_GRAPH = 1, 2
@@ -19,6 +19,7 @@ MM_NO_RENORM, MM_NO_GRAPH = 1, 2
 # Exported names (kept in sync with include/mmx.h; a CPU test checks both).
 EXPORTS = [
     "mm_plan_opts_default", "demag_tensor_init", "mm_plan_destroy", "mm_plan_set_stream", "mm_plan_info",
+    "mm_plan_bytes", "mm_plan_attach_memory",
     "h_eff", "llg_step", "h_eff_adjoint", "llg_step_adjoint",
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
     "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_info", "mm_batch_destroy",
@@ -53,6 +54,9 @@ def _load():
         "mm_plan_opts_default": [ctypes.POINTER(PlanOpts)],
         "demag_tensor_init": [ctypes.POINTER(vp), i64p, dp, ci, vp, ctypes.POINTER(PlanOpts)],
         "mm_plan_destroy": [vp],
+        "mm_plan_bytes": [i64p, ci, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_size_t),
+                          ctypes.POINTER(ctypes.c_size_t)],
+        "mm_plan_attach_memory": [vp, vp, vp],
         "mm_plan_set_stream": [vp, vp],
         "mm_plan_info": [vp, i64p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)],
         "h_eff": [vp, vp, vp, cd, cd, vp, cu, dp],

@@ -25,6 +25,26 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
+def _opts(far_radius=16.0, L=None, autotune=False):
+    opts = PlanOpts()
+    check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
+    opts.far_radius = float(far_radius)
+    if L is not None:
+        for a in range(3):
+            opts.L[a] = int(L[a])
+    opts.autotune = 1 if autotune else 0
+    return opts
+
+
+def plan_bytes(grid, precision="f32", far_radius=16.0, L=None):
+    """(tensor_bytes, workspace_bytes) of a plan for this grid (no GPU call)."""
+    opts = _opts(far_radius, L)
+    g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    t, w = ctypes.c_size_t(), ctypes.c_size_t()
+    check(_lib.lib().mm_plan_bytes(g, _prec(precision), ctypes.byref(opts), ctypes.byref(t), ctypes.byref(w)))
+    return t.value, w.value
+
+
 class DemagPlan:
     """One geometry: grid (nx,ny,nz), cell (dx,dy,dz) in metres, FP32 or FP64.
     Creating it computes the Newell tensor spectrum on the GPU (FP64)."""
@@ -34,13 +54,9 @@ class DemagPlan:
         self.cell = tuple(float(v) for v in cell)
         self.prec = _prec(precision)
         self.dtype = _DT[self.prec]
-        opts = PlanOpts()
-        check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
-        opts.far_radius = float(far_radius)
-        if L is not None:
-            for a in range(3):
-                opts.L[a] = int(L[a])
-        opts.autotune = 1 if autotune else 0
+        self._far, self._L = float(far_radius), L
+        self._attached = None
+        opts = _opts(far_radius, L, autotune)
         g = (ctypes.c_int64 * 3)(*self.grid)
         c = (ctypes.c_double * 3)(*self.cell)
         self._h = ctypes.c_void_p()
@@ -66,6 +82,21 @@ class DemagPlan:
         check(_lib.lib().mm_plan_set_stream(self._h, _stream()))
 
     # -- API ------------------------------------------------------------------
+    def attach_memory(self):
+        """Move the plan's tensor spectrum and workspace into torch-owned
+        device buffers (torch's caching allocator then holds all of the
+        plan's forward memory); returns the two uint8 tensors, which the plan
+        keeps alive until close()."""
+        tb, wb = plan_bytes(self.grid, self.prec, self._far, self._L)
+        # 256-byte alignment: torch's CUDA allocator returns 512-byte aligned blocks
+        t = torch.empty(max(tb, 1), dtype=torch.uint8, device=self.device)
+        w = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.device)
+        self._sync_stream()
+        torch.cuda.current_stream().synchronize()
+        check(_lib.lib().mm_plan_attach_memory(self._h, _ptr(t), _ptr(w)))
+        self._attached = (t, w)
+        return t, w
+
     def info(self):
         L = (ctypes.c_int64 * 3)()
         b = ctypes.c_size_t()
@@ -139,8 +170,9 @@ class DemagPlan:
 
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
-            _lib.lib().mm_plan_destroy(self._h)
+            _lib.lib().mm_plan_destroy(self._h)   # synchronises the plan's stream
             self._h = ctypes.c_void_p()
+        self._attached = None
 
     def __del__(self):
         try:

@@ -168,11 +168,36 @@ struct mm_plan {
     std::vector<unsigned char> gkey;
     // adjoint scratch (allocated on first use)
     void *adj = nullptr;
+    // memory sizing and caller-owned memory: a dry plan only adds up sizes;
+    // with a workspace attached, allocations are carved from it and the tensor
+    // spectrum lives in the caller's tensor buffer
+    bool dry = false;
+    size_t ws_used = 0, tensor_bytes = 0;
+    char *ws = nullptr;
+    void *tensor_ext = nullptr;
 };
 
 namespace {
 
+int dalloc_own(mm_plan *p, void **out, size_t bytes);
+
+// plan memory: carved from the attached workspace, counted in a dry plan,
+// else allocated by the plan
 int dalloc(mm_plan *p, void **out, size_t bytes) {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (p->dry || p->ws) {
+        // sub-buffers of the workspace start on 256-byte boundaries
+        const size_t off = (p->ws_used + 255) & ~(size_t)255;
+        p->ws_used = off + bytes;
+        if (p->ws) *out = p->ws + off;
+        return MM_OK;
+    }
+    return dalloc_own(p, out, bytes);
+}
+
+// memory the plan allocates and frees itself
+int dalloc_own(mm_plan *p, void **out, size_t bytes) {
     *out = nullptr;
     if (bytes == 0) bytes = 256;
     if (getenv("MMX_TEST_FAIL_ALLOC")) return fail(MM_ENOMEM, "allocation of %zu bytes refused (MMX_TEST_FAIL_ALLOC)", bytes);
@@ -264,7 +289,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     }
     int rc;
     if ((rc = dalloc(p, &p->twT, std::max<size_t>(tw.size() * sizeof(T), 16)))) return rc;
-    HIPCK(hipMemcpy(p->twT, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+    if (!p->dry) HIPCK(hipMemcpy(p->twT, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
     const C *twc = reinterpret_cast<const C *>(p->twT);
     // workspace: S1 [kz][x][y][c] (kz < hz), S2 [kz][kx][y][c] (kx < Lx), tensor
     const int64_t npos = nx * ny;
@@ -273,7 +298,10 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     const size_t cells3 = (size_t)nx * ny * nz * 3 * sizeof(T);
     if ((rc = dalloc(p, &p->S1, s1))) return rc;
     if ((rc = dalloc(p, &p->S2, s2))) return rc;
-    if ((rc = dalloc(p, &p->tensor, tens))) return rc;
+    p->tensor_bytes = tens;
+    if (p->dry) p->tensor = nullptr;
+    else if (p->tensor_ext) p->tensor = p->tensor_ext;
+    else if ((rc = dalloc(p, &p->tensor, tens))) return rc;
     if ((rc = dalloc(p, &p->ms[0], cells3))) return rc;
     if ((rc = dalloc(p, &p->ms[1], cells3))) return rc;
     if ((rc = dalloc(p, &p->acc, cells3))) return rc;
@@ -347,14 +375,16 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     if ((rc = dalloc(p, (void **)&p->d_lp, 2 * sizeof(LinePass)))) return rc;
     if ((rc = dalloc(p, (void **)&p->d_fp, sizeof(FusedPass)))) return rc;
     LinePass two[2] = {p->lp_fwd, p->lp_inv};
-    HIPCK(hipMemcpy(p->d_lp, two, sizeof two, hipMemcpyHostToDevice));
-    HIPCK(hipMemcpy(p->d_fp, &p->fp, sizeof(FusedPass), hipMemcpyHostToDevice));
+    if (!p->dry) {
+        HIPCK(hipMemcpy(p->d_lp, two, sizeof two, hipMemcpyHostToDevice));
+        HIPCK(hipMemcpy(p->d_fp, &p->fp, sizeof(FusedPass), hipMemcpyHostToDevice));
+    }
     // FP64 twiddles for the tensor transforms
     std::vector<double> tw64;
     auto app64 = [&](const HostFft &h) { size_t off = tw64.size() / 2; auto v = round_tw<double>(h); tw64.insert(tw64.end(), v.begin(), v.end()); return off; };
     (void)app64(p->fx); (void)app64(p->fy); (void)app64(p->fz);
     if ((rc = dalloc(p, &p->tw64, std::max<size_t>(tw64.size() * sizeof(double), 16)))) return rc;
-    HIPCK(hipMemcpy(p->tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
+    if (!p->dry) HIPCK(hipMemcpy(p->tw64, tw64.data(), tw64.size() * sizeof(double), hipMemcpyHostToDevice));
     return MM_OK;
 }
 
@@ -574,7 +604,7 @@ void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double
 
 int check_plan(mm_plan *p) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
-    if (!p->tensor) return fail(MM_ESTATE, "plan has no tensor (demag_tensor_init did not complete)");
+    if (!p->tensor) return fail(MM_ESTATE, "plan has no tensor (demag_tensor_init or mm_plan_attach_memory did not complete)");
     return MM_OK;
 }
 
@@ -604,6 +634,7 @@ int heff_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, 
         const double V = p->d[0] * p->d[1] * p->d[2];
         E[0] = -0.5 * kMu0 * V * s[0];
         E[1] = -0.5 * kMu0 * V * s[1];
+        if (!std::isfinite(E[0]) || !std::isfinite(E[1])) return fail(MM_ENONFINITE, "energies are not finite (E_d=%g, E_ex=%g)", E[0], E[1]);
     }
     return MM_OK;
 }
@@ -693,7 +724,8 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
     const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
     const size_t f3 = (size_t)ncell * 3 * sizeof(T);
     int rc;
-    if (!p->adj && (rc = dalloc(p, &p->adj, 14 * f3))) return rc;
+    // not part of an attached workspace: allocated by the plan on first use
+    if (!p->adj && (rc = dalloc_own(p, &p->adj, 14 * f3))) return rc;
     T *base = (T *)p->adj;
     auto buf = [&](int i) { return (void *)(base + (size_t)i * ncell * 3); };
     void *srec[4] = {(void *)m, buf(0), buf(1), buf(2)};
@@ -780,10 +812,12 @@ int mm_plan_opts_default(mm_plan_opts *o) {
     return MM_OK;
 }
 
-int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3], int precision, void *hip_stream,
-                      const mm_plan_opts *opts) {
-    if (!out) return fail(MM_EINVAL, "out is NULL");
-    *out = nullptr;
+}  // extern "C"
+
+namespace {
+// argument checks and padded lengths shared by plan creation and sizing
+int plan_params(const int64_t grid[3], const double cell[3], int precision, const mm_plan_opts *opts,
+                mm_plan_opts *o_out, int64_t L[3]) {
     int rc = validate_grid(grid, cell);
     if (rc) return rc;
     if (precision != MM_F32 && precision != MM_F64) return fail(MM_EINVAL, "precision must be MM_F32 or MM_F64");
@@ -791,7 +825,6 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     mm_plan_opts_default(&o);
     if (opts) o = *opts;
     if (!std::isfinite(o.far_radius)) return fail(MM_EINVAL, "far_radius must be finite");
-    int64_t L[3];
     for (int a = 0; a < 3; ++a) {
         L[a] = o.L[a] > 0 ? o.L[a] : (o.pow2_padding ? pow2_L(grid[a]) : default_L(grid[a]));
         if (L[a] < 2 * grid[a] - 1 || !is_7smooth(L[a]))
@@ -802,6 +835,21 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     if (o.pow2_padding < 0 || o.pow2_padding > 1) return fail(MM_EINVAL, "pow2_padding must be 0 or 1");
     const int64_t ncell = grid[0] * grid[1] * grid[2];
     if (grid[0] * grid[1] > 0x7fffffffLL / 2 || ncell > (1LL << 34)) return fail(MM_ENOTSUP, "grid too large");
+    *o_out = o;
+    return MM_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3], int precision, void *hip_stream,
+                      const mm_plan_opts *opts) {
+    if (!out) return fail(MM_EINVAL, "out is NULL");
+    *out = nullptr;
+    mm_plan_opts o;
+    int64_t L[3];
+    int rc = plan_params(grid, cell, precision, opts, &o, L);
+    if (rc) return rc;
     int dev = 0;
     HIPCK(hipGetDevice(&dev));
     mm_plan *p = new (std::nothrow) mm_plan();
@@ -832,6 +880,53 @@ int mm_plan_destroy(mm_plan *p) {
     (void)hipStreamSynchronize(p->stream);
     free_all(p);
     delete p;
+    return MM_OK;
+}
+
+int mm_plan_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts, size_t *tensor_bytes,
+                  size_t *workspace_bytes) {
+    if (!tensor_bytes || !workspace_bytes) return fail(MM_EINVAL, "tensor_bytes and workspace_bytes must be non-NULL");
+    const double unit[3] = {1.0, 1.0, 1.0};   // sizes do not depend on the cell
+    mm_plan_opts o;
+    int64_t L[3];
+    int rc = plan_params(grid, unit, precision, opts, &o, L);
+    if (rc) return rc;
+    mm_plan q;
+    q.dry = true;
+    q.prec = precision;
+    q.rsz = precision == MM_F32 ? 4 : 8;
+    for (int a = 0; a < 3; ++a) { q.n[a] = grid[a]; q.d[a] = 1.0; q.L[a] = L[a]; }
+    rc = precision == MM_F32 ? setup_plan<float>(&q, &o) : setup_plan<double>(&q, &o);
+    if (rc) return rc;
+    *tensor_bytes = q.tensor_bytes;
+    *workspace_bytes = q.ws_used;
+    return MM_OK;
+}
+
+int mm_plan_attach_memory(mm_plan *p, void *tensor_buf, void *workspace_buf) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!tensor_buf || !workspace_buf) return fail(MM_EINVAL, "tensor_buf and workspace_buf must be non-NULL");
+    if (((uintptr_t)tensor_buf | (uintptr_t)workspace_buf) & 255) return fail(MM_EINVAL, "buffers must be 256-byte aligned");
+    if (p->ws) return fail(MM_ESTATE, "memory is already attached to this plan");
+    HIPCK(hipStreamSynchronize(p->stream));
+    // the tensor spectrum moves into the caller's buffer
+    HIPCK(hipMemcpy(tensor_buf, p->tensor, p->tensor_bytes, hipMemcpyDeviceToDevice));
+    const int xv0 = p->x_var[0], xv1 = p->x_var[1], yv = p->y_var;
+    free_all(p);   // the plan's own buffers, captured graph and adjoint scratch
+    p->bytes = 0;
+    p->adj = nullptr;
+    p->tensor = nullptr;
+    p->ws = static_cast<char *>(workspace_buf);
+    p->ws_used = 0;
+    p->tensor_ext = tensor_buf;
+    mm_plan_opts o;
+    mm_plan_opts_default(&o);
+    rc = p->prec == MM_F32 ? setup_plan<float>(p, &o) : setup_plan<double>(p, &o);
+    if (!rc) rc = configure_x(p, 0, xv0);
+    if (!rc) rc = configure_x(p, 1, xv1);
+    if (rc) { p->tensor = nullptr; return rc; }   // the plan is unusable (MM_ESTATE) from here
+    p->y_var = p->y_ct ? yv : 0;
     return MM_OK;
 }
 
@@ -999,6 +1094,7 @@ const char *mm_strerror(int s) {
     case MM_EHIP: return "HIP runtime error";
     case MM_ESTATE: return "invalid plan state";
     case MM_ENOTSUP: return "not supported";
+    case MM_ENONFINITE: return "non-finite result";
     default: return "unknown status";
     }
 }

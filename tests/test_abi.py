@@ -93,3 +93,50 @@ def test_no_gpu_is_a_hip_error():
     from paper_2606_01114_amd import _lib
     rc, h = _init((4, 4, 2), (1e-9, 1e-9, 1e-9), 1)
     assert rc == _lib.MM_EHIP and not h.value
+
+
+def test_strerror_nonfinite():
+    from paper_2606_01114_amd import _lib
+    assert _lib.lib().mm_strerror(_lib.MM_ENONFINITE) == b"non-finite result"
+
+
+def _bytes(grid, prec, opts=None):
+    from paper_2606_01114_amd import _lib
+    t, w = ctypes.c_size_t(), ctypes.c_size_t()
+    g = (ctypes.c_int64 * 3)(*grid)
+    rc = _lib.lib().mm_plan_bytes(g, prec, opts, ctypes.byref(t), ctypes.byref(w))
+    return rc, t.value, w.value
+
+
+def test_plan_bytes_host_only():
+    """mm_plan_bytes needs no GPU: the tensor octant and the forward
+    workspace of the 1024x1024x128 grid (padded 2048x2048x256)."""
+    from paper_2606_01114_amd import _lib
+    n, L = (1024, 1024, 128), (2048, 2048, 256)
+    hx, hy, hz = L[0] // 2 + 1, L[1] // 2 + 1, L[2] // 2 + 1
+    for prec, r in ((_lib.MM_F32, 4), (_lib.MM_F64, 8)):
+        rc, t, w = _bytes(n, prec)
+        assert rc == _lib.MM_OK
+        assert t == hx * hy * hz * 6 * r
+        c = 2 * r
+        s1 = hz * n[0] * n[1] * 3 * c
+        s2 = hz * L[0] * n[1] * 3 * c
+        cells3 = n[0] * n[1] * n[2] * 3 * r
+        big = s1 + s2 + 3 * cells3
+        assert big <= w <= big + (64 << 20), (w, big)
+    # explicit padding changes the sizes the same way plan creation does
+    o = _lib.PlanOpts()
+    _lib.lib().mm_plan_opts_default(ctypes.byref(o))
+    o.pow2_padding = 1
+    rc, t, _ = _bytes((48, 20, 3), _lib.MM_F32, ctypes.byref(o))
+    assert rc == 0 and t == (128 // 2 + 1) * (64 // 2 + 1) * (8 // 2 + 1) * 6 * 4
+    g = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert _lib.lib().mm_plan_bytes(g, 1, None, None, None) == _lib.MM_EINVAL
+    assert _bytes((0, 4, 4), 1)[0] == _lib.MM_EINVAL
+    assert _bytes((4, 4, 4), 5)[0] == _lib.MM_EINVAL
+
+
+def test_attach_on_null_plan():
+    from paper_2606_01114_amd import _lib
+    dummy = ctypes.c_void_p(256)
+    assert _lib.lib().mm_plan_attach_memory(None, dummy, dummy) == _lib.MM_EINVAL
