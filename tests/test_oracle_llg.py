@@ -64,3 +64,113 @@ def test_energy_decays_with_damping():
         m = oracle.rk4_step(m, MS, A, d, oct_, L, 0.5, GAMMA, 2e-14)
         es.append(E(m))
     assert all(b < a for a, b in zip(es, es[1:]))
+
+
+# ---- RKF45 pins ---------------------------------------------------------------
+def _trees(order):
+    """Rooted trees with `order` nodes, each as a sorted tuple of subtrees."""
+    if order == 1:
+        return [()]
+    out = set()
+
+    def parts(n, maxfirst):
+        # multisets of subtree sizes summing to n (non-increasing)
+        if n == 0:
+            yield []
+            return
+        for k in range(min(n, maxfirst), 0, -1):
+            for rest in parts(n - k, k):
+                yield [k] + rest
+
+    for sizes in parts(order - 1, order - 1):
+        combos = [[]]
+        for k in sizes:
+            combos = [c + [t] for c in combos for t in _trees(k)]
+        for c in combos:
+            out.add(tuple(sorted(c)))
+    return sorted(out)
+
+
+def _phi(tree, A, s):
+    """Elementary weight of stage s for a tree (sum over the stage matrix)."""
+    from fractions import Fraction
+    v = Fraction(1)
+    for sub in tree:
+        v *= sum((A[s][j] * _phi(sub, A, j) for j in range(len(A[s]))), Fraction(0))
+    return v
+
+
+def _density(tree):
+    n = 1 + sum(_size(t) for t in tree)
+    d = n
+    for t in tree:
+        d *= _density(t)
+    return d
+
+
+def _size(tree):
+    return 1 + sum(_size(t) for t in tree)
+
+
+def _satisfies(b, order):
+    from fractions import Fraction
+    A = oracle.RKF45_A
+    return all(sum(b[s] * _phi(t, A, s) for s in range(6)) == Fraction(1, _density(t))
+               for t in _trees(order))
+
+
+def test_rkf45_tableau_order_conditions_exact():
+    from fractions import Fraction
+    assert [len(_trees(k)) for k in range(1, 6)] == [1, 1, 2, 4, 9]
+    A, C = oracle.RKF45_A, oracle.RKF45_C
+    for s in range(6):
+        assert sum(A[s], Fraction(0)) == C[s]
+    for k in range(1, 6):
+        assert _satisfies(oracle.RKF45_B5, k), k
+    for k in range(1, 5):
+        assert _satisfies(oracle.RKF45_B4, k), k
+    assert not _satisfies(oracle.RKF45_B4, 5)
+
+
+def _ms_setup():
+    d = (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant((1, 1, 1), d)
+    th0, ph0, H = 1.0, 0.3, 2e5
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(1, 1, 1, 3)
+    return d, oct_, th0, ph0, H, m0
+
+
+def test_rkf45_local_orders_and_error_estimate():
+    """One step of the macrospin: y4's local error falls as dt^5, y5's as dt^6,
+    and err = |y5 - y4| matches y4's true local error."""
+    d, oct_, th0, ph0, H, m0 = _ms_setup()
+    heff = lambda s: oracle.h_eff(s, MS, A, d, oct_, (1, 1, 1), h_ext=(0, 0, H))
+    e4, e5, est = [], [], []
+    for dt in (3.2e-12, 1.6e-12, 8e-13):      # above the rounding floor of y5
+        ks = oracle.rkf45_stages(m0, heff, 0.1, GAMMA, dt)
+        y4 = m0 + dt * sum(float(b) * k for b, k in zip(oracle.RKF45_B4, ks))
+        y5 = m0 + dt * sum(float(b) * k for b, k in zip(oracle.RKF45_B5, ks))
+        ref = oracle.macrospin_closed_form(th0, ph0, H, 0.1, GAMMA, dt)
+        e4.append(np.abs(y4.reshape(3) - ref).max())
+        e5.append(np.abs(y5.reshape(3) - ref).max())
+        est.append(np.abs(y5 - y4).max())
+    for a, b in zip(e4, e4[1:]):
+        assert 24 < a / b < 40          # 2^5
+    for a, b in zip(e5, e5[1:]):
+        assert 48 < a / b < 80          # 2^6
+    for e, s in zip(e4, est):
+        assert 0.8 < s / e < 1.25
+
+
+def test_rkf45_adaptive_run_within_tolerance():
+    d, oct_, th0, ph0, H, m0 = _ms_setup()
+    T = 2e-10
+    for tol in (1e-6, 1e-8):
+        m, acc, rej = oracle.rkf45_run(m0, T, 1e-12, tol, MS, A, d, oct_, (1, 1, 1), 0.1, GAMMA,
+                                       h_ext=(0, 0, H))
+        ref = oracle.macrospin_closed_form(th0, ph0, H, 0.1, GAMMA, T)
+        assert np.abs(m.reshape(3) - ref).max() < 50 * tol
+        assert acc > 3
+    # a step far too long is rejected, leaves m unchanged and shrinks dt
+    m2, err, ok, dt2 = oracle.rkf45_step(m0, MS, A, d, oct_, (1, 1, 1), 0.1, GAMMA, 5e-11, 1e-8, h_ext=(0, 0, H))
+    assert not ok and np.array_equal(m2, m0) and dt2 == 0.2 * 5e-11 and err > 1e-8
