@@ -187,6 +187,31 @@ int llg_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A,
              double gamma, double dt, int n_steps, const double h_ext[3], unsigned flags);
 
 /*
+ * llg_rkf45_step -- one attempted step of eq. (1) with the Runge-Kutta-
+ * Fehlberg 4(5) method, the paper's integrator (section "Implementation":
+ * the step size follows from the maximum error over the whole grid).
+ *   m          device (nx,ny,nz,3); overwritten with the step's result only
+ *              when the step is accepted
+ *   Ms, Ms_scalar, A, alpha, gamma, h_ext  as in llg_step
+ *   dt         host double: in, the step to attempt (> 0); out, the next step
+ *              dt * min(5, max(0.2, 0.9 (tol/err)^(1/5))) (5 dt when err = 0),
+ *              after an accepted or a rejected attempt
+ *   tol        > 0: the step is accepted when err <= tol
+ *   flags      MM_NO_RENORM (else the accepted result is renormalised)
+ *   err_out    host double: err = max over cells and components of
+ *              |y5 - y4|, the difference of the fifth- and fourth-order
+ *              solutions (reduced on the device; a maximum is order-free)
+ *   accepted   host int: 1 if m was advanced by dt (to the fourth-order
+ *              solution, Fehlberg's pairing), else 0 (m unchanged)
+ * Synchronous (the host needs err to decide).  The six stage derivatives and
+ * the candidate are plan scratch (7 three-component fields), allocated on the
+ * first call.  A non-finite err returns MM_ENONFINITE with m unchanged.
+ */
+int llg_rkf45_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A, double alpha,
+                   double gamma, double *dt, double tol, const double h_ext[3], unsigned flags, double *err_out,
+                   int *accepted);
+
+/*
  * h_eff_adjoint -- vector-Jacobian product of h_eff (reverse-mode derivative
  * used for inverse problems, paper Introduction).  For the cotangent g_h:
  *   g_m  = Ms H_demag(g_h) + Lap(c g_h)          (c = 2A/(mu0 Ms))

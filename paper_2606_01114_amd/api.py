@@ -125,6 +125,36 @@ class DemagPlan:
                                   int(n_steps), he, flags))
         return m
 
+    def rkf45_step(self, m, Ms, A, alpha, gamma, dt, tol, h_ext=None, renorm=True):
+        """One attempted RKF45 step (in place on acceptance).  Returns
+        (accepted, err, dt_next)."""
+        self._vec(m, "m")
+        Mst, Mss = self._ms(Ms)
+        self._sync_stream()
+        he = (ctypes.c_double * 3)(*[float(v) for v in h_ext]) if h_ext is not None else None
+        d = ctypes.c_double(float(dt))
+        err = ctypes.c_double()
+        ok = ctypes.c_int()
+        check(_lib.lib().llg_rkf45_step(self._h, _ptr(m), _ptr(Mst), Mss, float(A), float(alpha), float(gamma),
+                                        ctypes.byref(d), float(tol), he, 0 if renorm else MM_NO_RENORM,
+                                        ctypes.byref(err), ctypes.byref(ok)))
+        return bool(ok.value), err.value, d.value
+
+    def rkf45_run(self, m, Ms, A, alpha, gamma, t_end, dt0, tol, h_ext=None, renorm=True, max_attempts=100000):
+        """Adaptive integration to t_end (the last step lands on it).
+        Returns (accepted steps, rejected attempts, last dt)."""
+        t, dt, acc, rej = 0.0, float(dt0), 0, 0
+        for _ in range(max_attempts):
+            if t >= t_end:
+                break
+            h = min(dt, t_end - t)
+            ok, _, dt = self.rkf45_step(m, Ms, A, alpha, gamma, h, tol, h_ext, renorm)
+            if ok:
+                t, acc = t + h, acc + 1
+            else:
+                rej += 1
+        return acc, rej, dt
+
     def h_eff_adjoint(self, m, Ms, A, g_h, terms=MM_DEMAG | MM_EXCHANGE, want_Ms=True):
         self._vec(m, "m")
         self._vec(g_h, "g_h")

@@ -168,6 +168,8 @@ struct mm_plan {
     std::vector<unsigned char> gkey;
     // adjoint scratch (allocated on first use)
     void *adj = nullptr;
+    // RKF45 stage derivatives (6 fields) and candidate solution (allocated on first use)
+    void *rk = nullptr;
     // memory sizing and caller-owned memory: a dry plan only adds up sizes;
     // with a workspace attached, allocations are carved from it and the tensor
     // spectrum lives in the caller's tensor buffer
@@ -765,6 +767,56 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
     return MM_OK;
 }
 
+// Fehlberg's 4(5) pair: stage matrix rows, fourth- and fifth-order weights
+const double kRkfA[6][5] = {{0, 0, 0, 0, 0},
+                            {1.0 / 4, 0, 0, 0, 0},
+                            {3.0 / 32, 9.0 / 32, 0, 0, 0},
+                            {1932.0 / 2197, -7200.0 / 2197, 7296.0 / 2197, 0, 0},
+                            {439.0 / 216, -8.0, 3680.0 / 513, -845.0 / 4104, 0},
+                            {-8.0 / 27, 2.0, -3544.0 / 2565, 1859.0 / 4104, -11.0 / 40}};
+const double kRkfB4[6] = {25.0 / 216, 0, 1408.0 / 2565, 2197.0 / 4104, -1.0 / 5, 0};
+const double kRkfB5[6] = {16.0 / 135, 0, 6656.0 / 12825, 28561.0 / 56430, -9.0 / 50, 2.0 / 55};
+
+// one attempted RKF45 step: six stages through the demag pipeline, the
+// fourth-order candidate in the plan's buffer, the max-norm error on the host
+template <typename T>
+int rkf45_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, double alpha, double gamma, double dt,
+               const double *hext, int renorm, double *err) {
+    const size_t f3 = (size_t)p->n[0] * p->n[1] * p->n[2] * 3 * sizeof(T);
+    int rc;
+    if (!p->rk && (rc = dalloc_own(p, &p->rk, 7 * f3))) return rc;
+    void *K = p->rk;
+    void *cand = static_cast<char *>(p->rk) + 6 * f3;
+    if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
+    for (int s = 0; s < 6; ++s) {
+        if ((rc = run_xyx<T>(p))) return rc;
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
+        if (hext) for (int i = 0; i < 3; ++i) a.hext[i] = hext[i];
+        a.tab_s = s;
+        a.tab_last = s == 5;
+        a.next_r2c = s < 5;
+        a.renorm = renorm;
+        a.dt = dt; a.alpha = alpha; a.gp = gamma / (1.0 + alpha * alpha);
+        a.ms_in = s == 0 ? m : p->ms[(s - 1) & 1];
+        a.m_n = m;
+        a.ms_out = s < 5 ? p->ms[s & 1] : nullptr;
+        a.K = K; a.kstride = (int64_t)p->n[0] * p->n[1] * p->n[2] * 3; a.cand = cand;
+        for (int j = 0; j <= s; ++j) {
+            if (s < 5) a.tab_a[j] = kRkfA[s + 1][j];
+            else { a.tab_a[j] = kRkfB4[j]; a.tab_e[j] = kRkfB5[j] - kRkfB4[j]; }
+        }
+        a.epart = p->epart;
+        HIPCK(zinv_any<T>(p, a, EPI_TAB));
+    }
+    HIPCK(launch_max_reduce(p->epart, p->zg.tiles, p->esum, p->stream));
+    double e = 0.0;
+    HIPCK(hipMemcpyAsync(&e, p->esum, sizeof e, hipMemcpyDeviceToHost, p->stream));
+    HIPCK(hipStreamSynchronize(p->stream));
+    *err = e;
+    return MM_OK;
+}
+
 // one launch of pass k on the plan's scratch arrays (timing only)
 template <typename T>
 int time_one(mm_plan *p, int k) {
@@ -916,6 +968,7 @@ int mm_plan_attach_memory(mm_plan *p, void *tensor_buf, void *workspace_buf) {
     free_all(p);   // the plan's own buffers, captured graph and adjoint scratch
     p->bytes = 0;
     p->adj = nullptr;
+    p->rk = nullptr;
     p->tensor = nullptr;
     p->ws = static_cast<char *>(workspace_buf);
     p->ws_used = 0;
@@ -1001,6 +1054,35 @@ int llg_step_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar
     if ((rc = check_llg(alpha, gamma, dt, h_ext))) return rc;
     return p->prec == MM_F32 ? llg_adjoint_impl<float>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms)
                              : llg_adjoint_impl<double>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms);
+}
+
+int llg_rkf45_step(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double A, double alpha, double gamma,
+                   double *dt, double tol, const double h_ext[3], unsigned flags, double *err_out, int *accepted) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m) return fail(MM_EINVAL, "m must be non-NULL");
+    if (!dt || !err_out || !accepted) return fail(MM_EINVAL, "dt, err_out and accepted must be non-NULL");
+    if (!(tol > 0.0) || !std::isfinite(tol)) return fail(MM_EINVAL, "tol must be finite and > 0");
+    if (flags & ~MM_NO_RENORM) return fail(MM_EINVAL, "unknown flags (RKF45 takes MM_NO_RENORM only)");
+    if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;
+    if ((rc = check_llg(alpha, gamma, *dt, h_ext))) return rc;
+    double err = 0.0;
+    rc = p->prec == MM_F32 ? rkf45_impl<float>(p, m, Ms, Ms_scalar, A, alpha, gamma, *dt, h_ext,
+                                                (flags & MM_NO_RENORM) ? 0 : 1, &err)
+                           : rkf45_impl<double>(p, m, Ms, Ms_scalar, A, alpha, gamma, *dt, h_ext,
+                                                 (flags & MM_NO_RENORM) ? 0 : 1, &err);
+    if (rc) return rc;
+    *err_out = err;
+    *accepted = 0;
+    if (!std::isfinite(err)) return fail(MM_ENONFINITE, "RKF45 error estimate is not finite");
+    if (err <= tol) {
+        const size_t f3 = (size_t)p->n[0] * p->n[1] * p->n[2] * 3 * p->rsz;
+        HIPCK(hipMemcpyAsync(m, static_cast<char *>(p->rk) + 6 * f3, f3, hipMemcpyDeviceToDevice, p->stream));
+        *accepted = 1;
+    }
+    const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(tol / err, 0.2)));
+    *dt *= fac;
+    return MM_OK;
 }
 
 int mm_demag_tensor_get(mm_plan *p, double *host) {

@@ -166,7 +166,7 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
             }
             T src[3];
             cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, src);
-            if (EPI == EPI_STAGE && a.next_r2c) {
+            if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
                     const int l = pl * 3 + c;
@@ -176,7 +176,8 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
         }
     }
     if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
-    if (EPI == EPI_STAGE && a.next_r2c) {
+    if (EPI == EPI_TAB && a.tab_last) block_max(ed, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
         // zero the padding rows and the unused half of an odd last line, then
         // transform the next stage's source along z
         if (tid < g.nthr) {
@@ -245,6 +246,7 @@ hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t
     switch (epi) {
     case EPI_HEFF: hipLaunchKernelGGL((k_zinv<T, EPI_HEFF>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     case EPI_STAGE: hipLaunchKernelGGL((k_zinv<T, EPI_STAGE>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    case EPI_TAB: hipLaunchKernelGGL((k_zinv<T, EPI_TAB>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     default: hipLaunchKernelGGL((k_zinv<T, EPI_ADJ>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     }
     return hipGetLastError();
@@ -278,6 +280,19 @@ template hipError_t launch_zfwd_batch<float>(const ZFwdArgs *, const int2 *, int
 template hipError_t launch_zfwd_batch<double>(const ZFwdArgs *, const int2 *, int, int, int, size_t, hipStream_t);
 template hipError_t launch_zinv_batch<float>(const ZInvArgs *, const int2 *, int, int, int, size_t, hipStream_t);
 template hipError_t launch_zinv_batch<double>(const ZInvArgs *, const int2 *, int, int, int, size_t, hipStream_t);
+
+// maximum of the per-block maxima (first of each pair), NaN propagating
+__global__ void __launch_bounds__(256) k_max_reduce(const double *__restrict__ part, int nblk, double *out) {
+    __shared__ double red[4];
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) v = nmax(v, part[2 * (int64_t)b]);
+    block_max(v, red, out, threadIdx.x);
+}
+
+hipError_t launch_max_reduce(const double *part, int nblk, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, part, nblk, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, part, nblk, out);

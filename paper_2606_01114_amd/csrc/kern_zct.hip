@@ -122,7 +122,7 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
         }
         T srcn[3];
         cell_compute<T, EPI, MSV>(a, in, hd, ed, ex, srcn);
-        if (EPI == EPI_STAGE && a.next_r2c) {
+        if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
         }
@@ -228,7 +228,8 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     if (a.Ms) zepi_cells<T, N, EPI, true>(a, lds, pos0, ncells, demag, ed, ex, tid);
     else zepi_cells<T, N, EPI, false>(a, lds, pos0, ncells, demag, ed, ex, tid);
     if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
-    if (EPI == EPI_STAGE && a.next_r2c) {
+    if (EPI == EPI_TAB && a.tab_last) block_max(ed, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
         // 3. the next stage's source, already folded in LDS: clear the slots
         //    between the last cell and the transform's input half, then
         //    transform forward
@@ -312,6 +313,7 @@ hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
     case NN:                                                                                                          \
         if (epi == EPI_HEFF) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_HEFF>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
         else if (epi == EPI_STAGE) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_STAGE>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
+        else if (epi == EPI_TAB) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_TAB>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
         else hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_ADJ>), dim3(tiles), dim3(zthreads(NN)), lds, s, a);          \
         break;
         ZN_CASES(ZI)

@@ -65,7 +65,7 @@ struct ZFwdArgs {
     double gp, alpha;          // gamma/(1+alpha^2), alpha
 };
 
-enum EpiMode { EPI_HEFF = 0, EPI_STAGE = 1, EPI_ADJ = 2 };
+enum EpiMode { EPI_HEFF = 0, EPI_STAGE = 1, EPI_ADJ = 2, EPI_TAB = 3 };
 
 // Arguments of the z-inverse (C2R) pass and its epilogue.
 struct ZInvArgs {
@@ -85,6 +85,16 @@ struct ZInvArgs {
     const void *ms_in, *m_n; void *acc, *ms_out, *m_out, *h_rec, *u_rec;
     // adjoint
     const void *g_h; void *g_m, *g_Ms; int acc_gMs;
+    // explicit Runge-Kutta stage from a Butcher tableau (EPI_TAB; uses dt,
+    // gp, alpha, renorm, ms_in, m_n, ms_out, next_r2c above): stage tab_s
+    // writes its derivative k_s to K + tab_s * kstride; before the last stage
+    // the next stage input m_n + dt sum_j tab_a[j] k_j goes to ms_out; the
+    // last stage writes the solution m_n + dt sum_j tab_a[j] k_j (renormalised
+    // when renorm) to cand and the per-block max over cells and components of
+    // |dt sum_j tab_e[j] k_j| to epart[2 blk]
+    int tab_s, tab_last;
+    double tab_a[8], tab_e[8];
+    void *K; int64_t kstride; void *cand;
 };
 
 }  // namespace mmx

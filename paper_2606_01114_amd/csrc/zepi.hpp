@@ -25,6 +25,9 @@ __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float rnorm(float n2) { return __builtin_amdgcn_rsqf(n2); }
 __device__ __forceinline__ double rnorm(double n2) { return 1.0 / sqrt(n2); }
 
+// maximum that propagates NaN (a non-finite error must not be hidden)
+__device__ __forceinline__ double nmax(double a, double b) { return (b > a || b != b) ? b : a; }
+
 // Inputs of one cell's epilogue, loaded before any arithmetic so that the
 // loads of several cells can be in flight together.  MSV: Ms is a per-cell
 // field (else the scalar).  A neighbour outside the domain is replaced by the
@@ -33,7 +36,7 @@ __device__ __forceinline__ double rnorm(double n2) { return 1.0 / sqrt(n2); }
 template <typename T>
 struct CellIn {
     int64_t cell;
-    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3];
+    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[7][3];
 };
 
 template <typename T, int EPI, bool MSV>
@@ -42,7 +45,7 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
     const int64_t sx = (int64_t)ny * nz, sy = nz;
     const bool exch = (a.terms & 2u) != 0;
     const T *Ms = reinterpret_cast<const T *>(a.Ms);
-    const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE ? a.ms_in : a.m);
+    const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE || EPI == EPI_TAB ? a.ms_in : a.m);
     int64_t nc[6];
     nc[0] = i > 0 ? cell - sx : cell;
     nc[1] = i < nx - 1 ? cell + sx : cell;
@@ -71,6 +74,15 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
 #pragma unroll
             for (int c = 0; c < 3; ++c) in.ac[c] = accp[c];
         }
+    }
+    if (EPI == EPI_TAB) {
+        const T *mnp = reinterpret_cast<const T *>(a.m_n) + cell * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) in.mn[c] = mnp[c];
+        const T *K = reinterpret_cast<const T *>(a.K) + cell * 3;
+        for (int j = 0; j < a.tab_s; ++j)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) in.kj[j][c] = K[j * a.kstride + c];
     }
     if (EPI == EPI_ADJ) {
         const T *gh = reinterpret_cast<const T *>(a.g_h);
@@ -168,6 +180,52 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
         }
 #pragma unroll
         for (int c = 0; c < 3; ++c) src_next[c] = msi * nxt[c];
+    } else if (EPI == EPI_TAB) {
+        T h[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + T(a.hext[c]);
+        T mxh[3], mxmxh[3], f[3];
+        cross3(mi, h, mxh);
+        cross3(mi, mxh, mxmxh);
+        const T gp = T(a.gp), al = T(a.alpha), dt = T(a.dt);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) f[c] = -gp * (mxh[c] + al * mxmxh[c]);
+        const int s = a.tab_s;
+        T *K = reinterpret_cast<T *>(a.K) + cell * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) K[s * a.kstride + c] = f[c];
+        // sum_j w_j k_j over the earlier stages and this one
+        T sa[3], se[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { sa[c] = T(a.tab_a[s]) * f[c]; se[c] = T(a.tab_e[s]) * f[c]; }
+        for (int j = 0; j < s; ++j) {
+            const T wa = T(a.tab_a[j]), we = T(a.tab_e[j]);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) { sa[c] += wa * in.kj[j][c]; se[c] += we * in.kj[j][c]; }
+        }
+        T nxt[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) nxt[c] = in.mn[c] + dt * sa[c];
+        if (!a.tab_last) {
+            T *mo = reinterpret_cast<T *>(a.ms_out) + cell * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) mo[c] = nxt[c];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) src_next[c] = msi * nxt[c];
+        } else {
+            double e = 0.0;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) e = nmax(e, (double)fabs(dt * se[c]));
+            ed = nmax(ed, e);
+            if (a.renorm) {
+                const T r = rnorm(nxt[0] * nxt[0] + nxt[1] * nxt[1] + nxt[2] * nxt[2]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) nxt[c] *= r;
+            }
+            T *co = reinterpret_cast<T *>(a.cand) + cell * 3;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) co[c] = nxt[c];
+        }
     } else {  // EPI_ADJ
         T gm[3] = {T(0), T(0), T(0)};
         T gms = T(0);
@@ -212,6 +270,22 @@ __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, i
     } else {
         cell_load<T, EPI, false>(a, cell, i, j, z, in);
         cell_compute<T, EPI, false>(a, in, hd, ed, ex, src_next);
+    }
+}
+
+// block maximum of one non-negative FP64 value per thread (the RK error);
+// a maximum does not depend on the order of the reduction
+__device__ __forceinline__ void block_max(double v, double *red, double *out, int tid) {
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) v = nmax(v, __shfl_down(v, off, 64));
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) red[wv] = v;
+    __syncthreads();
+    if (tid == 0) {
+        double m = 0.0;
+        const int nw = (blockDim.x + 63) / 64;
+        for (int w = 0; w < nw; ++w) m = nmax(m, red[w]);
+        out[0] = m;
     }
 }
 

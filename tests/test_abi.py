@@ -140,3 +140,12 @@ def test_attach_on_null_plan():
     from paper_2606_01114_amd import _lib
     dummy = ctypes.c_void_p(256)
     assert _lib.lib().mm_plan_attach_memory(None, dummy, dummy) == _lib.MM_EINVAL
+
+
+def test_rkf45_rejects_bad_arguments_on_host():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(256)
+    dt, err, ok = ctypes.c_double(1e-13), ctypes.c_double(), ctypes.c_int()
+    assert L.llg_rkf45_step(None, dummy, None, 8e5, 1e-11, 0.1, 2.2e5, ctypes.byref(dt), 1e-5, None, 0,
+                            ctypes.byref(err), ctypes.byref(ok)) == _lib.MM_EINVAL

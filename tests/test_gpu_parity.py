@@ -266,3 +266,64 @@ def test_attached_memory_same_results():
             plan.h_eff(bad, MS, A, energy=True)
         assert ei.value.code == MM_ENONFINITE
         plan.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_rkf45_step_against_oracle(prec):
+    """One attempted RKF45 step on 32x32x4 (random m, per-cell Ms): the accepted
+    result, the error estimate and the next step against the oracle (FP64 with
+    the tensor held equal); a rejected attempt leaves m untouched."""
+    import torch
+    n, d = (32, 32, 4), (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant(n, d)
+    L = tuple(oracle.default_L(v) for v in n)
+    plan, dt_ = _plan(n, d, prec, hold=oct_ if prec == "f64" else None)
+    m0 = rounded(synth.random_unit(n, 41), dt_)
+    Ms = rounded(synth.ms_field(n, 42), dt_)
+    dt, tol = 2e-14, 1e-2
+    ref, err_ref, ok_ref, dtn_ref = oracle.rkf45_step(m0, Ms, A, d, oct_, L, ALPHA, GAMMA, dt, tol)
+    assert ok_ref
+    m = to_dev(m0, dt_)
+    ok, err, dtn = plan.rkf45_step(m, to_dev(Ms, dt_), A, ALPHA, GAMMA, dt, tol)
+    _say(prec, "err", err, err_ref, "dt_next", dtn, dtn_ref)
+    assert ok
+    e = rel_l2(m.cpu().numpy() - m0, ref - m0)
+    assert e <= (1e-12 if prec == "f64" else 1e-5), e
+    # err is a small difference of stage derivatives: in FP32 its absolute
+    # error scales with dt max|k|, not with err itself
+    k1 = oracle.llg_rhs(m0, oracle.h_eff(m0, Ms, A, d, oct_, L), ALPHA, GAMMA)
+    scale = dt * np.abs(k1).max()
+    if prec == "f64":
+        assert abs(err / err_ref - 1) <= 1e-8
+    else:
+        assert abs(err - err_ref) <= 1e-5 * scale, (err, err_ref, scale)
+    assert abs(dtn / dtn_ref - 1) <= (1e-8 if prec == "f64" else 1e-2)
+    # a tolerance below the error: rejected, m bitwise unchanged, dt shrinks
+    m = to_dev(m0, dt_)
+    before = m.clone()
+    ok, err2, dtn2 = plan.rkf45_step(m, to_dev(Ms, dt_), A, ALPHA, GAMMA, dt, err_ref / 10)
+    assert not ok and torch.equal(m, before)
+    _, _, ok_ref2, dtn_ref2 = oracle.rkf45_step(m0, Ms, A, d, oct_, L, ALPHA, GAMMA, dt, err_ref / 10)
+    assert not ok_ref2 and abs(dtn2 / dtn_ref2 - 1) <= (1e-8 if prec == "f64" else 1e-2)
+
+
+def test_rkf45_macrospin_adaptive_run():
+    """Adaptive RKF45 on the 1x1x1 cubic cell in a field along z (FP64): the
+    same accepted/rejected sequence as the oracle and the closed form within
+    the tolerance scale."""
+    import torch
+    n, d = (1, 1, 1), (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant(n, d)
+    plan, dt_ = _plan(n, d, "f64", hold=oct_)
+    th0, ph0, H = 1.0, 0.3, 2e5
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(1, 1, 1, 3)
+    T, tol = 2e-10, 1e-8
+    m = to_dev(m0, dt_)
+    acc, rej, _ = plan.rkf45_run(m, MS, A, 0.1, GAMMA, T, 5e-11, tol, h_ext=(0, 0, H))
+    mr, acc_r, rej_r = oracle.rkf45_run(m0, T, 5e-11, tol, MS, A, d, oct_, n, 0.1, GAMMA, h_ext=(0, 0, H))
+    ref = oracle.macrospin_closed_form(th0, ph0, H, 0.1, GAMMA, T)
+    _say("rkf45 macrospin", acc, rej, acc_r, rej_r)
+    assert (acc, rej) == (acc_r, rej_r) and rej >= 1
+    got = m.cpu().numpy().reshape(3)
+    assert np.abs(got - mr.reshape(3)).max() < 1e-12
+    assert np.abs(got - ref).max() < 50 * tol
