@@ -806,6 +806,8 @@ int rkf45_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, doubl
             if (s < 5) a.tab_a[j] = kRkfA[s + 1][j];
             else { a.tab_a[j] = kRkfB4[j]; a.tab_e[j] = kRkfB5[j] - kRkfB4[j]; }
         }
+        a.tab_as = a.tab_a[s];
+        a.tab_es = a.tab_e[s];
         a.epart = p->epart;
         HIPCK(zinv_any<T>(p, a, EPI_TAB));
     }

@@ -164,7 +164,7 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
                     hd[c] = reinterpret_cast<const T *>(&lds[(l >> 1) * pitch + z])[l & 1];
                 }
             }
-            T src[3];
+            T src[3] = {T(0), T(0), T(0)};
             cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, src);
             if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll

@@ -120,7 +120,7 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
 #pragma unroll
             for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
         }
-        T srcn[3];
+        T srcn[3] = {T(0), T(0), T(0)};
         cell_compute<T, EPI, MSV>(a, in, hd, ed, ex, srcn);
         if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll

@@ -93,7 +93,8 @@ struct ZInvArgs {
     // when renorm) to cand and the per-block max over cells and components of
     // |dt sum_j tab_e[j] k_j| to epart[2 blk]
     int tab_s, tab_last;
-    double tab_a[8], tab_e[8];
+    double tab_a[8], tab_e[8];   // weights of the earlier stages j < tab_s
+    double tab_as, tab_es;       // weights of this stage's own derivative
     void *K; int64_t kstride; void *cand;
 };
 

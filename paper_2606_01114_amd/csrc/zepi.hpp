@@ -33,10 +33,13 @@ __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b 
 // field (else the scalar).  A neighbour outside the domain is replaced by the
 // cell itself (its difference term is exactly zero: the Neumann condition);
 // a vacuum neighbour gets weight 0.
+// stages of the largest Butcher tableau the stage epilogue runs (RKF45: 6)
+constexpr int kMaxTabStages = 6;
+
 template <typename T>
 struct CellIn {
     int64_t cell;
-    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[7][3];
+    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[kMaxTabStages - 1][3];
 };
 
 template <typename T, int EPI, bool MSV>
@@ -80,9 +83,14 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
 #pragma unroll
         for (int c = 0; c < 3; ++c) in.mn[c] = mnp[c];
         const T *K = reinterpret_cast<const T *>(a.K) + cell * 3;
-        for (int j = 0; j < a.tab_s; ++j)
+        // compile-time indices keep the earlier stages' derivatives in registers
 #pragma unroll
-            for (int c = 0; c < 3; ++c) in.kj[j][c] = K[j * a.kstride + c];
+        for (int j = 0; j < kMaxTabStages - 1; ++j) {
+            if (j < a.tab_s) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) in.kj[j][c] = K[j * a.kstride + c];
+            }
+        }
     }
     if (EPI == EPI_ADJ) {
         const T *gh = reinterpret_cast<const T *>(a.g_h);
@@ -197,11 +205,14 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
         // sum_j w_j k_j over the earlier stages and this one
         T sa[3], se[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) { sa[c] = T(a.tab_a[s]) * f[c]; se[c] = T(a.tab_e[s]) * f[c]; }
-        for (int j = 0; j < s; ++j) {
-            const T wa = T(a.tab_a[j]), we = T(a.tab_e[j]);
+        for (int c = 0; c < 3; ++c) { sa[c] = T(a.tab_as) * f[c]; se[c] = T(a.tab_es) * f[c]; }
 #pragma unroll
-            for (int c = 0; c < 3; ++c) { sa[c] += wa * in.kj[j][c]; se[c] += we * in.kj[j][c]; }
+        for (int j = 0; j < kMaxTabStages - 1; ++j) {
+            if (j < s) {
+                const T wa = T(a.tab_a[j]), we = T(a.tab_e[j]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) { sa[c] += wa * in.kj[j][c]; se[c] += we * in.kj[j][c]; }
+            }
         }
         T nxt[3];
 #pragma unroll
@@ -224,7 +235,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
             }
             T *co = reinterpret_cast<T *>(a.cand) + cell * 3;
 #pragma unroll
-            for (int c = 0; c < 3; ++c) co[c] = nxt[c];
+            for (int c = 0; c < 3; ++c) { co[c] = nxt[c]; src_next[c] = T(0); }
         }
     } else {  // EPI_ADJ
         T gm[3] = {T(0), T(0), T(0)};
