@@ -16,6 +16,7 @@ What it computes, in plain and slow form:
 * ``llg``     -- the LLG right-hand side, the classic RK4 step and the RKF45
   step with its step-size control.
 * ``adjoint`` -- vector-Jacobian products of h_eff and of one RK4 step.
+* ``minimize`` -- energy minimisation with Barzilai-Borwein step sizes.
 
 Parity status per function is stated in each module's docstring.
 """
@@ -26,3 +27,4 @@ from .field import (MU0, demag_fft, demag_direct, naive_dft, exchange_field, exc
 from .llg import (llg_rhs, rk4_step, rk4_run, macrospin_closed_form, rkf45_step, rkf45_run, rkf45_stages,
                   RKF45_A, RKF45_B4, RKF45_B5, RKF45_C)
 from .adjoint import h_eff_vjp, llg_rhs_vjp, rk4_step_vjp, rk4_run_grad_Ms
+from .minimize import bb_minimize, torque_dir, total_energy
