@@ -212,6 +212,28 @@ int llg_rkf45_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, dou
                    int *accepted);
 
 /*
+ * mm_minimize_bb -- relax m to a minimum of the energy (demag + exchange +
+ * applied field) with Barzilai-Borwein step lengths, the paper's minimiser
+ * (section "Implementation": the stopping criterion is reduced over the
+ * whole grid).  Per iteration k: h = h_eff(m) + h_ext, g = m x (m x h) per
+ * cell; stop when max |m x h| <= tol or k = max_iter; else
+ * m <- normalise(m - tau g) with tau = (s.s)/(s.y) for odd k, (s.y)/(y.y)
+ * for even k >= 2 (s, y: differences of m and g from the previous iterate,
+ * sums over all cells and components in FP64), and 0.01 / max |m x h| at
+ * k = 0 or when that value is not positive and finite.
+ *   m          device (nx,ny,nz,3) unit vectors, overwritten with the result
+ *   Ms, Ms_scalar, A, h_ext  as in llg_step
+ *   tol        >= 0 (A/m); max_iter >= 0
+ *   iters_out  host int: updates made; torque_out host double: max |m x h|
+ *              of the returned m
+ * Synchronous (one host read of four FP64 values per iteration).  Scratch
+ * (3 three-component fields and the per-block sums) is allocated on the
+ * first call.  A non-finite torque returns MM_ENONFINITE.
+ */
+int mm_minimize_bb(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A, const double h_ext[3],
+                   double tol, int max_iter, int *iters_out, double *torque_out);
+
+/*
  * h_eff_adjoint -- vector-Jacobian product of h_eff (reverse-mode derivative
  * used for inverse problems, paper Introduction).  For the cotangent g_h:
  *   g_m  = Ms H_demag(g_h) + Lap(c g_h)          (c = 2A/(mu0 Ms))

@@ -11,12 +11,12 @@ Exl et al. that the original magnum.np follows):
   respect to m_i is -mu0 Ms_i V h_i, whose tangential part gives the descent
   direction -g_i with g_i = m_i x (m_i x h_i) = (m_i . h_i) m_i - h_i.
 * update m <- normalise(m - tau g) for every cell.
-* tau: the first iteration takes tau = 0.01 / max_i |g_i| (the most tilted
-  moment turns by about 0.01 rad); iteration k >= 1 takes the Barzilai-
+* tau: the first iteration takes tau = 0.01 / max_i |m_i x h_i| (equal to
+  max_i |g_i| for unit m_i: the most tilted moment turns by about 0.01 rad); iteration k >= 1 takes the Barzilai-
   Borwein lengths alternately, tau = (s.s)/(s.y) for odd k and
   (s.y)/(y.y) for even k, with s = m_k - m_{k-1}, y = g_k - g_{k-1} summed
   over all cells and components (FP64); a non-positive or non-finite value
-  falls back to 0.01 / max_i |g_i|.
+  falls back to 0.01 / max_i |m_i x h_i|.
 * stop at the first iterate with max_i |m_i x h_i| <= tol (that reduction
   is the global criterion), or after max_iter updates.
 
@@ -60,7 +60,7 @@ def bb_minimize(m, Ms, A, d, octant, L, h_ext=None, tol=1.0, max_iter=10000, hef
             ss, sy, yy = float(np.sum(s * s)), float(np.sum(s * y)), float(np.sum(y * y))
             tau = ss / sy if k % 2 == 1 else sy / yy
         if not (np.isfinite(tau) and tau > 0.0):
-            tau = 0.01 / float(np.max(np.linalg.norm(g, axis=-1)))
+            tau = 0.01 / torque   # |g_i| = |m_i x h_i| for unit m_i
         m_prev, g_prev = m, g
         u = m - tau * g
         m = u / np.linalg.norm(u, axis=-1, keepdims=True)

@@ -20,7 +20,7 @@ MM_NO_RENORM, MM_NO_GRAPH = 1, 2
 EXPORTS = [
     "mm_plan_opts_default", "demag_tensor_init", "mm_plan_destroy", "mm_plan_set_stream", "mm_plan_info",
     "mm_plan_bytes", "mm_plan_attach_memory",
-    "h_eff", "llg_step", "llg_rkf45_step", "h_eff_adjoint", "llg_step_adjoint",
+    "h_eff", "llg_step", "llg_rkf45_step", "mm_minimize_bb", "h_eff_adjoint", "llg_step_adjoint",
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
     "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_info", "mm_batch_destroy",
     "mm_plan_time_passes", "mm_device_copy",
@@ -62,6 +62,7 @@ def _load():
         "h_eff": [vp, vp, vp, cd, cd, vp, cu, dp],
         "llg_step": [vp, vp, vp, cd, cd, cd, cd, cd, ci, dp, cu],
         "llg_rkf45_step": [vp, vp, vp, cd, cd, cd, cd, dp, cd, dp, cu, dp, ctypes.POINTER(ci)],
+        "mm_minimize_bb": [vp, vp, vp, cd, cd, dp, cd, ci, ctypes.POINTER(ci), dp],
         "h_eff_adjoint": [vp, vp, vp, cd, cd, vp, vp, vp, cu],
         "llg_step_adjoint": [vp, vp, vp, cd, cd, cd, cd, cd, dp, cu, vp, vp],
         "mm_demag_tensor_get": [vp, dp],

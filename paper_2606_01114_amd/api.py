@@ -155,6 +155,19 @@ class DemagPlan:
                 rej += 1
         return acc, rej, dt
 
+    def minimize(self, m, Ms, A, tol=1.0, max_iter=10000, h_ext=None):
+        """Barzilai-Borwein energy minimisation in place.  Returns
+        (iterations, final max torque |m x h| in A/m)."""
+        self._vec(m, "m")
+        Mst, Mss = self._ms(Ms)
+        self._sync_stream()
+        he = (ctypes.c_double * 3)(*[float(v) for v in h_ext]) if h_ext is not None else None
+        it = ctypes.c_int()
+        tq = ctypes.c_double()
+        check(_lib.lib().mm_minimize_bb(self._h, _ptr(m), _ptr(Mst), Mss, float(A), he, float(tol), int(max_iter),
+                                        ctypes.byref(it), ctypes.byref(tq)))
+        return it.value, tq.value
+
     def h_eff_adjoint(self, m, Ms, A, g_h, terms=MM_DEMAG | MM_EXCHANGE, want_Ms=True):
         self._vec(m, "m")
         self._vec(g_h, "g_h")

@@ -170,6 +170,8 @@ struct mm_plan {
     void *adj = nullptr;
     // RKF45 stage derivatives (6 fields) and candidate solution (allocated on first use)
     void *rk = nullptr;
+    // minimiser scratch: previous m, two gradient fields, per-block and total sums
+    void *bb = nullptr;
     // memory sizing and caller-owned memory: a dry plan only adds up sizes;
     // with a workspace attached, allocations are carved from it and the tensor
     // spectrum lives in the caller's tensor buffer
@@ -367,7 +369,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     z.dnz = make_fastdiv((uint32_t)nz); z.dny = make_fastdiv((uint32_t)ny);
     z.nthr = std::min(1024, std::max(256, fft_threads(p->fz.d, (3 * P + 1) / 2, P * (int)nz)));
     z.f = p->fz.d; z.tw = twc + oz; z.twh = twc + ozh; z.S1 = p->S1;
-    p->lds_z = std::max<size_t>((size_t)((3 * P + 1) / 2) * pz * csz, 16 * 2 * sizeof(double) + 64);
+    p->lds_z = std::max<size_t>((size_t)((3 * P + 1) / 2) * pz * csz, 16 * 4 * sizeof(double) + 64);
     if (p->z_ct) p->lds_z = std::max(p->lds_z, zct_lds(Lz, csz));
     if ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsMax) return fail(MM_ENOTSUP, "z length %d too long", Lz);
     // energy partials
@@ -819,6 +821,53 @@ int rkf45_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, doubl
     return MM_OK;
 }
 
+// Barzilai-Borwein energy minimisation (synchronous: the host reads the
+// global sums and the maximum torque after every gradient evaluation)
+template <typename T>
+int bb_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, const double *hext, double tol, int max_iter,
+            int *iters, double *torque_out) {
+    const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
+    const size_t f3 = (size_t)ncell * 3 * sizeof(T);
+    const size_t nb = (size_t)p->zg.tiles * 4 * sizeof(double);
+    int rc;
+    if (!p->bb && (rc = dalloc_own(p, &p->bb, 3 * f3 + nb + 4 * sizeof(double) + 256))) return rc;
+    char *base = static_cast<char *>(p->bb);
+    T *mprev = reinterpret_cast<T *>(base);
+    T *g[2] = {reinterpret_cast<T *>(base + f3), reinterpret_cast<T *>(base + 2 * f3)};
+    double *part = reinterpret_cast<double *>(base + 3 * f3);
+    double *tot = part + 4 * (size_t)p->zg.tiles;
+    double torque = 0.0;
+    int k = 0;
+    for (;; ++k) {
+        if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
+        if ((rc = run_xyx<T>(p))) return rc;
+        ZInvArgs a;
+        fill_common(p, a, MM_DEMAG | MM_EXCHANGE, Ms, Ms_s, A);
+        if (hext) for (int i = 0; i < 3; ++i) a.hext[i] = hext[i];
+        a.m = m;
+        a.bb_g = g[k & 1];
+        a.bb_mprev = mprev;
+        a.bb_gprev = g[(k + 1) & 1];
+        a.bb_prev = k >= 1;
+        a.bb_part = part;
+        HIPCK(zinv_any<T>(p, a, EPI_BB));
+        HIPCK(launch_bb_reduce(part, p->zg.tiles, tot, p->stream));
+        double s[4];
+        HIPCK(hipMemcpyAsync(s, tot, sizeof s, hipMemcpyDeviceToHost, p->stream));
+        HIPCK(hipStreamSynchronize(p->stream));
+        torque = s[3];
+        if (!std::isfinite(torque)) { *iters = k; *torque_out = torque; return fail(MM_ENONFINITE, "torque is not finite"); }
+        if (torque <= tol || k >= max_iter) break;
+        double tau = 0.0;
+        if (k >= 1) tau = (k & 1) ? s[0] / s[1] : s[1] / s[2];
+        if (!(std::isfinite(tau) && tau > 0.0)) tau = 0.01 / torque;
+        HIPCK(launch_bb_update<T>(static_cast<T *>(m), g[k & 1], mprev, tau, ncell, p->stream));
+    }
+    *iters = k;
+    *torque_out = torque;
+    return MM_OK;
+}
+
 // one launch of pass k on the plan's scratch arrays (timing only)
 template <typename T>
 int time_one(mm_plan *p, int k) {
@@ -971,6 +1020,7 @@ int mm_plan_attach_memory(mm_plan *p, void *tensor_buf, void *workspace_buf) {
     p->bytes = 0;
     p->adj = nullptr;
     p->rk = nullptr;
+    p->bb = nullptr;
     p->tensor = nullptr;
     p->ws = static_cast<char *>(workspace_buf);
     p->ws_used = 0;
@@ -1085,6 +1135,19 @@ int llg_rkf45_step(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double
     const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(tol / err, 0.2)));
     *dt *= fac;
     return MM_OK;
+}
+
+int mm_minimize_bb(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double A, const double h_ext[3],
+                   double tol, int max_iter, int *iters_out, double *torque_out) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m || !iters_out || !torque_out) return fail(MM_EINVAL, "m, iters_out and torque_out must be non-NULL");
+    if (!(tol >= 0.0) || !std::isfinite(tol)) return fail(MM_EINVAL, "tol must be finite and >= 0");
+    if (max_iter < 0) return fail(MM_EINVAL, "max_iter must be >= 0");
+    if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;
+    if (h_ext) for (int i = 0; i < 3; ++i) if (!std::isfinite(h_ext[i])) return fail(MM_EINVAL, "h_ext must be finite");
+    return p->prec == MM_F32 ? bb_impl<float>(p, m, Ms, Ms_scalar, A, h_ext, tol, max_iter, iters_out, torque_out)
+                             : bb_impl<double>(p, m, Ms, Ms_scalar, A, h_ext, tol, max_iter, iters_out, torque_out);
 }
 
 int mm_demag_tensor_get(mm_plan *p, double *host) {

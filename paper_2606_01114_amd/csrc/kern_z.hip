@@ -148,7 +148,7 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
     __syncthreads();
     if (demag) lds_fft<T, +1>(lds, nlc, pitch, g.f, reinterpret_cast<const C *>(g.tw), ltid, g.nthr);
     // 2. epilogue per cell
-    double ed = 0.0, ex = 0.0;
+    Acc4 acc;
     const int nz = g.nz, ny = g.ny;
     if (tid < g.nthr) {
         for (int e = tid; e < wp * nz; e += g.nthr) {
@@ -165,7 +165,7 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
                 }
             }
             T src[3] = {T(0), T(0), T(0)};
-            cell_epilogue<T, EPI>(a, cell, i, j, z, hd, ed, ex, src);
+            cell_epilogue<T, EPI>(a, cell, i, j, z, hd, acc, src);
             if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
@@ -175,8 +175,9 @@ __device__ __forceinline__ void zinv_body(const ZInvArgs &a, uint32_t blk) {
             }
         }
     }
-    if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
-    if (EPI == EPI_TAB && a.tab_last) block_max(ed, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (EPI == EPI_HEFF && a.epart) block_energy(acc.v[0], acc.v[1], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (EPI == EPI_TAB && a.tab_last) block_max(acc.v[0], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (EPI == EPI_BB) block_bb(acc, reinterpret_cast<double *>(smem), a.bb_part + 4 * (int64_t)blk, tid);
     if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
         // zero the padding rows and the unused half of an odd last line, then
         // transform the next stage's source along z
@@ -247,6 +248,7 @@ hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t
     case EPI_HEFF: hipLaunchKernelGGL((k_zinv<T, EPI_HEFF>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     case EPI_STAGE: hipLaunchKernelGGL((k_zinv<T, EPI_STAGE>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     case EPI_TAB: hipLaunchKernelGGL((k_zinv<T, EPI_TAB>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
+    case EPI_BB: hipLaunchKernelGGL((k_zinv<T, EPI_BB>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     default: hipLaunchKernelGGL((k_zinv<T, EPI_ADJ>), dim3(a.g.tiles), dim3(a.g.nthr), lds_bytes, s, a); break;
     }
     return hipGetLastError();
@@ -293,6 +295,52 @@ hipError_t launch_max_reduce(const double *part, int nblk, double *out, hipStrea
     hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, s, part, nblk, out);
     return hipGetLastError();
 }
+
+// minimiser: fixed-order sums of the per-block (s.s, s.y, y.y) and the
+// maximum torque (one block of 256 threads)
+__global__ void __launch_bounds__(256) k_bb_reduce(const double *__restrict__ part, int nblk, double *out4) {
+    __shared__ double red[16];
+    Acc4 acc;
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        acc.v[0] += part[4 * (int64_t)b];
+        acc.v[1] += part[4 * (int64_t)b + 1];
+        acc.v[2] += part[4 * (int64_t)b + 2];
+        acc.v[3] = nmax(acc.v[3], part[4 * (int64_t)b + 3]);
+    }
+    block_bb(acc, red, out4, threadIdx.x);
+}
+
+hipError_t launch_bb_reduce(const double *part, int nblk, double *out4, hipStream_t s) {
+    hipLaunchKernelGGL(k_bb_reduce, dim3(1), dim3(256), 0, s, part, nblk, out4);
+    return hipGetLastError();
+}
+
+// minimiser update: m_prev <- m, m <- (m - tau g) / |m - tau g| per cell
+template <typename T>
+__global__ void __launch_bounds__(256) k_bb_update(T *__restrict__ m, const T *__restrict__ g, T *__restrict__ mprev,
+                                                   double tau, int64_t ncell) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ncell) return;
+    T u[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const T v = m[3 * i + c];
+        mprev[3 * i + c] = v;
+        u[c] = v - T(tau) * g[3 * i + c];
+    }
+    const T r = rnorm(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) m[3 * i + c] = u[c] * r;
+}
+
+template <typename T>
+hipError_t launch_bb_update(T *m, const T *g, T *mprev, double tau, int64_t ncell, hipStream_t s) {
+    if (ncell <= 0) return hipSuccess;
+    hipLaunchKernelGGL((k_bb_update<T>), dim3((unsigned)((ncell + 255) / 256)), dim3(256), 0, s, m, g, mprev, tau, ncell);
+    return hipGetLastError();
+}
+template hipError_t launch_bb_update<float>(float *, const float *, float *, double, int64_t, hipStream_t);
+template hipError_t launch_bb_update<double>(double *, const double *, double *, double, int64_t, hipStream_t);
 
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_energy_reduce, dim3(1), dim3(256), 0, s, part, nblk, out);

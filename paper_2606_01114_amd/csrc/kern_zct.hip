@@ -102,7 +102,7 @@ __device__ __forceinline__ void zfwd_ct_body(const ZFwdArgs &a, uint32_t tile) {
 // stage's source is written back to the same place.
 template <typename T, int N, int EPI, bool MSV>
 __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int64_t pos0, int ncells, bool demag,
-                                           double &ed, double &ex, int tid) {
+                                           Acc4 &acc, int tid) {
     constexpr int NT = zthreads(N), PT = zpitch(N);
     const ZGeom &g = a.g;
     const int nz = g.nz, ny = g.ny;
@@ -121,7 +121,7 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
             for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
         }
         T srcn[3] = {T(0), T(0), T(0)};
-        cell_compute<T, EPI, MSV>(a, in, hd, ed, ex, srcn);
+        cell_compute<T, EPI, MSV>(a, in, hd, acc, srcn);
         if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
@@ -223,12 +223,13 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     }
     // 2. epilogue per cell; demag field sample z of component c sits in line
     //    3 pl + c, slot z/2, real part for even z
-    double ed = 0.0, ex = 0.0;
+    Acc4 acc;
     const int ncells = wp * nz;
-    if (a.Ms) zepi_cells<T, N, EPI, true>(a, lds, pos0, ncells, demag, ed, ex, tid);
-    else zepi_cells<T, N, EPI, false>(a, lds, pos0, ncells, demag, ed, ex, tid);
-    if (EPI == EPI_HEFF && a.epart) block_energy(ed, ex, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
-    if (EPI == EPI_TAB && a.tab_last) block_max(ed, reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (a.Ms) zepi_cells<T, N, EPI, true>(a, lds, pos0, ncells, demag, acc, tid);
+    else zepi_cells<T, N, EPI, false>(a, lds, pos0, ncells, demag, acc, tid);
+    if (EPI == EPI_HEFF && a.epart) block_energy(acc.v[0], acc.v[1], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (EPI == EPI_TAB && a.tab_last) block_max(acc.v[0], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
+    if (EPI == EPI_BB) block_bb(acc, reinterpret_cast<double *>(smem), a.bb_part + 4 * (int64_t)blk, tid);
     if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
         // 3. the next stage's source, already folded in LDS: clear the slots
         //    between the last cell and the transform's input half, then
@@ -314,6 +315,7 @@ hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
         if (epi == EPI_HEFF) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_HEFF>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
         else if (epi == EPI_STAGE) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_STAGE>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
         else if (epi == EPI_TAB) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_TAB>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
+        else if (epi == EPI_BB) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_BB>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
         else hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_ADJ>), dim3(tiles), dim3(zthreads(NN)), lds, s, a);          \
         break;
         ZN_CASES(ZI)

@@ -50,6 +50,8 @@ template <typename T>
 hipError_t launch_zinv_ct_b(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, hipStream_t s);
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s);
 hipError_t launch_max_reduce(const double *part, int nblk, double *out, hipStream_t s);
+hipError_t launch_bb_reduce(const double *part, int nblk, double *out4, hipStream_t s);
+template <typename T> hipError_t launch_bb_update(T *m, const T *g, T *mprev, double tau, int64_t ncell, hipStream_t s);
 hipError_t launch_tensor_octant(double *out, int nx, int ny, int nz, double dx, double dy, double dz, double P,
                                 hipStream_t s);
 template <typename T>

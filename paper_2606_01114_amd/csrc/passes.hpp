@@ -65,7 +65,7 @@ struct ZFwdArgs {
     double gp, alpha;          // gamma/(1+alpha^2), alpha
 };
 
-enum EpiMode { EPI_HEFF = 0, EPI_STAGE = 1, EPI_ADJ = 2, EPI_TAB = 3 };
+enum EpiMode { EPI_HEFF = 0, EPI_STAGE = 1, EPI_ADJ = 2, EPI_TAB = 3, EPI_BB = 4 };
 
 // Arguments of the z-inverse (C2R) pass and its epilogue.
 struct ZInvArgs {
@@ -96,6 +96,10 @@ struct ZInvArgs {
     double tab_a[8], tab_e[8];   // weights of the earlier stages j < tab_s
     double tab_as, tab_es;       // weights of this stage's own derivative
     void *K; int64_t kstride; void *cand;
+    // energy minimisation (EPI_BB; uses m, hext): writes g = m x (m x h) to
+    // bb_g and per block (sum s.s, sum s.y, sum y.y, max |m x h|) to
+    // bb_part[4 blk], with s = m - bb_mprev, y = g - bb_gprev when bb_prev
+    void *bb_g; const void *bb_mprev, *bb_gprev; int bb_prev; double *bb_part;
 };
 
 }  // namespace mmx

@@ -33,13 +33,19 @@ __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b 
 // field (else the scalar).  A neighbour outside the domain is replaced by the
 // cell itself (its difference term is exactly zero: the Neumann condition);
 // a vacuum neighbour gets weight 0.
+// per-thread accumulators of an epilogue: energies (sums 0, 1), the RK
+// error (max 0), or the minimiser's dot products (sums 0-2) and torque (max 3)
+struct Acc4 {
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+};
+
 // stages of the largest Butcher tableau the stage epilogue runs (RKF45: 6)
 constexpr int kMaxTabStages = 6;
 
 template <typename T>
 struct CellIn {
     int64_t cell;
-    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[kMaxTabStages - 1][3];
+    T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[kMaxTabStages - 1][3], mp[3], gp[3];
 };
 
 template <typename T, int EPI, bool MSV>
@@ -92,6 +98,12 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
             }
         }
     }
+    if (EPI == EPI_BB && a.bb_prev) {
+        const T *mp = reinterpret_cast<const T *>(a.bb_mprev) + cell * 3;
+        const T *gp = reinterpret_cast<const T *>(a.bb_gprev) + cell * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) { in.mp[c] = mp[c]; in.gp[c] = gp[c]; }
+    }
     if (EPI == EPI_ADJ) {
         const T *gh = reinterpret_cast<const T *>(a.g_h);
 #pragma unroll
@@ -108,8 +120,8 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
 // hd = demag field at the cell (0 if not requested).  Returns in src_next the
 // next stage's z-transform source Ms * m_next (EPI_STAGE only).
 template <typename T, int EPI, bool MSV>
-__device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> &in, const T hd[3], double &ed,
-                                             double &ex, T src_next[3]) {
+__device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> &in, const T hd[3], Acc4 &acc,
+                                             T src_next[3]) {
     const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
     const T exp_ = T(a.ex_pref);
     const int64_t cell = in.cell;
@@ -136,8 +148,8 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
 #pragma unroll
         for (int c = 0; c < 3; ++c) ho[c] = hd[c] + hex[c] + T(a.hext[c]);
         if (a.epart) {
-            ed += (double)msi * ((double)mi[0] * hd[0] + (double)mi[1] * hd[1] + (double)mi[2] * hd[2]);
-            ex += (double)msi * ((double)mi[0] * hex[0] + (double)mi[1] * hex[1] + (double)mi[2] * hex[2]);
+            acc.v[0] += (double)msi * ((double)mi[0] * hd[0] + (double)mi[1] * hd[1] + (double)mi[2] * hd[2]);
+            acc.v[1] += (double)msi * ((double)mi[0] * hex[0] + (double)mi[1] * hex[1] + (double)mi[2] * hex[2]);
         }
     } else if (EPI == EPI_STAGE) {
         T h[3];
@@ -227,7 +239,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
             double e = 0.0;
 #pragma unroll
             for (int c = 0; c < 3; ++c) e = nmax(e, (double)fabs(dt * se[c]));
-            ed = nmax(ed, e);
+            acc.v[0] = nmax(acc.v[0], e);
             if (a.renorm) {
                 const T r = rnorm(nxt[0] * nxt[0] + nxt[1] * nxt[1] + nxt[2] * nxt[2]);
 #pragma unroll
@@ -236,6 +248,26 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
             T *co = reinterpret_cast<T *>(a.cand) + cell * 3;
 #pragma unroll
             for (int c = 0; c < 3; ++c) { co[c] = nxt[c]; src_next[c] = T(0); }
+        }
+    } else if (EPI == EPI_BB) {
+        T h[3], mxh[3], g[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + T(a.hext[c]);
+        cross3(mi, h, mxh);
+        cross3(mi, mxh, g);
+        T *go = reinterpret_cast<T *>(a.bb_g) + cell * 3;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) go[c] = g[c];
+        const double t2 = (double)mxh[0] * mxh[0] + (double)mxh[1] * mxh[1] + (double)mxh[2] * mxh[2];
+        acc.v[3] = nmax(acc.v[3], sqrt(t2));
+        if (a.bb_prev) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const double s = (double)mi[c] - (double)in.mp[c], y = (double)g[c] - (double)in.gp[c];
+                acc.v[0] += s * s;
+                acc.v[1] += s * y;
+                acc.v[2] += y * y;
+            }
         }
     } else {  // EPI_ADJ
         T gm[3] = {T(0), T(0), T(0)};
@@ -273,14 +305,14 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
 // one cell, loads then arithmetic
 template <typename T, int EPI>
 __device__ __forceinline__ void cell_epilogue(const ZInvArgs &a, int64_t cell, int i, int j, int z, const T hd[3],
-                                              double &ed, double &ex, T src_next[3]) {
+                                              Acc4 &acc, T src_next[3]) {
     CellIn<T> in;
     if (a.Ms) {
         cell_load<T, EPI, true>(a, cell, i, j, z, in);
-        cell_compute<T, EPI, true>(a, in, hd, ed, ex, src_next);
+        cell_compute<T, EPI, true>(a, in, hd, acc, src_next);
     } else {
         cell_load<T, EPI, false>(a, cell, i, j, z, in);
-        cell_compute<T, EPI, false>(a, in, hd, ed, ex, src_next);
+        cell_compute<T, EPI, false>(a, in, hd, acc, src_next);
     }
 }
 
@@ -297,6 +329,27 @@ __device__ __forceinline__ void block_max(double v, double *red, double *out, in
         const int nw = (blockDim.x + 63) / 64;
         for (int w = 0; w < nw; ++w) m = nmax(m, red[w]);
         out[0] = m;
+    }
+}
+
+// fixed-order block reduction of the minimiser's three sums and its maximum
+__device__ __forceinline__ void block_bb(const Acc4 &acc, double *red, double *out4, int tid) {
+    double v0 = acc.v[0], v1 = acc.v[1], v2 = acc.v[2], v3 = acc.v[3];
+    __syncthreads();
+    for (int off = 32; off > 0; off >>= 1) {
+        v0 += __shfl_down(v0, off, 64);
+        v1 += __shfl_down(v1, off, 64);
+        v2 += __shfl_down(v2, off, 64);
+        v3 = nmax(v3, __shfl_down(v3, off, 64));
+    }
+    const int lane = tid & 63, wv = tid >> 6;
+    if (lane == 0) { red[4 * wv] = v0; red[4 * wv + 1] = v1; red[4 * wv + 2] = v2; red[4 * wv + 3] = v3; }
+    __syncthreads();
+    if (tid == 0) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, mx = 0.0;
+        const int nw = (blockDim.x + 63) / 64;
+        for (int w = 0; w < nw; ++w) { s0 += red[4 * w]; s1 += red[4 * w + 1]; s2 += red[4 * w + 2]; mx = nmax(mx, red[4 * w + 3]); }
+        out4[0] = s0; out4[1] = s1; out4[2] = s2; out4[3] = mx;
     }
 }
 

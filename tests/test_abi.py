@@ -149,3 +149,12 @@ def test_rkf45_rejects_bad_arguments_on_host():
     dt, err, ok = ctypes.c_double(1e-13), ctypes.c_double(), ctypes.c_int()
     assert L.llg_rkf45_step(None, dummy, None, 8e5, 1e-11, 0.1, 2.2e5, ctypes.byref(dt), 1e-5, None, 0,
                             ctypes.byref(err), ctypes.byref(ok)) == _lib.MM_EINVAL
+
+
+def test_minimize_rejects_bad_arguments_on_host():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    dummy = ctypes.c_void_p(256)
+    it, tq = ctypes.c_int(), ctypes.c_double()
+    assert L.mm_minimize_bb(None, dummy, None, 8e5, 1e-11, None, 1.0, 10, ctypes.byref(it),
+                            ctypes.byref(tq)) == _lib.MM_EINVAL

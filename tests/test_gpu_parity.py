@@ -327,3 +327,37 @@ def test_rkf45_macrospin_adaptive_run():
     got = m.cpu().numpy().reshape(3)
     assert np.abs(got - mr.reshape(3)).max() < 1e-12
     assert np.abs(got - ref).max() < 50 * tol
+
+
+def test_minimize_bb_against_oracle():
+    """Barzilai-Borwein minimisation of a 20x5x1 platelet (5x5x3 nm cells)
+    from the uniform (1,1,1) state: FP64 iterates against the oracle's
+    after 1, 2, 5 and 12 updates (tensor held equal), and the converged
+    state in FP64 and FP32."""
+    import torch
+    n, d = (20, 5, 1), (5e-9, 5e-9, 3e-9)
+    oct_ = oracle.tensor_octant(n, d)
+    L = tuple(oracle.default_L(v) for v in n)
+    m0 = np.ones(n + (3,)) / np.sqrt(3.0)
+    hz = (1e3, -2e3, 0.0)
+    plan, dt_ = _plan(n, d, "f64", hold=oct_)
+    for k in (1, 2, 5, 12):
+        m = to_dev(m0, dt_)
+        it, tq = plan.minimize(m, MS, A, tol=0.0, max_iter=k, h_ext=hz)
+        ref, kr, tqr = oracle.bb_minimize(m0, MS, A, d, oct_, L, h_ext=hz, tol=0.0, max_iter=k)
+        assert it == kr == k
+        e = np.abs(m.cpu().numpy() - ref).max()
+        _say("bb iterate", k, e, tq, tqr)
+        assert e <= 1e-10 and abs(tq / tqr - 1) <= 1e-8
+    ref, kr, tqr = oracle.bb_minimize(m0, MS, A, d, oct_, L, h_ext=hz, tol=1e-2)
+    Eref = oracle.total_energy(ref, MS, A, d, oct_, L, h_ext=hz)
+    for prec, tol, mtol, etol in (("f64", 1e-2, 1e-6, 1e-8), ("f32", 1.0, 2e-4, 1e-6)):
+        plan, dt_ = _plan(n, d, prec, hold=oct_ if prec == "f64" else None)
+        m = to_dev(rounded(m0, dt_), dt_)
+        it, tq = plan.minimize(m, MS, A, tol=tol, max_iter=5000, h_ext=hz)
+        got = m.cpu().numpy()
+        E = oracle.total_energy(got, MS, A, d, oct_, L, h_ext=hz)
+        _say("bb converged", prec, it, kr, tq, np.abs(got - ref).max(), E / Eref - 1)
+        assert tq <= tol
+        assert np.abs(got - ref).max() <= mtol
+        assert abs(E / Eref - 1) <= etol
