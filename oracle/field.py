@@ -8,12 +8,18 @@
   sum over the 6 neighbours j inside the grid of (m_j - m_i)/d_a^2 (a missing
   neighbour contributes nothing).  A cell with Ms = 0 is vacuum: it is no
   neighbour of anything and its own exchange field is 0.
+* DMI (paper eq. (3)): h_dmi,i = 2D/(mu0 Ms_i) sum_k e_k^DMI x dm/dk with
+  e^DMI = (e_y, -e_x, 0) for interfacial and (e_x, e_y, e_z) for bulk DMI;
+  dm/dk by central differences (m_{i+1} - m_{i-1}) / (2 d_k).  The paper is
+  silent on the boundary; reading: a neighbour outside the grid or in vacuum
+  is replaced by the cell itself (as for exchange), so its difference is 0.
 * energies: E = -(mu0/2) V sum_i Ms_i m_i . h_i for each term, in FP64.
 
 Pins (tests/test_oracle_field.py): direct sum == FFT convolution; naive DFT ==
 numpy.fft; a uniformly magnetised cube/prism block gives the block's Newell
 self term (Aharoni); exchange of a uniform m is 0; the discrete helix closed
-form; the exchange energy pair-sum identity.
+form; the exchange energy pair-sum identity; the discrete cycloid (interfacial)
+and helix (bulk) closed forms of the DMI field; DMI of a uniform m is 0.
 """
 import numpy as np
 
@@ -148,12 +154,53 @@ def exchange_field(m, Ms, A, d):
     return pref[..., None] * lap
 
 
-def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None):
+def dmi_field(m, Ms, D, d, kind):
+    """DMI field of eq. (3); kind "interfacial" or "bulk"."""
+    m = np.asarray(m, dtype=np.float64)
+    nx, ny, nz, _ = m.shape
+    Msa = _ms_array(Ms, (nx, ny, nz))
+    mag = Msa > 0
+    # central difference along each axis, missing / vacuum neighbour -> the cell
+    dm = []
+    for ax in range(3):
+        diff = np.zeros_like(m)
+        for s in (+1, -1):
+            nb = m.copy()
+            src = [slice(None)] * 3
+            dst = [slice(None)] * 3
+            if s == +1:
+                src[ax], dst[ax] = slice(1, None), slice(0, -1)
+            else:
+                src[ax], dst[ax] = slice(0, -1), slice(1, None)
+            okm = np.zeros(mag.shape, dtype=bool)
+            okm[tuple(dst)] = mag[tuple(src)]
+            nb[tuple(dst)] = m[tuple(src)]
+            nb = np.where(okm[..., None], nb, m)
+            diff += s * (nb - m)
+        dm.append(diff / (2.0 * d[ax]))
+    ex, ey, ez = np.eye(3)
+    if kind == "interfacial":
+        evec = (ey, -ex, np.zeros(3))
+    elif kind == "bulk":
+        evec = (ex, ey, ez)
+    else:
+        raise ValueError("kind must be interfacial or bulk")
+    h = np.zeros_like(m)
+    for k in range(3):
+        h += np.cross(np.broadcast_to(evec[k], m.shape), dm[k])
+    pref = np.where(mag, 2.0 * D / (MU0 * np.where(mag, Msa, 1.0)), 0.0)
+    return pref[..., None] * h
+
+
+def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None, dmi=None):
+    """dmi: None or (kind, D)."""
     h = np.zeros(np.asarray(m).shape)
     if demag:
         h = h + demag_fft(m, Ms, octant, L)
     if exchange:
         h = h + exchange_field(m, Ms, A, d)
+    if dmi is not None:
+        h = h + dmi_field(m, Ms, dmi[1], d, dmi[0])
     if h_ext is not None:
         h = h + np.asarray(h_ext, dtype=np.float64)
     return h

@@ -165,3 +165,54 @@ def test_exchange_at_matches_field():
     cells = synth.sample_cells(n, 3, 12)
     full = oracle.exchange_field(m, Ms, A, d)
     assert np.array_equal(oracle.exchange_at(m, Ms, A, d, cells), full[cells[:, 0], cells[:, 1], cells[:, 2]])
+
+
+# ---- DMI (eq. (3)) -----------------------------------------------------------
+def test_dmi_uniform_is_zero():
+    m = np.zeros((5, 4, 3, 3))
+    m[..., 0] = 0.6
+    m[..., 2] = 0.8
+    d = (2e-9, 3e-9, 1e-9)
+    for kind in ("interfacial", "bulk"):
+        assert np.abs(oracle.dmi_field(m, 8e5, 3e-3, d, kind)).max() == 0.0
+
+
+def _pref(D, Ms):
+    return 2.0 * D / (oracle.MU0 * Ms)
+
+
+def test_dmi_interfacial_cycloid_closed_form():
+    """m = (sin kx, 0, cos kx): in the interior the central differences give
+    dm/dx = sin(kd)/d (cos kx, 0, -sin kx), so eq. (3) with
+    e^DMI = (e_y, -e_x, 0) gives h = -(2D/mu0 Ms) sin(kd)/d m."""
+    nx, d, D, Ms, k = 24, (2e-9, 2e-9, 1e-9), 3e-3, 8e5, 2 * np.pi / 17e-9
+    x = (np.arange(nx) + 0.5) * d[0]
+    m = np.zeros((nx, 3, 1, 3))
+    m[..., 0] = np.sin(k * x)[:, None, None]
+    m[..., 2] = np.cos(k * x)[:, None, None]
+    h = oracle.dmi_field(m, Ms, D, d, "interfacial")
+    ref = -_pref(D, Ms) * np.sin(k * d[0]) / d[0] * m
+    assert np.abs(h[1:-1] - ref[1:-1]).max() <= 1e-12 * np.abs(ref).max()
+    # the same texture along z feels no interfacial DMI (e_z^DMI = 0)
+    mz = np.transpose(m, (2, 1, 0, 3))
+    assert np.abs(oracle.dmi_field(mz, Ms, D, d, "interfacial")).max() == 0.0
+
+
+def test_dmi_bulk_helix_closed_form():
+    """m = (cos kz, sin kz, 0) along z and m = (0, cos kx, sin kx) along x:
+    bulk DMI (e^DMI = e_k) gives h = -(2D/mu0 Ms) sin(kd)/d m in the interior."""
+    n, d, D, Ms, k = 20, (1.5e-9, 2e-9, 2.5e-9), 2e-3, 6e5, 2 * np.pi / 23e-9
+    z = (np.arange(n) + 0.5) * d[2]
+    m = np.zeros((2, 2, n, 3))
+    m[..., 0] = np.cos(k * z)
+    m[..., 1] = np.sin(k * z)
+    h = oracle.dmi_field(m, Ms, D, d, "bulk")
+    ref = -_pref(D, Ms) * np.sin(k * d[2]) / d[2] * m
+    assert np.abs(h[:, :, 1:-1] - ref[:, :, 1:-1]).max() <= 1e-12 * np.abs(ref).max()
+    x = (np.arange(n) + 0.5) * d[0]
+    m = np.zeros((n, 2, 2, 3))
+    m[..., 1] = np.cos(k * x)[:, None, None]
+    m[..., 2] = np.sin(k * x)[:, None, None]
+    h = oracle.dmi_field(m, Ms, D, d, "bulk")
+    ref = -_pref(D, Ms) * np.sin(k * d[0]) / d[0] * m
+    assert np.abs(h[1:-1] - ref[1:-1]).max() <= 1e-12 * np.abs(ref).max()
