@@ -146,6 +146,20 @@ int mm_plan_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts
 int mm_plan_attach_memory(mm_plan *plan, void *tensor_buf, void *workspace_buf);
 int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
 
+/*
+ * mm_plan_set_dmi -- add the Dzyaloshinskii-Moriya field of eq. (3),
+ *   h_dmi = 2D/(mu0 Ms_i) sum_k e_k^DMI x dm/dk,
+ * with e^DMI = (e_y, -e_x, 0) (kind 1, interfacial) or (e_x, e_y, e_z)
+ * (kind 2, bulk), to every later field evaluation of the plan (h_eff,
+ * llg_step, llg_rkf45_step, mm_minimize_bb).  dm/dk are central differences
+ * (m_{i+1} - m_{i-1})/(2 d_k); the paper gives no boundary condition, and a
+ * neighbour outside the grid or with Ms = 0 is taken equal to the cell (its
+ * difference is zero).  kind 0 or D = 0 removes the term.  D in J/m^2.
+ * The energies of h_eff report demag and exchange only; the adjoint entry
+ * points return MM_ENOTSUP while the term is set.  Synchronises the stream.
+ */
+int mm_plan_set_dmi(mm_plan *plan, int kind, double D);
+
 /* Padded lengths, device bytes held, and the launch shapes in use (each
  * nullable): tiles = {z cell columns per tile, forward x columns per tile,
  * y pencils per tile (negated when the register-resident pencil kernel runs

@@ -82,6 +82,13 @@ class DemagPlan:
         check(_lib.lib().mm_plan_set_stream(self._h, _stream()))
 
     # -- API ------------------------------------------------------------------
+    def set_dmi(self, kind, D):
+        """Add the DMI field of eq. (3) to every later field evaluation:
+        kind "interfacial" or "bulk" (or None / D = 0 to remove it), D in J/m^2."""
+        k = {None: 0, "none": 0, "interfacial": 1, "bulk": 2}[kind]
+        self._sync_stream()
+        check(_lib.lib().mm_plan_set_dmi(self._h, k, float(D)))
+
     def attach_memory(self):
         """Move the plan's tensor spectrum and workspace into torch-owned
         device buffers (torch's caching allocator then holds all of the

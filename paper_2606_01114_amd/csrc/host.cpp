@@ -141,6 +141,8 @@ struct mm_plan {
     int64_t L[3] = {0, 0, 0};
     int hx = 0, hy = 0, hz = 0;
     double P = 16.0;
+    int dmi_kind = 0;          // 0 none, 1 interfacial, 2 bulk
+    double dmi_D = 0.0;        // J/m^2
     hipStream_t stream = nullptr;
     int device = 0;
     // device memory
@@ -604,6 +606,9 @@ void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double
     a.Ms = Ms; a.Ms_scalar = Ms_s;
     a.ex_pref = 2.0 * A / kMu0;
     for (int i = 0; i < 3; ++i) a.inv_d2[i] = 1.0 / (p->d[i] * p->d[i]);
+    a.dmi_kind = p->dmi_kind;
+    a.dmi_pref = 2.0 * p->dmi_D / kMu0;
+    for (int i = 0; i < 3; ++i) a.inv_2d[i] = 0.5 / p->d[i];
 }
 
 int check_plan(mm_plan *p) {
@@ -1035,6 +1040,18 @@ int mm_plan_attach_memory(mm_plan *p, void *tensor_buf, void *workspace_buf) {
     return MM_OK;
 }
 
+int mm_plan_set_dmi(mm_plan *p, int kind, double D) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    if (kind < 0 || kind > 2) return fail(MM_EINVAL, "kind must be 0 (none), 1 (interfacial) or 2 (bulk)");
+    if (!std::isfinite(D)) return fail(MM_EINVAL, "D must be finite");
+    (void)hipStreamSynchronize(p->stream);
+    p->dmi_kind = D != 0.0 ? kind : 0;
+    p->dmi_D = D;
+    // a captured step holds the field arguments by value
+    if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    return MM_OK;
+}
+
 int mm_plan_set_stream(mm_plan *p, void *s) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     p->stream = (hipStream_t)s;
@@ -1088,6 +1105,7 @@ int h_eff_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, d
     int rc = check_plan(p);
     if (rc) return rc;
     if (!m || !g_h || !g_m) return fail(MM_EINVAL, "m, g_h and g_m must be non-NULL");
+    if (p->dmi_kind) return fail(MM_ENOTSUP, "the adjoint does not include the DMI term");
     if (g_m == g_h || g_m == m) return fail(MM_EINVAL, "g_m must not alias m or g_h");
     if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "terms must be a non-empty subset of MM_DEMAG|MM_EXCHANGE");
     if ((rc = check_material(Ms, Ms_scalar, A, terms))) return rc;
@@ -1100,6 +1118,7 @@ int llg_step_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar
     int rc = check_plan(p);
     if (rc) return rc;
     if (!m || !g) return fail(MM_EINVAL, "m and g must be non-NULL");
+    if (p->dmi_kind) return fail(MM_ENOTSUP, "the adjoint does not include the DMI term");
     if (g == m) return fail(MM_EINVAL, "g must not alias m");
     if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
     if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;

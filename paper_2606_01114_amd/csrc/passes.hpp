@@ -74,6 +74,9 @@ struct ZInvArgs {
     const void *Ms; double Ms_scalar;
     double ex_pref;            // 2A/mu0
     double inv_d2[3];
+    int dmi_kind;              // 0 none, 1 interfacial, 2 bulk (eq. (3))
+    double dmi_pref;           // 2D/mu0
+    double inv_2d[3];          // 1/(2 d_k): central differences
     double hext[3];
     // heff
     const void *m; void *h_out; double *epart;  // epart: per-block (E_d, E_ex) partials or null

@@ -52,7 +52,7 @@ template <typename T, int EPI, bool MSV>
 __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i, int j, int z, CellIn<T> &in) {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int64_t sx = (int64_t)ny * nz, sy = nz;
-    const bool exch = (a.terms & 2u) != 0;
+    const bool exch = (a.terms & 2u) != 0 || a.dmi_kind != 0;   // both read the six neighbours
     const T *Ms = reinterpret_cast<const T *>(a.Ms);
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE || EPI == EPI_TAB ? a.ms_in : a.m);
     int64_t nc[6];
@@ -127,11 +127,39 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
     const int64_t cell = in.cell;
     const T msi = in.msi;
     const T *mi = in.mi;
-    // ---- exchange field
+    // ---- exchange field (and DMI, eq. (3), added to it for the dynamics)
     const bool magi = msi > T(0);
     T hex[3] = {T(0), T(0), T(0)};
+    T hdm[3] = {T(0), T(0), T(0)};
     T wq[6];
-    if (exch) {
+    if (a.dmi_kind != 0 && magi) {
+        // central differences; a missing or vacuum neighbour counts as the cell itself
+        T dq[6][3];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const bool ok = !MSV || in.msn[q] > T(0);
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dq[q][c] = ok ? in.mnb[q][c] - mi[c] : T(0);
+        }
+        T dm[3][3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dm[k][c] = (dq[2 * k + 1][c] - dq[2 * k][c]) * T(a.inv_2d[k]);
+        const T pd = T(a.dmi_pref) * recip(msi);
+        if (a.dmi_kind == 1) {
+            // e^DMI = (e_y, -e_x, 0): h = (d_x m_z, d_y m_z, -d_x m_x - d_y m_y)
+            hdm[0] = pd * dm[0][2];
+            hdm[1] = pd * dm[1][2];
+            hdm[2] = -pd * (dm[0][0] + dm[1][1]);
+        } else {
+            // e^DMI = e_k: h = curl m
+            hdm[0] = pd * (dm[1][2] - dm[2][1]);
+            hdm[1] = pd * (dm[2][0] - dm[0][2]);
+            hdm[2] = pd * (dm[0][1] - dm[1][0]);
+        }
+    }
+    if ((a.terms & 2u) != 0) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) wq[q] = (MSV && !(in.msn[q] > T(0))) ? T(0) : T(a.inv_d2[q >> 1]);
         T lap[3] = {T(0), T(0), T(0)};
@@ -146,7 +174,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
     if (EPI == EPI_HEFF) {
         T *ho = reinterpret_cast<T *>(a.h_out) + cell * 3;
 #pragma unroll
-        for (int c = 0; c < 3; ++c) ho[c] = hd[c] + hex[c] + T(a.hext[c]);
+        for (int c = 0; c < 3; ++c) ho[c] = hd[c] + hex[c] + hdm[c] + T(a.hext[c]);
         if (a.epart) {
             acc.v[0] += (double)msi * ((double)mi[0] * hd[0] + (double)mi[1] * hd[1] + (double)mi[2] * hd[2]);
             acc.v[1] += (double)msi * ((double)mi[0] * hex[0] + (double)mi[1] * hex[1] + (double)mi[2] * hex[2]);
@@ -154,7 +182,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
     } else if (EPI == EPI_STAGE) {
         T h[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + T(a.hext[c]);
+        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + hdm[c] + T(a.hext[c]);
         if (a.h_rec) {
             T *hr = reinterpret_cast<T *>(a.h_rec) + cell * 3;
 #pragma unroll
@@ -203,7 +231,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
     } else if (EPI == EPI_TAB) {
         T h[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + T(a.hext[c]);
+        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + hdm[c] + T(a.hext[c]);
         T mxh[3], mxmxh[3], f[3];
         cross3(mi, h, mxh);
         cross3(mi, mxh, mxmxh);
@@ -252,7 +280,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
     } else if (EPI == EPI_BB) {
         T h[3], mxh[3], g[3];
 #pragma unroll
-        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + T(a.hext[c]);
+        for (int c = 0; c < 3; ++c) h[c] = hd[c] + hex[c] + hdm[c] + T(a.hext[c]);
         cross3(mi, h, mxh);
         cross3(mi, mxh, g);
         T *go = reinterpret_cast<T *>(a.bb_g) + cell * 3;

@@ -158,3 +158,9 @@ def test_minimize_rejects_bad_arguments_on_host():
     it, tq = ctypes.c_int(), ctypes.c_double()
     assert L.mm_minimize_bb(None, dummy, None, 8e5, 1e-11, None, 1.0, 10, ctypes.byref(it),
                             ctypes.byref(tq)) == _lib.MM_EINVAL
+
+
+def test_set_dmi_rejects_bad_arguments_on_host():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    assert L.mm_plan_set_dmi(None, 1, 1e-3) == _lib.MM_EINVAL

@@ -361,3 +361,40 @@ def test_minimize_bb_against_oracle():
         assert tq <= tol
         assert np.abs(got - ref).max() <= mtol
         assert abs(E / Eref - 1) <= etol
+
+
+@pytest.mark.parametrize("kind,D", [("interfacial", 3e-3), ("bulk", -2e-3)])
+def test_dmi_against_oracle(kind, D):
+    """h_eff and one RK4 step with the DMI field of eq. (3) on a 24x20x3 grid
+    with per-cell Ms and a few vacuum cells, FP64 (tensor held equal) and
+    FP32; removing the term restores the plain field; the adjoint refuses."""
+    import torch
+    from paper_2606_01114_amd._lib import MM_ENOTSUP, MMError
+    n, d = (24, 20, 3), (2e-9, 2.5e-9, 1.5e-9)
+    oct_ = oracle.tensor_octant(n, d)
+    L = tuple(oracle.default_L(v) for v in n)
+    m0 = synth.random_unit(n, 51)
+    Ms = synth.ms_field(n, 52)
+    Ms[3, 4, 1] = Ms[10, 0, 2] = Ms[23, 19, 0] = 0.0
+    ref_h = oracle.h_eff(m0, Ms, A, d, oct_, L, dmi=(kind, D))
+    heff = lambda s: oracle.h_eff(s, Ms, A, d, oct_, L, dmi=(kind, D))
+    dt = 2e-14
+    ref_s = oracle.rk4_step(m0, Ms, A, d, oct_, L, ALPHA, GAMMA, dt, heff=heff)
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        plan, dt_ = _plan(n, d, prec, hold=oct_ if prec == "f64" else None)
+        mr, Msr = rounded(m0, dt_), rounded(Ms, dt_)
+        plan.set_dmi(kind, D)
+        h = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A)
+        e = rel_l2(h.cpu().numpy(), ref_h)
+        m = to_dev(mr, dt_)
+        plan.llg_step(m, to_dev(Msr, dt_), A, ALPHA, GAMMA, dt)
+        es = rel_l2(m.cpu().numpy() - m0, ref_s - m0)
+        _say("dmi", kind, prec, e, es)
+        assert e <= tol and es <= tol
+        with pytest.raises(MMError) as ei:
+            plan.h_eff_adjoint(to_dev(mr, dt_), to_dev(Msr, dt_), A, h)
+        assert ei.value.code == MM_ENOTSUP
+        plan.set_dmi(None, 0.0)
+        h0 = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A)
+        assert rel_l2(h0.cpu().numpy(), oracle.h_eff(m0, Ms, A, d, oct_, L)) <= tol
+        plan.close()
