@@ -13,6 +13,8 @@
   dm/dk by central differences (m_{i+1} - m_{i-1}) / (2 d_k).  The paper is
   silent on the boundary; reading: a neighbour outside the grid or in vacuum
   is replaced by the cell itself (as for exchange), so its difference is 0.
+* uniaxial anisotropy (one of the local fields of section "Implementation"):
+  h_ani,i = 2 Ku/(mu0 Ms_i) (m_i . u) u with the unit easy axis u; 0 in vacuum.
 * energies: E = -(mu0/2) V sum_i Ms_i m_i . h_i for each term, in FP64.
 
 Pins (tests/test_oracle_field.py): direct sum == FFT convolution; naive DFT ==
@@ -192,9 +194,22 @@ def dmi_field(m, Ms, D, d, kind):
     return pref[..., None] * h
 
 
-def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None, dmi=None):
-    """dmi: None or (kind, D)."""
+def anisotropy_field(m, Ms, Ku, u):
+    """Uniaxial anisotropy field 2 Ku/(mu0 Ms) (m . u) u, u normalised here."""
+    m = np.asarray(m, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    u = u / np.linalg.norm(u)
+    Msa = _ms_array(Ms, m.shape[:3])
+    mag = Msa > 0
+    pref = np.where(mag, 2.0 * Ku / (MU0 * np.where(mag, Msa, 1.0)), 0.0)
+    return (pref * (m @ u))[..., None] * u
+
+
+def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None, dmi=None, aniso=None):
+    """dmi: None or (kind, D); aniso: None or (Ku, u)."""
     h = np.zeros(np.asarray(m).shape)
+    if aniso is not None:
+        h = h + anisotropy_field(m, Ms, aniso[0], aniso[1])
     if demag:
         h = h + demag_fft(m, Ms, octant, L)
     if exchange:

@@ -174,3 +174,47 @@ def test_rkf45_adaptive_run_within_tolerance():
     # a step far too long is rejected, leaves m unchanged and shrinks dt
     m2, err, ok, dt2 = oracle.rkf45_step(m0, MS, A, d, oct_, (1, 1, 1), 0.1, GAMMA, 5e-11, 1e-8, h_ext=(0, 0, H))
     assert not ok and np.array_equal(m2, m0) and dt2 == 0.2 * 5e-11 and err > 1e-8
+
+
+# ---- uniaxial anisotropy ---------------------------------------------------------
+def _aniso_cell(Ku, u, theta0, phi0):
+    d = (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant((1, 1, 1), d)
+    m0 = np.array([np.sin(theta0) * np.cos(phi0), np.sin(theta0) * np.sin(phi0), np.cos(theta0)]).reshape(1, 1, 1, 3)
+    heff = lambda s: oracle.h_eff(s, MS, A, d, oct_, (1, 1, 1), aniso=(Ku, u))
+    return d, oct_, m0, heff
+
+
+def test_anisotropy_undamped_precession_closed_form():
+    """One cubic cell with a z easy axis and alpha = 0: the demag self field is
+    parallel to m, so m precesses about z at fixed theta with angular rate
+    gamma H_k cos(theta), H_k = 2 Ku/(mu0 Ms)."""
+    Ku, th0, ph0 = 5e5, 0.7, 0.2
+    d, oct_, m0, heff = _aniso_cell(Ku, (0, 0, 1), th0, ph0)
+    Hk = 2 * Ku / (oracle.MU0 * MS)
+    ref = oracle.macrospin_closed_form(th0, ph0, Hk * np.cos(th0), 0.0, GAMMA, 3e-11)
+    errs = []
+    for dt, n in ((1e-13, 300), (5e-14, 600)):
+        m = oracle.rk4_run(m0, n, MS, A, d, oct_, (1, 1, 1), 0.0, GAMMA, dt, heff=heff)
+        errs.append(np.abs(m.reshape(3) - ref).max())
+    # RK4's own error, fourth order, on the exact precession
+    assert errs[1] < 2e-10 and 12 < errs[0] / errs[1] < 20
+
+
+def test_anisotropy_stoner_wohlfarth_switching_field():
+    """Field antiparallel to the easy axis: a single cell stays near +u below
+    H_k = 2 Ku/(mu0 Ms) and reverses above it (the minimiser from a slightly
+    tilted start)."""
+    Ku = 2e5
+    Hk = 2 * Ku / (oracle.MU0 * MS)
+    u = np.array([0.0, 0.6, 0.8])
+    d = (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant((1, 1, 1), d)
+    t = np.cross(u, [1.0, 0.0, 0.0])
+    m0 = (u + 0.05 * t / np.linalg.norm(t)).reshape(1, 1, 1, 3)
+    m0 = m0 / np.linalg.norm(m0)
+    for f, sign in ((0.97, 1.0), (1.03, -1.0)):
+        heff = lambda s, f=f: oracle.h_eff(s, MS, A, d, oct_, (1, 1, 1), aniso=(Ku, u)) - f * Hk * u
+        m, k, tq = oracle.bb_minimize(m0, MS, A, d, oct_, (1, 1, 1), tol=1e-6, max_iter=100000, heff=heff)
+        assert tq <= 1e-6
+        assert np.dot(m.reshape(3), u) * sign > 0.99, (f, m)
