@@ -160,6 +160,17 @@ int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
  */
 int mm_plan_set_dmi(mm_plan *plan, int kind, double D);
 
+/*
+ * mm_plan_set_anisotropy -- add the uniaxial anisotropy field
+ * 2 Ku/(mu0 Ms_i) (m_i . u) u, one of the local fields of section
+ * "Implementation", to every later field evaluation of the plan (as for
+ * mm_plan_set_dmi).  Ku in J/m^3 (0 removes the term); axis: host double[3],
+ * any non-zero length (normalised here; ignored when Ku = 0).  The energies
+ * of h_eff do not include it; the adjoint entry points return MM_ENOTSUP
+ * while it is set.  Synchronises the stream.
+ */
+int mm_plan_set_anisotropy(mm_plan *plan, double Ku, const double axis[3]);
+
 /* Padded lengths, device bytes held, and the launch shapes in use (each
  * nullable): tiles = {z cell columns per tile, forward x columns per tile,
  * y pencils per tile (negated when the register-resident pencil kernel runs

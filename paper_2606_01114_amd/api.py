@@ -89,6 +89,13 @@ class DemagPlan:
         self._sync_stream()
         check(_lib.lib().mm_plan_set_dmi(self._h, k, float(D)))
 
+    def set_anisotropy(self, Ku, axis=(0.0, 0.0, 1.0)):
+        """Add the uniaxial anisotropy field 2 Ku/(mu0 Ms) (m.u) u to every
+        later field evaluation (Ku = 0 removes it)."""
+        self._sync_stream()
+        ax = (ctypes.c_double * 3)(*[float(v) for v in axis])
+        check(_lib.lib().mm_plan_set_anisotropy(self._h, float(Ku), ax))
+
     def attach_memory(self):
         """Move the plan's tensor spectrum and workspace into torch-owned
         device buffers (torch's caching allocator then holds all of the

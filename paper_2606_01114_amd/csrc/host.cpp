@@ -143,6 +143,8 @@ struct mm_plan {
     double P = 16.0;
     int dmi_kind = 0;          // 0 none, 1 interfacial, 2 bulk
     double dmi_D = 0.0;        // J/m^2
+    double ku = 0.0;           // uniaxial anisotropy constant (J/m^3)
+    double ku_axis[3] = {0.0, 0.0, 1.0};
     hipStream_t stream = nullptr;
     int device = 0;
     // device memory
@@ -609,6 +611,8 @@ void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double
     a.dmi_kind = p->dmi_kind;
     a.dmi_pref = 2.0 * p->dmi_D / kMu0;
     for (int i = 0; i < 3; ++i) a.inv_2d[i] = 0.5 / p->d[i];
+    a.ku_pref = 2.0 * p->ku / kMu0;
+    for (int i = 0; i < 3; ++i) a.ku_axis[i] = p->ku_axis[i];
 }
 
 int check_plan(mm_plan *p) {
@@ -1052,6 +1056,23 @@ int mm_plan_set_dmi(mm_plan *p, int kind, double D) {
     return MM_OK;
 }
 
+int mm_plan_set_anisotropy(mm_plan *p, double Ku, const double axis[3]) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    if (!std::isfinite(Ku)) return fail(MM_EINVAL, "Ku must be finite");
+    double u[3] = {0.0, 0.0, 1.0};
+    if (Ku != 0.0) {
+        if (!axis) return fail(MM_EINVAL, "axis must be non-NULL");
+        const double nrm = std::sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return fail(MM_EINVAL, "axis must be finite and non-zero");
+        for (int i = 0; i < 3; ++i) u[i] = axis[i] / nrm;
+    }
+    (void)hipStreamSynchronize(p->stream);
+    p->ku = Ku;
+    for (int i = 0; i < 3; ++i) p->ku_axis[i] = u[i];
+    if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    return MM_OK;
+}
+
 int mm_plan_set_stream(mm_plan *p, void *s) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     p->stream = (hipStream_t)s;
@@ -1105,7 +1126,7 @@ int h_eff_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, d
     int rc = check_plan(p);
     if (rc) return rc;
     if (!m || !g_h || !g_m) return fail(MM_EINVAL, "m, g_h and g_m must be non-NULL");
-    if (p->dmi_kind) return fail(MM_ENOTSUP, "the adjoint does not include the DMI term");
+    if (p->dmi_kind || p->ku != 0.0) return fail(MM_ENOTSUP, "the adjoint does not include the DMI or anisotropy terms");
     if (g_m == g_h || g_m == m) return fail(MM_EINVAL, "g_m must not alias m or g_h");
     if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "terms must be a non-empty subset of MM_DEMAG|MM_EXCHANGE");
     if ((rc = check_material(Ms, Ms_scalar, A, terms))) return rc;
@@ -1118,7 +1139,7 @@ int llg_step_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar
     int rc = check_plan(p);
     if (rc) return rc;
     if (!m || !g) return fail(MM_EINVAL, "m and g must be non-NULL");
-    if (p->dmi_kind) return fail(MM_ENOTSUP, "the adjoint does not include the DMI term");
+    if (p->dmi_kind || p->ku != 0.0) return fail(MM_ENOTSUP, "the adjoint does not include the DMI or anisotropy terms");
     if (g == m) return fail(MM_EINVAL, "g must not alias m");
     if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
     if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;

@@ -77,6 +77,8 @@ struct ZInvArgs {
     int dmi_kind;              // 0 none, 1 interfacial, 2 bulk (eq. (3))
     double dmi_pref;           // 2D/mu0
     double inv_2d[3];          // 1/(2 d_k): central differences
+    double ku_pref;            // 2 Ku/mu0 (uniaxial anisotropy; 0 = none)
+    double ku_axis[3];         // unit easy axis
     double hext[3];
     // heff
     const void *m; void *h_out; double *epart;  // epart: per-block (E_d, E_ex) partials or null

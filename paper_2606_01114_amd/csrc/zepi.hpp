@@ -159,6 +159,15 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
             hdm[2] = pd * (dm[0][1] - dm[1][0]);
         }
     }
+    if (a.ku_pref != 0.0 && magi) {
+        // uniaxial anisotropy 2 Ku/(mu0 Ms) (m . u) u, a local term: it goes
+        // with the DMI field into every output and right-hand side
+        const T ux = T(a.ku_axis[0]), uy = T(a.ku_axis[1]), uz = T(a.ku_axis[2]);
+        const T s = T(a.ku_pref) * recip(msi) * (mi[0] * ux + mi[1] * uy + mi[2] * uz);
+        hdm[0] += s * ux;
+        hdm[1] += s * uy;
+        hdm[2] += s * uz;
+    }
     if ((a.terms & 2u) != 0) {
 #pragma unroll
         for (int q = 0; q < 6; ++q) wq[q] = (MSV && !(in.msn[q] > T(0))) ? T(0) : T(a.inv_d2[q >> 1]);

@@ -398,3 +398,45 @@ def test_dmi_against_oracle(kind, D):
         h0 = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A)
         assert rel_l2(h0.cpu().numpy(), oracle.h_eff(m0, Ms, A, d, oct_, L)) <= tol
         plan.close()
+
+
+def test_anisotropy_with_dmi_against_oracle():
+    """Uniaxial anisotropy (tilted axis) together with interfacial DMI: h_eff
+    and one RK4 step against the oracle, FP64 (tensor held equal) and FP32;
+    the minimiser reproduces the Stoner-Wohlfarth reversal of a single cell."""
+    import torch
+    n, d = (16, 12, 2), (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant(n, d)
+    L = tuple(oracle.default_L(v) for v in n)
+    m0 = synth.random_unit(n, 61)
+    Ms = synth.ms_field(n, 62)
+    Ku, u = 4e5, (0.3, -0.4, 0.866)
+    heff = lambda s: oracle.h_eff(s, Ms, A, d, oct_, L, dmi=("interfacial", 2e-3), aniso=(Ku, u))
+    ref_h = heff(m0)
+    dt = 2e-14
+    ref_s = oracle.rk4_step(m0, Ms, A, d, oct_, L, ALPHA, GAMMA, dt, heff=heff)
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        plan, dt_ = _plan(n, d, prec, hold=oct_ if prec == "f64" else None)
+        mr, Msr = rounded(m0, dt_), rounded(Ms, dt_)
+        plan.set_dmi("interfacial", 2e-3)
+        plan.set_anisotropy(Ku, u)
+        h = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A)
+        m = to_dev(mr, dt_)
+        plan.llg_step(m, to_dev(Msr, dt_), A, ALPHA, GAMMA, dt)
+        e, es = rel_l2(h.cpu().numpy(), ref_h), rel_l2(m.cpu().numpy() - m0, ref_s - m0)
+        _say("aniso", prec, e, es)
+        assert e <= tol and es <= tol
+        plan.close()
+    # single cell: reverses above H_k = 2 Ku/(mu0 Ms), stays below
+    d1 = (2e-9, 2e-9, 2e-9)
+    Hk = 2 * 2e5 / (oracle.MU0 * MS)
+    uu = np.array([0.0, 0.6, 0.8])
+    t = np.cross(uu, [1.0, 0.0, 0.0])
+    m1 = (uu + 0.05 * t / np.linalg.norm(t)).reshape(1, 1, 1, 3)
+    m1 = m1 / np.linalg.norm(m1)
+    plan, dt_ = _plan((1, 1, 1), d1, "f64")
+    plan.set_anisotropy(2e5, uu)
+    for f, sign in ((0.97, 1.0), (1.03, -1.0)):
+        m = to_dev(m1, dt_)
+        it, tq = plan.minimize(m, MS, A, tol=1e-6, max_iter=100000, h_ext=tuple(-f * Hk * uu))
+        assert tq <= 1e-6 and np.dot(m.cpu().numpy().reshape(3), uu) * sign > 0.99, (f, it)
