@@ -49,11 +49,11 @@ PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
 # kernel-name patterns of each pass (specialised first, runtime-planned second)
 KERNEL_PATTERNS = {
     "z_fwd": [r"k_zfwd_ct<float", r"k_zfwd<float"],
-    "x_fwd": [r"k_line_(ct|pp)<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
+    "x_fwd": [r"k_line_(ct|hx)<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
     "y_fused": [r"k_fused_y_(ct|hx)<float", r"k_fused_y<float"],
-    "x_inv": [r"k_line_(ct|pp)<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
-    "z_inv_stage": [r"k_zinv_ct<float, \d+, 1>", r"k_zinv<float, 1>"],
-    "z_inv_heff": [r"k_zinv_ct<float, \d+, 0>", r"k_zinv<float, 0>"],
+    "x_inv": [r"k_line_(ct|hx)<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
+    "z_inv_stage": [r"k_zinv_ct<float, \d+, 1,", r"k_zinv<float, 1>"],
+    "z_inv_heff": [r"k_zinv_ct<float, \d+, 0,", r"k_zinv<float, 0>"],
 }
 KERNEL_SYMBOL = {"z_fwd": "k_zfwd_ct", "x_fwd": "k_line_ct", "y_fused": "k_fused_y_ct", "x_inv": "k_line_ct",
                  "z_inv_stage": "k_zinv_ct", "z_inv_heff": "k_zinv_ct"}
@@ -477,7 +477,13 @@ def main():
     share = {k: res["passes"][k] * launches[k] for k in launches}
     dom = max(share, key=share.get)
     ach = pb[dom] / (res["passes"][dom] * 1e-3)
-    roof = {"bound": "hbm", "kernel": KERNEL_SYMBOL[dom] + " (" + dom + ")", "achieved": ach / 1e9,
+    sym = dict(KERNEL_SYMBOL)
+    if res["tiles"][2] < 0:
+        sym["y_fused"] = "k_fused_y_hx"
+    for pname, v in (("x_fwd", res["tiles"][3]), ("x_inv", res["tiles"][4])):
+        if v == 2:
+            sym[pname] = "k_line_hx"
+    roof = {"bound": "hbm", "kernel": sym[dom] + " (" + dom + ")", "achieved": ach / 1e9,
             "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach / HBM_PEAK,
             "traffic": load_traffic(dom, args.workload, args.prec),
             "algorithmic_bytes_per_launch": pb[dom], "launch_ms": res["passes"][dom]}

@@ -100,7 +100,7 @@ __device__ __forceinline__ void zfwd_ct_body(const ZFwdArgs &a, uint32_t tile) {
 // loads are issued before either's arithmetic.  The demag field sample z of
 // component c sits in line 3 pl + c, slot z/2, real part for even z; the next
 // stage's source is written back to the same place.
-template <typename T, int N, int EPI, bool MSV>
+template <typename T, int N, int EPI, bool MSV, bool LOC>
 __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int64_t pos0, int ncells, bool demag,
                                            Acc4 &acc, int tid) {
     constexpr int NT = zthreads(N), PT = zpitch(N);
@@ -121,7 +121,7 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
             for (int c = 0; c < 3; ++c) hd[c] = reinterpret_cast<const T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1];
         }
         T srcn[3] = {T(0), T(0), T(0)};
-        cell_compute<T, EPI, MSV>(a, in, hd, acc, srcn);
+        cell_compute<T, EPI, MSV, LOC>(a, in, hd, acc, srcn);
         if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) reinterpret_cast<T *>(&lds[(pl * 3 + c) * PT + sw<N>(z >> 1)])[z & 1] = srcn[c];
@@ -134,17 +134,17 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
         int64_t c0, c1 = 0;
         where(e0, pl0, z0, c0, i0, j0);
         CellIn<T> in0, in1;
-        cell_load<T, EPI, MSV>(a, c0, i0, j0, z0, in0);
+        cell_load<T, EPI, MSV, LOC>(a, c0, i0, j0, z0, in0);
         if (two) {
             where(e1, pl1, z1, c1, i1, j1);
-            cell_load<T, EPI, MSV>(a, c1, i1, j1, z1, in1);
+            cell_load<T, EPI, MSV, LOC>(a, c1, i1, j1, z1, in1);
         }
         finish(pl0, z0, in0);
         if (two) finish(pl1, z1, in1);
     }
 }
 
-template <typename T, int N, int EPI>
+template <typename T, int N, int EPI, bool LOC>
 __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     using C = cplx<T>;
     constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
@@ -225,8 +225,8 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     //    3 pl + c, slot z/2, real part for even z
     Acc4 acc;
     const int ncells = wp * nz;
-    if (a.Ms) zepi_cells<T, N, EPI, true>(a, lds, pos0, ncells, demag, acc, tid);
-    else zepi_cells<T, N, EPI, false>(a, lds, pos0, ncells, demag, acc, tid);
+    if (a.Ms) zepi_cells<T, N, EPI, true, LOC>(a, lds, pos0, ncells, demag, acc, tid);
+    else zepi_cells<T, N, EPI, false, LOC>(a, lds, pos0, ncells, demag, acc, tid);
     if (EPI == EPI_HEFF && a.epart) block_energy(acc.v[0], acc.v[1], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_TAB && a.tab_last) block_max(acc.v[0], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_BB) block_bb(acc, reinterpret_cast<double *>(smem), a.bb_part + 4 * (int64_t)blk, tid);
@@ -261,15 +261,17 @@ __global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct_b(const ZFwdArgs *__res
     zfwd_ct_body<T, N, SRC>(d[e.x], (uint32_t)e.y);
 }
 
-template <typename T, int N, int EPI>
+// LOC: the plan carries DMI or anisotropy (a separate instantiation keeps
+// the plain exchange epilogue free of those registers)
+template <typename T, int N, int EPI, bool LOC>
 __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
-    zinv_ct_body<T, N, EPI>(a, xcd_tile(blockIdx.x, gridDim.x));
+    zinv_ct_body<T, N, EPI, LOC>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename T, int N, int EPI>
 __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct_b(const ZInvArgs *__restrict__ d, const int2 *__restrict__ map) {
     const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
-    zinv_ct_body<T, N, EPI>(d[e.x], (uint32_t)e.y);
+    zinv_ct_body<T, N, EPI, false>(d[e.x], (uint32_t)e.y);   // batch plans carry no local terms
 }
 
 // ---------------- launchers -------------------------------------------------
@@ -309,17 +311,23 @@ hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
     const int N = a.g.Lz / 2;
     const int tiles = (int)(((int64_t)a.g.nx * a.g.ny + zcols(N) - 1) / zcols(N));
     const size_t lds = zct_lds(a.g.Lz, sizeof(cplx<T>));
+    const bool loc = a.dmi_kind != 0 || a.ku_pref != 0.0;
+#define ZL(NN, E, L) hipLaunchKernelGGL((k_zinv_ct<T, NN, E, L>), dim3(tiles), dim3(zthreads(NN)), lds, s, a)
     switch (N) {
 #define ZI(NN)                                                                                                        \
     case NN:                                                                                                          \
-        if (epi == EPI_HEFF) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_HEFF>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
-        else if (epi == EPI_STAGE) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_STAGE>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
-        else if (epi == EPI_TAB) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_TAB>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
-        else if (epi == EPI_BB) hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_BB>), dim3(tiles), dim3(zthreads(NN)), lds, s, a); \
-        else hipLaunchKernelGGL((k_zinv_ct<T, NN, EPI_ADJ>), dim3(tiles), dim3(zthreads(NN)), lds, s, a);          \
+        if (epi == EPI_HEFF && loc) ZL(NN, EPI_HEFF, true);                                                           \
+        else if (epi == EPI_HEFF) ZL(NN, EPI_HEFF, false);                                                            \
+        else if (epi == EPI_STAGE && loc) ZL(NN, EPI_STAGE, true);                                                    \
+        else if (epi == EPI_STAGE) ZL(NN, EPI_STAGE, false);                                                          \
+        else if (epi == EPI_TAB && loc) ZL(NN, EPI_TAB, true);                                                        \
+        else if (epi == EPI_TAB) ZL(NN, EPI_TAB, false);                                                              \
+        else if (epi == EPI_BB) ZL(NN, EPI_BB, true);                                                                 \
+        else ZL(NN, EPI_ADJ, false);                                                                                  \
         break;
         ZN_CASES(ZI)
 #undef ZI
+#undef ZL
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

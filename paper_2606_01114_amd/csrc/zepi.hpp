@@ -32,7 +32,8 @@ __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b 
 // loads of several cells can be in flight together.  MSV: Ms is a per-cell
 // field (else the scalar).  A neighbour outside the domain is replaced by the
 // cell itself (its difference term is exactly zero: the Neumann condition);
-// a vacuum neighbour gets weight 0.
+// a vacuum neighbour gets weight 0.  LOC: the plan may carry DMI or
+// anisotropy (else those terms are compiled out; their runtime checks stay).
 // per-thread accumulators of an epilogue: energies (sums 0, 1), the RK
 // error (max 0), or the minimiser's dot products (sums 0-2) and torque (max 3)
 struct Acc4 {
@@ -48,11 +49,11 @@ struct CellIn {
     T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[kMaxTabStages - 1][3], mp[3], gp[3];
 };
 
-template <typename T, int EPI, bool MSV>
+template <typename T, int EPI, bool MSV, bool LOC = true>
 __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i, int j, int z, CellIn<T> &in) {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const int64_t sx = (int64_t)ny * nz, sy = nz;
-    const bool exch = (a.terms & 2u) != 0 || a.dmi_kind != 0;   // both read the six neighbours
+    const bool exch = (a.terms & 2u) != 0 || (LOC && a.dmi_kind != 0);   // both read the six neighbours
     const T *Ms = reinterpret_cast<const T *>(a.Ms);
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE || EPI == EPI_TAB ? a.ms_in : a.m);
     int64_t nc[6];
@@ -119,7 +120,7 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
 
 // hd = demag field at the cell (0 if not requested).  Returns in src_next the
 // next stage's z-transform source Ms * m_next (EPI_STAGE only).
-template <typename T, int EPI, bool MSV>
+template <typename T, int EPI, bool MSV, bool LOC = true>
 __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> &in, const T hd[3], Acc4 &acc,
                                              T src_next[3]) {
     const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
@@ -132,7 +133,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
     T hex[3] = {T(0), T(0), T(0)};
     T hdm[3] = {T(0), T(0), T(0)};
     T wq[6];
-    if (a.dmi_kind != 0 && magi) {
+    if (LOC && a.dmi_kind != 0 && magi) {
         // central differences; a missing or vacuum neighbour counts as the cell itself
         T dq[6][3];
 #pragma unroll
@@ -159,7 +160,7 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
             hdm[2] = pd * (dm[0][1] - dm[1][0]);
         }
     }
-    if (a.ku_pref != 0.0 && magi) {
+    if (LOC && a.ku_pref != 0.0 && magi) {
         // uniaxial anisotropy 2 Ku/(mu0 Ms) (m . u) u, a local term: it goes
         // with the DMI field into every output and right-hand side
         const T ux = T(a.ku_axis[0]), uy = T(a.ku_axis[1]), uz = T(a.ku_axis[2]);
