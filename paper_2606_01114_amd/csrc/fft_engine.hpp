@@ -19,10 +19,18 @@ constexpr int ptw(int L, bool rev, int s) { return s == 0 ? 0 : ptw(L, rev, s - 
 // LDS banks instead of hitting every 16th word.
 constexpr int swz(int L, int p) { return L >= 32 ? p + (p >> 4) : p; }
 constexpr int line_len(int L) { return L >= 32 ? L + L / 16 : L; }
-// LDS pitch of a line (swizzled length plus a shift that spreads the NL
-// interleaved lines over the banks)
-constexpr int lds_pitch(int L, int NL) {
-    return line_len(L) + (NL >= 32 ? 1 : (NL == 3 ? 11 : 32 / (NL < 1 ? 1 : NL)));
+// LDS pitch of a line of csz-byte values: the swizzled length plus a shift
+// that spreads the NL interleaved lines over the banks.  LDS serves 128 bytes
+// (32 four-byte banks) per cycle, i.e. 16 lanes of a 64-bit access or 8 lanes
+// of a 128-bit one; the lanes of one such group read or write neighbouring
+// lines at the same position, so consecutive lines are shifted by
+// (lanes per group / NL) values, or by one when NL covers the group.  Three
+// lines (the components of one pencil) take an odd shift that also separates
+// the radix-16 scatter of short lines.
+constexpr int lds_pitch(int L, int NL, int csz) {
+    const int lanes = 128 / csz;
+    const int pad = NL == 3 ? (L == 64 ? 7 : L == 128 ? 3 : 11) : (NL >= lanes ? 1 : lanes / (NL < 1 ? 1 : NL));
+    return line_len(L) + pad;
 }
 }  // namespace ct
 
@@ -112,7 +120,7 @@ template <int L, bool REV, int S> struct HxStage {
     static constexpr int TWO = ct::ptw(L, REV, S);
 };
 
-template <int L, int NL> constexpr int hx_pitch() { return ct::lds_pitch(L / 2, NL); }
+template <int L, int NL, int CS> constexpr int hx_pitch() { return ct::lds_pitch(L / 2, NL, CS); }
 
 // twiddles and the radix-R DFT of stage S (order REV, table tw) on registers
 template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int PR, int U, int R>
@@ -144,7 +152,7 @@ __device__ __forceinline__ void hx_compute(cplx<T> (&v)[U][R], const cplx<T> *__
 template <typename T, int L, bool REV, int S, int NT, int NL, int UO, int RO>
 __device__ __forceinline__ void hx_put(cplx<T> *lds, const cplx<T> (&o)[UO][RO], int h, int tid) {
     using A = HxStage<L, REV, S>;
-    constexpr int PH = hx_pitch<L, NL>();
+    constexpr int PH = hx_pitch<L, NL, (int)sizeof(cplx<T>)>();
     static_assert(A::Ns * A::R <= L / 2, "a stage before the last writes whole blocks of one half");
 #pragma unroll
     for (int u = 0; u < UO; ++u) {
@@ -166,7 +174,7 @@ __device__ __forceinline__ void hx_put(cplx<T> *lds, const cplx<T> (&o)[UO][RO],
 template <typename T, int L, bool REV, int S, int NT, int NL, int UI, int RI>
 __device__ __forceinline__ void hx_get(const cplx<T> *lds, cplx<T> (&v)[UI][RI], int h, int tid) {
     using B = HxStage<L, REV, S>;
-    constexpr int PH = hx_pitch<L, NL>();
+    constexpr int PH = hx_pitch<L, NL, (int)sizeof(cplx<T>)>();
 #pragma unroll
     for (int u = 0; u < UI; ++u) {
         const int b = tid + u * NT;
@@ -260,7 +268,7 @@ __device__ __forceinline__ void eng_fft_hx(cplx<T> *lds, const cplx<T> *__restri
 
 template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int PR = 0, class Ld, class St>
 __device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
-    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL), PR>(lds, tw, tid, ld, st);
+    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL, (int)sizeof(cplx<T>)), PR>(lds, tw, tid, ld, st);
 }
 
 // stages [S, E) LDS -> LDS with interleave LA and pitch P

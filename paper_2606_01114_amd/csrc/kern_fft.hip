@@ -252,7 +252,7 @@ template <typename T, int L, int NT, class Pr>
 __device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restrict__ twf, int tid, const Pr &prod) {
     using C = cplx<T>;
     constexpr int NS = ct::nst(L);
-    constexpr int P = ct::lds_pitch(L, 3);
+    constexpr int P = ct::lds_pitch(L, 3, (int)sizeof(cplx<T>));
     constexpr int R = ct::prad(L, false, NS - 1);
     constexpr int NB = L / R;
     constexpr int Nsf = ct::pns(L, false, NS - 1);
@@ -335,7 +335,7 @@ __device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__r
                                                 const PencilTensor<T, L, NT> &pt) {
     using C = cplx<T>;
     constexpr int NS = ct::nst(L);
-    constexpr int P = ct::lds_pitch(L, 3);
+    constexpr int P = ct::lds_pitch(L, 3, (int)sizeof(cplx<T>));
     constexpr int R = ct::prad(L, false, NS - 1);
     constexpr int NB = L / R;
     constexpr int Nsf = ct::pns(L, false, NS - 1);
@@ -471,7 +471,7 @@ template <int L, int NT> struct FusedHx {
     static constexpr int RC = ct::prad(L, false, NS - 1);
     static constexpr int NBC = L / RC;
     static constexpr int UC = (NBC + NT - 1) / NT;
-    static constexpr int PH = hx_pitch<L, 3>();
+    static constexpr int PH = hx_pitch<L, 3, 8>();   // the three-line shift is the same for both value sizes
 };
 
 // forward stage S's outputs v -> ... -> the middle's inputs vc
@@ -710,9 +710,9 @@ hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStrea
 }
 #undef LINE_CASE
 
-size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W) * csz; }
-size_t line_hx_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L / 2, W) * csz; }
-size_t fused_ct_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L, 3) * csz; }
+size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W, (int)csz) * csz; }
+size_t line_hx_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L / 2, W, (int)csz) * csz; }
+size_t fused_ct_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L, 3, (int)csz) * csz; }
 
 int fused_ct_threads(int L, size_t csz) {
     switch (L) {
@@ -757,7 +757,7 @@ int fused_hx_threads(int L) {
     default: return 0;
     }
 }
-size_t fused_hx_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L / 2, 3) * csz; }
+size_t fused_hx_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L / 2, 3, (int)csz) * csz; }
 
 template <typename T>
 hipError_t launch_fused_hx(const FusedPass &a, hipStream_t s) {

@@ -10,7 +10,12 @@
 namespace mmx {
 
 namespace {
-constexpr int zpitch(int N) { return N < 16 ? N + 1 : ct::line_len(N) + 11; }
+// LDS pitch of a folded z line; the tile interleaves the three components of
+// each of its 3 zcols(N) columns, and the shift keeps the lanes of one
+// 128-byte LDS cycle in distinct banks in the transform's exchanges
+constexpr int zpitch(int N) {
+    return N < 16 ? N + 1 : ct::line_len(N) + (N == 32 ? 9 : N == 64 ? 7 : N == 128 ? 3 : 11);
+}
 constexpr int zcols(int N) { return N >= 1024 ? 1 : 1024 / N; }   // P: ~3072 complex per tile
 constexpr int zthreads(int N) { return 256; }
 }  // namespace
