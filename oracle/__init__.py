@@ -12,7 +12,8 @@ What it computes, in plain and slow form:
   dipole quadrature outside), its periodic wrap and its (real) spectrum.
 * ``field``   -- the demag field H = -N (*) (Ms m) as a zero-padded FFT
   convolution (numpy's FFT as the library step), as an O(N^2) direct sum, and a
-  naive DFT; the 6-point exchange field; the FP64 energies.
+  naive DFT; the 6-point exchange field; the DMI, uniaxial anisotropy and
+  Slonczewski spin-transfer fields; the FP64 energies.
 * ``llg``     -- the LLG right-hand side, the classic RK4 step and the RKF45
   step with its step-size control.
 * ``adjoint`` -- vector-Jacobian products of h_eff and of one RK4 step.
@@ -22,8 +23,8 @@ Parity status per function is stated in each module's docstring.
 """
 from .tensor import (tensor_octant, tensor_at, newell_at, far_at, newell_scale_at,
                      wrap_full, tensor_spectrum, default_L, is_7smooth)
-from .field import (MU0, demag_fft, demag_direct, naive_dft, exchange_field, exchange_at,
-                    dmi_field, anisotropy_field, h_eff, energies)
+from .field import (MU0, HBAR, E_CHARGE, demag_fft, demag_direct, naive_dft, exchange_field, exchange_at,
+                    dmi_field, anisotropy_field, stt_field, h_eff, energies)
 from .llg import (llg_rhs, rk4_step, rk4_run, macrospin_closed_form, rkf45_step, rkf45_run, rkf45_stages,
                   RKF45_A, RKF45_B4, RKF45_B5, RKF45_C)
 from .adjoint import h_eff_vjp, llg_rhs_vjp, rk4_step_vjp, rk4_run_grad_Ms

@@ -15,6 +15,16 @@
   is replaced by the cell itself (as for exchange), so its difference is 0.
 * uniaxial anisotropy (one of the local fields of section "Implementation"):
   h_ani,i = 2 Ku/(mu0 Ms_i) (m_i . u) u with the unit easy axis u; 0 in vacuum.
+* Slonczewski spin-transfer torque (the other local field named in section
+  "Implementation"; the paper takes its model from the cited literature and
+  prints no formula).  Reading: the torque of Slonczewski's model written as an
+  effective field that enters the LLG equation like every other field,
+  h_stt,i = beta_i [eps(m_i . p) (m_i x p) + eps' p],
+  beta_i = hbar j / (mu0 e Ms_i d), eps(x) = P Lam^2 / ((Lam^2 + 1) + (Lam^2 - 1) x),
+  with current density j, free-layer thickness d, spin polarisation P, the
+  asymmetry parameter Lam, the field-like ratio eps' and the unit
+  polarisation vector p; 0 in vacuum.  No energy (the torque is not
+  conservative).
 * energies: E = -(mu0/2) V sum_i Ms_i m_i . h_i for each term, in FP64.
 
 Pins (tests/test_oracle_field.py): direct sum == FFT convolution; naive DFT ==
@@ -22,12 +32,18 @@ numpy.fft; a uniformly magnetised cube/prism block gives the block's Newell
 self term (Aharoni); exchange of a uniform m is 0; the discrete helix closed
 form; the exchange energy pair-sum identity; the discrete cycloid (interfacial)
 and helix (bulk) closed forms of the DMI field; DMI of a uniform m is 0.
+Spin-transfer torque (tests/test_oracle_llg.py): the macrospin closed form
+with Lam = 1 (constant eps, field-like part and an applied field along p), and
+for Lam != 1 the polar-angle travel time from a quadrature of the exact
+angular equation together with the closed-form azimuth phi(theta).
 """
 import numpy as np
 
 from .tensor import wrap_full, PARITY
 
 MU0 = 4e-7 * np.pi
+HBAR = 1.054571817e-34      # J s (CODATA 2018)
+E_CHARGE = 1.602176634e-19  # C (exact in the SI since 2019)
 
 
 def _ms_array(Ms, shape):
@@ -205,9 +221,26 @@ def anisotropy_field(m, Ms, Ku, u):
     return (pref * (m @ u))[..., None] * u
 
 
-def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None, dmi=None, aniso=None):
-    """dmi: None or (kind, D); aniso: None or (Ku, u)."""
+def stt_field(m, Ms, j, P, Lam, eps_prime, d_layer, p):
+    """Slonczewski torque as an effective field (reading in the module
+    docstring); p is normalised here."""
+    m = np.asarray(m, dtype=np.float64)
+    p = np.asarray(p, dtype=np.float64)
+    p = p / np.linalg.norm(p)
+    Msa = _ms_array(Ms, m.shape[:3])
+    mag = Msa > 0
+    beta = np.where(mag, HBAR * j / (MU0 * E_CHARGE * np.where(mag, Msa, 1.0) * d_layer), 0.0)
+    L2 = Lam * Lam
+    eps = P * L2 / ((L2 + 1.0) + (L2 - 1.0) * (m @ p))
+    return beta[..., None] * (eps[..., None] * np.cross(m, p) + eps_prime * p)
+
+
+def h_eff(m, Ms, A, d, octant, L, demag=True, exchange=True, h_ext=None, dmi=None, aniso=None, stt=None):
+    """dmi: None or (kind, D); aniso: None or (Ku, u); stt: None or
+    (j, P, Lam, eps_prime, d_layer, p)."""
     h = np.zeros(np.asarray(m).shape)
+    if stt is not None:
+        h = h + stt_field(m, Ms, *stt)
     if aniso is not None:
         h = h + anisotropy_field(m, Ms, aniso[0], aniso[1])
     if demag:

@@ -218,3 +218,70 @@ def test_anisotropy_stoner_wohlfarth_switching_field():
         m, k, tq = oracle.bb_minimize(m0, MS, A, d, oct_, (1, 1, 1), tol=1e-6, max_iter=100000, heff=heff)
         assert tq <= 1e-6
         assert np.dot(m.reshape(3), u) * sign > 0.99, (f, m)
+
+
+# ---- Slonczewski spin-transfer torque ------------------------------------------
+def _stt_beta(j, d_layer):
+    return oracle.HBAR * j / (oracle.MU0 * oracle.E_CHARGE * MS * d_layer)
+
+
+def test_stt_macrospin_closed_form_constant_eps():
+    """Lam = 1 makes eps = P/2 constant.  One cubic cell (no demag torque, no
+    exchange) with p and an applied field H along z: the field is
+    H' z + b (m x z) with H' = H + beta eps', b = beta eps, and the motion is
+    phi = phi0 + g (H' - alpha b) t, tan(theta/2) = tan(theta0/2) exp(-g (b + alpha H') t)."""
+    j, d_layer, P, epsp, alpha, H = 5e11, 2e-9, 0.4, 0.1, 0.05, 1e5
+    d = (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant((1, 1, 1), d)
+    th0, ph0 = 1.1, -0.4
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(1, 1, 1, 3)
+    stt = (j, P, 1.0, epsp, d_layer, (0.0, 0.0, 2.0))
+    heff = lambda s: oracle.h_eff(s, MS, A, d, oct_, (1, 1, 1), h_ext=(0, 0, H), stt=stt)
+    beta = _stt_beta(j, d_layer)
+    b, Hp = beta * P / 2, H + beta * epsp
+    g = GAMMA / (1 + alpha * alpha)
+    T = 4e-11
+    ph = ph0 + g * (Hp - alpha * b) * T
+    th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-g * (b + alpha * Hp) * T))
+    ref = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    errs = []
+    for dt, n in ((2e-13, 200), (1e-13, 400)):
+        m = oracle.rk4_run(m0, n, MS, A, d, oct_, (1, 1, 1), alpha, GAMMA, dt, heff=heff)
+        errs.append(np.abs(m.reshape(3) - ref).max())
+    assert errs[1] < 1e-9 and 12 < errs[0] / errs[1] < 20, errs
+
+
+def test_stt_polar_travel_time_and_azimuth():
+    """Lam = 2 (eps depends on m . p), no applied field, eps' = 0, negative
+    current: theta obeys dtheta/dt = -g beta eps(cos theta) sin theta, so the
+    time from theta0 to theta1 is a quadrature, and dphi/dtheta = alpha/sin theta
+    gives phi1 - phi0 = alpha ln(tan(theta1/2)/tan(theta0/2)) whatever eps is."""
+    from scipy.integrate import quad
+    j, d_layer, P, Lam, alpha = -8e11, 2e-9, 0.5, 2.0, 0.02
+    d = (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant((1, 1, 1), d)
+    th0, th1, ph0 = 0.3, 2.0, 0.25
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(1, 1, 1, 3)
+    stt = (j, P, Lam, 0.0, d_layer, (0.0, 0.0, 1.0))
+    heff = lambda s: oracle.h_eff(s, MS, A, d, oct_, (1, 1, 1), stt=stt)
+    beta = _stt_beta(j, d_layer)
+    g = GAMMA / (1 + alpha * alpha)
+    L2 = Lam * Lam
+    eps = lambda th: P * L2 / ((L2 + 1) + (L2 - 1) * np.cos(th))
+    t1, qerr = quad(lambda th: 1.0 / (-g * beta * eps(th) * np.sin(th)), th0, th1, epsabs=0, epsrel=1e-13, limit=200)
+    assert qerr < 1e-12 * t1
+    n = 1500
+    m = oracle.rk4_run(m0, n, MS, A, d, oct_, (1, 1, 1), alpha, GAMMA, t1 / n, heff=heff).reshape(3)
+    assert abs(np.arccos(m[2]) - th1) < 1e-8
+    dphi = np.arctan2(m[1], m[0]) - ph0
+    assert abs(dphi - alpha * np.log(np.tan(th1 / 2) / np.tan(th0 / 2))) < 1e-8
+
+
+def test_stt_field_vanishes_without_current_and_in_vacuum():
+    m = synth.random_unit((3, 2, 2), 4)
+    Ms = np.full((3, 2, 2), MS)
+    Ms[1, 0, 1] = 0.0
+    h0 = oracle.stt_field(m, Ms, 0.0, 0.4, 1.5, 0.1, 2e-9, (1, 0, 0))
+    assert np.all(h0 == 0.0)
+    h = oracle.stt_field(m, Ms, 1e12, 0.4, 1.5, 0.1, 2e-9, (1, 0, 0))
+    assert np.all(h[1, 0, 1] == 0.0) and np.all(np.abs(h[0, 0, 0]) > 0)
