@@ -40,6 +40,9 @@ WORKLOADS = {
                 name="standard problem 4 as in the paper's script: 100x25x1 cells of 5x5x3 nm, relaxation with "
                      "the Barzilai-Borwein minimiser, then 1 ns of RKF45 LLG in (-24.6, 4.3, 0) mT, "
                      "output every 10 ps"),
+    "fields": dict(grid=None, cell=(2e-9, 2e-9, 2e-9), m="random", seed=7,
+                   name="each field term alone on a %dx%dx%d cube of random m (demag, exchange, Slonczewski "
+                        "spin-transfer torque), FP64 as the paper times them"),
     "grad": dict(grid=(256, 256, 8), cell=(2.5e-9, 2.5e-9, 3e-9), m="smooth", seed=5,
                  name="differentiable 256x256x8: 200 RK4 steps, checkpoint every 20, gradient of mean m_z "
                       "w.r.t. per-cell Ms through the adjoint"),
@@ -233,6 +236,71 @@ def run_grad(prec="f32", steps=200, every=20):
     return out
 
 
+# the paper's own per-field timings (FP64, N x N x N cube): context, another machine
+PAPER_FIELD_MS = {
+    350: {"demag": {"ms": 164.9, "hardware": "1x H100 HBM3"}},
+    400: {"demag": {"ms": 31.2, "hardware": "8x H100 HBM3 (one node)"},
+          "exchange": {"ms": 1.4, "hardware": "8x H100 HBM3 (one node)"},
+          "stt": {"ms": 0.4, "hardware": "8x H100 HBM3 (one node)"}},
+}
+
+
+def run_fields(prec, N, steps, warmup):
+    """Per-field evaluation time on an N x N x N cube as the paper times its
+    field terms (each term alone, FP64 by default): demag, exchange and the
+    Slonczewski spin-transfer torque, for the 7-smooth padding 2N and the
+    power-of-two padding."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2606_01114_amd import DemagPlan, MM_DEMAG, MM_EXCHANGE
+    dt = torch.float32 if prec == "f32" else torch.float64
+    r = 4 if prec == "f32" else 8
+    grid, cell = (N, N, N), (2e-9, 2e-9, 2e-9)
+    print("# generating inputs: random unit m on %d^3" % N, file=sys.stderr, flush=True)
+    m = torch.tensor(synth.random_unit(grid, 7), dtype=dt, device="cuda")
+    h = torch.empty_like(m)
+    out = {"grid": list(grid), "cells": N ** 3, "prec": prec, "paddings": {}}
+    p2 = 1 << int(np.ceil(np.log2(2 * N - 1)))
+    for name, L in (("7-smooth", None), ("pow2", (p2, p2, p2))):
+        print("# timing %s padding" % name, file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        plan = DemagPlan(grid, cell, prec, L=L, autotune=True)
+        torch.cuda.synchronize()
+        res = {"L": list(plan.info()["L"]), "setup_s": time.perf_counter() - t0}
+
+        def timed(terms):
+            for _ in range(warmup):
+                plan.h_eff(m, MS, A, out=h, terms=terms)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(steps):
+                plan.h_eff(m, MS, A, out=h, terms=terms)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) / steps
+
+        res["demag_ms"] = timed(MM_DEMAG)
+        res["exchange_ms"] = timed(MM_EXCHANGE)
+        plan.set_stt(1e11, P=0.4, Lambda=2.0, eps_prime=0.1, d_layer=1e-9, p=(0.0, 0.0, 1.0))
+        res["stt_ms"] = timed(0)
+        plan.set_stt(0.0)
+        # the stencil and local terms read m (neighbours from cache) and write h
+        res["exchange_GBps"] = 6 * r * N ** 3 / (res["exchange_ms"] * 1e-3) / 1e9
+        res["stt_GBps"] = 6 * r * N ** 3 / (res["stt_ms"] * 1e-3) / 1e9
+        res["demag_Mcell_per_s"] = N ** 3 / (res["demag_ms"] * 1e-3) / 1e6
+        out["paddings"][name] = res
+        plan.close()
+        del plan
+        torch.cuda.empty_cache()
+    best = min(out["paddings"].values(), key=lambda v: v["demag_ms"])
+    out["best"] = {k: best[k] for k in ("L", "demag_ms", "exchange_ms", "stt_ms")}
+    out["paper"] = PAPER_FIELD_MS.get(N)
+    return out
+
+
 def run_rkf45(steps, warmup, prec, m_host, tol=1e-3):
     """Adaptive RKF45 on the large grid: attempted steps per second and
     accepted cell-updates per second (each attempt synchronises to read the
@@ -422,6 +490,8 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--fields-n", type=int, default=350, help="cube edge of the fields workload")
+    ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
@@ -438,6 +508,17 @@ def main():
                           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,
                           "data": "synthetic", "config": {"workload": WORKLOADS["sweep"]["name"]}, "extra": r}))
+        return
+    if args.workload == "fields":
+        prec = "f64" if args.prec == "f32" and not args.fields_f32 else args.prec
+        r = run_fields(prec, args.fields_n, args.steps, args.warmup)
+        print(json.dumps({"metric": "ms per demag field evaluation (each field term timed alone)",
+                          "value": r["best"]["demag_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                          "warmup": args.warmup, "ms_per_step": r["best"]["demag_ms"], "higher_is_better": False,
+                          "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+                          "config": {"workload": WORKLOADS["fields"]["name"] % (args.fields_n, args.fields_n,
+                                                                               args.fields_n)},
+                          "extra": r}))
         return
     if args.workload == "rkf45":
         print("# generating inputs: %s" % WORKLOADS["rkf45"]["name"], file=sys.stderr, flush=True)

@@ -171,6 +171,26 @@ int mm_plan_set_dmi(mm_plan *plan, int kind, double D);
  */
 int mm_plan_set_anisotropy(mm_plan *plan, double Ku, const double axis[3]);
 
+/*
+ * mm_plan_set_stt -- add the Slonczewski spin-transfer torque, the other
+ * local field of section "Implementation" (the paper times it beside demag
+ * and exchange and takes its model from the cited literature), as an
+ * effective field in every later field evaluation of the plan (as for
+ * mm_plan_set_dmi):
+ *   h_stt = beta_i [eps(m . p) (m x p) + eps_prime p],
+ *   beta_i = hbar j / (mu0 e Ms_i d_layer),
+ *   eps(x) = P lambda^2 / ((lambda^2 + 1) + (lambda^2 - 1) x).
+ * j: current density (A/m^2, 0 removes the term); P: spin polarisation;
+ * lambda > 0: the Slonczewski asymmetry parameter; eps_prime: the field-like
+ * ratio; d_layer > 0: free-layer thickness (m); pol: host double[3], the
+ * polarisation direction, any non-zero length (normalised here).  The other
+ * arguments are ignored when j = 0.  0 in cells with Ms = 0.  The energies of
+ * h_eff do not include it (the torque is not conservative); the adjoint entry
+ * points return MM_ENOTSUP while it is set.  Synchronises the stream.
+ */
+int mm_plan_set_stt(mm_plan *plan, double j, double P, double lambda, double eps_prime, double d_layer,
+                    const double pol[3]);
+
 /* Padded lengths, device bytes held, and the launch shapes in use (each
  * nullable): tiles = {z cell columns per tile, forward x columns per tile,
  * y pencils per tile (negated when the register-resident pencil kernel runs
@@ -185,7 +205,9 @@ int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int ti
  *              to use Ms_scalar for every cell
  *   A          exchange stiffness (J/m), uniform
  *   h_out      device (nx,ny,nz,3); must not alias m
- *   terms      MM_DEMAG | MM_EXCHANGE (non-zero)
+ *   terms      a subset of MM_DEMAG | MM_EXCHANGE; the plan's local terms
+ *              (DMI, anisotropy, spin-transfer torque) are always added, and
+ *              terms = 0 evaluates them alone (MM_EINVAL if the plan has none)
  *   energy_out host double[2] or NULL: receives (E_demag, E_exchange) in J,
  *              E = -(mu0/2) V sum Ms m.h per term, accumulated in FP64 with a
  *              fixed-order reduction; non-NULL makes the call synchronous,

@@ -20,6 +20,7 @@ MM_NO_RENORM, MM_NO_GRAPH = 1, 2
 EXPORTS = [
     "mm_plan_opts_default", "demag_tensor_init", "mm_plan_destroy", "mm_plan_set_stream", "mm_plan_info",
     "mm_plan_bytes", "mm_plan_attach_memory", "mm_plan_set_dmi", "mm_plan_set_anisotropy",
+    "mm_plan_set_stt",
     "h_eff", "llg_step", "llg_rkf45_step", "mm_minimize_bb", "h_eff_adjoint", "llg_step_adjoint",
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
     "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_info", "mm_batch_destroy",
@@ -59,6 +60,7 @@ def _load():
         "mm_plan_attach_memory": [vp, vp, vp],
         "mm_plan_set_dmi": [vp, ci, cd],
         "mm_plan_set_anisotropy": [vp, cd, dp],
+        "mm_plan_set_stt": [vp, cd, cd, cd, cd, cd, dp],
         "mm_plan_set_stream": [vp, vp],
         "mm_plan_info": [vp, i64p, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_int)],
         "h_eff": [vp, vp, vp, cd, cd, vp, cu, dp],

@@ -96,6 +96,16 @@ class DemagPlan:
         ax = (ctypes.c_double * 3)(*[float(v) for v in axis])
         check(_lib.lib().mm_plan_set_anisotropy(self._h, float(Ku), ax))
 
+    def set_stt(self, j, P=0.4, Lambda=1.0, eps_prime=0.0, d_layer=1e-9, p=(0.0, 0.0, 1.0)):
+        """Add the Slonczewski spin-transfer torque as an effective field,
+        beta (eps(m.p) (m x p) + eps_prime p), beta = hbar j/(mu0 e Ms d_layer),
+        eps(x) = P Lambda^2/((Lambda^2+1) + (Lambda^2-1) x), to every later
+        field evaluation (j = 0 removes it)."""
+        self._sync_stream()
+        pv = (ctypes.c_double * 3)(*[float(v) for v in p])
+        check(_lib.lib().mm_plan_set_stt(self._h, float(j), float(P), float(Lambda), float(eps_prime),
+                                         float(d_layer), pv))
+
     def attach_memory(self):
         """Move the plan's tensor spectrum and workspace into torch-owned
         device buffers (torch's caching allocator then holds all of the

@@ -39,6 +39,8 @@ int fail(int code, const char *fmt, ...) {
     } while (0)
 
 const double kMu0 = 4e-7 * M_PI;
+const double kHbar = 1.054571817e-34;     // J s (CODATA 2018)
+const double kECharge = 1.602176634e-19;  // C (exact in the SI since 2019)
 const size_t kLdsMax = 160 * 1024;        // LDS per workgroup on gfx950
 const size_t kLdsTarget = 80 * 1024;      // default budget: two workgroups per CU
 
@@ -145,6 +147,9 @@ struct mm_plan {
     double dmi_D = 0.0;        // J/m^2
     double ku = 0.0;           // uniaxial anisotropy constant (J/m^3)
     double ku_axis[3] = {0.0, 0.0, 1.0};
+    double stt_j = 0.0;        // Slonczewski torque: current density (A/m^2), 0 = none
+    double stt_P = 0.0, stt_lambda = 1.0, stt_epsp = 0.0, stt_d = 1.0;
+    double stt_p[3] = {0.0, 0.0, 1.0};
     hipStream_t stream = nullptr;
     int device = 0;
     // device memory
@@ -613,6 +618,13 @@ void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double
     for (int i = 0; i < 3; ++i) a.inv_2d[i] = 0.5 / p->d[i];
     a.ku_pref = 2.0 * p->ku / kMu0;
     for (int i = 0; i < 3; ++i) a.ku_axis[i] = p->ku_axis[i];
+    a.stt_pref = p->stt_j != 0.0 ? kHbar * p->stt_j / (kMu0 * kECharge * p->stt_d) : 0.0;
+    const double l2 = p->stt_lambda * p->stt_lambda;
+    a.stt_pl2 = p->stt_P * l2;
+    a.stt_l2p1 = l2 + 1.0;
+    a.stt_l2m1 = l2 - 1.0;
+    a.stt_epsp = p->stt_epsp;
+    for (int i = 0; i < 3; ++i) a.stt_p[i] = p->stt_p[i];
 }
 
 int check_plan(mm_plan *p) {
@@ -1073,6 +1085,30 @@ int mm_plan_set_anisotropy(mm_plan *p, double Ku, const double axis[3]) {
     return MM_OK;
 }
 
+int mm_plan_set_stt(mm_plan *p, double j, double P, double lambda, double eps_prime, double d_layer,
+                    const double pol[3]) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    if (!std::isfinite(j) || !std::isfinite(P) || !std::isfinite(lambda) || !std::isfinite(eps_prime) ||
+        !std::isfinite(d_layer))
+        return fail(MM_EINVAL, "spin-transfer parameters must be finite");
+    double u[3] = {0.0, 0.0, 1.0};
+    if (j != 0.0) {
+        if (!(lambda > 0.0)) return fail(MM_EINVAL, "lambda must be > 0");
+        if (!(d_layer > 0.0)) return fail(MM_EINVAL, "the free-layer thickness must be > 0");
+        if (!pol) return fail(MM_EINVAL, "the polarisation vector must be non-NULL");
+        const double nrm = std::sqrt(pol[0] * pol[0] + pol[1] * pol[1] + pol[2] * pol[2]);
+        if (!(nrm > 0.0) || !std::isfinite(nrm)) return fail(MM_EINVAL, "the polarisation vector must be finite and non-zero");
+        for (int i = 0; i < 3; ++i) u[i] = pol[i] / nrm;
+    }
+    (void)hipStreamSynchronize(p->stream);
+    p->stt_j = j;
+    p->stt_P = P; p->stt_lambda = j != 0.0 ? lambda : 1.0; p->stt_epsp = eps_prime;
+    p->stt_d = j != 0.0 ? d_layer : 1.0;
+    for (int i = 0; i < 3; ++i) p->stt_p[i] = u[i];
+    if (p->gexec) { (void)hipGraphExecDestroy(p->gexec); p->gexec = nullptr; }
+    return MM_OK;
+}
+
 int mm_plan_set_stream(mm_plan *p, void *s) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     p->stream = (hipStream_t)s;
@@ -1093,7 +1129,9 @@ int h_eff(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, double A,
     if (rc) return rc;
     if (!m || !h_out) return fail(MM_EINVAL, "m and h_out must be non-NULL");
     if (m == h_out) return fail(MM_EINVAL, "h_out must not alias m");
-    if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "terms must be a non-empty subset of MM_DEMAG|MM_EXCHANGE");
+    if (terms & ~(MM_DEMAG | MM_EXCHANGE)) return fail(MM_EINVAL, "terms must be a subset of MM_DEMAG|MM_EXCHANGE");
+    if (terms == 0 && !p->dmi_kind && p->ku == 0.0 && p->stt_j == 0.0)
+        return fail(MM_EINVAL, "terms is empty and the plan has no local terms");
     if ((rc = check_material(Ms, Ms_scalar, A, terms))) return rc;
     return p->prec == MM_F32 ? heff_impl<float>(p, m, Ms, Ms_scalar, A, h_out, terms, energy_out)
                              : heff_impl<double>(p, m, Ms, Ms_scalar, A, h_out, terms, energy_out);
@@ -1126,7 +1164,8 @@ int h_eff_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, d
     int rc = check_plan(p);
     if (rc) return rc;
     if (!m || !g_h || !g_m) return fail(MM_EINVAL, "m, g_h and g_m must be non-NULL");
-    if (p->dmi_kind || p->ku != 0.0) return fail(MM_ENOTSUP, "the adjoint does not include the DMI or anisotropy terms");
+    if (p->dmi_kind || p->ku != 0.0 || p->stt_j != 0.0)
+        return fail(MM_ENOTSUP, "the adjoint does not include the DMI, anisotropy or spin-transfer terms");
     if (g_m == g_h || g_m == m) return fail(MM_EINVAL, "g_m must not alias m or g_h");
     if (terms == 0 || (terms & ~(MM_DEMAG | MM_EXCHANGE))) return fail(MM_EINVAL, "terms must be a non-empty subset of MM_DEMAG|MM_EXCHANGE");
     if ((rc = check_material(Ms, Ms_scalar, A, terms))) return rc;
@@ -1139,7 +1178,8 @@ int llg_step_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar
     int rc = check_plan(p);
     if (rc) return rc;
     if (!m || !g) return fail(MM_EINVAL, "m and g must be non-NULL");
-    if (p->dmi_kind || p->ku != 0.0) return fail(MM_ENOTSUP, "the adjoint does not include the DMI or anisotropy terms");
+    if (p->dmi_kind || p->ku != 0.0 || p->stt_j != 0.0)
+        return fail(MM_ENOTSUP, "the adjoint does not include the DMI, anisotropy or spin-transfer terms");
     if (g == m) return fail(MM_EINVAL, "g must not alias m");
     if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
     if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;

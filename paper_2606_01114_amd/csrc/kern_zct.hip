@@ -266,8 +266,8 @@ __global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct_b(const ZFwdArgs *__res
     zfwd_ct_body<T, N, SRC>(d[e.x], (uint32_t)e.y);
 }
 
-// LOC: the plan carries DMI or anisotropy (a separate instantiation keeps
-// the plain exchange epilogue free of those registers)
+// LOC: the plan carries DMI, anisotropy or spin-transfer torque (a separate
+// instantiation keeps the plain exchange epilogue free of those registers)
 template <typename T, int N, int EPI, bool LOC>
 __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
     zinv_ct_body<T, N, EPI, LOC>(a, xcd_tile(blockIdx.x, gridDim.x));
@@ -316,7 +316,7 @@ hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
     const int N = a.g.Lz / 2;
     const int tiles = (int)(((int64_t)a.g.nx * a.g.ny + zcols(N) - 1) / zcols(N));
     const size_t lds = zct_lds(a.g.Lz, sizeof(cplx<T>));
-    const bool loc = a.dmi_kind != 0 || a.ku_pref != 0.0;
+    const bool loc = a.dmi_kind != 0 || a.ku_pref != 0.0 || a.stt_pref != 0.0;
 #define ZL(NN, E, L) hipLaunchKernelGGL((k_zinv_ct<T, NN, E, L>), dim3(tiles), dim3(zthreads(NN)), lds, s, a)
     switch (N) {
 #define ZI(NN)                                                                                                        \

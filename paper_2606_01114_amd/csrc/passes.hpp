@@ -79,6 +79,11 @@ struct ZInvArgs {
     double inv_2d[3];          // 1/(2 d_k): central differences
     double ku_pref;            // 2 Ku/mu0 (uniaxial anisotropy; 0 = none)
     double ku_axis[3];         // unit easy axis
+    // Slonczewski spin-transfer torque as a field: beta_i = stt_pref / Ms_i,
+    // eps(x) = stt_pl2 / (stt_l2p1 + stt_l2m1 x), h = beta (eps (m x p) + stt_epsp p)
+    double stt_pref;           // hbar j / (mu0 e d); 0 = none
+    double stt_pl2, stt_l2p1, stt_l2m1, stt_epsp;
+    double stt_p[3];           // unit polarisation
     double hext[3];
     // heff
     const void *m; void *h_out; double *epart;  // epart: per-block (E_d, E_ex) partials or null

@@ -32,8 +32,8 @@ __device__ __forceinline__ double nmax(double a, double b) { return (b > a || b 
 // loads of several cells can be in flight together.  MSV: Ms is a per-cell
 // field (else the scalar).  A neighbour outside the domain is replaced by the
 // cell itself (its difference term is exactly zero: the Neumann condition);
-// a vacuum neighbour gets weight 0.  LOC: the plan may carry DMI or
-// anisotropy (else those terms are compiled out; their runtime checks stay).
+// a vacuum neighbour gets weight 0.  LOC: the plan may carry DMI, anisotropy
+// or spin-transfer torque (else those terms are compiled out).
 // per-thread accumulators of an epilogue: energies (sums 0, 1), the RK
 // error (max 0), or the minimiser's dot products (sums 0-2) and torque (max 3)
 struct Acc4 {
@@ -168,6 +168,18 @@ __device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> 
         hdm[0] += s * ux;
         hdm[1] += s * uy;
         hdm[2] += s * uz;
+    }
+    if (LOC && a.stt_pref != 0.0 && magi) {
+        // Slonczewski torque as a field: beta (eps(m . p) (m x p) + eps' p)
+        const T p[3] = {T(a.stt_p[0]), T(a.stt_p[1]), T(a.stt_p[2])};
+        const T beta = T(a.stt_pref) * recip(msi);
+        const T mp = mi[0] * p[0] + mi[1] * p[1] + mi[2] * p[2];
+        const T be = beta * T(a.stt_pl2) * recip(T(a.stt_l2p1) + T(a.stt_l2m1) * mp);
+        const T bf = beta * T(a.stt_epsp);
+        T mxp[3];
+        cross3(mi, p, mxp);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) hdm[c] += be * mxp[c] + bf * p[c];
     }
     if ((a.terms & 2u) != 0) {
 #pragma unroll

@@ -171,3 +171,10 @@ def test_set_anisotropy_rejects_bad_arguments_on_host():
     L = _lib.lib()
     ax = (ctypes.c_double * 3)(0.0, 0.0, 1.0)
     assert L.mm_plan_set_anisotropy(None, 1e5, ax) == _lib.MM_EINVAL
+
+
+def test_set_stt_rejects_bad_arguments_on_host():
+    from paper_2606_01114_amd import _lib
+    L = _lib.lib()
+    pv = (ctypes.c_double * 3)(0.0, 0.0, 1.0)
+    assert L.mm_plan_set_stt(None, 1e11, 0.4, 1.0, 0.0, 1e-9, pv) == _lib.MM_EINVAL

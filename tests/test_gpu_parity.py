@@ -440,3 +440,74 @@ def test_anisotropy_with_dmi_against_oracle():
         m = to_dev(m1, dt_)
         it, tq = plan.minimize(m, MS, A, tol=1e-6, max_iter=100000, h_ext=tuple(-f * Hk * uu))
         assert tq <= 1e-6 and np.dot(m.cpu().numpy().reshape(3), uu) * sign > 0.99, (f, it)
+
+
+def test_stt_against_oracle():
+    """Slonczewski spin-transfer torque (lambda != 1, field-like part, tilted
+    polarisation) with anisotropy, per-cell Ms with vacuum cells: h_eff, the
+    term alone (terms = 0) and one RK4 step against the oracle, FP64 (tensor
+    held equal) and FP32, through the compile-time z kernel (nz = 2) and the
+    runtime-planned one (nz = 3, Lz = 6); removing it restores the plain
+    field; the adjoint refuses it."""
+    import torch
+    from paper_2606_01114_amd import MMError
+    stt = (6e11, 0.45, 1.7, 0.15, 2e-9, (0.2, -0.5, 0.8))
+    for n, d in (((16, 12, 2), (2e-9, 2e-9, 2e-9)), ((10, 6, 3), (2.5e-9, 2e-9, 3e-9))):
+        oct_ = oracle.tensor_octant(n, d)
+        L = tuple(oracle.default_L(v) for v in n)
+        m0 = synth.random_unit(n, 71)
+        Ms = synth.ms_field(n, 72)
+        Ms.reshape(-1)[::7] = 0.0
+        heff = lambda s: oracle.h_eff(s, Ms, A, d, oct_, L, aniso=(3e5, (0, 1, 1)), stt=stt)
+        ref_h = heff(m0)
+        ref_loc = oracle.stt_field(m0, Ms, *stt) + oracle.anisotropy_field(m0, Ms, 3e5, (0, 1, 1))
+        ref_plain = oracle.h_eff(m0, Ms, A, d, oct_, L)
+        dt = 2e-14
+        ref_s = oracle.rk4_step(m0, Ms, A, d, oct_, L, ALPHA, GAMMA, dt, heff=heff)
+        for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+            plan, dt_ = _plan(n, d, prec, hold=oct_ if prec == "f64" else None)
+            mr, Msr = rounded(m0, dt_), rounded(Ms, dt_)
+            plan.set_anisotropy(3e5, (0, 1, 1))
+            plan.set_stt(stt[0], P=stt[1], Lambda=stt[2], eps_prime=stt[3], d_layer=stt[4], p=stt[5])
+            h = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A)
+            hl = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A, terms=0)
+            m = to_dev(mr, dt_)
+            plan.llg_step(m, to_dev(Msr, dt_), A, ALPHA, GAMMA, dt)
+            e, el = rel_l2(h.cpu().numpy(), ref_h), rel_l2(hl.cpu().numpy(), ref_loc)
+            es = rel_l2(m.cpu().numpy() - m0, ref_s - m0)
+            _say("stt", n, prec, e, el, es)
+            assert e <= tol and el <= tol and es <= tol
+            with pytest.raises(MMError):
+                plan.h_eff_adjoint(to_dev(mr, dt_), to_dev(Msr, dt_), A, torch.zeros_like(h))
+            plan.set_stt(0.0)
+            plan.set_anisotropy(0.0)
+            h0 = plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A)
+            assert rel_l2(h0.cpu().numpy(), ref_plain) <= tol
+            with pytest.raises(MMError):
+                plan.h_eff(to_dev(mr, dt_), to_dev(Msr, dt_), A, terms=0)
+            plan.close()
+
+
+def test_stt_macrospin_closed_form_on_gpu():
+    """One cubic cell, lambda = 1 (constant eps), p and an applied field along
+    z: the GPU's RK4 run follows the closed-form precession and relaxation
+    with rates g (H' - alpha b) and g (b + alpha H') (FP64)."""
+    j, d_layer, P, epsp, alpha, H = 5e11, 2e-9, 0.4, 0.1, 0.05, 1e5
+    d = (2e-9, 2e-9, 2e-9)
+    th0, ph0 = 1.1, -0.4
+    m0 = np.array([np.sin(th0) * np.cos(ph0), np.sin(th0) * np.sin(ph0), np.cos(th0)]).reshape(1, 1, 1, 3)
+    beta = oracle.HBAR * j / (oracle.MU0 * oracle.E_CHARGE * MS * d_layer)
+    b, Hp = beta * P / 2, H + beta * epsp
+    g = GAMMA / (1 + alpha * alpha)
+    T = 4e-11
+    ph = ph0 + g * (Hp - alpha * b) * T
+    th = 2 * np.arctan(np.tan(th0 / 2) * np.exp(-g * (b + alpha * Hp) * T))
+    ref = np.array([np.sin(th) * np.cos(ph), np.sin(th) * np.sin(ph), np.cos(th)])
+    plan, dt_ = _plan((1, 1, 1), d, "f64")
+    plan.set_stt(j, P=P, Lambda=1.0, eps_prime=epsp, d_layer=d_layer, p=(0, 0, 3))
+    m = to_dev(m0, dt_)
+    plan.llg_step(m, MS, A, alpha, GAMMA, 1e-13, n_steps=400, h_ext=(0, 0, H))
+    err = np.abs(m.cpu().numpy().reshape(3) - ref).max()
+    _say("stt macrospin", err)
+    assert err < 1e-9
+    plan.close()
