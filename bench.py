@@ -261,12 +261,11 @@ def run_fields(prec, N, steps, warmup):
     m = torch.tensor(synth.random_unit(grid, 7), dtype=dt, device="cuda")
     h = torch.empty_like(m)
     out = {"grid": list(grid), "cells": N ** 3, "prec": prec, "paddings": {}}
-    p2 = 1 << int(np.ceil(np.log2(2 * N - 1)))
-    for name, L in (("7-smooth", None), ("pow2", (p2, p2, p2))):
+    for name, pad in (("7-smooth", "smooth"), ("pow2", "pow2")):
         print("# timing %s padding" % name, file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        plan = DemagPlan(grid, cell, prec, L=L, autotune=True)
+        plan = DemagPlan(grid, cell, prec, autotune=True, padding=pad)
         torch.cuda.synchronize()
         res = {"L": list(plan.info()["L"]), "setup_s": time.perf_counter() - t0}
 

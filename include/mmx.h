@@ -70,18 +70,22 @@ typedef struct mm_plan_opts {
                            |r|_2 <= P*max(cell) and a 27-node moment-matched
                            dipole quadrature beyond; P <= 0: Newell everywhere.
                            Default 16. */
-    int64_t L[3];       /* zero-padded FFT length per axis; 0 = default (1 if
-                           n == 1, 2n if n is 7-smooth, else the smallest
-                           7-smooth length >= 2n-1).  A given L must be
-                           7-smooth and >= 2n-1 (any such L gives the same
-                           linear convolution). */
+    int64_t L[3];       /* zero-padded FFT length per axis; 0 = chosen by
+                           pow2_padding.  A given L must be 7-smooth and
+                           >= 2n-1 (any such L gives the same linear
+                           convolution). */
     int autotune;       /* 0: default tile widths; 1: time the candidate tile
                            widths of every pass at plan creation and keep the
                            fastest. */
-    int pow2_padding;   /* for axes without an explicit L: 0 = the default
-                           above; 1 = the smallest power of two >= 2n-1
-                           (specialised power-of-two kernels; the default of
-                           mm_batch_create). */
+    int pow2_padding;   /* for axes without an explicit L.  0: the 7-smooth
+                           length (1 if n == 1, 2n if n is 7-smooth, else
+                           the smallest 7-smooth length >= 2n-1); 1: the
+                           smallest power of two >= 2n-1 (compile-time
+                           power-of-two kernels; what mm_batch_create uses);
+                           2 (default): the power of two when it is at most
+                           1.5 times the 7-smooth length and no longer than
+                           the compile-time kernels take (x, y 4096; z and
+                           an FP64 y 2048), else the 7-smooth length. */
 } mm_plan_opts;
 
 int mm_plan_opts_default(mm_plan_opts *opts);

@@ -25,10 +25,14 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-def _opts(far_radius=16.0, L=None, autotune=False):
+_PADDING = {"auto": 2, "smooth": 0, "pow2": 1}
+
+
+def _opts(far_radius=16.0, L=None, autotune=False, padding="auto"):
     opts = PlanOpts()
     check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
     opts.far_radius = float(far_radius)
+    opts.pow2_padding = _PADDING[padding]
     if L is not None:
         for a in range(3):
             opts.L[a] = int(L[a])
@@ -36,9 +40,9 @@ def _opts(far_radius=16.0, L=None, autotune=False):
     return opts
 
 
-def plan_bytes(grid, precision="f32", far_radius=16.0, L=None):
+def plan_bytes(grid, precision="f32", far_radius=16.0, L=None, padding="auto"):
     """(tensor_bytes, workspace_bytes) of a plan for this grid (no GPU call)."""
-    opts = _opts(far_radius, L)
+    opts = _opts(far_radius, L, padding=padding)
     g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
     t, w = ctypes.c_size_t(), ctypes.c_size_t()
     check(_lib.lib().mm_plan_bytes(g, _prec(precision), ctypes.byref(opts), ctypes.byref(t), ctypes.byref(w)))
@@ -49,14 +53,14 @@ class DemagPlan:
     """One geometry: grid (nx,ny,nz), cell (dx,dy,dz) in metres, FP32 or FP64.
     Creating it computes the Newell tensor spectrum on the GPU (FP64)."""
 
-    def __init__(self, grid, cell, precision="f32", far_radius=16.0, L=None, autotune=False):
+    def __init__(self, grid, cell, precision="f32", far_radius=16.0, L=None, autotune=False, padding="auto"):
         self.grid = tuple(int(v) for v in grid)
         self.cell = tuple(float(v) for v in cell)
         self.prec = _prec(precision)
         self.dtype = _DT[self.prec]
-        self._far, self._L = float(far_radius), L
+        self._far, self._L, self._pad = float(far_radius), L, padding
         self._attached = None
-        opts = _opts(far_radius, L, autotune)
+        opts = _opts(far_radius, L, autotune, padding)
         g = (ctypes.c_int64 * 3)(*self.grid)
         c = (ctypes.c_double * 3)(*self.cell)
         self._h = ctypes.c_void_p()
@@ -111,7 +115,7 @@ class DemagPlan:
         device buffers (torch's caching allocator then holds all of the
         plan's forward memory); returns the two uint8 tensors, which the plan
         keeps alive until close()."""
-        tb, wb = plan_bytes(self.grid, self.prec, self._far, self._L)
+        tb, wb = plan_bytes(self.grid, self.prec, self._far, self._L, self._pad)
         # 256-byte alignment: torch's CUDA allocator returns 512-byte aligned blocks
         t = torch.empty(max(tb, 1), dtype=torch.uint8, device=self.device)
         w = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.device)

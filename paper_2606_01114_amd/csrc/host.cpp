@@ -66,6 +66,18 @@ int64_t default_L(int64_t n) {
     return L;
 }
 
+// Automatic padding of one axis: the power of two when it is at most 1.5
+// times the 7-smooth length and within the compile-time kernels' lengths
+// (x and y up to 4096, an FP64 y pencil and z up to 2048), else the 7-smooth
+// length.  The compile-time kernels move the extra padded bytes faster than
+// the runtime-planned mixed-radix kernels move the smaller problem (FP64,
+// 350^3 cube: 16.1 ms at 1024^3 against 26.3 ms at 700^3).
+int64_t auto_L(int64_t n, int axis, int precision) {
+    const int64_t s = default_L(n), q = pow2_L(n);
+    const int64_t lim = axis == 2 ? 2048 : (axis == 1 && precision == MM_F64 ? 2048 : 4096);
+    return (q <= lim && 2 * q <= 3 * s) ? q : s;
+}
+
 // radices for a 7-smooth length (power-of-two part as 16s with an 8/4/2 tail)
 std::vector<int> factorize(int L) {
     std::vector<int> r;
@@ -933,6 +945,7 @@ int mm_plan_opts_default(mm_plan_opts *o) {
     if (!o) return fail(MM_EINVAL, "opts is NULL");
     std::memset(o, 0, sizeof *o);
     o->far_radius = 16.0;
+    o->pow2_padding = 2;
     return MM_OK;
 }
 
@@ -949,14 +962,17 @@ int plan_params(const int64_t grid[3], const double cell[3], int precision, cons
     mm_plan_opts_default(&o);
     if (opts) o = *opts;
     if (!std::isfinite(o.far_radius)) return fail(MM_EINVAL, "far_radius must be finite");
+    if (o.pow2_padding < 0 || o.pow2_padding > 2) return fail(MM_EINVAL, "pow2_padding must be 0, 1 or 2");
     for (int a = 0; a < 3; ++a) {
-        L[a] = o.L[a] > 0 ? o.L[a] : (o.pow2_padding ? pow2_L(grid[a]) : default_L(grid[a]));
+        L[a] = o.L[a] > 0 ? o.L[a]
+               : o.pow2_padding == 1 ? pow2_L(grid[a])
+               : o.pow2_padding == 2 ? auto_L(grid[a], a, precision)
+                                     : default_L(grid[a]);
         if (L[a] < 2 * grid[a] - 1 || !is_7smooth(L[a]))
             return fail(MM_EINVAL, "L[%d]=%lld must be 7-smooth and >= 2n-1 = %lld", a, (long long)L[a], (long long)(2 * grid[a] - 1));
         if (L[a] > 16384) return fail(MM_ENOTSUP, "L[%d]=%lld exceeds 16384", a, (long long)L[a]);
     }
     if (o.autotune < 0 || o.autotune > 1) return fail(MM_EINVAL, "autotune must be 0 or 1");
-    if (o.pow2_padding < 0 || o.pow2_padding > 1) return fail(MM_EINVAL, "pow2_padding must be 0 or 1");
     const int64_t ncell = grid[0] * grid[1] * grid[2];
     if (grid[0] * grid[1] > 0x7fffffffLL / 2 || ncell > (1LL << 34)) return fail(MM_ENOTSUP, "grid too large");
     *o_out = o;

@@ -178,3 +178,36 @@ def test_set_stt_rejects_bad_arguments_on_host():
     L = _lib.lib()
     pv = (ctypes.c_double * 3)(0.0, 0.0, 1.0)
     assert L.mm_plan_set_stt(None, 1e11, 0.4, 1.0, 0.0, 1e-9, pv) == _lib.MM_EINVAL
+
+
+def test_automatic_padding_on_host():
+    """The default padding takes the power of two when it is at most 1.5
+    times the 7-smooth length and within the compile-time kernels' lengths
+    (x, y 4096; z and an FP64 y 2048); 0 keeps the 7-smooth lengths."""
+    from paper_2606_01114_amd import _lib
+
+    def tensor_L(grid, prec, pad=None):
+        o = None
+        if pad is not None:
+            o = _lib.PlanOpts()
+            _lib.lib().mm_plan_opts_default(ctypes.byref(o))
+            o.pow2_padding = pad
+            o = ctypes.byref(o)
+        rc, t, _ = _bytes(grid, prec, o)
+        assert rc == _lib.MM_OK
+        return t
+
+    def octant(L, r):
+        return (L[0] // 2 + 1) * (L[1] // 2 + 1) * (L[2] // 2 + 1) * 6 * r
+
+    F32, F64 = _lib.MM_F32, _lib.MM_F64
+    assert tensor_L((350, 350, 350), F64) == octant((1024, 1024, 1024), 8)
+    assert tensor_L((350, 350, 350), F64, 0) == octant((700, 700, 700), 8)
+    assert tensor_L((300, 6, 2), F32) == octant((600, 16, 4), 4)
+    assert tensor_L((4, 1500, 1100), F32) == octant((8, 4096, 2205), 4)
+    assert tensor_L((4, 1500, 3), F64) == octant((8, 3000, 8), 8)
+    o = _lib.PlanOpts()
+    _lib.lib().mm_plan_opts_default(ctypes.byref(o))
+    assert o.pow2_padding == 2
+    o.pow2_padding = 3
+    assert _bytes((4, 4, 4), F32, ctypes.byref(o))[0] == _lib.MM_EINVAL

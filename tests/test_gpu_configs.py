@@ -286,10 +286,10 @@ def test_longest_specialised_lengths(n):
             # a 4096-long FP64 pencil of three components exceeds the LDS
             from paper_2606_01114_amd._lib import MM_ENOTSUP, MMError
             with pytest.raises(MMError) as ei:
-                DemagPlan(n, D, prec)
+                DemagPlan(n, D, prec, padding="smooth")
             assert ei.value.code == MM_ENOTSUP
             continue
-        plan = DemagPlan(n, D, prec)
+        plan = DemagPlan(n, D, prec, padding="smooth")
         assert tuple(plan.info()["L"]) == L
         mr = rounded(m0, dt)
         Msr = to_dev(rounded(Ms, dt), dt)

@@ -65,8 +65,8 @@ def test_sp4_relaxation_and_field_one_against_oracle():
     import torch
     from paper_2606_01114_amd import DemagPlan
     oct_ = oracle.tensor_octant(N, D)
-    L = tuple(oracle.default_L(v) for v in N)
     plan = DemagPlan(N, D, "f64")
+    L = tuple(plan.info()["L"])
     plan.tensor_set(oct_)
     m0 = initial_state()
     # relaxation
