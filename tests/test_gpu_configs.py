@@ -71,16 +71,20 @@ def test_large_grid_fp32_vs_fp64_and_sampled():
     n = (1024, 1024, 128)
     _say("large: inputs")
     m0 = rounded(synth.voronoi_grains(n, D, 3), torch.float32)
-    p32 = DemagPlan(n, D, "f32")
+    # the benchmark's launch configuration: tile variants chosen by the autotuner
+    p32 = DemagPlan(n, D, "f32", autotune=True)
+    _say("large: fp32 tiles", p32.info()["tiles"])
     m = to_dev(m0, torch.float32)
     h32 = p32.h_eff(m, MS, A)
     hd32 = p32.h_eff(m, MS, A, terms=1)
     cells = synth.sample_cells(n, 3, 2)
     s32 = h32[cells[:, 0], cells[:, 1], cells[:, 2]].double().cpu().numpy()
     sd32 = hd32[cells[:, 0], cells[:, 1], cells[:, 2]].double().cpu().numpy()
+    p32.llg_step(m, MS, A, ALPHA, GAMMA, DT)
+    dm32 = (m.double() - to_dev(m0, torch.float64)).cpu()
     del m
     _say("large: fp64 plan")
-    p64 = DemagPlan(n, D, "f64")
+    p64 = DemagPlan(n, D, "f64", autotune=True)
     m = to_dev(m0, torch.float64)
     def dev_rel(x, ref):       # relative L2 on the device, FP64 accumulation
         return float(torch.linalg.vector_norm(x.double() - ref) / torch.linalg.vector_norm(ref))
@@ -89,7 +93,14 @@ def test_large_grid_fp32_vs_fp64_and_sampled():
     del h64
     hd64 = p64.h_eff(m, MS, A, terms=1)
     assert dev_rel(hd32, hd64) <= 1e-5
-    del m, hd64, h32, hd32
+    del hd64, h32, hd32
+    # one RK4 step: the FP32 increment against the FP64 one
+    p64.llg_step(m, MS, A, ALPHA, GAMMA, DT)
+    dm64 = m - to_dev(m0, torch.float64)
+    e_step = float(torch.linalg.vector_norm(dm32.to(dm64.device) - dm64) / torch.linalg.vector_norm(dm64))
+    _say("large: step increment rel-L2", e_step)
+    assert e_step <= 1e-5
+    del m, dm64, dm32
     p64.close()
     torch.cuda.empty_cache()
     _say("large: oracle tensor and direct sums")
