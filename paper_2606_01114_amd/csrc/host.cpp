@@ -170,6 +170,7 @@ struct mm_plan {
     void *S1 = nullptr, *S2 = nullptr, *tensor = nullptr, *twT = nullptr, *tw64 = nullptr;
     void *ms[2] = {nullptr, nullptr}, *acc = nullptr;
     double *epart = nullptr, *esum = nullptr;
+    int st_cx = 0, st_nqb = 0, st_blocks = 0;   // stencil kernel of h_eff without demag (0: not applicable)
     LinePass *d_lp = nullptr;   // [0] y forward, [1] y inverse
     FusedPass *d_fp = nullptr;
     // host copies
@@ -395,6 +396,8 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     if ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsMax) return fail(MM_ENOTSUP, "z length %d too long", Lz);
     // energy partials
     if ((rc = dalloc(p, (void **)&p->epart, (size_t)z.tiles * 2 * sizeof(double)))) return rc;
+    if (!getenv("MMX_NO_STENCIL") && !stencil_shape(p->n[0], p->n[1], p->n[2], z.tiles, &p->st_cx, &p->st_nqb, &p->st_blocks))
+        p->st_blocks = 0;
     if ((rc = dalloc(p, (void **)&p->esum, 2 * sizeof(double)))) return rc;
     // device descriptor copies
     if ((rc = dalloc(p, (void **)&p->d_lp, 2 * sizeof(LinePass)))) return rc;
@@ -662,9 +665,17 @@ int heff_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, 
     ZInvArgs a;
     fill_common(p, a, terms, Ms, Ms_s, A);
     a.m = m; a.h_out = h; a.epart = E ? p->epart : nullptr;
-    HIPCK(zinv_any<T>(p, a, EPI_HEFF));
+    int nblk = p->zg.tiles;
+    if (!(terms & MM_DEMAG) && ((terms & MM_EXCHANGE) || p->dmi_kind) && p->st_blocks > 0) {
+        // no transform, neighbours needed: the stencil kernel streams m once
+        // (local terms alone take the z pass's epilogue, which loads no neighbours)
+        HIPCK(launch_stencil_heff<T>(a, p->st_cx, p->st_nqb, p->st_blocks, p->stream));
+        nblk = p->st_blocks;
+    } else {
+        HIPCK(zinv_any<T>(p, a, EPI_HEFF));
+    }
     if (E) {
-        HIPCK(launch_energy_reduce(p->epart, p->zg.tiles, p->esum, p->stream));
+        HIPCK(launch_energy_reduce(p->epart, nblk, p->esum, p->stream));
         double s[2];
         HIPCK(hipMemcpyAsync(s, p->esum, sizeof s, hipMemcpyDeviceToHost, p->stream));
         HIPCK(hipStreamSynchronize(p->stream));

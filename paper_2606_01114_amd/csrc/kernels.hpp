@@ -49,6 +49,11 @@ hipError_t launch_zfwd_ct_b(const ZFwdArgs *d, const int2 *map, int tiles, int L
 template <typename T>
 hipError_t launch_zinv_ct_b(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, hipStream_t s);
 hipError_t launch_energy_reduce(const double *part, int nblk, double *out, hipStream_t s);
+// h_eff without the demag term as a streaming stencil (kern_stencil.hip)
+int stencil_shape(int nx, int ny, int nz, int max_blocks, int *cx, int *nqb, int *blocks);
+size_t stencil_lds(int nz, size_t rsz);
+template <typename T>
+hipError_t launch_stencil_heff(const ZInvArgs &a, int cx, int nqb, int blocks, hipStream_t s);
 hipError_t launch_max_reduce(const double *part, int nblk, double *out, hipStream_t s);
 hipError_t launch_bb_reduce(const double *part, int nblk, double *out4, hipStream_t s);
 template <typename T> hipError_t launch_bb_update(T *m, const T *g, T *mprev, double tau, int64_t ncell, hipStream_t s);

@@ -511,3 +511,46 @@ def test_stt_macrospin_closed_form_on_gpu():
     _say("stt macrospin", err)
     assert err < 1e-9
     plan.close()
+
+
+STENCIL_GRIDS = [(5, 7, 3), (3, 40, 33), (70, 9, 17), (1, 1, 1), (2, 600, 2), (4, 3, 512), (40, 2, 1), (3, 2, 600)]
+
+
+@pytest.mark.parametrize("n", STENCIL_GRIDS)
+def test_h_eff_without_demag_against_oracle(n):
+    """h_eff without the demag term runs the streaming stencil kernel (for
+    nz <= 512; nz = 600 takes the z pass): exchange alone with per-cell Ms and
+    vacuum cells, its energy, and the local terms (DMI, anisotropy,
+    spin-transfer torque) alone and with exchange, FP64 to 1e-12 and FP32 to
+    1e-5 against the oracle; ragged plane blocks, x chunks, nz = 1 and the
+    largest nz."""
+    from paper_2606_01114_amd import MM_EXCHANGE
+    d = (2e-9, 2.5e-9, 3e-9)
+    m0 = synth.random_unit(n, 81)
+    Ms = synth.ms_field(n, 82)
+    Ms.reshape(-1)[::5] = 0.0
+    stt = (4e11, 0.35, 1.6, 0.2, 2e-9, (0.3, 0.4, -0.5))
+    ref_ex = oracle.exchange_field(m0, Ms, A, d)
+    ref_loc = (oracle.dmi_field(m0, Ms, 1.5e-3, d, "bulk") + oracle.anisotropy_field(m0, Ms, 2e5, (1, 0, 1))
+               + oracle.stt_field(m0, Ms, *stt))
+    ref_e = oracle.energies(m0, Ms, np.zeros_like(ref_ex), ref_ex, d)[1]
+
+    def rel(x, ref):       # a field that is exactly zero (a single cell) must come out zero
+        return rel_l2(x, ref) if np.any(ref) else float(np.abs(x).max())
+
+    for prec, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        plan, dt_ = _plan(n, d, prec)
+        mr, Msr = to_dev(rounded(m0, dt_), dt_), to_dev(rounded(Ms, dt_), dt_)
+        h, (e_d, e_x) = plan.h_eff(mr, Msr, A, terms=MM_EXCHANGE, energy=True)
+        e1 = rel(h.cpu().numpy(), ref_ex)
+        ee = abs(e_x - ref_e) / abs(ref_e) if ref_e != 0.0 else abs(e_x)
+        plan.set_dmi("bulk", 1.5e-3)
+        plan.set_anisotropy(2e5, (1, 0, 1))
+        plan.set_stt(stt[0], P=stt[1], Lambda=stt[2], eps_prime=stt[3], d_layer=stt[4], p=stt[5])
+        hl = plan.h_eff(mr, Msr, A, terms=0)
+        hx = plan.h_eff(mr, Msr, A, terms=MM_EXCHANGE)
+        e2 = rel(hl.cpu().numpy(), ref_loc)
+        e3 = rel(hx.cpu().numpy(), ref_ex + ref_loc)
+        _say("no-demag", n, prec, e1, ee, e2, e3, e_d)
+        assert e1 <= tol and ee <= tol and e2 <= tol and e3 <= tol and e_d == 0.0
+        plan.close()
