@@ -396,7 +396,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     if ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsMax) return fail(MM_ENOTSUP, "z length %d too long", Lz);
     // energy partials
     if ((rc = dalloc(p, (void **)&p->epart, (size_t)z.tiles * 2 * sizeof(double)))) return rc;
-    if (!getenv("MMX_NO_STENCIL") && !stencil_shape(p->n[0], p->n[1], p->n[2], z.tiles, &p->st_cx, &p->st_nqb, &p->st_blocks))
+    if (!stencil_shape((int)p->n[0], (int)p->n[1], (int)p->n[2], z.tiles, &p->st_cx, &p->st_nqb, &p->st_blocks))
         p->st_blocks = 0;
     if ((rc = dalloc(p, (void **)&p->esum, 2 * sizeof(double)))) return rc;
     // device descriptor copies
