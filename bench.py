@@ -41,7 +41,7 @@ WORKLOADS = {
                      "the Barzilai-Borwein minimiser, then 1 ns of RKF45 LLG in (-24.6, 4.3, 0) mT, "
                      "output every 10 ps"),
     "fields": dict(grid=None, cell=(2e-9, 2e-9, 2e-9), m="random", seed=7,
-                   name="each field term alone on a %dx%dx%d cube of random m (demag, exchange, Slonczewski "
+                   name="each field term alone on a %sx%sx%s cube of random m (demag, exchange, Slonczewski "
                         "spin-transfer torque), FP64 as the paper times them"),
     "grad": dict(grid=(256, 256, 8), cell=(2.5e-9, 2.5e-9, 3e-9), m="smooth", seed=5,
                  name="differentiable 256x256x8: 200 RK4 steps, checkpoint every 20, gradient of mean m_z "
@@ -245,11 +245,11 @@ PAPER_FIELD_MS = {
 }
 
 
-def run_fields(prec, N, steps, warmup):
+def run_fields(prec, N, steps, warmup, paddings=("smooth", "pow2")):
     """Per-field evaluation time on an N x N x N cube as the paper times its
     field terms (each term alone, FP64 by default): demag, exchange and the
     Slonczewski spin-transfer torque, for the 7-smooth padding 2N and the
-    power-of-two padding."""
+    power-of-two padding (or the given paddings)."""
     import numpy as np
     import torch
     import synth
@@ -261,7 +261,8 @@ def run_fields(prec, N, steps, warmup):
     m = torch.tensor(synth.random_unit(grid, 7), dtype=dt, device="cuda")
     h = torch.empty_like(m)
     out = {"grid": list(grid), "cells": N ** 3, "prec": prec, "paddings": {}}
-    for name, pad in (("7-smooth", "smooth"), ("pow2", "pow2")):
+    names = {"smooth": "7-smooth", "pow2": "pow2", "auto": "auto"}
+    for name, pad in ((names[p], p) for p in paddings):
         print("# timing %s padding" % name, file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -489,7 +490,7 @@ def main():
     ap.add_argument("--prec", default="f32", choices=["f32", "f64"])
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison run")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--fields-n", type=int, default=350, help="cube edge of the fields workload")
+    ap.add_argument("--fields-n", default="350", help="cube edge of the fields workload (a comma list sweeps sizes)")
     ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -510,6 +511,24 @@ def main():
         return
     if args.workload == "fields":
         prec = "f64" if args.prec == "f32" and not args.fields_f32 else args.prec
+        ns = [int(v) for v in str(args.fields_n).split(",")]
+        if len(ns) > 1:
+            # a sweep over cube sizes with the default padding, as the paper's
+            # per-field curves over N
+            rows = []
+            for n in ns:
+                r = run_fields(prec, n, args.steps, args.warmup, paddings=("auto",))
+                rows.append(dict(N=n, cells=n ** 3, **r["best"]))
+                print("# N=%d: %s" % (n, json.dumps(rows[-1])), file=sys.stderr, flush=True)
+            print(json.dumps({"metric": "ms per field evaluation over cube sizes (each field term timed alone)",
+                              "value": rows[-1]["demag_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,
+                              "warmup": args.warmup, "ms_per_step": rows[-1]["demag_ms"], "higher_is_better": False,
+                              "scaling": "weak", "vs_baseline": None, "dtype": prec, "data": "synthetic",
+                              "config": {"workload": WORKLOADS["fields"]["name"] % ("N", "N", "N")
+                                         + ", N in " + ",".join(map(str, ns))},
+                              "extra": {"sweep": rows}}))
+            return
+        args.fields_n = ns[0]
         r = run_fields(prec, args.fields_n, args.steps, args.warmup)
         print(json.dumps({"metric": "ms per demag field evaluation (each field term timed alone)",
                           "value": r["best"]["demag_ms"], "unit": "ms", "n_gpus": 1, "steps": args.steps,

@@ -83,7 +83,7 @@ typedef struct mm_plan_opts {
                            smallest power of two >= 2n-1 (compile-time
                            power-of-two kernels; what mm_batch_create uses);
                            2 (default): the power of two when it is at most
-                           1.5 times the 7-smooth length and no longer than
+                           1.75 times the 7-smooth length and no longer than
                            the compile-time kernels take (x, y 4096; z and
                            an FP64 y 2048), else the 7-smooth length. */
 } mm_plan_opts;

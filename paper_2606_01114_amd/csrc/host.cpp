@@ -66,16 +66,18 @@ int64_t default_L(int64_t n) {
     return L;
 }
 
-// Automatic padding of one axis: the power of two when it is at most 1.5
+// Automatic padding of one axis: the power of two when it is at most 1.75
 // times the 7-smooth length and within the compile-time kernels' lengths
 // (x and y up to 4096, an FP64 y pencil and z up to 2048), else the 7-smooth
 // length.  The compile-time kernels move the extra padded bytes faster than
-// the runtime-planned mixed-radix kernels move the smaller problem (FP64,
-// 350^3 cube: 16.1 ms at 1024^3 against 26.3 ms at 700^3).
+// the runtime-planned mixed-radix kernels move the smaller problem (FP64
+// demag of an N^3 cube: N = 350, 1024^3 16.0 ms against 700^3 26.3 ms;
+// N = 160, 512^3 1.69 ms against 320^3 2.22 ms; but N = 260, 1024^3 12.6 ms
+// against 525^3 11.0 ms).
 int64_t auto_L(int64_t n, int axis, int precision) {
     const int64_t s = default_L(n), q = pow2_L(n);
     const int64_t lim = axis == 2 ? 2048 : (axis == 1 && precision == MM_F64 ? 2048 : 4096);
-    return (q <= lim && 2 * q <= 3 * s) ? q : s;
+    return (q <= lim && 4 * q <= 7 * s) ? q : s;
 }
 
 // radices for a 7-smooth length (power-of-two part as 16s with an 8/4/2 tail)

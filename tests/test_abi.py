@@ -181,7 +181,7 @@ def test_set_stt_rejects_bad_arguments_on_host():
 
 
 def test_automatic_padding_on_host():
-    """The default padding takes the power of two when it is at most 1.5
+    """The default padding takes the power of two when it is at most 1.75
     times the 7-smooth length and within the compile-time kernels' lengths
     (x, y 4096; z and an FP64 y 2048); 0 keeps the 7-smooth lengths."""
     from paper_2606_01114_amd import _lib
@@ -203,7 +203,8 @@ def test_automatic_padding_on_host():
     F32, F64 = _lib.MM_F32, _lib.MM_F64
     assert tensor_L((350, 350, 350), F64) == octant((1024, 1024, 1024), 8)
     assert tensor_L((350, 350, 350), F64, 0) == octant((700, 700, 700), 8)
-    assert tensor_L((300, 6, 2), F32) == octant((600, 16, 4), 4)
+    assert tensor_L((300, 6, 2), F32) == octant((1024, 16, 4), 4)
+    assert tensor_L((260, 6, 2), F32) == octant((525, 16, 4), 4)
     assert tensor_L((4, 1500, 1100), F32) == octant((8, 4096, 2205), 4)
     assert tensor_L((4, 1500, 3), F64) == octant((8, 3000, 8), 8)
     o = _lib.PlanOpts()

@@ -551,6 +551,16 @@ def test_h_eff_without_demag_against_oracle(n):
         hx = plan.h_eff(mr, Msr, A, terms=MM_EXCHANGE)
         e2 = rel(hl.cpu().numpy(), ref_loc)
         e3 = rel(hx.cpu().numpy(), ref_ex + ref_loc)
-        _say("no-demag", n, prec, e1, ee, e2, e3, e_d)
-        assert e1 <= tol and ee <= tol and e2 <= tol and e3 <= tol and e_d == 0.0
+        # scalar Ms (no vacuum): exchange with the local terms
+        hs = plan.h_eff(mr, MS, A, terms=MM_EXCHANGE)
+        plan.set_stt(0.0)
+        plan.set_anisotropy(0.0)
+        plan.set_dmi(None, 0.0)
+        hs0 = plan.h_eff(mr, MS, A, terms=MM_EXCHANGE)
+        ref_s0 = oracle.exchange_field(m0, MS, A, d)
+        ref_s = (ref_s0 + oracle.dmi_field(m0, MS, 1.5e-3, d, "bulk") + oracle.anisotropy_field(m0, MS, 2e5, (1, 0, 1))
+                 + oracle.stt_field(m0, MS, *stt))
+        e4, e5 = rel(hs.cpu().numpy(), ref_s), rel(hs0.cpu().numpy(), ref_s0)
+        _say("no-demag", n, prec, e1, ee, e2, e3, e4, e5, e_d)
+        assert e1 <= tol and ee <= tol and e2 <= tol and e3 <= tol and e4 <= tol and e5 <= tol and e_d == 0.0
         plan.close()
