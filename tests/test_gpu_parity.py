@@ -564,3 +564,42 @@ def test_h_eff_without_demag_against_oracle(n):
         _say("no-demag", n, prec, e1, ee, e2, e3, e4, e5, e_d)
         assert e1 <= tol and ee <= tol and e2 <= tol and e3 <= tol and e4 <= tol and e5 <= tol and e_d == 0.0
         plan.close()
+
+
+@pytest.mark.parametrize("padding", ["auto", "smooth"])
+def test_rkf45_with_local_terms_against_oracle(padding):
+    """One RKF45 step with DMI, anisotropy and the spin-transfer torque set
+    (the tableau epilogue's local-term instantiation), through the
+    compile-time z kernels (automatic padding) and the runtime-planned ones
+    (7-smooth padding, Lz = 6), FP64 with the tensor held equal and FP32,
+    against the oracle."""
+    from paper_2606_01114_amd import DemagPlan
+    import torch
+    n, d = (20, 12, 3), (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant(n, d)
+    m0 = synth.random_unit(n, 91)
+    Ms = synth.ms_field(n, 92)
+    stt = (3e11, 0.4, 1.8, 0.1, 2e-9, (0.0, 0.6, 0.8))
+    dt, tol = 2e-14, 1e-2
+    for prec, tolp in (("f64", 1e-12), ("f32", 1e-5)):
+        plan = DemagPlan(n, d, prec, padding=padding)
+        dt_ = torch.float64 if prec == "f64" else torch.float32
+        if prec == "f64":
+            plan.tensor_set(oct_)
+        L = tuple(plan.info()["L"])
+        if padding == "smooth":
+            assert L[2] == 6
+        mr, Msr = rounded(m0, dt_), rounded(Ms, dt_)
+        heff = lambda s: oracle.h_eff(s, Msr, A, d, oct_, L, dmi=("interfacial", 1e-3), aniso=(2e5, (1, 1, 0)),
+                                      stt=stt)
+        ref, err_ref, ok_ref, _ = oracle.rkf45_step(mr, Msr, A, d, oct_, L, ALPHA, GAMMA, dt, tol, heff=heff)
+        assert ok_ref
+        plan.set_dmi("interfacial", 1e-3)
+        plan.set_anisotropy(2e5, (1, 1, 0))
+        plan.set_stt(stt[0], P=stt[1], Lambda=stt[2], eps_prime=stt[3], d_layer=stt[4], p=stt[5])
+        m = to_dev(mr, dt_)
+        ok, err, _ = plan.rkf45_step(m, to_dev(Msr, dt_), A, ALPHA, GAMMA, dt, tol)
+        e = rel_l2(m.cpu().numpy() - mr, ref - mr)
+        _say("rkf45 local", padding, prec, L, e, err, err_ref)
+        assert ok and e <= tolp
+        plan.close()
