@@ -495,7 +495,7 @@ def main():
     ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see DESIGN.md, sharding)",
+        print("bench.py runs on exactly one GPU: the library has no multi-GPU path",
               file=sys.stderr)
         sys.exit(2)
     import numpy as np
