@@ -3,9 +3,13 @@
  *
  * The operations follow the paper's statement of the finite-difference
  * micromagnetic problem (Cheng, Kurokawa, Yuasa, "Magnum.np.distributed"):
- *   - the LLG equation, eq. (1), advanced here by classic fixed-step RK4;
+ *   - the LLG equation, eq. (1), advanced by classic fixed-step RK4 and by
+ *     the paper's adaptive Runge-Kutta-Fehlberg 4(5) step;
  *   - the effective field as a sum of terms (text after eq. (1));
  *   - the Heisenberg exchange field, eq. (2), with uniform A;
+ *   - the DMI field, eq. (3), and the local fields the Implementation
+ *     section names (uniaxial anisotropy, Slonczewski spin-transfer torque);
+ *   - the Barzilai-Borwein energy minimiser of the Implementation section;
  *   - the demagnetisation field as the convolution of eq. (4) with the
  *     cell-averaged Newell tensor, done as a zero-padded FFT convolution
  *     (Implementation section and Fig. 1), on one GPU, unsharded;
