@@ -413,15 +413,18 @@ def cpu_baseline(w, budget_s=20.0):
         m0 = synth.random_unit(sub, w["seed"])
     oct_ = oracle.tensor_octant(sub, w["cell"])
     L = tuple(oracle.default_L(v) for v in sub)
-    t0 = time.perf_counter()
-    steps = 0
-    m = m0
-    while True:
-        m = oracle.rk4_step(m, MS, A, w["cell"], oct_, L, ALPHA, GAMMA, DT)
-        steps += 1
-        if time.perf_counter() - t0 > budget_s or steps >= 50:
-            break
-    el = time.perf_counter() - t0
+    # one thread: numpy's FFT is single-threaded; any BLAS pool is held to 1
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        steps = 0
+        m = m0
+        while True:
+            m = oracle.rk4_step(m, MS, A, w["cell"], oct_, L, ALPHA, GAMMA, DT)
+            steps += 1
+            if time.perf_counter() - t0 > budget_s or steps >= 50:
+                break
+        el = time.perf_counter() - t0
     cells = int(np.prod(sub))
     return {"value": cells * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
             "sample": "%d RK4 steps of the FP64 oracle (numpy FFT, single thread) on a %dx%dx%d sub-grid "
