@@ -584,7 +584,7 @@ def main():
     if res["tiles"][2] < 0:
         sym["y_fused"] = "k_fused_y_hx"
     for pname, v in (("x_fwd", res["tiles"][3]), ("x_inv", res["tiles"][4])):
-        if v == 2:
+        if v >= 2:
             sym[pname] = "k_line_hx"
     roof = {"bound": "hbm", "kernel": sym[dom] + " (" + dom + ")", "achieved": ach / 1e9,
             "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach / HBM_PEAK,

@@ -203,7 +203,8 @@ int mm_plan_set_stt(mm_plan *plan, double j, double P, double lambda, double eps
  * nullable): tiles = {z cell columns per tile, forward x columns per tile,
  * y pencils per tile (negated when the register-resident pencil kernel runs
  * the y pass), forward x variant, inverse x variant}; x variants 0 and 1 are
- * two tile widths, 2 the half-LDS kernel with variant 1's tiles. */
+ * two tile widths, 2 the half-LDS kernel with variant 1's tiles, 3 the
+ * half-LDS kernel with tiles twice as wide (lines of 1024 points or more). */
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 
 /*

@@ -183,7 +183,7 @@ struct mm_plan {
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
     int y_var = 0;                                   // specialised y pass: 0 LDS-resident pencil, 1 register-resident
-    int x_var[2] = {0, 0};                          // variants of the forward / inverse x pass (0, 1: tile widths; 2: half-LDS)
+    int x_var[2] = {0, 0};                          // variants of the forward / inverse x pass (0, 1: tile widths; 2: half-LDS; 3: half-LDS, wide tiles)
     int tiles_fwd = 0, tiles_inv = 0;
     // llg graph cache; graphs are captured on a private stream (capture is not
     // permitted on the legacy default stream) and launched on `stream`
@@ -339,12 +339,14 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     size_t lds;
     choose_line_tile(Lx, (int)ny3, csz, kLdsTarget, 0, W, nthr, lds);
     int Wct = 0, NTct = 0;
-    if (getenv("MMX_XVAR")) p->x_var[0] = p->x_var[1] = std::min(2, std::max(0, atoi(getenv("MMX_XVAR"))));
+    if (getenv("MMX_XVAR")) p->x_var[0] = p->x_var[1] = std::min(3, std::max(0, atoi(getenv("MMX_XVAR"))));
+    if (p->x_var[0] == 3 && !line_ct_shape(Lx, csz, 3, &Wct, &NTct)) p->x_var[0] = p->x_var[1] = 2;   // no wide tiles
     // the specialised kernels address one kz plane (Lx rows) through a buffer
     // resource, whose size is a 31-bit byte count
-    p->x_ct = line_ct_shape(Lx, csz, p->x_var[0], &Wct, &NTct) && line_ct_lds(Lx, Wct, csz) <= kLdsMax &&
+    p->x_ct = line_ct_shape(Lx, csz, p->x_var[0], &Wct, &NTct) &&
+              (p->x_var[0] >= 2 ? line_hx_lds(Lx, Wct, csz) : line_ct_lds(Lx, Wct, csz)) <= kLdsMax &&
               (int64_t)Lx * ny3 * (int64_t)csz < (int64_t(1) << 31) && !getenv("MMX_NO_CT");
-    if (p->x_ct) { W = Wct; nthr = NTct; lds = p->x_var[0] == 2 ? line_hx_lds(Lx, W, csz) : line_ct_lds(Lx, W, csz); }
+    if (p->x_ct) { W = Wct; nthr = NTct; lds = p->x_var[0] >= 2 ? line_hx_lds(Lx, W, csz) : line_ct_lds(Lx, W, csz); }
     LinePass &f = p->lp_fwd;
     std::memset(&f, 0, sizeof f);
     f.in = p->S1; f.out = p->S2; f.tw = twc + ox;
@@ -478,7 +480,9 @@ template <typename T>
 hipError_t launch_x(mm_plan *p, int dir) {
     const LinePass &a = dir < 0 ? p->lp_fwd : p->lp_inv;
     const int v = p->x_var[dir < 0 ? 0 : 1];
-    return launch_line_ct<T>(a, dir < 0 ? p->tiles_fwd : p->tiles_inv, a.W, dir, p->stream, v == 2 ? 1 : 0);
+    const int tiles = dir < 0 ? p->tiles_fwd : p->tiles_inv;
+    if (v == 3) return launch_line_wide<T>(a, tiles, a.W, dir, p->stream);
+    return launch_line_ct<T>(a, tiles, a.W, dir, p->stream, v == 2 ? 1 : 0);
 }
 
 // the specialised fused y pass in the plan's variant
@@ -529,7 +533,7 @@ int configure_x(mm_plan *p, int d, int v) {
     f->W = W;
     f->nthr = NT;
     f->tiles_inner = (f->inner + W - 1) / W;
-    const size_t lds = v == 2 ? line_hx_lds((int)p->L[0], W, csz) : line_ct_lds((int)p->L[0], W, csz);
+    const size_t lds = v >= 2 ? line_hx_lds((int)p->L[0], W, csz) : line_ct_lds((int)p->L[0], W, csz);
     (d == 0 ? p->lds_fwd : p->lds_inv) = lds;
     (d == 0 ? p->tiles_fwd : p->tiles_inv) = f->tiles_inner * f->outer;
     LinePass two[2] = {p->lp_fwd, p->lp_inv};
@@ -555,10 +559,11 @@ int autotune_x(mm_plan *p) {
         const int dir = d == 0 ? -1 : +1;
         double best = 1e300;
         int bestv = p->x_var[d];
-        for (int v = 0; v < 3 && !rc; ++v) {
+        for (int v = 0; v < 4 && !rc; ++v) {
             const size_t csz = sizeof(cplx<T>);
             int W = 0, NT = 0;
-            if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT) || line_ct_lds((int)p->L[0], W, csz) > kLdsMax) continue;
+            if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT)) continue;
+            if ((v >= 2 ? line_hx_lds((int)p->L[0], W, csz) : line_ct_lds((int)p->L[0], W, csz)) > kLdsMax) continue;
             if ((rc = configure_x(p, d, v))) break;
             float ms = 0.f;
             for (int rep = 0; rep < 2 && !rc; ++rep) {

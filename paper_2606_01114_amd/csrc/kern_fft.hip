@@ -659,7 +659,10 @@ hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles
 
 // Specialised shapes of the x pass: for each power-of-two length two tile
 // widths W (columns per tile); NT = W L / 16 threads so each holds 16 complex
-// values.  Variant 0 keeps a tile's LDS near 64 KB, variant 1 doubles it.
+// values.  Variant 0 keeps a tile's LDS near 64 KB, variant 1 doubles it;
+// variant 2 is the half-LDS kernel on variant 1's tiles, variant 3 the
+// half-LDS kernel on tiles twice as wide (lines of 1024 to 4096 points, at
+// most 1024 threads holding two or more butterflies each).
 static int line_ct_w(int L, bool f32, int variant) {
     int w;
     switch (L) {
@@ -670,15 +673,16 @@ static int line_ct_w(int L, bool f32, int variant) {
     case 4096: w = f32 ? 2 : 1; break;
     default: return 0;
     }
-    return variant ? 2 * w : w;   // variant 2 (half-LDS kernel) has variant 1's tiles
+    if (variant == 3) return L >= 1024 ? 4 * w : 0;
+    return variant ? 2 * w : w;
 }
 
 int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT) {
     const int w = line_ct_w(L, csz == 8, variant);
     if (!w) return 0;
     *W = w;
-    *NT = w * L / 16;
-    return *NT >= 64 && *NT <= 1024;
+    *NT = std::min(1024, w * L / 16);
+    return *NT >= 64;
 }
 
 #define LINE_CASE(LL, WW)                                                                                             \
@@ -709,6 +713,27 @@ hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStrea
     return hipErrorInvalidValue;
 }
 #undef LINE_CASE
+
+// variant 3: the half-LDS kernel with 1024 threads on the wide tiles
+#define LINE_CASE_W(LL, WW)                                                                                           \
+    if (a.f.L == LL && W == WW) {                                                                                     \
+        const size_t lh = line_hx_lds(LL, WW, sizeof(cplx<T>));                                                       \
+        if (dir < 0) hipLaunchKernelGGL((k_line_hx<T, LL, -1, 1024, WW>), dim3(tiles), dim3(1024), lh, s, a);        \
+        else hipLaunchKernelGGL((k_line_hx<T, LL, +1, 1024, WW>), dim3(tiles), dim3(1024), lh, s, a);                \
+        return hipGetLastError();                                                                                     \
+    }
+
+template <typename T>
+hipError_t launch_line_wide(const LinePass &a, int tiles, int W, int dir, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    if constexpr (sizeof(T) == 4) {
+        LINE_CASE_W(1024, 32) LINE_CASE_W(2048, 16) LINE_CASE_W(4096, 8)
+    } else {
+        LINE_CASE_W(1024, 16) LINE_CASE_W(2048, 8) LINE_CASE_W(4096, 4)
+    }
+    return hipErrorInvalidValue;
+}
+#undef LINE_CASE_W
 
 size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W, (int)csz) * csz; }
 size_t line_hx_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L / 2, W, (int)csz) * csz; }
@@ -824,6 +849,8 @@ template hipError_t launch_fused_y<float>(const FusedPass *, const int2 *, int, 
 template hipError_t launch_fused_y<double>(const FusedPass *, const int2 *, int, int, size_t, hipStream_t);
 template hipError_t launch_line_ct<float>(const LinePass &, int, int, int, hipStream_t, int);
 template hipError_t launch_line_ct<double>(const LinePass &, int, int, int, hipStream_t, int);
+template hipError_t launch_line_wide<float>(const LinePass &, int, int, int, hipStream_t);
+template hipError_t launch_line_wide<double>(const LinePass &, int, int, int, hipStream_t);
 template hipError_t launch_fused_ct<float>(const FusedPass &, hipStream_t);
 template hipError_t launch_fused_ct<double>(const FusedPass &, hipStream_t);
 

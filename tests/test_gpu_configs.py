@@ -244,31 +244,38 @@ def test_gradient_c5_against_fd():
 
 
 def test_x_pass_variants_against_oracle():
-    """Every variant of the specialised x pass (two tile widths and the
-    persistent kernel, selected with MMX_XVAR at plan creation) on a grid with
-    more x tiles than the persistent grid holds and a ragged last tile, FP32
-    and FP64, against the oracle's h_eff and one RK4 step."""
+    """Every variant of the specialised x pass, selected with MMX_XVAR at plan
+    creation: two tile widths (0, 1), the half-LDS kernel (2) and the
+    half-LDS kernel on tiles twice as wide (3, lines of 1024 and 2048
+    points), with ragged last tiles, FP32 and FP64, against the oracle's
+    h_eff."""
     import os
     import torch
     from paper_2606_01114_amd import DemagPlan
-    n = (64, 500, 16)
-    oct_ = oracle.tensor_octant(n, D)
-    L = tuple(oracle.default_L(v) for v in n)
-    m0 = synth.random_unit(n, 17)
-    _say("x variants: oracle h_eff", n, L)
-    ref = oracle.h_eff(m0, MS, A, D, oct_, L)
+    cases = [((64, 500, 16), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-9))),
+             ((400, 40, 3), (("f32", 3, 1e-5), ("f64", 3, 1e-9), ("f32", 2, 1e-5))),
+             ((1024, 8, 2), (("f32", 3, 1e-5), ("f64", 3, 1e-9)))]
     old = os.environ.get("MMX_XVAR")
     try:
-        for prec, var, tol in (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-9)):
-            _say("x variant", prec, var)
-            os.environ["MMX_XVAR"] = str(var)
-            dt = torch.float32 if prec == "f32" else torch.float64
-            plan = DemagPlan(n, D, prec)
-            h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
-            e = rel_l2(h.cpu().numpy(), ref)
-            _say("  rel-L2", e)
-            assert e <= tol, (prec, var, e)
-            plan.close()
+        for n, runs in cases:
+            oct_ = oracle.tensor_octant(n, D)
+            m0 = synth.random_unit(n, 17)
+            ref = None
+            for prec, var, tol in runs:
+                os.environ["MMX_XVAR"] = str(var)
+                dt = torch.float32 if prec == "f32" else torch.float64
+                plan = DemagPlan(n, D, prec)
+                info = plan.info()
+                L = tuple(info["L"])
+                if ref is None:
+                    _say("x variants: oracle h_eff", n, L)
+                    ref = oracle.h_eff(m0, MS, A, D, oct_, L)
+                assert info["tiles"][3] == var and info["tiles"][4] == var, info["tiles"]
+                h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
+                e = rel_l2(h.cpu().numpy(), ref)
+                _say("x variant", n, prec, var, "W", info["tiles"][1], "rel-L2", e)
+                assert e <= tol, (n, prec, var, e)
+                plan.close()
     finally:
         if old is None:
             os.environ.pop("MMX_XVAR", None)
