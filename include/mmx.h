@@ -33,6 +33,11 @@
  * call that synchronises.  No C++ exception crosses this boundary.
  *
  * Threading: a plan is not thread-safe; distinct plans are independent.
+ *
+ * Test hooks (environment, read at plan creation; every choice computes the
+ * same result): MMX_XVAR=0..3 and MMX_YVAR=1 force an x or y pass variant
+ * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
+ * pass, MMX_TEST_FAIL_ALLOC makes every device allocation fail (MM_ENOMEM).
  */
 #ifndef MMX_H
 #define MMX_H
