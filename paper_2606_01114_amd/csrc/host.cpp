@@ -1374,6 +1374,7 @@ struct BGroup {
     int nthr = 64;
     size_t lds = 0;
     int2 *map = nullptr;  // device tile map (geometry, local tile)
+    int var = 0;          // x pass: 3 = half-LDS kernel on wide tiles, else the full-LDS kernel
 };
 
 struct mm_batch {
@@ -1464,7 +1465,8 @@ int batch_zinv(mm_batch *b, const ZInvArgs *d, int epi) {
 template <typename T>
 int batch_xyx(mm_batch *b) {
     for (const BGroup &g : b->gx) {
-        if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpf, g.map, g.tiles, g.L, g.W, -1, b->stream));
+        if (g.L && g.var == 3) HIPCK(launch_line_wide_b<T>(b->d_lpf, g.map, g.tiles, g.L, g.W, -1, b->stream));
+        else if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpf, g.map, g.tiles, g.L, g.W, -1, b->stream));
         else HIPCK(launch_line_pass<T>(b->d_lpf, g.map, g.tiles, g.nthr, g.lds, -1, false, b->stream));
     }
     for (const BGroup &g : b->gy) {
@@ -1472,7 +1474,8 @@ int batch_xyx(mm_batch *b) {
         else HIPCK(launch_fused_y<T>(b->d_fp, g.map, g.tiles, g.nthr, g.lds, b->stream));
     }
     for (const BGroup &g : b->gx) {
-        if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpi, g.map, g.tiles, g.L, g.W, +1, b->stream));
+        if (g.L && g.var == 3) HIPCK(launch_line_wide_b<T>(b->d_lpi, g.map, g.tiles, g.L, g.W, +1, b->stream));
+        else if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpi, g.map, g.tiles, g.L, g.W, +1, b->stream));
         else HIPCK(launch_line_pass<T>(b->d_lpi, g.map, g.tiles, g.nthr, g.lds, +1, false, b->stream));
     }
     return MM_OK;
@@ -1569,8 +1572,15 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         mm_plan *p = nullptr;
         rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &o);
         if (!rc) b->plans.push_back(p);
-        // grouped launches use the narrow-tile x kernels
-        if (!rc && (p->x_var[0] != 0 || p->x_var[1] != 0)) rc = configure_x(p, 0);
+        // grouped x launches: the half-LDS kernel on wide tiles for lines of
+        // 1024 points or more, the narrow full-LDS kernel below
+        if (!rc) {
+            int W = 0, NT = 0;
+            const size_t csz = precision == MM_F32 ? sizeof(float2) : sizeof(double2);
+            const int v = p->x_ct && line_ct_shape((int)p->L[0], csz, 3, &W, &NT) &&
+                                  line_hx_lds((int)p->L[0], W, csz) <= kLdsMax ? 3 : 0;
+            if (p->x_var[0] != v || p->x_var[1] != v) rc = configure_x(p, v);
+        }
         if (!rc) p->y_var = 0;
     }
     std::vector<LinePass> lf, li;
@@ -1580,7 +1590,7 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
     }
     if (!rc) rc = build_groups(b, b->gx, [](mm_plan *p) { return p->x_ct ? (int)p->L[0] : 0; },
                                [](mm_plan *p) { return p->tiles_fwd; },
-                               [](mm_plan *p, BGroup &g) { g.W = p->lp_fwd.W; g.nthr = std::max(g.nthr, p->lp_fwd.nthr); g.lds = std::max(g.lds, p->lds_fwd); });
+                               [](mm_plan *p, BGroup &g) { g.W = p->lp_fwd.W; g.var = p->x_var[0]; g.nthr = std::max(g.nthr, p->lp_fwd.nthr); g.lds = std::max(g.lds, p->lds_fwd); });
     if (!rc) rc = build_groups(b, b->gy, [](mm_plan *p) { return p->y_ct ? (int)p->L[1] : 0; },
                                [](mm_plan *p) { return p->fp.tiles; },
                                [](mm_plan *p, BGroup &g) { g.nthr = std::max(g.nthr, p->fp.nthr); g.lds = std::max(g.lds, p->lds_fp); });

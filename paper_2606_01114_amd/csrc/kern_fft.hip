@@ -133,11 +133,10 @@ __global__ void __launch_bounds__(NT) k_line_ct_b(const LinePass *__restrict__ d
 // tiles as k_line_ct at half the LDS, so two workgroups share a CU and one's
 // global loads and stores overlap the other's exchanges and arithmetic.
 template <typename T, int L, int DIR, int NT, int W>
-__global__ void __launch_bounds__(NT) k_line_hx(const LinePass a) {
+__device__ __forceinline__ void line_hx_body(const LinePass &a, int tile) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
-    const int tile = (int)xcd_tile(blockIdx.x, gridDim.x);
     const int o = tile / a.tiles_inner;
     const int c0 = (tile - o * a.tiles_inner) * W;
     const int wc = min(W, a.inner - c0);
@@ -151,6 +150,18 @@ __global__ void __launch_bounds__(NT) k_line_hx(const LinePass a) {
         buf_store(ro, (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff), v);
     };
     eng_fft_hx<T, L, DIR, NT, W, DIR < 0 ? 1 : 2>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
+}
+
+template <typename T, int L, int DIR, int NT, int W>
+__global__ void __launch_bounds__(NT) k_line_hx(const LinePass a) {
+    line_hx_body<T, L, DIR, NT, W>(a, (int)xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// grouped launch over many geometries of the same length L
+template <typename T, int L, int DIR, int NT, int W>
+__global__ void __launch_bounds__(NT) k_line_hx_b(const LinePass *__restrict__ descs, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    line_hx_body<T, L, DIR, NT, W>(descs[e.x], e.y);
 }
 
 // ---------------- fused y pass -------------------------------------------
@@ -735,6 +746,27 @@ hipError_t launch_line_wide(const LinePass &a, int tiles, int W, int dir, hipStr
 }
 #undef LINE_CASE_W
 
+#define LINE_CASE_WB(LL, WW)                                                                                          \
+    if (L == LL && W == WW) {                                                                                         \
+        const size_t lh = line_hx_lds(LL, WW, sizeof(cplx<T>));                                                       \
+        if (dir < 0) hipLaunchKernelGGL((k_line_hx_b<T, LL, -1, 1024, WW>), dim3(tiles), dim3(1024), lh, s, d, map); \
+        else hipLaunchKernelGGL((k_line_hx_b<T, LL, +1, 1024, WW>), dim3(tiles), dim3(1024), lh, s, d, map);         \
+        return hipGetLastError();                                                                                     \
+    }
+
+// variant 3 over many geometries of the same length
+template <typename T>
+hipError_t launch_line_wide_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    if constexpr (sizeof(T) == 4) {
+        LINE_CASE_WB(1024, 32) LINE_CASE_WB(2048, 16) LINE_CASE_WB(4096, 8)
+    } else {
+        LINE_CASE_WB(1024, 16) LINE_CASE_WB(2048, 8) LINE_CASE_WB(4096, 4)
+    }
+    return hipErrorInvalidValue;
+}
+#undef LINE_CASE_WB
+
 size_t line_ct_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L, W, (int)csz) * csz; }
 size_t line_hx_lds(int L, int W, size_t csz) { return (size_t)W * ct::lds_pitch(L / 2, W, (int)csz) * csz; }
 size_t fused_ct_lds(int L, size_t csz) { return (size_t)3 * ct::lds_pitch(L, 3, (int)csz) * csz; }
@@ -851,6 +883,8 @@ template hipError_t launch_line_ct<float>(const LinePass &, int, int, int, hipSt
 template hipError_t launch_line_ct<double>(const LinePass &, int, int, int, hipStream_t, int);
 template hipError_t launch_line_wide<float>(const LinePass &, int, int, int, hipStream_t);
 template hipError_t launch_line_wide<double>(const LinePass &, int, int, int, hipStream_t);
+template hipError_t launch_line_wide_b<float>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
+template hipError_t launch_line_wide_b<double>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
 template hipError_t launch_fused_ct<float>(const FusedPass &, hipStream_t);
 template hipError_t launch_fused_ct<double>(const FusedPass &, hipStream_t);
 

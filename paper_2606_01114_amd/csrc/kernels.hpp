@@ -26,6 +26,8 @@ size_t fused_ct_lds(int L, size_t csz);
 // half != 0 launches the half-LDS variant (k_line_hx)
 template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int half = 0);
 template <typename T> hipError_t launch_line_wide(const LinePass &a, int tiles, int W, int dir, hipStream_t s);
+template <typename T>
+hipError_t launch_line_wide_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s);
 template <typename T> hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s);
 template <typename T> hipError_t launch_zfwd(const ZFwdArgs &a, int src_mode, size_t lds_bytes, hipStream_t s);
 template <typename T> hipError_t launch_zinv(const ZInvArgs &a, int epi, size_t lds_bytes, hipStream_t s);

@@ -156,6 +156,33 @@ def test_batch_against_oracle_and_plans(prec, pow2):
         assert e <= (1e-9 if prec == "f64" else 1e-5), (g, e)
 
 
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_wide_x_tiles_against_oracle(prec):
+    """A batch whose x lines are 2048 and 1024 points long runs the grouped
+    half-LDS x kernel on wide tiles (and 64 points the full-LDS one): h_eff
+    and one RK4 step of every geometry against the oracle."""
+    import torch
+    from paper_2606_01114_amd import Batch
+    dt = torch.float32 if prec == "f32" else torch.float64
+    geo = [((600, 4, 2), 8e5), ((300, 5, 3), 6e5), ((20, 6, 2), 1e6)]
+    grids = [g for g, _ in geo]
+    Ms = [ms for _, ms in geo]
+    b = Batch(grids, [D] * len(grids), prec)
+    m0 = [rounded(synth.random_unit(g, 60 + k), dt) for k, g in enumerate(grids)]
+    ms = [to_dev(x, dt) for x in m0]
+    hs = b.h_eff(ms, Ms, A)
+    b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=1)
+    tol = 1e-9 if prec == "f64" else 1e-5
+    for k, g in enumerate(grids):
+        oct_ = oracle.tensor_octant(g, D)
+        L = tuple(_pow2_L(v) for v in g)
+        e = rel_l2(hs[k].cpu().numpy(), oracle.h_eff(m0[k], Ms[k], A, D, oct_, L))
+        ref = oracle.rk4_step(m0[k], Ms[k], A, D, oct_, L, ALPHA, GAMMA, DT)
+        es = rel_l2(ms[k].cpu().numpy() - m0[k], ref - m0[k])
+        _say("batch wide", prec, g, L, e, es)
+        assert e <= tol and es <= tol, (g, e, es)
+
+
 def test_batch_sweep_64_geometries():
     import torch
     from paper_2606_01114_amd import Batch, DemagPlan
