@@ -609,3 +609,22 @@ def test_rkf45_with_local_terms_against_oracle(padding):
         _say("rkf45 local", padding, prec, L, e, err, err_ref)
         assert ok and e <= tolp
         plan.close()
+
+
+def test_minimize_stoner_wohlfarth_angle_on_gpu():
+    """The GPU minimiser on one cubic cell with a z easy axis and a field at
+    50 degrees lands on the Stoner-Wohlfarth equilibrium angle, the root of
+    Ku sin(2 theta) = mu0 Ms H sin(psi - theta) (FP64)."""
+    from scipy.optimize import brentq
+    Ku, H, psi = 3e5, 2e5, np.deg2rad(50.0)
+    d = (2e-9, 2e-9, 2e-9)
+    theta = brentq(lambda t: Ku * np.sin(2 * t) - oracle.MU0 * MS * H * np.sin(psi - t), 0.0, psi, xtol=1e-15)
+    plan, dt_ = _plan((1, 1, 1), d, "f64")
+    plan.set_anisotropy(Ku, (0, 0, 1))
+    m0 = np.array([0.1, 0.0, 1.0]).reshape(1, 1, 1, 3)
+    m = to_dev(m0 / np.linalg.norm(m0), dt_)
+    it, tq = plan.minimize(m, MS, A, tol=1e-8, max_iter=100000, h_ext=(H * np.sin(psi), 0.0, H * np.cos(psi)))
+    mm = m.cpu().numpy().reshape(3)
+    _say("SW angle", it, tq, np.arctan2(mm[0], mm[2]), theta)
+    assert tq <= 1e-8 and abs(np.arctan2(mm[0], mm[2]) - theta) < 1e-10
+    plan.close()

@@ -55,3 +55,25 @@ def test_thin_film_relaxes_in_plane():
     assert tq <= 1e-1
     assert np.abs(m[..., 2]).max() < 0.05
     assert oracle.total_energy(m, MS, A, d, oct_, L) < oracle.total_energy(m0, MS, A, d, oct_, L)
+
+
+def test_stoner_wohlfarth_equilibrium_angle():
+    """One cubic cell (no demag torque, no exchange) with a uniaxial easy axis
+    along z and a field at 50 degrees to it in the x-z plane: the minimum of
+    E(theta) = Ku sin^2(theta) - mu0 Ms H cos(theta - psi) solves
+    Ku sin(2 theta) = mu0 Ms H sin(psi - theta), found here by bracketing; the
+    minimiser must land on that angle."""
+    from scipy.optimize import brentq
+    Ku, H, psi = 3e5, 2e5, np.deg2rad(50.0)
+    d = (2e-9, 2e-9, 2e-9)
+    oct_ = oracle.tensor_octant((1, 1, 1), d)
+    heff = lambda s: oracle.h_eff(s, MS, A, d, oct_, (1, 1, 1), aniso=(Ku, (0, 0, 1))) + \
+        np.array([H * np.sin(psi), 0.0, H * np.cos(psi)])
+    f = lambda t: Ku * np.sin(2 * t) - oracle.MU0 * MS * H * np.sin(psi - t)
+    theta = brentq(f, 0.0, psi, xtol=1e-15)
+    m0 = np.array([0.1, 0.0, 1.0]).reshape(1, 1, 1, 3)
+    m0 = m0 / np.linalg.norm(m0)
+    m, k, tq = oracle.bb_minimize(m0, MS, A, d, oct_, (1, 1, 1), tol=1e-8, max_iter=100000, heff=heff)
+    mm = m.reshape(3)
+    assert tq <= 1e-8 and abs(mm[1]) < 1e-12
+    assert abs(np.arctan2(mm[0], mm[2]) - theta) < 1e-10, (np.arctan2(mm[0], mm[2]), theta)
