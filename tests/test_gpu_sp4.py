@@ -18,10 +18,24 @@ from tests.gpu_util import to_dev
 
 pytestmark = pytest.mark.gpu
 
-N, D = (100, 25, 1), (5e-9, 5e-9, 3e-9)
-MS, A, ALPHA, GAMMA = 8e5, 1.3e-11, 0.02, 2.211e5
-H1 = (-24.6e-3 / oracle.MU0, 4.3e-3 / oracle.MU0, 0.0)
-OUT_DT, TOL, MIN_TOL = 1e-11, 1e-5, 0.1
+def _problem():
+    """The paper's inputs, from tests/golden/sp4_problem.txt."""
+    import os
+    vals = {}
+    with open(os.path.join(os.path.dirname(__file__), "golden", "sp4_problem.txt")) as f:
+        for line in f:
+            line = line.split("#")[0].strip()
+            if line:
+                k, v = line.split("=")
+                vals[k.strip()] = [float(x) for x in v.split()]
+    return vals
+
+
+P = _problem()
+N, D = tuple(int(v) for v in P["cells"]), tuple(P["cell_size"])
+MS, A, ALPHA, GAMMA = P["Ms"][0], P["A"][0], P["alpha"][0], 2.211e5
+H1 = tuple(v / oracle.MU0 for v in P["mu0_H"])
+OUT_DT, TOL, MIN_TOL = P["output_interval"][0], 1e-5, 0.1
 
 
 def _say(*a):
@@ -31,9 +45,9 @@ def _say(*a):
 
 def initial_state():
     m = np.zeros(N + (3,))
-    m[1:-1, :, :, 0] = 1.0
-    m[0, :, :, 1] = 1.0
-    m[-1, :, :, 1] = 1.0
+    m[1:-1, :, :] = P["initial_inner"]
+    m[0, :, :] = P["initial_ends"]
+    m[-1, :, :] = P["initial_ends"]
     return m
 
 
