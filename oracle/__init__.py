@@ -23,7 +23,7 @@ Parity status per function is stated in each module's docstring.
 """
 from .tensor import (tensor_octant, tensor_at, newell_at, far_at, newell_scale_at,
                      wrap_full, tensor_spectrum, default_L, is_7smooth)
-from .field import (MU0, HBAR, E_CHARGE, demag_fft, demag_direct, naive_dft, exchange_field, exchange_at,
+from .field import (MU0, HBAR, E_CHARGE, demag_fft, demag_direct, demag_direct_at, naive_dft, exchange_field, exchange_at,
                     dmi_field, anisotropy_field, stt_field, h_eff, energies)
 from .llg import (llg_rhs, rk4_step, rk4_run, macrospin_closed_form, rkf45_step, rkf45_run, rkf45_stages,
                   RKF45_A, RKF45_B4, RKF45_B5, RKF45_C)

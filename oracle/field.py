@@ -128,6 +128,33 @@ def demag_direct(m, Ms, octant, cells=None, chunk=1 << 22):
     return H if cells is not None else H.reshape(nx, ny, nz, 3)
 
 
+def demag_direct_at(m, Ms, octant, cells):
+    """The same direct sum as ``demag_direct`` at the listed target cells
+    (K,3) -> (K,3), looped in plain C over every source cell with
+    compensated summation (direct_sum.c), for grids where the numpy sum
+    is too slow (10^8 cells and more)."""
+    import ctypes
+    from . import _native
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    nx, ny, nz, _ = m.shape
+    oc = np.ascontiguousarray(octant, dtype=np.float64)
+    assert oc.shape == (nx, ny, nz, 6)
+    Msa = np.asarray(Ms, dtype=np.float64)
+    Msp = None
+    if Msa.ndim != 0:
+        Msa = np.ascontiguousarray(Msa)
+        assert Msa.shape == (nx, ny, nz)
+    tg = np.ascontiguousarray(np.asarray(cells, dtype=np.int64).reshape(-1, 3))
+    out = np.zeros((tg.shape[0], 3))
+    pd = ctypes.POINTER(ctypes.c_double)
+    if Msa.ndim != 0:
+        Msp = Msa.ctypes.data_as(pd)
+    _native.lib().oracle_demag_direct_at(nx, ny, nz, oc.ctypes.data_as(pd), m.ctypes.data_as(pd), Msp,
+                                         float(Msa) if Msa.ndim == 0 else 0.0, tg.shape[0],
+                                         tg.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), out.ctypes.data_as(pd))
+    return out
+
+
 def exchange_at(m, Ms, A, d, cells):
     """Exchange field at the listed cells only (K,3) -> (K,3), same rule as
     ``exchange_field``."""
