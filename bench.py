@@ -71,7 +71,7 @@ def pass_bytes(grid, L, r):
     hx, hy, hz = Lx // 2 + 1, Ly // 2 + 1, Lz // 2 + 1
     N3 = 3 * nx * ny * nz
     S1 = 3 * nx * ny * hz
-    S2 = 3 * nx * Ly * hz
+    S2 = 3 * Lx * ny * hz      # [kz][kx][y][c]: every kx < Lx, the ny rows that exist
     T6 = 6 * hx * hy * hz
     b = {
         "z_fwd": r * N3 + c * S1,
@@ -205,8 +205,25 @@ def run_sweep(steps, warmup, prec="f32"):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     cells = int(sum(np.prod(g) for g in grids))
-    return {"cells": cells, "geometries": len(grids), "ms_per_step": wall * 1e3 / steps,
-            "Mcell_updates_per_s": cells * steps / wall / 1e6, "setup_s": setup, "prec": prec}
+    # algorithmic bytes: the single-grid pass model of every geometry at its
+    # padded lengths (batches pad each axis to the power of two >= 2n-1)
+    r = 4 if prec == "f32" else 8
+    step_bytes = sum(pass_bytes(g, tuple(_pow2_len(v) for v in g), r)[1] for g in grids)
+    ms_step = wall * 1e3 / steps
+    b.close()
+    return {"cells": cells, "geometries": len(grids), "ms_per_step": ms_step,
+            "Mcell_updates_per_s": cells * steps / wall / 1e6, "setup_s": setup, "prec": prec,
+            "step_algorithmic_bytes": step_bytes, "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK}
+
+
+def _pow2_len(n):
+    """Smallest power of two >= 2n-1 (1 for one cell): a batch's padding."""
+    if n == 1:
+        return 1
+    L = 1
+    while L < 2 * n - 1:
+        L *= 2
+    return L
 
 
 def run_grad(prec="f32", steps=200, every=20):
@@ -233,6 +250,7 @@ def run_grad(prec="f32", steps=200, every=20):
         out = {"forward_s": t1 - t0, "backward_s": t2 - t1, "steps": steps, "checkpoint_every": every,
                "cells": int(m0.numel() // 3), "prec": prec,
                "grad_finite": bool(torch.isfinite(Mst.grad).all().item())}
+    plan.close()
     return out
 
 
@@ -380,6 +398,64 @@ def run_sp4(prec="f64", t_end=1e-9, out_dt=1e-11, tol=1e-5, min_tol=None):
             "mean_m_every_100ps": series[9::10], "prec": prec}
 
 
+def run_film_compare(steps=100):
+    """The thin film in FP32 and FP64: RK4 throughput of each, the FP32 field
+    error against the FP64 mode at step 0 over every cell, and the FP32
+    trajectory against FP64 after `steps` steps (the increment m_n - m_0,
+    relative L2)."""
+    import numpy as np
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    w = WORKLOADS["film"]
+    m_host = make_m(w)
+    m32h = torch.tensor(m_host, dtype=torch.float32)
+    p = {prec: DemagPlan(w["grid"], w["cell"], prec, autotune=True) for prec in ("f32", "f64")}
+    m0 = {"f32": m32h.to("cuda"), "f64": m32h.double().to("cuda")}
+
+    def dev_rel(x, ref):
+        return float(torch.linalg.vector_norm(x.double() - ref) / torch.linalg.vector_norm(ref))
+    h32 = p["f32"].h_eff(m0["f32"], MS, A)
+    h64 = p["f64"].h_eff(m0["f64"], MS, A)
+    out = {"grid": list(w["grid"]), "heff_fp32_vs_fp64_rel_l2": dev_rel(h32, h64)}
+    del h32, h64
+    for prec in ("f32", "f64"):
+        m = m0[prec].clone()
+        p[prec].llg_step(m, MS, A, ALPHA, GAMMA, DT, n_steps=2)
+        torch.cuda.synchronize()
+        m = m0[prec].clone()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        p[prec].llg_step(m, MS, A, ALPHA, GAMMA, DT, n_steps=steps)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[prec] = {"ms_per_step": ms, "Mcell_updates_per_s": int(np.prod(w["grid"])) / (ms * 1e-3) / 1e6}
+        out["m_" + prec] = m
+    d32 = out.pop("m_f32").double() - m0["f64"]
+    d64 = out.pop("m_f64") - m0["f64"]
+    out["steps"] = steps
+    out["increment_fp32_vs_fp64_rel_l2_after_steps"] = dev_rel(d32, d64)
+    out["fp32_over_fp64"] = out["f32"]["Mcell_updates_per_s"] / out["f64"]["Mcell_updates_per_s"]
+    for q in p.values():
+        q.close()
+    return out
+
+
+def tensor_setup_time(w, prec):
+    """Wall time of plan creation without the autotuner: the FP64 Newell
+    tensor, its transforms and rounding, plus the plan's tables."""
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = DemagPlan(w["grid"], w["cell"], prec, autotune=False)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    plan.close()
+    torch.cuda.empty_cache()
+    return t
+
+
 def copy_bandwidth():
     import torch
     from paper_2606_01114_amd import _lib
@@ -398,37 +474,85 @@ def copy_bandwidth():
     return 2.0 * n * 10 / (e0.elapsed_time(e1) * 1e-3)
 
 
-def cpu_baseline(w, budget_s=20.0):
-    """The oracle as it stands, on a bounded sub-grid of the same workload."""
+def _cpu_worker(args):
+    """One process of the CPU baseline: RK4 steps of the FP64 oracle on its
+    own sub-grid of the workload's recipe until the time budget is spent."""
+    w, sub, seed, budget_s = args
     import numpy as np
     import oracle
     import synth
-    nx, ny, nz = w["grid"]
-    sub = (min(nx, 64), min(ny, 64), min(nz, 32))
+    from threadpoolctl import threadpool_limits
     if w["m"] == "voronoi":
-        m0 = synth.voronoi_grains(sub, w["cell"], w["seed"])
+        m0 = synth.voronoi_grains(sub, w["cell"], seed)
     elif w["m"] == "smooth":
-        m0 = synth.smooth_film(sub, w["cell"], w["seed"])
+        m0 = synth.smooth_film(sub, w["cell"], seed)
     else:
-        m0 = synth.random_unit(sub, w["seed"])
+        m0 = synth.random_unit(sub, seed)
     oct_ = oracle.tensor_octant(sub, w["cell"])
     L = tuple(oracle.default_L(v) for v in sub)
-    # one thread: numpy's FFT is single-threaded; any BLAS pool is held to 1
-    from threadpoolctl import threadpool_limits
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        steps = 0
-        m = m0
+        steps, m = 0, m0
         while True:
             m = oracle.rk4_step(m, MS, A, w["cell"], oct_, L, ALPHA, GAMMA, DT)
             steps += 1
-            if time.perf_counter() - t0 > budget_s or steps >= 50:
+            if time.perf_counter() - t0 > budget_s or steps >= 200:
                 break
         el = time.perf_counter() - t0
-    cells = int(np.prod(sub))
-    return {"value": cells * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d RK4 steps of the FP64 oracle (numpy FFT, single thread) on a %dx%dx%d sub-grid "
-                      "of the same recipe (%.1f s)" % (steps, sub[0], sub[1], sub[2], el)}
+    return int(np.prod(sub)) * steps, steps, el
+
+
+def _cpu_config_worker(name):
+    """The oracle's h_eff and one RK4 step on a whole small workload (one
+    process, one thread)."""
+    import numpy as np
+    import oracle
+    import synth
+    from threadpoolctl import threadpool_limits
+    w = WORKLOADS[name]
+    m0 = make_m(w)
+    with threadpool_limits(limits=1):
+        oct_ = oracle.tensor_octant(w["grid"], w["cell"])
+        L = tuple(oracle.default_L(v) for v in w["grid"])
+        t0 = time.perf_counter()
+        oracle.h_eff(m0, MS, A, w["cell"], oct_, L)
+        t1 = time.perf_counter()
+        oracle.rk4_step(m0, MS, A, w["cell"], oct_, L, ALPHA, GAMMA, DT)
+        t2 = time.perf_counter()
+    cells = int(np.prod(w["grid"]))
+    return {"workload": name, "grid": list(w["grid"]), "heff_s": t1 - t0, "rk4_step_s": t2 - t1,
+            "Mcell_updates_per_s": cells / (t2 - t1) / 1e6}
+
+
+def cpu_baseline(w, budget_s=15.0, configs=("small", "grad")):
+    """The oracle as it stands (FP64, numpy FFT, one thread per process) on
+    every host core the box gives this job (at most 16): each process steps
+    its own 64x64x32 sub-grid of the workload's recipe (a bounded sample:
+    the whole grid would take hours), and the rate is their sum.  Beside it,
+    the oracle's h_eff and RK4 step on the whole 32x32x4 and 256x256x8
+    workloads, one process each."""
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+    nx, ny, nz = w["grid"]
+    sub = (min(nx, 64), min(ny, 64), min(nz, 32))
+    cores = max(1, min(16, os.cpu_count() or 1))
+    t0 = time.perf_counter()
+    ctx = mp.get_context("spawn")
+    with ProcessPoolExecutor(max_workers=cores, mp_context=ctx) as ex:
+        res = list(ex.map(_cpu_worker, [(w, sub, w["seed"] + 1000 * k, budget_s) for k in range(cores)]))
+    wall = time.perf_counter() - t0
+    upd = sum(r[0] for r in res)
+    steps = sum(r[1] for r in res)
+    busy = max(r[2] for r in res)
+    out = {"value": upd / busy / 1e6, "unit": "Mcell-updates/s", "cores": cores, "kind": "oracle",
+           "sample": "%d processes (one thread each), each RK4-stepping its own %dx%dx%d sub-grid of the same "
+                     "recipe with the FP64 oracle (numpy FFT) for %.0f s: %d steps in all (%.1f s wall with "
+                     "start-up)" % (cores, sub[0], sub[1], sub[2], budget_s, steps, wall),
+           "host_cpus": os.cpu_count()}
+    if configs:
+        with ProcessPoolExecutor(max_workers=len(configs), mp_context=ctx) as ex:
+            out["per_workload"] = list(ex.map(_cpu_config_worker, configs))
+    return out
 
 
 def _pmc_means(path, counter):
@@ -494,6 +618,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true",
                     help="skip the FP64 runs (the FP64 step and the per-field FP64 timings)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-others", action="store_true",
+                    help="skip the film, sweep, gradient and small-grid runs of the default workload")
     ap.add_argument("--fields-n", default="350", help="cube edge of the fields workload (a comma list sweeps sizes)")
     ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
     args = ap.parse_args()
@@ -625,6 +751,17 @@ def main():
         print("# timing the per-field FP64 evaluations on a 350^3 cube", file=sys.stderr, flush=True)
         rf = run_fields("f64", 350, 10, 2, paddings=("auto",))
         extra["paper_fields_350_fp64"] = dict(rf["best"], paper=rf["paper"])
+    if args.workload == "large":
+        # the FP64 tensor setup alone (a plan without the autotuner's trials)
+        for prec in ("f32", "f64"):
+            extra.setdefault("tensor_setup_s", {})[prec] = tensor_setup_time(w, prec)
+    if args.workload == "large" and not args.no_others:
+        print("# the other workloads: thin film, sweep, gradient, small grid", file=sys.stderr, flush=True)
+        extra["film"] = run_film_compare(100)
+        extra["sweep"] = run_sweep(10, 3)
+        extra["grad"] = run_grad("f32")
+        rs = run_gpu("small", "f32", 200, 20, make_m(WORKLOADS["small"]))
+        extra["small"] = {"ms_per_step": rs["ev_ms"] / 200, "Mcell_updates_per_s": 32 * 32 * 4 * 200 / rs["wall_s"] / 1e6}
     out = {
         "metric": METRIC, "value": value, "unit": "Mcell-updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": res["wall_s"] * 1e3 / args.steps, "higher_is_better": True,

@@ -133,8 +133,8 @@ int mm_plan_destroy(mm_plan *plan);
  *              keeps: the two spectrum workspaces, the RK4 stage and
  *              accumulator fields, twiddle tables, descriptors and energy
  *              partials (sub-buffers start on 256-byte boundaries).
- * The adjoint entry points' scratch (14 three-component fields) is not part
- * of it: they allocate it on first use.
+ * The scratch of the RK4-step adjoint, RKF45 and minimiser entry points is not part of
+ * it: see mm_plan_scratch_bytes.
  */
 int mm_plan_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts, size_t *tensor_bytes,
                   size_t *workspace_bytes);
@@ -146,10 +146,12 @@ int mm_plan_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts
  *                  receives the tensor spectrum
  *   workspace_buf  device buffer of at least workspace_bytes, 256-byte aligned
  * Synchronises the plan's stream, copies the spectrum into tensor_buf, frees
- * the plan's own buffers (and any captured graph or adjoint scratch) and
+ * the plan's own buffers (and any captured graph or plan-owned scratch) and
  * rebuilds the plan's tables in workspace_buf; the autotuned launch shapes
- * are kept.  From then on the plan uses only these buffers (plus adjoint
- * scratch, allocated on first use); the caller keeps them alive and
+ * are kept.  From then on the plan allocates no device memory of its own:
+ * it uses only these buffers and the scratch attached with
+ * mm_plan_attach_scratch (an entry point that needs more scratch than is
+ * attached returns MM_ESTATE); the caller keeps them alive and
  * untouched until mm_plan_destroy, which does not free them.  At most once
  * per plan (MM_ESTATE otherwise).  The sizes cannot be checked: smaller
  * buffers than mm_plan_bytes reports are undefined behaviour.  On an error
@@ -157,6 +159,35 @@ int mm_plan_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts
  * returns MM_ESTATE.
  */
 int mm_plan_attach_memory(mm_plan *plan, void *tensor_buf, void *workspace_buf);
+
+/*
+ * mm_plan_scratch_bytes -- device scratch that the entry points beyond the
+ * forward path need, per call (host only; no GPU call):
+ *   bytes_out[0]  llg_step_adjoint (14 vector fields: the recomputed stages)
+ *   bytes_out[1]  llg_rkf45_step (six stage derivatives and the candidate)
+ *   bytes_out[2]  mm_minimize_bb (previous m, two gradients, block sums)
+ * grid, precision, opts as for demag_tensor_init.  One region serves all of
+ * them (each uses it only within one call, in stream order), so the largest
+ * of the three covers every entry point.  h_eff, llg_step and h_eff_adjoint
+ * need no scratch.
+ *
+ * mm_plan_attach_scratch -- use the caller's device buffer (256-byte
+ * aligned, `bytes` long) as that scratch from now on.  Synchronises the
+ * plan's stream and frees any scratch the plan allocated itself.  The
+ * caller keeps the buffer alive until mm_plan_destroy (which does not free
+ * it) or the next attach.  A plan that owns its memory (no
+ * mm_plan_attach_memory) and has no attached scratch allocates the region
+ * on the first call that needs it and grows it when a later call needs more.
+ */
+int mm_plan_scratch_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts, size_t bytes_out[3]);
+int mm_plan_attach_scratch(mm_plan *plan, void *buf, size_t bytes);
+
+/*
+ * mm_plan_set_stream -- enqueue the plan's later work on hip_stream.  The new
+ * stream first waits (an event, no host synchronisation) for everything
+ * already enqueued on the previous one, since the plan's workspace, scratch
+ * and captured graph serve every call.
+ */
 int mm_plan_set_stream(mm_plan *plan, void *hip_stream);
 
 /*
@@ -265,8 +296,8 @@ int llg_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A,
  *   accepted   host int: 1 if m was advanced by dt (to the fourth-order
  *              solution, Fehlberg's pairing), else 0 (m unchanged)
  * Synchronous (the host needs err to decide).  The six stage derivatives and
- * the candidate are plan scratch (7 three-component fields), allocated on the
- * first call.  A non-finite err returns MM_ENONFINITE with m unchanged.
+ * the candidate live in the plan's scratch (mm_plan_scratch_bytes).  A
+ * non-finite err returns MM_ENONFINITE with m unchanged.
  */
 int llg_rkf45_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A, double alpha,
                    double gamma, double *dt, double tol, const double h_ext[3], unsigned flags, double *err_out,
@@ -287,9 +318,9 @@ int llg_rkf45_step(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, dou
  *   tol        >= 0 (A/m); max_iter >= 0
  *   iters_out  host int: updates made; torque_out host double: max |m x h|
  *              of the returned m
- * Synchronous (one host read of four FP64 values per iteration).  Scratch
- * (3 three-component fields and the per-block sums) is allocated on the
- * first call.  A non-finite torque returns MM_ENONFINITE.
+ * Synchronous (one host read of four FP64 values per iteration).  Its three
+ * vector fields and per-block sums live in the plan's scratch
+ * (mm_plan_scratch_bytes).  A non-finite torque returns MM_ENONFINITE.
  */
 int mm_minimize_bb(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, double A, const double h_ext[3],
                    double tol, int max_iter, int *iters_out, double *torque_out);
@@ -301,7 +332,8 @@ int mm_minimize_bb(mm_plan *plan, void *m, const void *Ms, double Ms_scalar, dou
  *   g_Ms = m . H_demag(g_h) - g_h . H_exchange(m) / Ms
  * The demag operator is self-adjoint, so it runs the same FFT pipeline and
  * tensor on g_h.  g_m: device (nx,ny,nz,3), overwritten.  g_Ms: device
- * (nx,ny,nz) or NULL, overwritten (per cell, also for a scalar Ms).
+ * (nx,ny,nz) or NULL, overwritten (per cell, also for a scalar Ms).  Runs
+ * in the plan's workspace (no scratch).  Asynchronous.
  */
 int h_eff_adjoint(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A,
                   const void *g_h, void *g_m, void *g_Ms, unsigned terms);
@@ -311,7 +343,9 @@ int h_eff_adjoint(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar
  *   g        device (nx,ny,nz,3): in = cotangent of m(t+dt), out = cotangent
  *            of m(t)
  *   g_Ms     device (nx,ny,nz) accumulated (+=) with d<g, m(t+dt)>/dMs, or NULL
- * Other arguments as in llg_step.  Recomputes the four stages internally.
+ * Other arguments as in llg_step.  Recomputes the four stages internally,
+ * recording them in the plan's scratch (mm_plan_scratch_bytes).
+ * Asynchronous.
  */
 int llg_step_adjoint(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A,
                      double alpha, double gamma, double dt, const double h_ext[3], unsigned flags,
@@ -352,6 +386,13 @@ int mm_batch_h_eff(mm_batch *b, void *const *m_ptrs, const double *Ms, double A,
                    unsigned terms);
 int mm_batch_llg_step(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, double alpha,
                       double gamma, double dt, int n_steps, unsigned flags);
+/*
+ * mm_batch_tensor_set -- replace the tensor of one geometry of the batch by
+ * the transform of a HOST real-space octant (nx,ny,nz,6) of that geometry,
+ * as mm_demag_tensor_set does for a plan (the test hook that holds the
+ * tensor equal in FP64 parity).  Synchronises.
+ */
+int mm_batch_tensor_set(mm_batch *b, int geometry, const double *host_octant);
 int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes);
 int mm_batch_destroy(mm_batch *b);
 
@@ -360,8 +401,8 @@ int mm_batch_destroy(mm_batch *b);
  * mm_plan_time_passes runs each pass of the pipeline `reps` times on the plan
  * stream between HIP events and writes the mean duration in ms of
  *   ms_out[0] z-forward (real-to-complex along z, source Ms m)
- *   ms_out[1] y-forward        ms_out[2] fused x (FFT, tensor product, IFFT)
- *   ms_out[3] y-inverse        ms_out[4] z-inverse + RK4 stage epilogue
+ *   ms_out[1] x-forward        ms_out[2] fused y (FFT, tensor product, IFFT)
+ *   ms_out[3] x-inverse        ms_out[4] z-inverse + RK4 stage epilogue
  *   ms_out[5] z-inverse + h_eff epilogue
  * on the plan's own scratch arrays (contents irrelevant).  Synchronises.
  * mm_device_copy copies `bytes` (a multiple of 16) between device buffers with

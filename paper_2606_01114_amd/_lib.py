@@ -19,11 +19,12 @@ MM_NO_RENORM, MM_NO_GRAPH = 1, 2
 # Exported names (kept in sync with include/mmx.h; a CPU test checks both).
 EXPORTS = [
     "mm_plan_opts_default", "demag_tensor_init", "mm_plan_destroy", "mm_plan_set_stream", "mm_plan_info",
-    "mm_plan_bytes", "mm_plan_attach_memory", "mm_plan_set_dmi", "mm_plan_set_anisotropy",
+    "mm_plan_bytes", "mm_plan_attach_memory", "mm_plan_scratch_bytes", "mm_plan_attach_scratch", "mm_plan_set_dmi", "mm_plan_set_anisotropy",
     "mm_plan_set_stt",
     "h_eff", "llg_step", "llg_rkf45_step", "mm_minimize_bb", "h_eff_adjoint", "llg_step_adjoint",
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
-    "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_info", "mm_batch_destroy",
+    "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_tensor_set", "mm_batch_info",
+    "mm_batch_destroy",
     "mm_plan_time_passes", "mm_device_copy",
     "mm_strerror", "mm_last_error",
 ]
@@ -58,6 +59,8 @@ def _load():
         "mm_plan_bytes": [i64p, ci, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_size_t),
                           ctypes.POINTER(ctypes.c_size_t)],
         "mm_plan_attach_memory": [vp, vp, vp],
+        "mm_plan_scratch_bytes": [i64p, ci, ctypes.POINTER(PlanOpts), ctypes.POINTER(ctypes.c_size_t)],
+        "mm_plan_attach_scratch": [vp, vp, ctypes.c_size_t],
         "mm_plan_set_dmi": [vp, ci, cd],
         "mm_plan_set_anisotropy": [vp, cd, dp],
         "mm_plan_set_stt": [vp, cd, cd, cd, cd, cd, dp],
@@ -75,6 +78,7 @@ def _load():
         "mm_batch_create": [ctypes.POINTER(vp), ci, i64p, dp, ci, vp, ctypes.POINTER(PlanOpts)],
         "mm_batch_h_eff": [vp, ctypes.POINTER(vp), dp, cd, ctypes.POINTER(vp), cu],
         "mm_batch_llg_step": [vp, ctypes.POINTER(vp), dp, cd, cd, cd, cd, ci, cu],
+        "mm_batch_tensor_set": [vp, ci, dp],
         "mm_batch_info": [vp, i64p, ctypes.POINTER(ctypes.c_size_t)],
         "mm_batch_destroy": [vp],
         "mm_plan_time_passes": [vp, ci, dp],

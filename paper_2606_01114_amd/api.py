@@ -49,6 +49,16 @@ def plan_bytes(grid, precision="f32", far_radius=16.0, L=None, padding="auto"):
     return t.value, w.value
 
 
+def plan_scratch_bytes(grid, precision="f32", far_radius=16.0, L=None, padding="auto"):
+    """Scratch bytes per call of (the adjoint entry points, the RKF45 step,
+    the minimiser) for this grid (no GPU call)."""
+    opts = _opts(far_radius, L, padding=padding)
+    g = (ctypes.c_int64 * 3)(*[int(v) for v in grid])
+    out = (ctypes.c_size_t * 3)()
+    check(_lib.lib().mm_plan_scratch_bytes(g, _prec(precision), ctypes.byref(opts), out))
+    return tuple(out)
+
+
 class DemagPlan:
     """One geometry: grid (nx,ny,nz), cell (dx,dy,dz) in metres, FP32 or FP64.
     Creating it computes the Newell tensor spectrum on the GPU (FP64)."""
@@ -110,20 +120,30 @@ class DemagPlan:
         check(_lib.lib().mm_plan_set_stt(self._h, float(j), float(P), float(Lambda), float(eps_prime),
                                          float(d_layer), pv))
 
-    def attach_memory(self):
+    def attach_memory(self, scratch=("adjoint", "rkf45", "minimize")):
         """Move the plan's tensor spectrum and workspace into torch-owned
-        device buffers (torch's caching allocator then holds all of the
-        plan's forward memory); returns the two uint8 tensors, which the plan
-        keeps alive until close()."""
+        device buffers, and give it a torch-owned scratch region large enough
+        for the listed entry points ("adjoint": llg_step_adjoint, "rkf45",
+        "minimize"; empty: none, and those calls then fail): torch's caching
+        allocator then
+        holds all of the plan's device memory.  Returns the uint8 tensors
+        (tensor, workspace, scratch or None), which the plan keeps alive
+        until close()."""
         tb, wb = plan_bytes(self.grid, self.prec, self._far, self._L, self._pad)
+        need = plan_scratch_bytes(self.grid, self.prec, self._far, self._L, self._pad)
+        which = {"adjoint": 0, "rkf45": 1, "minimize": 2}
+        sb = max([need[which[k]] for k in scratch], default=0)
         # 256-byte alignment: torch's CUDA allocator returns 512-byte aligned blocks
         t = torch.empty(max(tb, 1), dtype=torch.uint8, device=self.device)
         w = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.device)
+        sc = torch.empty(sb, dtype=torch.uint8, device=self.device) if sb else None
         self._sync_stream()
         torch.cuda.current_stream().synchronize()
         check(_lib.lib().mm_plan_attach_memory(self._h, _ptr(t), _ptr(w)))
-        self._attached = (t, w)
-        return t, w
+        if sc is not None:
+            check(_lib.lib().mm_plan_attach_scratch(self._h, _ptr(sc), sb))
+        self._attached = (t, w, sc)
+        return t, w, sc
 
     def info(self):
         L = (ctypes.c_int64 * 3)()
@@ -297,6 +317,15 @@ class Batch:
                                            int(n_steps), flags))
         return ms
 
+    def tensor_set(self, k, octant):
+        """Replace geometry k's tensor by the transform of a real-space FP64
+        octant (nx,ny,nz,6) of that geometry (the parity tests' hook)."""
+        import numpy as np
+        a = np.ascontiguousarray(octant, dtype=np.float64)
+        if a.shape != self.grids[k] + (6,):
+            raise ValueError("octant must have shape %s" % (self.grids[k] + (6,),))
+        check(_lib.lib().mm_batch_tensor_set(self._h, int(k), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
     def close(self):
         if getattr(self, "_h", None) and self._h.value:
             _lib.lib().mm_batch_destroy(self._h)
@@ -314,9 +343,11 @@ class HEff(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx, m, Ms, plan, A, terms=MM_DEMAG | MM_EXCHANGE):
-        h = plan.h_eff(m.contiguous(), Ms.contiguous() if isinstance(Ms, torch.Tensor) else Ms, A, terms=terms)
-        ctx.save_for_backward(m, Ms if isinstance(Ms, torch.Tensor) else None)
-        ctx.plan, ctx.A, ctx.terms, ctx.Ms_scalar = plan, A, terms, None if isinstance(Ms, torch.Tensor) else Ms
+        mc = m.contiguous()
+        Msc = Ms.contiguous() if isinstance(Ms, torch.Tensor) else None
+        h = plan.h_eff(mc, Msc if Msc is not None else Ms, A, terms=terms)
+        ctx.save_for_backward(mc, Msc)
+        ctx.plan, ctx.A, ctx.terms, ctx.Ms_scalar = plan, A, terms, None if Msc is not None else Ms
         return h
 
     @staticmethod
@@ -349,17 +380,23 @@ class _LLGRun(torch.autograd.Function):
         g = g_out.detach().contiguous().clone()
         gMs = torch.zeros_like(Ms)
         starts = [s for s, _ in ctx.ckpts] + [n_steps]
+        # the recompute steps all run on one work buffer, so the step's graph
+        # (keyed by the m pointer) is captured once for the whole backward
+        work = torch.empty_like(g)
+        states = None
         for seg in range(len(ctx.ckpts) - 1, -1, -1):
             start, ck = ctx.ckpts[seg]
             end = starts[seg + 1]
             # states m_start .. m_{end-1} of this segment, recomputed from its checkpoint
-            states = [ck.clone()]
-            for _ in range(end - start - 1):
-                s = states[-1].clone()
-                plan.llg_step(s, Ms, A, alpha, gamma, dt, n_steps=1)
-                states.append(s)
-            for s in reversed(states):
-                plan.llg_step_adjoint(s, Ms, A, alpha, gamma, dt, g, gMs)
+            if states is None or states.shape[0] < end - start:
+                states = torch.empty((end - start,) + tuple(g.shape), dtype=g.dtype, device=g.device)
+            states[0].copy_(ck)
+            work.copy_(ck)
+            for i in range(1, end - start):
+                plan.llg_step(work, Ms, A, alpha, gamma, dt, n_steps=1)
+                states[i].copy_(work)
+            for i in range(end - start - 1, -1, -1):
+                plan.llg_step_adjoint(states[i], Ms, A, alpha, gamma, dt, g, gMs)
         return g, gMs, None, None, None, None, None, None, None
 
 

@@ -190,12 +190,17 @@ struct mm_plan {
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<unsigned char> gkey;
-    // adjoint scratch (allocated on first use)
-    void *adj = nullptr;
-    // RKF45 stage derivatives (6 fields) and candidate solution (allocated on first use)
-    void *rk = nullptr;
-    // minimiser scratch: previous m, two gradient fields, per-block and total sums
-    void *bb = nullptr;
+    // scratch of the RK4 step's adjoint (14 vector fields), of the RKF45
+    // step (6 stage derivatives and the candidate) and of the minimiser
+    // (previous m, two gradient fields, per-block and total sums): one region
+    // that each of them uses only within one call, in stream order.  Either
+    // caller-owned (mm_plan_attach_scratch) or, for a plan that owns its
+    // memory, allocated on first use and grown when a call needs more.
+    void *scr = nullptr;
+    size_t scr_bytes = 0;
+    bool scr_ext = false;
+    // orders a newly set stream after the work enqueued on the previous one
+    hipEvent_t ev = nullptr;
     // memory sizing and caller-owned memory: a dry plan only adds up sizes;
     // with a workspace attached, allocations are carved from it and the tensor
     // spectrum lives in the caller's tensor buffer
@@ -245,6 +250,42 @@ void free_all(mm_plan *p) {
     if (p->cap) { (void)hipStreamDestroy(p->cap); p->cap = nullptr; }
     for (void *q : p->allocs) (void)hipFree(q);
     p->allocs.clear();
+    if (!p->scr_ext) { p->scr = nullptr; p->scr_bytes = 0; }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// Scratch bytes of the entry points that need more than the plan's workspace:
+// [0] llg_step_adjoint, [1] llg_rkf45_step, [2] mm_minimize_bb.
+void scratch_need(int64_t ncell, size_t rsz, int tiles, size_t out[3]) {
+    const size_t f3 = (size_t)ncell * 3 * rsz;
+    out[0] = 14 * f3;
+    out[1] = 7 * f3;
+    out[2] = 3 * align256(f3) + align256((size_t)tiles * 4 * sizeof(double)) + 4 * sizeof(double);
+}
+
+// the scratch region for a call that needs `need` bytes
+int get_scratch(mm_plan *p, size_t need, void **out) {
+    *out = nullptr;
+    if (p->scr && p->scr_bytes >= need) { *out = p->scr; return MM_OK; }
+    if (p->scr_ext || p->ws)
+        return fail(MM_ESTATE, "this call needs %zu bytes of scratch memory and the plan has %zu attached "
+                               "(mm_plan_scratch_bytes, mm_plan_attach_scratch)", need, p->scr_ext ? p->scr_bytes : (size_t)0);
+    if (p->scr) {
+        // grow: work still queued may use the old region
+        HIPCK(hipStreamSynchronize(p->stream));
+        auto it = std::find(p->allocs.begin(), p->allocs.end(), p->scr);
+        if (it != p->allocs.end()) p->allocs.erase(it);
+        (void)hipFree(p->scr);
+        p->bytes -= p->scr_bytes;
+        p->scr = nullptr;
+        p->scr_bytes = 0;
+    }
+    int rc = dalloc_own(p, &p->scr, need);
+    if (rc) return rc;
+    p->scr_bytes = need;
+    *out = p->scr;
+    return MM_OK;
 }
 
 template <typename T>
@@ -777,11 +818,12 @@ template <typename T>
 int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, double alpha, double gamma,
                      double dt, const double *hext, unsigned flags, void *g, void *g_Ms) {
     const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
-    const size_t f3 = (size_t)ncell * 3 * sizeof(T);
     int rc;
-    // not part of an attached workspace: allocated by the plan on first use
-    if (!p->adj && (rc = dalloc_own(p, &p->adj, 14 * f3))) return rc;
-    T *base = (T *)p->adj;
+    size_t need[3];
+    scratch_need(ncell, sizeof(T), p->zg.tiles, need);
+    void *scr = nullptr;
+    if ((rc = get_scratch(p, need[0], &scr))) return rc;
+    T *base = (T *)scr;
     auto buf = [&](int i) { return (void *)(base + (size_t)i * ncell * 3); };
     void *srec[4] = {(void *)m, buf(0), buf(1), buf(2)};
     void *hrec[4] = {buf(3), buf(4), buf(5), buf(6)};
@@ -837,9 +879,11 @@ int rkf45_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, doubl
                const double *hext, int renorm, double *err) {
     const size_t f3 = (size_t)p->n[0] * p->n[1] * p->n[2] * 3 * sizeof(T);
     int rc;
-    if (!p->rk && (rc = dalloc_own(p, &p->rk, 7 * f3))) return rc;
-    void *K = p->rk;
-    void *cand = static_cast<char *>(p->rk) + 6 * f3;
+    size_t need[3];
+    scratch_need(p->n[0] * p->n[1] * p->n[2], sizeof(T), p->zg.tiles, need);
+    void *K = nullptr;
+    if ((rc = get_scratch(p, need[1], &K))) return rc;
+    void *cand = static_cast<char *>(K) + 6 * f3;
     if ((rc = run_zfwd<T>(p, SRC_MS_M, m, Ms, Ms_s))) return rc;
     for (int s = 0; s < 6; ++s) {
         if ((rc = run_xyx<T>(p))) return rc;
@@ -878,15 +922,17 @@ template <typename T>
 int bb_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, const double *hext, double tol, int max_iter,
             int *iters, double *torque_out) {
     const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
-    const size_t f3 = (size_t)ncell * 3 * sizeof(T);
-    const size_t nb = (size_t)p->zg.tiles * 4 * sizeof(double);
+    const size_t f3 = align256((size_t)ncell * 3 * sizeof(T));
     int rc;
-    if (!p->bb && (rc = dalloc_own(p, &p->bb, 3 * f3 + nb + 4 * sizeof(double) + 256))) return rc;
-    char *base = static_cast<char *>(p->bb);
+    size_t need[3];
+    scratch_need(ncell, sizeof(T), p->zg.tiles, need);
+    void *scr = nullptr;
+    if ((rc = get_scratch(p, need[2], &scr))) return rc;
+    char *base = static_cast<char *>(scr);
     T *mprev = reinterpret_cast<T *>(base);
     T *g[2] = {reinterpret_cast<T *>(base + f3), reinterpret_cast<T *>(base + 2 * f3)};
     double *part = reinterpret_cast<double *>(base + 3 * f3);
-    double *tot = part + 4 * (size_t)p->zg.tiles;
+    double *tot = reinterpret_cast<double *>(base + 3 * f3 + align256((size_t)p->zg.tiles * 4 * sizeof(double)));
     double torque = 0.0;
     int k = 0;
     for (;; ++k) {
@@ -1037,6 +1083,7 @@ int mm_plan_destroy(mm_plan *p) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     (void)hipStreamSynchronize(p->stream);
     free_all(p);
+    if (p->ev) (void)hipEventDestroy(p->ev);
     delete p;
     return MM_OK;
 }
@@ -1071,11 +1118,8 @@ int mm_plan_attach_memory(mm_plan *p, void *tensor_buf, void *workspace_buf) {
     // the tensor spectrum moves into the caller's buffer
     HIPCK(hipMemcpy(tensor_buf, p->tensor, p->tensor_bytes, hipMemcpyDeviceToDevice));
     const int xv0 = p->x_var[0], xv1 = p->x_var[1], yv = p->y_var;
-    free_all(p);   // the plan's own buffers, captured graph and adjoint scratch
+    free_all(p);   // the plan's own buffers, captured graph and plan-owned scratch
     p->bytes = 0;
-    p->adj = nullptr;
-    p->rk = nullptr;
-    p->bb = nullptr;
     p->tensor = nullptr;
     p->ws = static_cast<char *>(workspace_buf);
     p->ws_used = 0;
@@ -1145,7 +1189,49 @@ int mm_plan_set_stt(mm_plan *p, double j, double P, double lambda, double eps_pr
 
 int mm_plan_set_stream(mm_plan *p, void *s) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
-    p->stream = (hipStream_t)s;
+    hipStream_t ns = (hipStream_t)s;
+    if (ns == p->stream) return MM_OK;
+    // the plan's workspace, scratch and graph are shared by every call: the
+    // new stream waits for what is already queued on the old one
+    if (!p->ev) HIPCK(hipEventCreateWithFlags(&p->ev, hipEventDisableTiming));
+    HIPCK(hipEventRecord(p->ev, p->stream));
+    HIPCK(hipStreamWaitEvent(ns, p->ev, 0));
+    p->stream = ns;
+    return MM_OK;
+}
+
+int mm_plan_scratch_bytes(const int64_t grid[3], int precision, const mm_plan_opts *opts, size_t bytes_out[3]) {
+    if (!bytes_out) return fail(MM_EINVAL, "bytes_out must be non-NULL");
+    const double unit[3] = {1.0, 1.0, 1.0};
+    mm_plan_opts o;
+    int64_t L[3];
+    int rc = plan_params(grid, unit, precision, opts, &o, L);
+    if (rc) return rc;
+    mm_plan q;
+    q.dry = true;
+    q.prec = precision;
+    q.rsz = precision == MM_F32 ? 4 : 8;
+    for (int a = 0; a < 3; ++a) { q.n[a] = grid[a]; q.d[a] = 1.0; q.L[a] = L[a]; }
+    rc = precision == MM_F32 ? setup_plan<float>(&q, &o) : setup_plan<double>(&q, &o);
+    if (rc) return rc;
+    scratch_need(grid[0] * grid[1] * grid[2], q.rsz, q.zg.tiles, bytes_out);
+    return MM_OK;
+}
+
+int mm_plan_attach_scratch(mm_plan *p, void *buf, size_t bytes) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    if (!buf || bytes == 0) return fail(MM_EINVAL, "buf must be non-NULL and bytes > 0");
+    if ((uintptr_t)buf & 255) return fail(MM_EINVAL, "buf must be 256-byte aligned");
+    HIPCK(hipStreamSynchronize(p->stream));
+    if (p->scr && !p->scr_ext) {
+        auto it = std::find(p->allocs.begin(), p->allocs.end(), p->scr);
+        if (it != p->allocs.end()) p->allocs.erase(it);
+        (void)hipFree(p->scr);
+        p->bytes -= p->scr_bytes;
+    }
+    p->scr = buf;
+    p->scr_bytes = bytes;
+    p->scr_ext = true;
     return MM_OK;
 }
 
@@ -1243,7 +1329,7 @@ int llg_rkf45_step(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double
     if (!std::isfinite(err)) return fail(MM_ENONFINITE, "RKF45 error estimate is not finite");
     if (err <= tol) {
         const size_t f3 = (size_t)p->n[0] * p->n[1] * p->n[2] * 3 * p->rsz;
-        HIPCK(hipMemcpyAsync(m, static_cast<char *>(p->rk) + 6 * f3, f3, hipMemcpyDeviceToDevice, p->stream));
+        HIPCK(hipMemcpyAsync(m, static_cast<char *>(p->scr) + 6 * f3, f3, hipMemcpyDeviceToDevice, p->stream));
         *accepted = 1;
     }
     const double fac = err == 0.0 ? 5.0 : std::min(5.0, std::max(0.2, 0.9 * std::pow(tol / err, 0.2)));
@@ -1681,6 +1767,14 @@ int mm_batch_llg_step(mm_batch *b, void *const *m_ptrs, const double *Ms, double
     }
     for (int k = 0; k < n_steps; ++k) HIPCK(hipGraphLaunch(b->gexec, b->stream));
     return MM_OK;
+}
+
+int mm_batch_tensor_set(mm_batch *b, int geometry, const double *host_octant) {
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    if (geometry < 0 || geometry >= b->count) return fail(MM_EINVAL, "geometry %d out of range [0, %d)", geometry, b->count);
+    HIPCK(hipStreamSynchronize(b->stream));
+    // the plan's spectrum buffer stays where the batch's descriptors point
+    return mm_demag_tensor_set(b->plans[geometry], host_octant);
 }
 
 int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes) {

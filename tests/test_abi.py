@@ -136,10 +136,54 @@ def test_plan_bytes_host_only():
     assert _bytes((4, 4, 4), 5)[0] == _lib.MM_EINVAL
 
 
+def test_bench_pass_bytes_against_plan_bytes_non_square():
+    """The benchmark's byte model uses the spectrum sizes the library
+    allocates: S1 = 3 nx ny hz and S2 = 3 Lx ny hz complex values (a
+    non-square grid, so that nx, ny and Lx, Ly differ), plus the three
+    stage fields, within the small tables of the workspace."""
+    import bench
+    from paper_2606_01114_amd import _lib
+    n = (96, 40, 6)
+    o = _lib.PlanOpts()
+    _lib.lib().mm_plan_opts_default(ctypes.byref(o))
+    o.pow2_padding = 1
+    L = (256, 128, 16)
+    hx, hy, hz = L[0] // 2 + 1, L[1] // 2 + 1, L[2] // 2 + 1
+    for prec, r in ((_lib.MM_F32, 4), (_lib.MM_F64, 8)):
+        rc, t, w = _bytes(n, prec, ctypes.byref(o))
+        assert rc == 0
+        b, _ = bench.pass_bytes(n, L, r)
+        c = 2 * r
+        S1, S2 = 3 * n[0] * n[1] * hz, 3 * L[0] * n[1] * hz
+        T6 = 6 * hx * hy * hz
+        assert b["x_fwd"] == c * (S1 + S2) and b["y_fused"] == 2 * c * S2 + r * T6
+        assert t == r * T6
+        big = c * (S1 + S2) + 3 * 3 * n[0] * n[1] * n[2] * r
+        assert big <= w <= big + (1 << 20), (w, big)
+
+
+def test_scratch_bytes_host_only():
+    """mm_plan_scratch_bytes: 14 vector fields for the adjoint, 7 for RKF45,
+    3 plus block sums for the minimiser (no GPU call)."""
+    from paper_2606_01114_amd import _lib
+    n = (1024, 1024, 128)
+    for prec, r in ((_lib.MM_F32, 4), (_lib.MM_F64, 8)):
+        out = (ctypes.c_size_t * 3)()
+        g = (ctypes.c_int64 * 3)(*n)
+        assert _lib.lib().mm_plan_scratch_bytes(g, prec, None, out) == 0
+        f3 = n[0] * n[1] * n[2] * 3 * r
+        assert out[0] == 14 * f3 and out[1] == 7 * f3
+        assert 3 * f3 < out[2] < 3 * f3 + (16 << 20)
+    g = (ctypes.c_int64 * 3)(4, 4, 4)
+    assert _lib.lib().mm_plan_scratch_bytes(g, 1, None, None) == _lib.MM_EINVAL
+
+
 def test_attach_on_null_plan():
     from paper_2606_01114_amd import _lib
     dummy = ctypes.c_void_p(256)
     assert _lib.lib().mm_plan_attach_memory(None, dummy, dummy) == _lib.MM_EINVAL
+    assert _lib.lib().mm_plan_attach_scratch(None, dummy, 256) == _lib.MM_EINVAL
+    assert _lib.lib().mm_batch_tensor_set(None, 0, None) == _lib.MM_EINVAL
 
 
 def test_rkf45_rejects_bad_arguments_on_host():

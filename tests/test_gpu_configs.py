@@ -25,7 +25,7 @@ def _say(*a):
 
 
 def _sampled_ref(m, Ms, oct_, cells):
-    hd = oracle.demag_direct(m, Ms, oct_, cells=cells)
+    hd = oracle.demag_direct_at(m, Ms, oct_, cells)
     hx = oracle.exchange_at(m, Ms, A, D, cells)
     return hd, hx
 
@@ -62,38 +62,68 @@ def test_film_step0_sampled_and_fp32_vs_fp64():
     b = to_dev(m32, torch.float64)
     p32.llg_step(a, MS, A, ALPHA, GAMMA, DT)
     p64.llg_step(b, MS, A, ALPHA, GAMMA, DT)
-    assert rel_l2(a.double().cpu().numpy() - m32, b.cpu().numpy() - m32) <= 1e-5
+    e1 = rel_l2(a.double().cpu().numpy() - m32, b.cpu().numpy() - m32)
+    assert e1 <= 1e-5
+    # 100 steps (the workload's run): the FP32 trajectory against FP64,
+    # reported (not a parity bar: the FP32 rounding of every step accumulates)
+    p32.llg_step(a, MS, A, ALPHA, GAMMA, DT, n_steps=99)
+    p64.llg_step(b, MS, A, ALPHA, GAMMA, DT, n_steps=99)
+    e100 = rel_l2(a.double().cpu().numpy() - m32, b.cpu().numpy() - m32)
+    _say("film: FP32 vs FP64 increment rel-L2 after 1 step %.3e, after 100 steps %.3e" % (e1, e100))
+    assert e100 <= 1e-3
 
 
 def test_large_grid_fp32_vs_fp64_and_sampled():
+    """1024x1024x128 (Voronoi grains) in the benchmark's launch configuration
+    (autotuned tiles): FP32 h_eff and demag field against the oracle's
+    compensated direct sum plus local exchange at 16 seeded cells (1e-5);
+    the FP64 mode with the oracle's tensor held equal against the same sums
+    (1e-12); FP32 against the FP64 mode over every cell; the FP32 RK4 step
+    increment against the FP64 one over every cell."""
     import torch
     from paper_2606_01114_amd import DemagPlan
     n = (1024, 1024, 128)
-    _say("large: inputs")
+    _say("large: inputs and oracle tensor")
     m0 = rounded(synth.voronoi_grains(n, D, 3), torch.float32)
-    # the benchmark's launch configuration: tile variants chosen by the autotuner
+    oct_ = oracle.tensor_octant(n, D)
+    cells = synth.sample_cells(n, 3, 16)
+    ci = (cells[:, 0], cells[:, 1], cells[:, 2])
+    _say("large: direct sums at", len(cells), "cells")
+    rd = oracle.demag_direct_at(m0, MS, oct_, cells)
+    rx = oracle.exchange_at(m0, MS, A, D, cells)
     p32 = DemagPlan(n, D, "f32", autotune=True)
     _say("large: fp32 tiles", p32.info()["tiles"])
     m = to_dev(m0, torch.float32)
     h32 = p32.h_eff(m, MS, A)
     hd32 = p32.h_eff(m, MS, A, terms=1)
-    cells = synth.sample_cells(n, 3, 2)
-    s32 = h32[cells[:, 0], cells[:, 1], cells[:, 2]].double().cpu().numpy()
-    sd32 = hd32[cells[:, 0], cells[:, 1], cells[:, 2]].double().cpu().numpy()
+    s32 = h32[ci].double().cpu().numpy()
+    sd32 = hd32[ci].double().cpu().numpy()
+    e_h32, e_d32 = rel_l2(s32, rd + rx), rel_l2(sd32, rd)
+    _say("large: fp32 sampled rel-L2 h_eff %.3e demag %.3e" % (e_h32, e_d32))
+    assert e_h32 <= 1e-5 and e_d32 <= 1e-5
     p32.llg_step(m, MS, A, ALPHA, GAMMA, DT)
     dm32 = (m.double() - to_dev(m0, torch.float64)).cpu()
     del m
-    _say("large: fp64 plan")
+    _say("large: fp64 plan, oracle tensor held")
     p64 = DemagPlan(n, D, "f64", autotune=True)
+    p64.tensor_set(oct_)
+    del oct_
     m = to_dev(m0, torch.float64)
+
     def dev_rel(x, ref):       # relative L2 on the device, FP64 accumulation
         return float(torch.linalg.vector_norm(x.double() - ref) / torch.linalg.vector_norm(ref))
     h64 = p64.h_eff(m, MS, A)
-    assert dev_rel(h32, h64) <= 1e-5
+    e_h64 = rel_l2(h64[ci].cpu().numpy(), rd + rx)
+    e_32_64 = dev_rel(h32, h64)
     del h64
     hd64 = p64.h_eff(m, MS, A, terms=1)
-    assert dev_rel(hd32, hd64) <= 1e-5
+    e_d64 = rel_l2(hd64[ci].cpu().numpy(), rd)
+    e_d32_64 = dev_rel(hd32, hd64)
     del hd64, h32, hd32
+    _say("large: fp64 sampled rel-L2 h_eff %.3e demag %.3e; fp32 vs fp64 every cell %.3e / %.3e"
+         % (e_h64, e_d64, e_32_64, e_d32_64))
+    assert e_h64 <= 1e-12 and e_d64 <= 1e-12
+    assert e_32_64 <= 1e-5 and e_d32_64 <= 1e-5
     # one RK4 step: the FP32 increment against the FP64 one
     p64.llg_step(m, MS, A, ALPHA, GAMMA, DT)
     dm64 = m - to_dev(m0, torch.float64)
@@ -102,12 +132,8 @@ def test_large_grid_fp32_vs_fp64_and_sampled():
     assert e_step <= 1e-5
     del m, dm64, dm32
     p64.close()
+    p32.close()
     torch.cuda.empty_cache()
-    _say("large: oracle tensor and direct sums")
-    oct_ = oracle.tensor_octant(n, D)
-    rd, rx = _sampled_ref(m0, MS, oct_, cells)
-    assert rel_l2(sd32, rd) <= 1e-5
-    assert rel_l2(s32, rd + rx) <= 1e-5
 
 
 GEOMS = [((53, 20, 3), 6e5), ((48, 61, 1), 1.1e6), ((7, 9, 5), 4e5), ((32, 16, 8), 9e5), ((1, 24, 2), 7e5)]
@@ -125,35 +151,47 @@ def _pow2_L(n):
 
 @pytest.mark.parametrize("prec,pow2", [("f32", True), ("f64", True), ("f32", False), ("f64", False)])
 def test_batch_against_oracle_and_plans(prec, pow2):
+    """Five uneven geometries (power-of-two and 7-smooth padding): h_eff and
+    one RK4 step (graph and direct launches) of each against the oracle --
+    FP64 with every geometry's tensor held equal (1e-12), FP32 with the
+    GPU's own tensors (1e-5) -- and against single plans of the same
+    geometry."""
     import torch
     from paper_2606_01114_amd import Batch, DemagPlan
     dt = torch.float32 if prec == "f32" else torch.float64
+    tol = 1e-12 if prec == "f64" else 1e-5
     grids = [g for g, _ in GEOMS]
     Ms = [ms for _, ms in GEOMS]
+    octs = [oracle.tensor_octant(g, D) for g in grids]
     b = Batch(grids, [D] * len(grids), prec, pow2_padding=pow2)
+    if prec == "f64":
+        for k in range(len(grids)):
+            b.tensor_set(k, octs[k])
     m0 = [rounded(synth.random_unit(g, 40 + k), dt) for k, g in enumerate(grids)]
     ms = [to_dev(x, dt) for x in m0]
     hs = b.h_eff(ms, Ms, A)
     for k, g in enumerate(grids):
-        oct_ = oracle.tensor_octant(g, D)
         L = tuple((_pow2_L if pow2 else oracle.default_L)(v) for v in g)
-        ref = oracle.h_eff(m0[k], Ms[k], A, D, oct_, L)
+        ref = oracle.h_eff(m0[k], Ms[k], A, D, octs[k], L)
         e = rel_l2(hs[k].cpu().numpy(), ref)
-        assert e <= (1e-9 if prec == "f64" else 1e-5), (g, e)
+        _say("batch", prec, pow2, g, "h_eff rel-L2", e)
+        assert e <= tol, (g, e)
         pl = DemagPlan(g, D, prec, L=L)
+        if prec == "f64":
+            pl.tensor_set(octs[k])
         single = pl.h_eff(ms[k], Ms[k], A)
         assert rel_l2(hs[k].cpu().numpy(), single.cpu().numpy()) <= (1e-14 if prec == "f64" else 1e-6)
-    # one and two RK4 steps, graph and direct, against the oracle
+    # one RK4 step, graph and direct, against the oracle
     b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=1)
     ms2 = [to_dev(x, dt) for x in m0]
     b.llg_step(ms2, Ms, A, ALPHA, GAMMA, DT, n_steps=1, graph=False)
     for k, g in enumerate(grids):
         assert torch.equal(ms[k], ms2[k])
-        oct_ = oracle.tensor_octant(g, D)
         L = tuple((_pow2_L if pow2 else oracle.default_L)(v) for v in g)
-        ref = oracle.rk4_step(m0[k], Ms[k], A, D, oct_, L, ALPHA, GAMMA, DT)
+        ref = oracle.rk4_step(m0[k], Ms[k], A, D, octs[k], L, ALPHA, GAMMA, DT)
         e = rel_l2(ms[k].cpu().numpy() - m0[k], ref - m0[k])
-        assert e <= (1e-9 if prec == "f64" else 1e-5), (g, e)
+        _say("batch", prec, pow2, g, "step rel-L2", e)
+        assert e <= tol, (g, e)
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
@@ -168,13 +206,17 @@ def test_batch_wide_x_tiles_against_oracle(prec):
     grids = [g for g, _ in geo]
     Ms = [ms for _, ms in geo]
     b = Batch(grids, [D] * len(grids), prec)
+    octs = [oracle.tensor_octant(g, D) for g in grids]
+    if prec == "f64":
+        for k in range(len(grids)):
+            b.tensor_set(k, octs[k])
     m0 = [rounded(synth.random_unit(g, 60 + k), dt) for k, g in enumerate(grids)]
     ms = [to_dev(x, dt) for x in m0]
     hs = b.h_eff(ms, Ms, A)
     b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=1)
-    tol = 1e-9 if prec == "f64" else 1e-5
+    tol = 1e-12 if prec == "f64" else 1e-5
     for k, g in enumerate(grids):
-        oct_ = oracle.tensor_octant(g, D)
+        oct_ = octs[k]
         L = tuple(_pow2_L(v) for v in g)
         e = rel_l2(hs[k].cpu().numpy(), oracle.h_eff(m0[k], Ms[k], A, D, oct_, L))
         ref = oracle.rk4_step(m0[k], Ms[k], A, D, oct_, L, ALPHA, GAMMA, DT)
@@ -184,30 +226,40 @@ def test_batch_wide_x_tiles_against_oracle(prec):
 
 
 def test_batch_sweep_64_geometries():
+    """The 64-geometry sweep (FP32, grouped launches, one graph per step):
+    every geometry's h_eff against the oracle (1e-5), and one RK4 step of
+    eight geometries spanning the size range against the oracle's step
+    (increment, 1e-5)."""
     import torch
-    from paper_2606_01114_amd import Batch, DemagPlan
+    from paper_2606_01114_amd import Batch
+    from tests.gpu_util import oracle_field_and_step, oracle_pool_map
     geo = synth.batch_geometries(4)
     grids = [g for g, _ in geo]
     Ms = [ms for _, ms in geo]
     _say("sweep: plans")
     b = Batch(grids, [D] * len(grids), "f32")
     m0 = [rounded(synth.random_unit(g, 100 + k), torch.float32) for k, g in enumerate(grids)]
+    hs = [h.cpu().numpy() for h in b.h_eff([to_dev(x, torch.float32) for x in m0], Ms, A)]
     ms = [to_dev(x, torch.float32) for x in m0]
     b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=1)
-    for k in (0, 17, 41, 63):
-        pl = DemagPlan(grids[k], D, "f32")
-        x = to_dev(m0[k], torch.float32)
-        pl.llg_step(x, Ms[k], A, ALPHA, GAMMA, DT)
-        assert rel_l2(ms[k].cpu().numpy() - m0[k], x.cpu().numpy() - m0[k]) <= 1e-5, k
-    # the oracle on the smallest geometries of the sweep
-    order = np.argsort([np.prod(g) for g in grids])[:3]
-    hs = b.h_eff([to_dev(x, torch.float32) for x in m0], Ms, A)
-    for k in order:
-        g = grids[k]
-        oct_ = oracle.tensor_octant(g, D)
-        L = tuple(oracle.default_L(v) for v in g)
-        ref = oracle.h_eff(m0[k], Ms[k], A, D, oct_, L)
-        assert rel_l2(hs[k].cpu().numpy(), ref) <= 1e-5, g
+    steps = [x.cpu().numpy() for x in ms]
+    size_order = list(np.argsort([np.prod(g) for g in grids]))
+    stepped = set(size_order[:: (len(size_order) - 1) // 7][:8]) | {size_order[-1]}
+    _say("sweep: oracle over", len(grids), "geometries, steps of", sorted(int(k) for k in stepped))
+    jobs = [(grids[k], D, m0[k], Ms[k], A, k in stepped, ALPHA, GAMMA, DT) for k in size_order[::-1]]
+    refs = dict(zip(size_order[::-1], oracle_pool_map(oracle_field_and_step, jobs)))
+    worst_h = worst_s = 0.0
+    for k, g in enumerate(grids):
+        rh, rs = refs[k]
+        e = rel_l2(hs[k], rh)
+        worst_h = max(worst_h, e)
+        assert e <= 1e-5, (k, g, e)
+        if rs is not None:
+            es = rel_l2(steps[k] - m0[k], rs - m0[k])
+            worst_s = max(worst_s, es)
+            assert es <= 1e-5, (k, g, es)
+    _say("sweep: worst h_eff rel-L2 %.3e, worst step rel-L2 %.3e (%d steps)" % (worst_h, worst_s, len(stepped)))
+    assert len(stepped) >= 8
 
 
 def test_gradient_small_against_oracle_adjoint():
