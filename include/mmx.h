@@ -352,6 +352,29 @@ int llg_step_adjoint(mm_plan *plan, const void *m, const void *Ms, double Ms_sca
                      void *g, void *g_Ms);
 
 /*
+ * llg_step_adjoint_noalloc -- llg_step_adjoint for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc).  Same arguments, kernels and
+ * result as llg_step_adjoint, but the 14 recorded fields live in a fixed
+ * device array of MM_NOALLOC_SCRATCH_BYTES that the library brings with it
+ * (one per GPU, held from the first call on that GPU until the process
+ * ends) instead of the plan's scratch, and the call allocates nothing: no
+ * hipMalloc, hipFree or allocating library routine.  The plan itself, its
+ * workspace and the caller's m, Ms, g, g_Ms are used as by llg_step_adjoint.
+ *   Errors: MM_ENOTSUP when the recorded fields need more than
+ *   MM_NOALLOC_SCRATCH_BYTES (14 * 3 * nx*ny*nz * sizeof(real)); otherwise
+ *   as llg_step_adjoint.  Checked on the host before anything is enqueued.
+ * Every call on one GPU shares that GPU's array, whose contents persist from
+ * the previous call (every recorded field is written before it is read):
+ * calls that overlap on one GPU -- on different streams or from different
+ * threads, for any plans -- race.  Asynchronous.
+ */
+#define MM_NOALLOC_SCRATCH_BYTES (128u << 20)
+int llg_step_adjoint_noalloc(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double A,
+                             double alpha, double gamma, double dt, const double h_ext[3], unsigned flags,
+                             void *g, void *g_Ms);
+
+/*
  * Tensor test hooks.  host_octant is the real-space tensor N(i,j,k) for
  * 0 <= i < nx, 0 <= j < ny, 0 <= k < nz as a HOST double array
  * (nx,ny,nz,6), components xx,yy,zz,xy,xz,yz.

@@ -22,6 +22,7 @@ EXPORTS = [
     "mm_plan_bytes", "mm_plan_attach_memory", "mm_plan_scratch_bytes", "mm_plan_attach_scratch", "mm_plan_set_dmi", "mm_plan_set_anisotropy",
     "mm_plan_set_stt",
     "h_eff", "llg_step", "llg_rkf45_step", "mm_minimize_bb", "h_eff_adjoint", "llg_step_adjoint",
+    "llg_step_adjoint_noalloc",
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
     "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_tensor_set", "mm_batch_info",
     "mm_batch_destroy",
@@ -72,6 +73,7 @@ def _load():
         "mm_minimize_bb": [vp, vp, vp, cd, cd, dp, cd, ci, ctypes.POINTER(ci), dp],
         "h_eff_adjoint": [vp, vp, vp, cd, cd, vp, vp, vp, cu],
         "llg_step_adjoint": [vp, vp, vp, cd, cd, cd, cd, cd, dp, cu, vp, vp],
+        "llg_step_adjoint_noalloc": [vp, vp, vp, cd, cd, cd, cd, cd, dp, cu, vp, vp],
         "mm_demag_tensor_get": [vp, dp],
         "mm_demag_tensor_set": [vp, dp],
         "mm_demag_spectrum_get": [vp, dp],

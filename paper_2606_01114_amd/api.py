@@ -239,6 +239,19 @@ class DemagPlan:
                                           float(dt), he, flags, _ptr(g), _ptr(g_Ms)))
         return g
 
+    def llg_step_adjoint_noalloc(self, m, Ms, A, alpha, gamma, dt, g, g_Ms=None, h_ext=None, renorm=True):
+        """llg_step_adjoint with its recorded fields in the library's fixed
+        per-GPU array: no device allocation (calls overlapping on one GPU race)."""
+        self._vec(m, "m")
+        self._vec(g, "g")
+        Mst, Mss = self._ms(Ms)
+        self._sync_stream()
+        he = (ctypes.c_double * 3)(*[float(v) for v in h_ext]) if h_ext is not None else None
+        flags = 0 if renorm else MM_NO_RENORM
+        check(_lib.lib().llg_step_adjoint_noalloc(self._h, _ptr(m), _ptr(Mst), Mss, float(A), float(alpha),
+                                                  float(gamma), float(dt), he, flags, _ptr(g), _ptr(g_Ms)))
+        return g
+
     def tensor_get(self):
         import numpy as np
         out = np.zeros(self.grid + (6,))

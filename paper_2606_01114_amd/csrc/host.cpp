@@ -816,13 +816,14 @@ int adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double 
 // scratch of the RK4 adjoint: s1..s3, h0..h3, u, ub, kb, ym, yh, gmh (14 vector fields)
 template <typename T>
 int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, double alpha, double gamma,
-                     double dt, const double *hext, unsigned flags, void *g, void *g_Ms) {
+                     double dt, const double *hext, unsigned flags, void *g, void *g_Ms, void *fixed_scr = nullptr) {
     const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
     int rc;
     size_t need[3];
     scratch_need(ncell, sizeof(T), p->zg.tiles, need);
-    void *scr = nullptr;
-    if ((rc = get_scratch(p, need[0], &scr))) return rc;
+    // the caller's fixed region (checked large enough), else the plan's scratch
+    void *scr = fixed_scr;
+    if (!scr && (rc = get_scratch(p, need[0], &scr))) return rc;
     T *base = (T *)scr;
     auto buf = [&](int i) { return (void *)(base + (size_t)i * ncell * 3); };
     void *srec[4] = {(void *)m, buf(0), buf(1), buf(2)};
@@ -1306,6 +1307,30 @@ int llg_step_adjoint(mm_plan *p, const void *m, const void *Ms, double Ms_scalar
     if ((rc = check_llg(alpha, gamma, dt, h_ext))) return rc;
     return p->prec == MM_F32 ? llg_adjoint_impl<float>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms)
                              : llg_adjoint_impl<double>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms);
+}
+
+int llg_step_adjoint_noalloc(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, double A, double alpha,
+                             double gamma, double dt, const double h_ext[3], unsigned flags, void *g, void *g_Ms) {
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!m || !g) return fail(MM_EINVAL, "m and g must be non-NULL");
+    if (p->dmi_kind || p->ku != 0.0 || p->stt_j != 0.0)
+        return fail(MM_ENOTSUP, "the adjoint does not include the DMI, anisotropy or spin-transfer terms");
+    if (g == m) return fail(MM_EINVAL, "g must not alias m");
+    if (flags & ~(MM_NO_RENORM | MM_NO_GRAPH)) return fail(MM_EINVAL, "unknown flags");
+    if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;
+    if ((rc = check_llg(alpha, gamma, dt, h_ext))) return rc;
+    size_t need[3];
+    scratch_need(p->n[0] * p->n[1] * p->n[2], p->rsz, p->zg.tiles, need);
+    if (need[0] > (size_t)MM_NOALLOC_SCRATCH_BYTES)
+        return fail(MM_ENOTSUP, "llg_step_adjoint_noalloc needs %zu bytes of fixed scratch for this grid; the "
+                                "library holds %zu (use llg_step_adjoint)", need[0], (size_t)MM_NOALLOC_SCRATCH_BYTES);
+    void *fixed = nullptr;
+    hipError_t e = noalloc_scratch(p->device, &fixed);
+    if (e != hipSuccess) return fail(MM_EHIP, "fixed scratch address: %s", hipGetErrorString(e));
+    return p->prec == MM_F32
+               ? llg_adjoint_impl<float>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms, fixed)
+               : llg_adjoint_impl<double>(p, m, Ms, Ms_scalar, A, alpha, gamma, dt, h_ext, flags, g, g_Ms, fixed);
 }
 
 int llg_rkf45_step(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double A, double alpha, double gamma,

@@ -71,6 +71,9 @@ template <typename T>
 hipError_t launch_adj_combine(const T *ym, const T *gmh, const T *ub, T *gsum, T *kb, double w, double coef, int64_t n,
                               hipStream_t s);
 
+// device address of this device's fixed scratch array (kern_scratch.hip)
+hipError_t noalloc_scratch(int device, void **out);
+
 template <typename T> hipError_t launch_scale_copy(const T *in, T *out, double s, int64_t n, hipStream_t st);
 
 }  // namespace mmx
