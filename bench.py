@@ -60,6 +60,8 @@ KERNEL_PATTERNS = {
 }
 KERNEL_SYMBOL = {"z_fwd": "k_zfwd_ct", "x_fwd": "k_line_ct", "y_fused": "k_fused_y_ct", "x_inv": "k_line_ct",
                  "z_inv_stage": "k_zinv_ct", "z_inv_heff": "k_zinv_ct"}
+# y pass variant (mm_plan_info tiles[2]) -> kernel; negative: runtime-planned
+Y_SYMBOL = {0: "k_fused_y_ct", 1: "k_fused_y_hx", 2: "k_fused_y_cr", 3: "k_fused_y_pf"}
 
 
 def pass_bytes(grid, L, r):
@@ -707,8 +709,7 @@ def main():
     dom = max(share, key=share.get)
     ach = pb[dom] / (res["passes"][dom] * 1e-3)
     sym = dict(KERNEL_SYMBOL)
-    if res["tiles"][2] < 0:
-        sym["y_fused"] = "k_fused_y_hx"
+    sym["y_fused"] = Y_SYMBOL.get(res["tiles"][2], "k_fused_y")
     for pname, v in (("x_fwd", res["tiles"][3]), ("x_inv", res["tiles"][4])):
         if v >= 2:
             sym[pname] = "k_line_hx"
@@ -725,8 +726,8 @@ def main():
         "pass_ms": res["passes"],
         "pass_GBps": {k: pb[k] / (res["passes"][k] * 1e-3) / 1e9 for k in pb},
         "padded_L": list(res["L"]),
-        "tiles": {"z_cols": res["tiles"][0], "x_cols": res["tiles"][1], "y_pencils": abs(res["tiles"][2]),
-                  "y_register_resident": res["tiles"][2] < 0,
+        "tiles": {"z_cols": res["tiles"][0], "x_cols": res["tiles"][1], "y_variant": res["tiles"][2],
+                  "y_kernel": sym["y_fused"],
                   "x_variant_fwd": res["tiles"][3], "x_variant_inv": res["tiles"][4]},
         "finite": res["finite"],
     }

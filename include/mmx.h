@@ -35,7 +35,7 @@
  * Threading: a plan is not thread-safe; distinct plans are independent.
  *
  * Test hooks (environment, read at plan creation; every choice computes the
- * same result): MMX_XVAR=0..3 and MMX_YVAR=1 force an x or y pass variant
+ * same result): MMX_XVAR=0..3 and MMX_YVAR=0..3 force an x or y pass variant
  * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
  * pass, MMX_TEST_FAIL_ALLOC makes every device allocation fail (MM_ENOMEM).
  */
@@ -237,10 +237,14 @@ int mm_plan_set_stt(mm_plan *plan, double j, double P, double lambda, double eps
 
 /* Padded lengths, device bytes held, and the launch shapes in use (each
  * nullable): tiles = {z cell columns per tile, forward x columns per tile,
- * y pencils per tile (negated when the register-resident pencil kernel runs
- * the y pass), forward x variant, inverse x variant}; x variants 0 and 1 are
- * two tile widths, 2 the half-LDS kernel with variant 1's tiles, 3 the
- * half-LDS kernel with tiles twice as wide (lines of 1024 points or more). */
+ * y pass variant, forward x variant, inverse x variant}; x variants 0 and 1
+ * are two tile widths, 2 the half-LDS kernel with variant 1's tiles, 3 the
+ * half-LDS kernel with tiles twice as wide (lines of 1024 points or more);
+ * y variants (power-of-two y lengths) 0 the LDS-resident pencil per
+ * workgroup, 1 the register-resident pencil with half-line exchanges, 2 the
+ * LDS-resident pencil with the waves' butterflies rotated per workgroup, 3
+ * the persistent kernel with the next pencil's loads in flight; -W: the
+ * runtime-planned kernel with W pencils per tile. */
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 
 /*

@@ -412,7 +412,10 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
         if (w <= std::max(1, npen) && (size_t)3 * w * py * csz <= kLdsTarget && fft_threads(p->fy.d, 3 * w, 3 * w * Ly) <= 1024) { Wp = w; break; }
     }
     p->y_ct = fused_ct_threads(Ly, csz) > 0 && fused_ct_lds(Ly, csz) <= kLdsMax && !getenv("MMX_NO_CT");
-    if (p->y_ct && getenv("MMX_YVAR") && atoi(getenv("MMX_YVAR")) == 1 && fused_hx_threads(Ly) > 0) p->y_var = 1;
+    if (p->y_ct && getenv("MMX_YVAR")) {
+        const int v = atoi(getenv("MMX_YVAR"));
+        if ((v == 1 && fused_hx_threads(Ly) > 0) || fused_pf_available(Ly, v)) p->y_var = v;
+    }
     if (p->y_ct) Wp = 1;
     q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy;
     q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;
@@ -529,20 +532,33 @@ hipError_t launch_x(mm_plan *p, int dir) {
 // the specialised fused y pass in the plan's variant
 template <typename T>
 hipError_t launch_y(mm_plan *p) {
+    if (p->y_var >= 2) return launch_fused_pf<T>(p->fp, p->y_var, p->stream);
     return p->y_var == 1 ? launch_fused_hx<T>(p->fp, p->stream) : launch_fused_ct<T>(p->fp, p->stream);
 }
 
-// Autotuner for the fused y pass: the LDS-resident and the register-resident
-// pencil kernels, timed on this plan's buffers.
+// the fused y pass variants a plan of y length Ly can run
+std::vector<int> y_variants(int Ly) {
+    std::vector<int> v{0};
+    if (fused_hx_threads(Ly) > 0) v.push_back(1);
+    for (int k = 2; k <= 3; ++k)
+        if (fused_pf_available(Ly, k)) v.push_back(k);
+    return v;
+}
+
+// Autotuner for the fused y pass: the LDS-resident, register-resident and
+// persistent (next pencil's loads in flight) pencil kernels, timed on this
+// plan's buffers.
 template <typename T>
 int autotune_y(mm_plan *p) {
-    if (!p->y_ct || fused_hx_threads((int)p->L[1]) <= 0) return MM_OK;
+    const std::vector<int> cand = y_variants((int)p->L[1]);
+    if (!p->y_ct || cand.size() < 2) return MM_OK;
     hipEvent_t e0, e1;
     HIPCK(hipEventCreate(&e0));
     HIPCK(hipEventCreate(&e1));
     int rc = MM_OK, best_v = p->y_var;
     double best = 1e300;
-    for (int v = 0; v < 2 && !rc; ++v) {
+    for (int v : cand) {
+        if (rc) break;
         p->y_var = v;
         float ms = 0.f;
         for (int rep = 0; rep < 2 && !rc; ++rep) {
@@ -1240,7 +1256,7 @@ int mm_plan_info(const mm_plan *p, int64_t L[3], size_t *bytes, int tiles[5]) {
     if (!p) return fail(MM_EINVAL, "plan is NULL");
     if (L) for (int a = 0; a < 3; ++a) L[a] = p->L[a];
     if (bytes) *bytes = p->bytes;
-    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->y_var == 1 ? -p->fp.W : p->fp.W; tiles[3] = p->x_var[0]; tiles[4] = p->x_var[1]; }
+    if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->y_ct ? p->y_var : -p->fp.W; tiles[3] = p->x_var[0]; tiles[4] = p->x_var[1]; }
     return MM_OK;
 }
 

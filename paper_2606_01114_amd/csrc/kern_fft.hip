@@ -429,14 +429,19 @@ __device__ __forceinline__ PencilProduct<T, L> pencil_product(const FusedPass &a
 // compile-time Ly; one (kz, kx) pencil of three components per tile.  The
 // tensor row is fetched into registers together with the pencil's first
 // radix-stage inputs.
+// rot: the workgroup's waves take the butterflies of the wave rot places on,
+// so that when a stage has fewer butterflies than threads in its last round
+// the busy waves differ from workgroup to workgroup and the SIMDs of a CU
+// share the uneven rounds.
 template <typename T, int L, int NT>
-__device__ __forceinline__ void fused_ct_body(const FusedPass &a, int p) {
+__device__ __forceinline__ void fused_ct_body(const FusedPass &a, int p, int rot = 0) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
     constexpr int NS = ct::nst(L);
     static_assert(NS >= 2, "fused pencil needs two or more radix stages");
-    const int tid = threadIdx.x;
+    const int tid = (NT & (NT - 1)) == 0 ? (int)(threadIdx.x ^ (64u * (unsigned)rot))
+                                         : (int)((threadIdx.x + 64u * (unsigned)rot) % (unsigned)NT);
     const int n = a.n;
     const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
     C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
@@ -639,10 +644,126 @@ __global__ void __launch_bounds__(NT) k_fused_y_ct(const FusedPass a) {
     fused_ct_body<T, L, NT>(a, (int)xcd_tile(blockIdx.x, gridDim.x));
 }
 
+// k_fused_y_ct with the waves' butterflies rotated per workgroup
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_cr(const FusedPass a) {
+    fused_ct_body<T, L, NT>(a, (int)xcd_tile(blockIdx.x, gridDim.x), (int)((blockIdx.x >> 3) % (NT / 64)));
+}
+
 template <typename T, int L, int NT>
 __global__ void __launch_bounds__(NT) k_fused_y_ct_b(const FusedPass *__restrict__ descs, const int2 *__restrict__ map) {
     const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
     fused_ct_body<T, L, NT>(descs[e.x], e.y);
+}
+
+// ---- fused y pass, persistent, with the next pencil's loads in flight -----
+// The first forward stage's inputs of one pencil (the rows below L/2 of its
+// three components), held in registers between their load and the stage.
+template <typename T, int L, int NT>
+struct PencilInputs {
+    using C = cplx<T>;
+    static constexpr int R = ct::prad(L, false, 0);
+    static constexpr int NB = L / R;
+    static constexpr int TOT = 3 * NB;
+    static constexpr int U = (TOT + NT - 1) / NT;
+    C v[U][R / 2];
+    // butterfly b = tid + u NT reads line b % 3 at rows j + r NB, j = b / 3
+    __device__ __forceinline__ void load(BufRsrc rp, int tid) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = tid + u * NT;
+            if (b < TOT) {
+                const int line = b % 3, j = b / 3;
+#pragma unroll
+                for (int r = 0; r < R / 2; ++r) v[u][r] = buf_load<C>(rp, (uint32_t)((j + r * NB) * 3 + line) * sizeof(C));
+            }
+        }
+    }
+    // the first stage (no twiddles, upper half of every input zero) into LDS;
+    // ends with a barrier
+    __device__ __forceinline__ void stage0(C *lds, int tid) const {
+        constexpr int P = ct::lds_pitch(L, 3, (int)sizeof(C));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int b = tid + u * NT;
+            if (b < TOT) {
+                const int line = b % 3, j = b / 3;
+                C w[R];
+#pragma unroll
+                for (int r = 0; r < R / 2; ++r) w[r] = v[u][r];
+                PDft<R, -1, 1, C>::run(w);
+                const int sd = line * P + sw<L>(j * R);
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[sd + swc<L>(r)] = w[r];
+            }
+        }
+        __syncthreads();
+    }
+};
+
+// Persistent form of fused_ct_body: a resident grid walks the pencils; the
+// first stage's global loads of the workgroup's next pencil are issued as
+// soon as the current pencil's first stage has consumed its own, so their
+// latency overlaps the remaining stages instead of stalling every pencil's
+// start.  Virtual tile v = blockIdx.x + i gridDim.x maps to a pencil through
+// xcd_tile, so each XCD's workgroups (gridDim.x a multiple of 8) walk that
+// XCD's contiguous run of pencils side by side.  EARLY: fetch the pencil's
+// tensor values when the pencil starts (else at the product).
+template <typename T, int L, int NT, bool EARLY>
+__global__ void __launch_bounds__(NT) k_fused_y_pf(const FusedPass a) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    constexpr int NS = ct::nst(L);
+    static_assert(NS >= 2, "fused pencil needs two or more radix stages");
+    // waves rotated per workgroup as in k_fused_y_cr
+    const unsigned rot = (blockIdx.x >> 3) % (NT / 64);
+    const int tid = (NT & (NT - 1)) == 0 ? (int)(threadIdx.x ^ (64u * rot)) : (int)((threadIdx.x + 64u * rot) % (unsigned)NT);
+    const int n = a.n, G = (int)gridDim.x, npos = a.npos;
+    const C *tw = reinterpret_cast<const C *>(a.tw);
+    const C *twr = tw + (L - 1);
+    auto pencil = [&](int v) {
+        const int p = (int)xcd_tile((uint32_t)v, (uint32_t)npos);
+        const int kz = p / a.Lx;
+        return make_int2(kz, pair_kx(p - kz * a.Lx, a.Lx));
+    };
+    auto rsrc = [&](int2 q) {
+        C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)q.x * a.Lx + q.y) * (3 * n);
+        return make_rsrc(pen, (uint32_t)(3 * n) * sizeof(C));
+    };
+    int v = (int)blockIdx.x;
+    if (v >= npos) return;
+    PencilInputs<T, L, NT> in;
+    int2 q = pencil(v);
+    in.load(rsrc(q), tid);
+    auto nold = [](int, int) { return C(); };
+    for (; v < npos; v += G) {
+        const BufRsrc rp = rsrc(q);
+        auto st = [&](int c, int pos, C x) { buf_store(rp, (uint32_t)(pos * 3 + c) * sizeof(C), x); };
+        const bool rx = q.y > a.Lx / 2;
+        const T *Trow = reinterpret_cast<const T *>(a.tensor) + ((int64_t)q.x * a.hxp + (rx ? a.Lx - q.y : q.y)) * a.hyp * 6;
+        const T sx = rx ? T(-1) : T(1);
+        PencilTensor<T, L, (EARLY ? NT : 1)> pt;
+        if constexpr (EARLY) pt.load(Trow, sx, tid);
+        // the previous pencil's last stage has finished reading LDS
+        __syncthreads();
+        in.stage0(lds, tid);
+        const int vn = v + G;
+        const int2 qn = vn < npos ? pencil(vn) : q;
+        if (vn < npos) in.load(rsrc(qn), tid);
+        eng_mid<T, L, false, 1, NS - 1, -1, NT, 3>(lds, tw, tid);
+        if constexpr (EARLY) {
+            conv_middle_pre<T, L, NT>(lds, tw, tid, pt);
+        } else {
+            PencilProduct<T, L> pr;
+            pr.Trow = Trow;
+            pr.sx = sx;
+            conv_middle<T, L, NT>(lds, tw, tid, pr);
+        }
+        eng_mid<T, L, true, 1, NS - 1, +1, NT, 3>(lds, twr, tid);
+        eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0, 2>(lds, twr, tid, nold, st);
+        q = qn;
+    }
 }
 
 // ---------------- launchers -------------------------------------------------
@@ -802,6 +923,61 @@ hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
 #undef FCASE
     return hipGetLastError();
 }
+
+// Persistent fused pass (k_fused_y_pf): as many workgroups as fit on the
+// device at once (a multiple of 8, so every XCD gets the same number), each
+// walking pencils with the next one's loads in flight.
+template <typename T, int L, int NT, bool EARLY>
+hipError_t launch_fused_pf_k(const FusedPass &a, hipStream_t s) {
+    const size_t lds = fused_ct_lds(L, sizeof(cplx<T>));
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_fused_y_pf<T, L, NT, EARLY>),
+                                                         NT, lds);
+    if (e != hipSuccess) return e;
+    int G = std::max(1, per_cu) * std::max(1, ncu);
+    G = std::max(8, G - G % 8);
+    G = std::min(G, a.npos);
+    hipLaunchKernelGGL((k_fused_y_pf<T, L, NT, EARLY>), dim3(G), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
+// variant 2: k_fused_y_cr (one pencil per workgroup, waves rotated);
+// variant 3: k_fused_y_pf (persistent, next pencil's loads in flight; in
+// FP32 with one radix-16 butterfly per thread, 384 threads for 2048 points,
+// and the tensor fetched at the product, which keeps it under 168 VGPRs)
+int fused_pf_available(int L, int var) {
+    if (var == 2) return L >= 256 && L <= 4096 && fused_ct_threads(L, 8) > 64;
+    return var == 3 && (L == 1024 || L == 2048);
+}
+
+template <typename T>
+hipError_t launch_fused_pf(const FusedPass &a, int var, hipStream_t s) {
+    if (a.npos <= 0) return hipSuccess;
+    if (var == 2) {
+        const size_t lds = fused_ct_lds(a.f.L, sizeof(cplx<T>));
+#define RCASE(LL, NTT)                                                                                                \
+    case LL:                                                                                                          \
+        hipLaunchKernelGGL((k_fused_y_cr<T, LL, NTT>), dim3(a.npos), dim3(NTT), lds, s, a);                         \
+        break;
+        switch (a.f.L) {
+            RCASE(512, 128) RCASE(1024, 256) RCASE(2048, (sizeof(T) == 4 ? 256 : 384)) RCASE(4096, 768)
+        default: return hipErrorInvalidValue;
+        }
+#undef RCASE
+        return hipGetLastError();
+    }
+    constexpr bool F32 = sizeof(T) == 4;
+    switch (a.f.L) {
+    case 1024: return launch_fused_pf_k<T, 1024, 256, F32>(a, s);
+    case 2048: return launch_fused_pf_k<T, 2048, 384, false>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_fused_pf<float>(const FusedPass &, int, hipStream_t);
+template hipError_t launch_fused_pf<double>(const FusedPass &, int, hipStream_t);
 
 // threads of the register-resident fused pass: one radix-16 butterfly per
 // thread and stage, rounded up to whole waves

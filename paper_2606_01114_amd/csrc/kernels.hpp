@@ -23,6 +23,9 @@ int fused_hx_threads(int L);
 size_t fused_hx_lds(int L, size_t csz);
 template <typename T> hipError_t launch_fused_hx(const FusedPass &a, hipStream_t s);
 size_t fused_ct_lds(int L, size_t csz);
+// persistent fused y pass with the next pencil's loads in flight (variants 2..4)
+int fused_pf_available(int L, int var);
+template <typename T> hipError_t launch_fused_pf(const FusedPass &a, int var, hipStream_t s);
 // half != 0 launches the half-LDS variant (k_line_hx)
 template <typename T> hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStream_t s, int half = 0);
 template <typename T> hipError_t launch_line_wide(const LinePass &a, int tiles, int W, int dir, hipStream_t s);

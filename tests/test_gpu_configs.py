@@ -402,12 +402,15 @@ def test_longest_specialised_lengths(n):
         plan.close()
 
 
-@pytest.mark.parametrize("n", [(6, 128, 3), (5, 256, 2), (4, 512, 2), (3, 1024, 2)])
+@pytest.mark.parametrize("n", [(6, 128, 3), (5, 256, 2), (4, 512, 2), (3, 1024, 2), (40, 600, 6), (200, 512, 8)])
 def test_y_pass_variants_against_oracle(n):
-    """Both specialised y passes (the LDS-resident pencil and the
-    register-resident one with half-line exchanges, selected with MMX_YVAR at
-    plan creation) for every length the register-resident kernel has, FP32 and
-    FP64, against the oracle's h_eff."""
+    """Every specialised y pass, selected with MMX_YVAR at plan creation: the
+    LDS-resident pencil (0), the register-resident one with half-line
+    exchanges (1), the LDS-resident pencil with rotated waves (2) and the
+    persistent kernel with the next pencil's loads in flight (3), for every
+    length each has (a variant a length lacks leaves the default in place),
+    FP32 and FP64, against the oracle's h_eff; the persistent kernel's
+    grid walks more pencils than it has workgroups."""
     import os
     import torch
     from paper_2606_01114_amd import DemagPlan
@@ -417,12 +420,16 @@ def test_y_pass_variants_against_oracle(n):
     ref = oracle.h_eff(m0, MS, A, D, oct_, L)
     old = os.environ.get("MMX_YVAR")
     try:
-        for var in (0, 1):
+        for var in (0, 1, 2, 3):
             os.environ["MMX_YVAR"] = str(var)
             for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
                 dt = torch.float32 if prec == "f32" else torch.float64
                 plan = DemagPlan(n, D, prec)
-                assert (plan.info()["tiles"][2] < 0) == (var == 1)
+                Ly = plan.info()["L"][1]
+                has = {0: Ly & (Ly - 1) == 0, 1: Ly in (256, 512, 1024, 2048), 2: Ly in (512, 1024, 2048, 4096),
+                       3: Ly in (1024, 2048)}[var]
+                yv = plan.info()["tiles"][2]
+                assert yv == (var if has else 0), (var, Ly, yv)
                 h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
                 e = rel_l2(h.cpu().numpy(), ref)
                 _say("y variant", var, prec, n, e)
