@@ -185,7 +185,10 @@ def run_gpu(wname, prec, steps, warmup, m_host):
 
 
 def run_sweep(steps, warmup, prec="f32"):
-    """Aggregate cell-updates/s of the batched sweep (all geometries per graph replay)."""
+    """Aggregate cell-updates/s of the batched sweep (all geometries per graph
+    replay) with the autotuned launch groups, the same with the default
+    schedule, the groups the tuner chose, and the sweep's algorithmic bytes
+    against the HBM roofline."""
     import numpy as np
     import torch
     import synth
@@ -194,28 +197,41 @@ def run_sweep(steps, warmup, prec="f32"):
     grids = [g for g, _ in geo]
     Ms = [ms for _, ms in geo]
     dt = torch.float32 if prec == "f32" else torch.float64
-    t0 = time.perf_counter()
-    b = Batch(grids, [WORKLOADS["sweep"]["cell"]] * len(grids), prec)
-    torch.cuda.synchronize()
-    setup = time.perf_counter() - t0
-    ms = [torch.tensor(synth.random_unit(g, 100 + k), dtype=dt, device="cuda") for k, g in enumerate(grids)]
-    for _ in range(warmup):
-        b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=steps)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
     cells = int(sum(np.prod(g) for g in grids))
     # algorithmic bytes: the single-grid pass model of every geometry at its
     # padded lengths (batches pad each axis to the power of two >= 2n-1)
     r = 4 if prec == "f32" else 8
     step_bytes = sum(pass_bytes(g, tuple(_pow2_len(v) for v in g), r)[1] for g in grids)
-    ms_step = wall * 1e3 / steps
-    b.close()
-    return {"cells": cells, "geometries": len(grids), "ms_per_step": ms_step,
-            "Mcell_updates_per_s": cells * steps / wall / 1e6, "setup_s": setup, "prec": prec,
-            "step_algorithmic_bytes": step_bytes, "step_hbm_frac": step_bytes / (ms_step * 1e-3) / HBM_PEAK}
+    out = {"cells": cells, "geometries": len(grids), "prec": prec, "step_algorithmic_bytes": step_bytes}
+    for mode in ("off", "search"):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b = Batch(grids, [WORKLOADS["sweep"]["cell"]] * len(grids), prec, autotune=mode)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        ms = [torch.tensor(synth.random_unit(g, 100 + k), dtype=dt, device="cuda") for k, g in enumerate(grids)]
+        for _ in range(warmup):
+            b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms_step = wall * 1e3 / steps
+        r_ = {"ms_per_step": ms_step, "Mcell_updates_per_s": cells * steps / wall / 1e6, "setup_s": setup}
+        if mode == "search":
+            out.update(r_)
+            out["schedule"] = [{k: g[k] for k in ("pass", "L", "specialised", "variant", "W", "geometries")}
+                               for g in b.schedule()["groups"]]
+            ach = step_bytes / (ms_step * 1e-3)
+            out["roofline"] = {"bound": "hbm", "achieved": ach / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                               "frac": ach / HBM_PEAK, "bytes": "per step, all geometries, pass model"}
+            out["step_hbm_frac"] = ach / HBM_PEAK
+        else:
+            out["default_schedule"] = r_
+        b.close()
+        del ms
+    return out
 
 
 def _pow2_len(n):

@@ -37,7 +37,10 @@
  * Test hooks (environment, read at plan creation; every choice computes the
  * same result): MMX_XVAR=0..3 and MMX_YVAR=0..3 force an x or y pass variant
  * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
- * pass, MMX_TEST_FAIL_ALLOC makes every device allocation fail (MM_ENOMEM).
+ * pass, MMX_ORDER="x:4,5,5;y:2,3,3,5" sets the radix order of runtime-planned
+ * (non-power-of-two) axes, MMX_TEST_FAIL_ALLOC makes every device
+ * allocation fail (MM_ENOMEM).  The autotuner reads MMX_AUTOTUNE and
+ * MMX_AUTOTUNE_CACHE (mm_plan_opts.autotune).
  */
 #ifndef MMX_H
 #define MMX_H
@@ -83,9 +86,20 @@ typedef struct mm_plan_opts {
                            pow2_padding.  A given L must be 7-smooth and
                            >= 2n-1 (any such L gives the same linear
                            convolution). */
-    int autotune;       /* 0: default tile widths; 1: time the candidate tile
-                           widths of every pass at plan creation and keep the
-                           fastest. */
+    int autotune;       /* launch schedule (x and y kernel variants and tile
+                           widths, radix order of the runtime-planned
+                           transforms), timed on the plan's own buffers at
+                           creation (by mm_batch_create per launch group):
+                           0 off (default schedule); 1 cached: take the
+                           winner recorded for this device, precision, pass,
+                           length and size, timing the candidates only on a
+                           miss; 2 search: always time them.  Winners are
+                           recorded in a per-process cache; the environment
+                           variable MMX_AUTOTUNE=off|cached|search overrides
+                           this field and MMX_AUTOTUNE_CACHE=<file> keeps
+                           the cache in a text file across processes.
+                           mm_plan_schedule / mm_batch_schedule report the
+                           outcome. */
     int pow2_padding;   /* for axes without an explicit L.  0: the 7-smooth
                            length (1 if n == 1, 2n if n is 7-smooth, else
                            the smallest 7-smooth length >= 2n-1); 1: the
@@ -248,6 +262,15 @@ int mm_plan_set_stt(mm_plan *plan, double j, double P, double lambda, double eps
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 
 /*
+ * mm_plan_schedule -- the launch schedule a plan runs, as JSON text: padded
+ * lengths, the x (forward, inverse), fused y and z kernels (specialised or
+ * runtime-planned, variant as in mm_plan_info, tile widths) and the radix
+ * order of each axis's transform.  buf: host buffer of len bytes, receives
+ * a NUL-terminated string; MM_EINVAL when it does not fit.  Host only.
+ */
+int mm_plan_schedule(const mm_plan *plan, char *buf, size_t len);
+
+/*
  * h_eff -- effective field h = [H_demag] + [H_exchange] in A/m (eqs. (2), (4)).
  *   m          device (nx,ny,nz,3) unit vectors
  *   Ms         device per-cell (nx,ny,nz) saturation magnetisation, or NULL
@@ -401,7 +424,8 @@ int mm_demag_spectrum_get(mm_plan *plan, double *host_spectrum);
  * padded length (geometries sharing a power-of-two length run the specialised
  * kernels; all others share one runtime-planned launch) -- and one step of all
  * geometries is captured in one HIP graph.  opts NULL selects power-of-two
- * padding.
+ * padding; opts->autotune times every kernel variant of each launch group
+ * (forward and inverse x separately) on the batch's own buffers.
  *   grids[count][3], cells[count][3]: host arrays
  *   m_ptrs[count]: host array of device pointers, each (nx,ny,nz,3)
  *   h_ptrs[count]: host array of device pointers for mm_batch_h_eff
@@ -421,6 +445,10 @@ int mm_batch_llg_step(mm_batch *b, void *const *m_ptrs, const double *Ms, double
  */
 int mm_batch_tensor_set(mm_batch *b, int geometry, const double *host_octant);
 int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes);
+/* mm_batch_schedule -- the batch's launch groups as JSON text (pass, length,
+ * kernel variant, tile width, geometries and tiles per group), as
+ * mm_plan_schedule. */
+int mm_batch_schedule(const mm_batch *b, char *buf, size_t len);
 int mm_batch_destroy(mm_batch *b);
 
 /*

@@ -36,8 +36,26 @@ def _opts(far_radius=16.0, L=None, autotune=False, padding="auto"):
     if L is not None:
         for a in range(3):
             opts.L[a] = int(L[a])
-    opts.autotune = 1 if autotune else 0
+    opts.autotune = _tune_mode(autotune)
     return opts
+
+
+_TUNE = {"off": 0, "cached": 1, "search": 2}
+
+
+def _tune_mode(autotune):
+    """False/"off" -> 0, True/"cached" -> 1 (recorded winners, time on a
+    miss), "search" -> 2 (always time)."""
+    if isinstance(autotune, str):
+        return _TUNE[autotune]
+    return 1 if autotune else 0
+
+
+def _schedule(fn, h):
+    import json
+    buf = ctypes.create_string_buffer(1 << 16)
+    check(fn(h, buf, len(buf)))
+    return json.loads(buf.value.decode())
 
 
 def plan_bytes(grid, precision="f32", far_radius=16.0, L=None, padding="auto"):
@@ -151,6 +169,10 @@ class DemagPlan:
         t = (ctypes.c_int * 5)()
         check(_lib.lib().mm_plan_info(self._h, L, ctypes.byref(b), t))
         return {"L": tuple(L), "device_bytes": b.value, "tiles": tuple(t)}
+
+    def schedule(self):
+        """The launch schedule the plan runs (mm_plan_schedule), as a dict."""
+        return _schedule(_lib.lib().mm_plan_schedule, self._h)
 
     def h_eff(self, m, Ms, A, out=None, terms=MM_DEMAG | MM_EXCHANGE, energy=False):
         self._vec(m, "m")
@@ -289,7 +311,7 @@ class Batch:
     """Many independent geometries advanced by grouped launches (one HIP graph
     per step of all of them)."""
 
-    def __init__(self, grids, cells, precision="f32", far_radius=16.0, pow2_padding=True):
+    def __init__(self, grids, cells, precision="f32", far_radius=16.0, pow2_padding=True, autotune=False):
         self.grids = [tuple(int(v) for v in g) for g in grids]
         self.cells = [tuple(float(v) for v in c) for c in cells]
         self.prec = _prec(precision)
@@ -301,6 +323,7 @@ class Batch:
         check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
         opts.far_radius = float(far_radius)
         opts.pow2_padding = 1 if pow2_padding else 0
+        opts.autotune = _tune_mode(autotune)
         self._h = ctypes.c_void_p()
         check(_lib.lib().mm_batch_create(ctypes.byref(self._h), n, G, C, self.prec, _stream(), ctypes.byref(opts)))
 
@@ -315,6 +338,10 @@ class Batch:
         b = ctypes.c_size_t()
         check(_lib.lib().mm_batch_info(self._h, ctypes.byref(n), ctypes.byref(b)))
         return {"total_cells": n.value, "device_bytes": b.value}
+
+    def schedule(self):
+        """The launch groups the batch runs (mm_batch_schedule), as a dict."""
+        return _schedule(_lib.lib().mm_batch_schedule, self._h)
 
     def h_eff(self, ms, Ms, A, outs=None, terms=MM_DEMAG | MM_EXCHANGE):
         if outs is None:

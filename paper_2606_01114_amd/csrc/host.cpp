@@ -9,6 +9,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -101,16 +103,30 @@ std::vector<int> factorize(int L) {
     return r;
 }
 
+// a radix order written as "4,5,5,7"
+std::vector<int> parse_order(const std::string &t) {
+    std::vector<int> o;
+    size_t i = 0;
+    while (i < t.size()) {
+        o.push_back(atoi(t.c_str() + i));
+        const size_t c = t.find(',', i);
+        if (c == std::string::npos) break;
+        i = c + 1;
+    }
+    return o;
+}
+
 struct HostFft {
     FftDesc d;
     std::vector<long double> tw;   // interleaved re, im; forward sign
 };
 
-HostFft make_fft(int L, bool rev = false) {
+// radix order `order` (a permutation of factorize(L)); empty: the default
+HostFft make_fft(int L, bool rev = false, const std::vector<int> &order = {}) {
     HostFft h;
     std::memset(&h.d, 0, sizeof h.d);
     h.d.L = L;
-    std::vector<int> rad = factorize(L);
+    std::vector<int> rad = order.empty() ? factorize(L) : order;
     if (rev) std::reverse(rad.begin(), rad.end());
     h.d.nst = (int)rad.size();
     int Ns = 1, off = 0;
@@ -177,6 +193,8 @@ struct mm_plan {
     FusedPass *d_fp = nullptr;
     // host copies
     HostFft fx, fy, fz;
+    std::vector<int> order[3];  // radix order per axis for the runtime-planned kernels (empty: default)
+    size_t tw_off[3] = {0, 0, 0};   // offsets (complex units) of the x, y, z tables in twT
     LinePass lp_fwd{}, lp_inv{};
     FusedPass fp{};
     ZGeom zg{};
@@ -337,15 +355,34 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     p->hx = Lx / 2 + 1;
     p->hy = Ly / 2 + 1;
     p->hz = Lz / 2 + 1;
-    p->fx = make_fft(Lx);
-    p->fy = make_fft(Ly);
-    p->fz = make_fft(Lz);
+    // test hook: MMX_ORDER="x:4,5,5;y:2,3,3,5" sets the radix order of
+    // runtime-planned (non-power-of-two) axes; a list that is not a
+    // permutation of the length's factors is ignored
+    if (const char *e = getenv("MMX_ORDER")) {
+        std::string t(e);
+        for (size_t i = 0; i + 2 <= t.size();) {
+            const size_t end = std::min(t.find(';', i), t.size());
+            const int a = t[i] == 'x' ? 0 : t[i] == 'y' ? 1 : t[i] == 'z' ? 2 : -1;
+            if (a >= 0 && t[i + 1] == ':' && (p->L[a] & (p->L[a] - 1)) != 0) {
+                std::vector<int> o = parse_order(t.substr(i + 2, end - i - 2));
+                std::vector<int> f = factorize((int)p->L[a]), q = o;
+                std::sort(f.begin(), f.end());
+                std::sort(q.begin(), q.end());
+                if (q == f) p->order[a] = o;
+            }
+            i = end + 1;
+        }
+    }
+    p->fx = make_fft(Lx, false, p->order[0]);
+    p->fy = make_fft(Ly, false, p->order[1]);
+    p->fz = make_fft(Lz, false, p->order[2]);
     // twiddles (plan precision): x, y, z tables concatenated
     std::vector<T> tw;
     auto app = [&](const HostFft &f) { size_t off = tw.size() / 2; auto v = round_tw<T>(f); tw.insert(tw.end(), v.begin(), v.end()); return off; };
     const size_t ox = app(p->fx), oy = app(p->fy);
     (void)app(make_fft(Ly, true));   // reversed radix order, right after y's table (fused inverse)
     const size_t oz = app(p->fz);
+    p->tw_off[0] = ox; p->tw_off[1] = oy; p->tw_off[2] = oz;
     // folded z transform (power-of-two Lz): table of length Lz/2, then exp(-2 pi i k / Lz), k <= Lz/2
     size_t ozh = 0;
     if (Lz >= 2 && (Lz & (Lz - 1)) == 0) {
@@ -545,40 +582,6 @@ std::vector<int> y_variants(int Ly) {
     return v;
 }
 
-// Autotuner for the fused y pass: the LDS-resident, register-resident and
-// persistent (next pencil's loads in flight) pencil kernels, timed on this
-// plan's buffers.
-template <typename T>
-int autotune_y(mm_plan *p) {
-    const std::vector<int> cand = y_variants((int)p->L[1]);
-    if (!p->y_ct || cand.size() < 2) return MM_OK;
-    hipEvent_t e0, e1;
-    HIPCK(hipEventCreate(&e0));
-    HIPCK(hipEventCreate(&e1));
-    int rc = MM_OK, best_v = p->y_var;
-    double best = 1e300;
-    for (int v : cand) {
-        if (rc) break;
-        p->y_var = v;
-        float ms = 0.f;
-        for (int rep = 0; rep < 2 && !rc; ++rep) {
-            (void)hipEventRecord(e0, p->stream);
-            for (int k = 0; k < 3; ++k) {
-                hipError_t e = launch_y<T>(p);
-                if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
-            }
-            (void)hipEventRecord(e1, p->stream);
-            (void)hipEventSynchronize(e1);
-            (void)hipEventElapsedTime(&ms, e0, e1);
-        }
-        if (!rc && ms < best) { best = ms; best_v = v; }
-    }
-    p->y_var = best_v;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    return rc;
-}
-
 // Switch the forward (d = 0) or inverse (d = 1) specialised x pass to
 // variant v (descriptor, LDS).
 int configure_x(mm_plan *p, int d, int v) {
@@ -603,42 +606,320 @@ int configure_x(mm_plan *p, int v) {
     return rc ? rc : configure_x(p, 1, v);
 }
 
-// Autotuner: time each variant of the forward and of the inverse x pass on
-// this plan's own buffers and keep the fastest of each.
+// ---- autotuner -------------------------------------------------------------
+// Launch schedules (x and y pass kernel variants, radix orders of the
+// runtime-planned transforms) are timed on the plan's own buffers and the
+// winners recorded in a schedule cache keyed by device, precision, pass,
+// transform length and problem size (log2 of the points a launch
+// transforms).  Modes: 0 off (default schedules), 1 cached (take a recorded
+// winner, time the candidates on a miss), 2 search (always time; record).
+// MMX_AUTOTUNE=off|cached|search overrides the plan option;
+// MMX_AUTOTUNE_CACHE=<file> keeps the cache across processes (one
+// "key<TAB>value" line per entry, appended as winners are found).
+enum { TUNE_OFF = 0, TUNE_CACHED = 1, TUNE_SEARCH = 2 };
+
+struct TuneCache {
+    std::mutex mu;
+    std::map<std::string, std::string> kv;
+    bool loaded = false;
+    std::string path;
+};
+
+TuneCache &tune_cache() {
+    static TuneCache c;
+    return c;
+}
+
+// (re)read the cache file when MMX_AUTOTUNE_CACHE names a file not read yet
+void tune_load_locked(TuneCache &c) {
+    const char *f = getenv("MMX_AUTOTUNE_CACHE");
+    const std::string path = f ? f : "";
+    if (c.loaded && path == c.path) return;
+    c.loaded = true;
+    c.path = path;
+    if (path.empty()) return;
+    FILE *fp = fopen(path.c_str(), "r");
+    if (!fp) return;
+    char line[512];
+    while (fgets(line, sizeof line, fp)) {
+        char *tab = strchr(line, '\t');
+        if (!tab) continue;
+        *tab = 0;
+        std::string v(tab + 1);
+        while (!v.empty() && (v.back() == '\n' || v.back() == '\r')) v.pop_back();
+        c.kv[line] = v;
+    }
+    fclose(fp);
+}
+
+bool tune_get(const std::string &k, std::string &v) {
+    TuneCache &c = tune_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    tune_load_locked(c);
+    auto it = c.kv.find(k);
+    if (it == c.kv.end()) return false;
+    v = it->second;
+    return true;
+}
+
+void tune_put(const std::string &k, const std::string &v) {
+    TuneCache &c = tune_cache();
+    std::lock_guard<std::mutex> g(c.mu);
+    tune_load_locked(c);
+    c.kv[k] = v;
+    if (!c.path.empty()) {
+        FILE *fp = fopen(c.path.c_str(), "a");
+        if (fp) { fprintf(fp, "%s\t%s\n", k.c_str(), v.c_str()); fclose(fp); }
+    }
+}
+
+int tune_mode(int opt) {
+    const char *e = getenv("MMX_AUTOTUNE");
+    if (e && !strcmp(e, "off")) return TUNE_OFF;
+    if (e && !strcmp(e, "cached")) return TUNE_CACHED;
+    if (e && !strcmp(e, "search")) return TUNE_SEARCH;
+    return opt;
+}
+
+// "<arch>/<CUs>" of a device, looked up once per device
+std::string device_tag(int dev) {
+    static std::mutex mu;
+    static std::map<int, std::string> tags;
+    std::lock_guard<std::mutex> g(mu);
+    auto it = tags.find(dev);
+    if (it != tags.end()) return it->second;
+    hipDeviceProp_t prop;
+    std::string t = "dev";
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) {
+        std::string arch = prop.gcnArchName;
+        const size_t colon = arch.find(':');
+        if (colon != std::string::npos) arch.resize(colon);
+        t = arch + "/" + std::to_string(prop.multiProcessorCount);
+    }
+    tags[dev] = t;
+    return t;
+}
+
+std::string tune_key(int dev, int prec, const char *what, int L, long long points) {
+    int b = 0;
+    while (b < 62 && (1LL << (b + 1)) <= points) ++b;
+    char buf[160];
+    snprintf(buf, sizeof buf, "%s %s %s L%d p2^%d", device_tag(dev).c_str(), prec == MM_F32 ? "f32" : "f64", what, L, b);
+    return buf;
+}
+
+// ms of three back-to-back launches, best of two repetitions
+template <class F>
+int time3(hipStream_t s, hipEvent_t e0, hipEvent_t e1, F launch, float *best) {
+    *best = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+        HIPCK(hipEventRecord(e0, s));
+        for (int k = 0; k < 3; ++k) {
+            hipError_t e = launch();
+            if (e != hipSuccess) return fail(MM_EHIP, "autotune: %s", hipGetErrorString(e));
+        }
+        HIPCK(hipEventRecord(e1, s));
+        HIPCK(hipEventSynchronize(e1));
+        float ms = 0.f;
+        HIPCK(hipEventElapsedTime(&ms, e0, e1));
+        *best = std::min(*best, ms);
+    }
+    return MM_OK;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    int make() {
+        HIPCK(hipEventCreate(&a));
+        HIPCK(hipEventCreate(&b));
+        return MM_OK;
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// the x pass variants a plan can run (LDS permitting)
+std::vector<int> x_variants(const mm_plan *p) {
+    std::vector<int> v;
+    if (!p->x_ct) return v;
+    const size_t csz = p->prec == MM_F32 ? sizeof(float2) : sizeof(double2);
+    for (int k = 0; k < 4; ++k) {
+        int W = 0, NT = 0;
+        if (!line_ct_shape((int)p->L[0], csz, k, &W, &NT)) continue;
+        if ((k >= 2 ? line_hx_lds((int)p->L[0], W, csz) : line_ct_lds((int)p->L[0], W, csz)) > kLdsMax) continue;
+        v.push_back(k);
+    }
+    return v;
+}
+
+// Forward and inverse x pass variants.
 template <typename T>
-int autotune_x(mm_plan *p) {
-    if (!p->x_ct) return MM_OK;
-    hipEvent_t e0, e1;
-    HIPCK(hipEventCreate(&e0));
-    HIPCK(hipEventCreate(&e1));
-    int rc = MM_OK;
+int autotune_x(mm_plan *p, int mode) {
+    const std::vector<int> cand = x_variants(p);
+    if (cand.size() < 2) return MM_OK;
+    EventPair ev;
+    int rc = ev.make();
+    const long long pts = (long long)p->hz * p->n[1] * 3 * p->L[0];
     for (int d = 0; d < 2 && !rc; ++d) {
-        const int dir = d == 0 ? -1 : +1;
-        double best = 1e300;
+        const std::string key = tune_key(p->device, p->prec, d == 0 ? "x_fwd" : "x_inv", (int)p->L[0], pts);
+        std::string got;
+        if (mode == TUNE_CACHED && tune_get(key, got)) {
+            const int v = atoi(got.c_str());
+            if (std::find(cand.begin(), cand.end(), v) != cand.end()) { rc = configure_x(p, d, v); continue; }
+        }
+        float best = 1e30f;
         int bestv = p->x_var[d];
-        for (int v = 0; v < 4 && !rc; ++v) {
-            const size_t csz = sizeof(cplx<T>);
-            int W = 0, NT = 0;
-            if (!line_ct_shape((int)p->L[0], csz, v, &W, &NT)) continue;
-            if ((v >= 2 ? line_hx_lds((int)p->L[0], W, csz) : line_ct_lds((int)p->L[0], W, csz)) > kLdsMax) continue;
+        for (int v : cand) {
             if ((rc = configure_x(p, d, v))) break;
             float ms = 0.f;
-            for (int rep = 0; rep < 2 && !rc; ++rep) {
-                (void)hipEventRecord(e0, p->stream);
-                for (int k = 0; k < 3; ++k) {
-                    hipError_t e = launch_x<T>(p, dir);
-                    if (e != hipSuccess) { rc = fail(MM_EHIP, "autotune: %s", hipGetErrorString(e)); break; }
-                }
-                (void)hipEventRecord(e1, p->stream);
-                (void)hipEventSynchronize(e1);
-                (void)hipEventElapsedTime(&ms, e0, e1);
-            }
-            if (!rc && ms < best) { best = ms; bestv = v; }
+            if ((rc = time3(p->stream, ev.a, ev.b, [&] { return launch_x<T>(p, d == 0 ? -1 : +1); }, &ms))) break;
+            if (ms < best) { best = ms; bestv = v; }
         }
         if (!rc) rc = configure_x(p, d, bestv);
+        if (!rc) tune_put(key, std::to_string(bestv));
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    return rc;
+}
+
+// Fused y pass variants: the LDS-resident, register-resident, wave-rotated
+// and persistent (next pencil's loads in flight) pencil kernels.
+template <typename T>
+int autotune_y(mm_plan *p, int mode) {
+    const std::vector<int> cand = y_variants((int)p->L[1]);
+    if (!p->y_ct || cand.size() < 2) return MM_OK;
+    const std::string key = tune_key(p->device, p->prec, "y_fused", (int)p->L[1], (long long)p->fp.npos * p->L[1]);
+    std::string got;
+    if (mode == TUNE_CACHED && tune_get(key, got)) {
+        const int v = atoi(got.c_str());
+        if (std::find(cand.begin(), cand.end(), v) != cand.end()) { p->y_var = v; return MM_OK; }
+    }
+    EventPair ev;
+    int rc = ev.make();
+    float best = 1e30f;
+    int bestv = p->y_var;
+    for (int v : cand) {
+        if (rc) break;
+        p->y_var = v;
+        float ms = 0.f;
+        if ((rc = time3(p->stream, ev.a, ev.b, [&] { return launch_y<T>(p); }, &ms))) break;
+        if (ms < best) { best = ms; bestv = v; }
+    }
+    p->y_var = bestv;
+    if (!rc) tune_put(key, std::to_string(bestv));
+    return rc;
+}
+
+// Candidate radix orders of a runtime-planned transform: every distinct
+// permutation of the factors when there are at most 24, else the default
+// order, its reverse, its rotations and the two sorted orders.
+std::vector<std::vector<int>> radix_orders(int L) {
+    std::vector<int> f = factorize(L);
+    std::vector<std::vector<int>> out;
+    std::vector<int> s = f;
+    std::sort(s.begin(), s.end());
+    long long count = 0;
+    do { ++count; } while (count <= 24 && std::next_permutation(s.begin(), s.end()));
+    std::sort(s.begin(), s.end());
+    auto add = [&](const std::vector<int> &o) {
+        if (std::find(out.begin(), out.end(), o) == out.end()) out.push_back(o);
+    };
+    add(f);
+    if (count <= 24) {
+        do { add(s); } while (std::next_permutation(s.begin(), s.end()));
+    } else {
+        std::vector<int> r = f;
+        std::reverse(r.begin(), r.end());
+        add(r);
+        for (size_t k = 1; k < f.size(); ++k) {
+            std::vector<int> q(f.begin() + k, f.end());
+            q.insert(q.end(), f.begin(), f.begin() + k);
+            add(q);
+        }
+        add(s);
+        std::reverse(s.begin(), s.end());
+        add(s);
+    }
+    return out;
+}
+
+std::string order_str(const std::vector<int> &o) {
+    std::string r;
+    for (size_t i = 0; i < o.size(); ++i) r += (i ? "," : "") + std::to_string(o[i]);
+    return r;
+}
+
+// Install radix order `o` for axis a of a runtime-planned pass: the host
+// descriptor, the twiddle table in place (its size, L-1, does not depend on
+// the order) and the device copies of the pass descriptors.
+template <typename T>
+int set_order(mm_plan *p, int a, const std::vector<int> &o) {
+    const int L = (int)p->L[a];
+    HostFft h = make_fft(L, false, o);
+    std::vector<T> tw = round_tw<T>(h);
+    if ((int)tw.size() != 2 * (L - 1)) return fail(MM_EINVAL, "radix order does not factor L=%d", L);
+    cplx<T> *base = reinterpret_cast<cplx<T> *>(p->twT) + p->tw_off[a];
+    HIPCK(hipMemcpy(base, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+    p->order[a] = o;
+    if (a == 0) {
+        p->fx = h;
+        p->lp_fwd.f = h.d;
+        p->lp_inv.f = h.d;
+        LinePass two[2] = {p->lp_fwd, p->lp_inv};
+        HIPCK(hipMemcpy(p->d_lp, two, sizeof two, hipMemcpyHostToDevice));
+    } else if (a == 1) {
+        p->fy = h;
+        p->fp.f = h.d;
+        HIPCK(hipMemcpy(p->d_fp, &p->fp, sizeof(FusedPass), hipMemcpyHostToDevice));
+    } else {
+        p->fz = h;
+        p->zg.f = h.d;
+    }
+    return MM_OK;
+}
+
+template <typename T> int time_one(mm_plan *p, int k);
+
+// Radix orders of the axes that run the runtime-planned kernels (lengths
+// with two or more distinct radices), each timed on the passes along it.
+template <typename T>
+int autotune_radix(mm_plan *p, int mode) {
+    const bool rt[3] = {!p->x_ct, !p->y_ct, !p->z_ct};
+    EventPair ev;
+    int rc = MM_OK;
+    bool made = false;
+    for (int a = 0; a < 3 && !rc; ++a) {
+        if (!rt[a] || p->L[a] < 2) continue;
+        const std::vector<std::vector<int>> cand = radix_orders((int)p->L[a]);
+        if (cand.size() < 2) continue;
+        static const char *what[3] = {"x_order", "y_order", "z_order"};
+        const long long pts = (long long)p->n[0] * p->n[1] * p->n[2] * 8;
+        const std::string key = tune_key(p->device, p->prec, what[a], (int)p->L[a], pts);
+        std::string got;
+        if (mode == TUNE_CACHED && tune_get(key, got)) {
+            const std::vector<int> o = parse_order(got);
+            if (std::find(cand.begin(), cand.end(), o) != cand.end()) { rc = set_order<T>(p, a, o); continue; }
+        }
+        if (!made) { if ((rc = ev.make())) break; made = true; }
+        float best = 1e30f;
+        std::vector<int> bo = cand[0];
+        for (const std::vector<int> &o : cand) {
+            if ((rc = set_order<T>(p, a, o))) break;
+            float ms = 0.f;
+            auto run = [&]() -> hipError_t {
+                int r = MM_OK;
+                if (a == 0) { r = time_one<T>(p, 1); if (!r) r = time_one<T>(p, 3); }
+                else if (a == 1) r = time_one<T>(p, 2);
+                else { r = time_one<T>(p, 0); if (!r) r = time_one<T>(p, 5); }
+                return r ? hipErrorUnknown : hipSuccess;
+            };
+            if ((rc = time3(p->stream, ev.a, ev.b, run, &ms))) break;
+            if (ms < best) { best = ms; bo = o; }
+        }
+        if (!rc) rc = set_order<T>(p, a, bo);
+        if (!rc) tune_put(key, order_str(bo));
+    }
     return rc;
 }
 
@@ -1053,7 +1334,7 @@ int plan_params(const int64_t grid[3], const double cell[3], int precision, cons
             return fail(MM_EINVAL, "L[%d]=%lld must be 7-smooth and >= 2n-1 = %lld", a, (long long)L[a], (long long)(2 * grid[a] - 1));
         if (L[a] > 16384) return fail(MM_ENOTSUP, "L[%d]=%lld exceeds 16384", a, (long long)L[a]);
     }
-    if (o.autotune < 0 || o.autotune > 1) return fail(MM_EINVAL, "autotune must be 0 or 1");
+    if (o.autotune < 0 || o.autotune > 2) return fail(MM_EINVAL, "autotune must be 0 (off), 1 (cached) or 2 (search)");
     const int64_t ncell = grid[0] * grid[1] * grid[2];
     if (grid[0] * grid[1] > 0x7fffffffLL / 2 || ncell > (1LL << 34)) return fail(MM_ENOTSUP, "grid too large");
     *o_out = o;
@@ -1083,8 +1364,10 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     for (int a = 0; a < 3; ++a) { p->n[a] = grid[a]; p->d[a] = cell[a]; p->L[a] = L[a]; }
     rc = precision == MM_F32 ? setup_plan<float>(p, &o) : setup_plan<double>(p, &o);
     if (!rc) rc = compute_tensor(p);
-    if (!rc && o.autotune) rc = precision == MM_F32 ? autotune_x<float>(p) : autotune_x<double>(p);
-    if (!rc && o.autotune) rc = precision == MM_F32 ? autotune_y<float>(p) : autotune_y<double>(p);
+    const int tm = tune_mode(o.autotune);
+    if (!rc && tm) rc = precision == MM_F32 ? autotune_x<float>(p, tm) : autotune_x<double>(p, tm);
+    if (!rc && tm) rc = precision == MM_F32 ? autotune_y<float>(p, tm) : autotune_y<double>(p, tm);
+    if (!rc && tm) rc = precision == MM_F32 ? autotune_radix<float>(p, tm) : autotune_radix<double>(p, tm);
     if (rc) {
         std::string keep = g_last;
         free_all(p);
@@ -1258,6 +1541,43 @@ int mm_plan_info(const mm_plan *p, int64_t L[3], size_t *bytes, int tiles[5]) {
     if (bytes) *bytes = p->bytes;
     if (tiles) { tiles[0] = p->zg.P; tiles[1] = p->lp_fwd.W; tiles[2] = p->y_ct ? p->y_var : -p->fp.W; tiles[3] = p->x_var[0]; tiles[4] = p->x_var[1]; }
     return MM_OK;
+}
+
+// schedule description as JSON text into buf (len bytes, NUL-terminated)
+static int put_text(const std::string &t, char *buf, size_t len) {
+    if (!buf) return fail(MM_EINVAL, "buf is NULL");
+    if (t.size() + 1 > len) return fail(MM_EINVAL, "buffer of %zu bytes too small for %zu", len, t.size() + 1);
+    std::memcpy(buf, t.c_str(), t.size() + 1);
+    return MM_OK;
+}
+
+static std::string plan_schedule_json(const mm_plan *p) {
+    char b[512];
+    std::string t = "{";
+    snprintf(b, sizeof b, "\"L\": [%lld, %lld, %lld], ", (long long)p->L[0], (long long)p->L[1], (long long)p->L[2]);
+    t += b;
+    snprintf(b, sizeof b, "\"x_fwd\": {\"specialised\": %d, \"variant\": %d, \"W\": %d}, ", p->x_ct ? 1 : 0, p->x_var[0], p->lp_fwd.W);
+    t += b;
+    snprintf(b, sizeof b, "\"x_inv\": {\"specialised\": %d, \"variant\": %d, \"W\": %d}, ", p->x_ct ? 1 : 0, p->x_var[1], p->lp_inv.W);
+    t += b;
+    snprintf(b, sizeof b, "\"y_fused\": {\"specialised\": %d, \"variant\": %d, \"pencils_per_tile\": %d}, ", p->y_ct ? 1 : 0, p->y_ct ? p->y_var : -1, p->fp.W);
+    t += b;
+    snprintf(b, sizeof b, "\"z\": {\"specialised\": %d, \"columns_per_tile\": %d}, ", p->z_ct ? 1 : 0, p->zg.P);
+    t += b;
+    const HostFft *f[3] = {&p->fx, &p->fy, &p->fz};
+    t += "\"radix_order\": {";
+    for (int a = 0; a < 3; ++a) {
+        std::string o;
+        for (int k = 0; k < f[a]->d.nst; ++k) o += (k ? "," : "") + std::to_string(f[a]->d.rad[k]);
+        t += std::string(a ? ", " : "") + "\"" + "xyz"[a] + "\": \"" + o + "\"";
+    }
+    t += "}}";
+    return t;
+}
+
+int mm_plan_schedule(const mm_plan *p, char *buf, size_t len) {
+    if (!p) return fail(MM_EINVAL, "plan is NULL");
+    return put_text(plan_schedule_json(p), buf, len);
 }
 
 int h_eff(mm_plan *p, const void *m, const void *Ms, double Ms_scalar, double A, void *h_out, unsigned terms,
@@ -1501,7 +1821,9 @@ struct BGroup {
     int nthr = 64;
     size_t lds = 0;
     int2 *map = nullptr;  // device tile map (geometry, local tile)
-    int var = 0;          // x pass: 3 = half-LDS kernel on wide tiles, else the full-LDS kernel
+    size_t cap = 0;       // entries the map buffer holds
+    int var = 0;          // kernel variant (x: 0..3, y: 0..2, as mm_plan_info)
+    std::vector<int> geo; // geometries of the group
 };
 
 struct mm_batch {
@@ -1511,7 +1833,7 @@ struct mm_batch {
     std::vector<mm_plan *> plans;
     std::vector<void *> allocs;
     size_t bytes = 0;
-    std::vector<BGroup> gx, gy, gz;
+    std::vector<BGroup> gxf, gxi, gy, gz;   // forward x, inverse x, fused y, z launch groups
     LinePass *d_lpf = nullptr, *d_lpi = nullptr;
     FusedPass *d_fp = nullptr;
     ZFwdArgs *d_zf = nullptr;
@@ -1590,21 +1912,23 @@ int batch_zinv(mm_batch *b, const ZInvArgs *d, int epi) {
 }
 
 template <typename T>
+hipError_t batch_x_group(mm_batch *b, const BGroup &g, int dir) {
+    const LinePass *d = dir < 0 ? b->d_lpf : b->d_lpi;
+    if (g.L) return launch_line_var_b<T>(d, g.map, g.tiles, g.L, g.W, dir, g.var, b->stream);
+    return launch_line_pass<T>(d, g.map, g.tiles, g.nthr, g.lds, dir, false, b->stream);
+}
+
+template <typename T>
+hipError_t batch_y_group(mm_batch *b, const BGroup &g) {
+    if (g.L) return launch_fused_var_b<T>(b->d_fp, g.map, g.tiles, g.L, g.var, b->stream);
+    return launch_fused_y<T>(b->d_fp, g.map, g.tiles, g.nthr, g.lds, b->stream);
+}
+
+template <typename T>
 int batch_xyx(mm_batch *b) {
-    for (const BGroup &g : b->gx) {
-        if (g.L && g.var == 3) HIPCK(launch_line_wide_b<T>(b->d_lpf, g.map, g.tiles, g.L, g.W, -1, b->stream));
-        else if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpf, g.map, g.tiles, g.L, g.W, -1, b->stream));
-        else HIPCK(launch_line_pass<T>(b->d_lpf, g.map, g.tiles, g.nthr, g.lds, -1, false, b->stream));
-    }
-    for (const BGroup &g : b->gy) {
-        if (g.L) HIPCK(launch_fused_ct_b<T>(b->d_fp, g.map, g.tiles, g.L, b->stream));
-        else HIPCK(launch_fused_y<T>(b->d_fp, g.map, g.tiles, g.nthr, g.lds, b->stream));
-    }
-    for (const BGroup &g : b->gx) {
-        if (g.L && g.var == 3) HIPCK(launch_line_wide_b<T>(b->d_lpi, g.map, g.tiles, g.L, g.W, +1, b->stream));
-        else if (g.L) HIPCK(launch_line_ct_b<T>(b->d_lpi, g.map, g.tiles, g.L, g.W, +1, b->stream));
-        else HIPCK(launch_line_pass<T>(b->d_lpi, g.map, g.tiles, g.nthr, g.lds, +1, false, b->stream));
-    }
+    for (const BGroup &g : b->gxf) HIPCK(batch_x_group<T>(b, g, -1));
+    for (const BGroup &g : b->gy) HIPCK(batch_y_group<T>(b, g));
+    for (const BGroup &g : b->gxi) HIPCK(batch_x_group<T>(b, g, +1));
     return MM_OK;
 }
 
@@ -1644,9 +1968,25 @@ std::vector<unsigned char> batch_key(mm_batch *b, void *const *m_ptrs, const dou
     return k;
 }
 
-// Build the launch groups of one pass kind: key(plan) = specialised length or 0.
-template <class Key, class Tiles, class Shape>
-int build_groups(mm_batch *b, std::vector<BGroup> &out, Key key, Tiles tiles, Shape shape) {
+// (Re)write a group's tile map from its geometries' current tile counts.
+template <class Tiles>
+int upload_map(BGroup &g, Tiles tiles) {
+    std::vector<int2> m;
+    for (int i : g.geo) {
+        const int t = tiles(i);
+        for (int j = 0; j < t; ++j) m.push_back(make_int2(i, j));
+    }
+    if (m.size() > g.cap) return fail(MM_EINVAL, "tile map of %zu entries exceeds its buffer (%zu)", m.size(), g.cap);
+    g.tiles = (int)m.size();
+    if (!m.empty()) HIPCK(hipMemcpy(g.map, m.data(), m.size() * sizeof(int2), hipMemcpyHostToDevice));
+    return MM_OK;
+}
+
+// Build the launch groups of one pass kind: key(plan) = specialised length or
+// 0; the map buffer holds `cap_tiles(plan)` tiles per geometry (the most any
+// variant the tuner may pick needs).
+template <class Key, class Tiles, class Shape, class Cap>
+int build_groups(mm_batch *b, std::vector<BGroup> &out, Key key, Tiles tiles, Shape shape, Cap cap_tiles) {
     std::vector<int> keys;
     for (mm_plan *p : b->plans) {
         const int k = key(p);
@@ -1655,21 +1995,111 @@ int build_groups(mm_batch *b, std::vector<BGroup> &out, Key key, Tiles tiles, Sh
     for (int k : keys) {
         BGroup g;
         g.L = k;
-        std::vector<int2> m;
+        size_t cap = 0;
         for (int i = 0; i < b->count; ++i) {
             mm_plan *p = b->plans[i];
             if (key(p) != k) continue;
-            const int t = tiles(p);
-            for (int j = 0; j < t; ++j) m.push_back(make_int2(i, j));
+            g.geo.push_back(i);
+            cap += (size_t)std::max(tiles(p), cap_tiles(p));
             shape(p, g);
         }
-        g.tiles = (int)m.size();
-        int rc = balloc(b, (void **)&g.map, m.size() * sizeof(int2));
+        int rc = balloc(b, (void **)&g.map, cap * sizeof(int2));
         if (rc) return rc;
-        HIPCK(hipMemcpy(g.map, m.data(), m.size() * sizeof(int2), hipMemcpyHostToDevice));
-        out.push_back(g);
+        g.cap = cap;
+        if ((rc = upload_map(g, [&](int i) { return tiles(b->plans[i]); }))) return rc;
+        out.push_back(std::move(g));
     }
     return MM_OK;
+}
+
+// x pass tiles of a plan at the narrowest tile width any variant uses
+int x_tiles_max(const mm_plan *p) {
+    int t = p->tiles_fwd;
+    const size_t csz = p->prec == MM_F32 ? sizeof(float2) : sizeof(double2);
+    for (int v : x_variants(p)) {
+        int W = 0, NT = 0;
+        if (line_ct_shape((int)p->L[0], csz, v, &W, &NT)) t = std::max(t, ((p->lp_fwd.inner + W - 1) / W) * p->lp_fwd.outer);
+    }
+    return t;
+}
+
+// Batch autotuner: per launch group, time every kernel variant the group's
+// length has on the batch's own buffers (tile maps rebuilt for each tile
+// width) and keep the fastest; winners go to the schedule cache.
+template <typename T>
+int batch_autotune(mm_batch *b, int mode) {
+    if (mode == TUNE_OFF || b->plans.empty()) return MM_OK;
+    const int dev = b->plans[0]->device;
+    EventPair ev;
+    int rc = ev.make();
+    for (int d = 0; d < 2 && !rc; ++d) {
+        std::vector<BGroup> &gs = d == 0 ? b->gxf : b->gxi;
+        LinePass *dd = d == 0 ? b->d_lpf : b->d_lpi;
+        for (BGroup &g : gs) {
+            if (rc || !g.L) continue;
+            mm_plan *p0 = b->plans[g.geo[0]];
+            const std::vector<int> cand = x_variants(p0);
+            if (cand.size() < 2) continue;
+            long long pts = 0;
+            for (int i : g.geo) pts += (long long)b->plans[i]->hz * b->plans[i]->n[1] * 3 * g.L;
+            const std::string key = tune_key(dev, b->prec, d == 0 ? "batch_x_fwd" : "batch_x_inv", g.L, pts);
+            auto apply = [&](int v) -> int {
+                for (int i : g.geo) {
+                    int r = configure_x(b->plans[i], d, v);
+                    if (r) return r;
+                    const LinePass &lp = d == 0 ? b->plans[i]->lp_fwd : b->plans[i]->lp_inv;
+                    HIPCK(hipMemcpy(dd + i, &lp, sizeof(LinePass), hipMemcpyHostToDevice));
+                }
+                mm_plan *q = b->plans[g.geo[0]];
+                g.var = v;
+                g.W = (d == 0 ? q->lp_fwd : q->lp_inv).W;
+                return upload_map(g, [&](int i) { return d == 0 ? b->plans[i]->tiles_fwd : b->plans[i]->tiles_inv; });
+            };
+            std::string got;
+            if (mode == TUNE_CACHED && tune_get(key, got)) {
+                const int v = atoi(got.c_str());
+                if (std::find(cand.begin(), cand.end(), v) != cand.end()) { rc = apply(v); continue; }
+            }
+            float best = 1e30f;
+            int bestv = g.var;
+            for (int v : cand) {
+                if ((rc = apply(v))) break;
+                float ms = 0.f;
+                if ((rc = time3(b->stream, ev.a, ev.b, [&] { return batch_x_group<T>(b, g, d == 0 ? -1 : +1); }, &ms))) break;
+                if (ms < best) { best = ms; bestv = v; }
+            }
+            if (!rc) rc = apply(bestv);
+            if (!rc) tune_put(key, std::to_string(bestv));
+        }
+    }
+    for (BGroup &g : b->gy) {
+        if (rc || !g.L) continue;
+        std::vector<int> cand{0};
+        if (fused_hx_threads(g.L) > 0) cand.push_back(1);
+        if (fused_pf_available(g.L, 2)) cand.push_back(2);
+        if (cand.size() < 2) continue;
+        long long pts = 0;
+        for (int i : g.geo) pts += (long long)b->plans[i]->fp.npos * g.L;
+        const std::string key = tune_key(dev, b->prec, "batch_y_fused", g.L, pts);
+        std::string got;
+        if (mode == TUNE_CACHED && tune_get(key, got)) {
+            const int v = atoi(got.c_str());
+            if (std::find(cand.begin(), cand.end(), v) != cand.end()) { g.var = v; continue; }
+        }
+        float best = 1e30f;
+        int bestv = g.var;
+        for (int v : cand) {
+            g.var = v;
+            float ms = 0.f;
+            if ((rc = time3(b->stream, ev.a, ev.b, [&] { return batch_y_group<T>(b, g); }, &ms))) break;
+            if (ms < best) { best = ms; bestv = v; }
+        }
+        g.var = bestv;
+        if (!rc) tune_put(key, std::to_string(bestv));
+    }
+    for (BGroup &g : b->gy)
+        for (int i : g.geo) b->plans[i]->y_var = g.L ? g.var : 0;
+    return rc;
 }
 
 }  // namespace
@@ -1699,31 +2129,40 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         mm_plan *p = nullptr;
         rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &o);
         if (!rc) b->plans.push_back(p);
-        // grouped x launches: the half-LDS kernel on wide tiles for lines of
-        // 1024 points or more, the narrow full-LDS kernel below
-        if (!rc) {
+        // default grouped x launches (the tuner may change them): the
+        // half-LDS kernel on wide tiles for lines of 1024 points or more, the
+        // narrow full-LDS kernel below; the MMX_XVAR / MMX_YVAR test hooks
+        // keep the variants they set
+        if (!rc && !getenv("MMX_XVAR")) {
             int W = 0, NT = 0;
             const size_t csz = precision == MM_F32 ? sizeof(float2) : sizeof(double2);
             const int v = p->x_ct && line_ct_shape((int)p->L[0], csz, 3, &W, &NT) &&
                                   line_hx_lds((int)p->L[0], W, csz) <= kLdsMax ? 3 : 0;
             if (p->x_var[0] != v || p->x_var[1] != v) rc = configure_x(p, v);
         }
-        if (!rc) p->y_var = 0;
+        // grouped y launches have variants 0..2
+        if (!rc && (!getenv("MMX_YVAR") || p->y_var > 2)) p->y_var = 0;
     }
     std::vector<LinePass> lf, li;
     std::vector<FusedPass> fp;
     for (int g = 0; g < count && !rc; ++g) {
         lf.push_back(b->plans[g]->lp_fwd); li.push_back(b->plans[g]->lp_inv); fp.push_back(b->plans[g]->fp);
     }
-    if (!rc) rc = build_groups(b, b->gx, [](mm_plan *p) { return p->x_ct ? (int)p->L[0] : 0; },
-                               [](mm_plan *p) { return p->tiles_fwd; },
-                               [](mm_plan *p, BGroup &g) { g.W = p->lp_fwd.W; g.var = p->x_var[0]; g.nthr = std::max(g.nthr, p->lp_fwd.nthr); g.lds = std::max(g.lds, p->lds_fwd); });
+    auto xkey = [](mm_plan *p) { return p->x_ct ? (int)p->L[0] : 0; };
+    if (!rc) rc = build_groups(b, b->gxf, xkey, [](mm_plan *p) { return p->tiles_fwd; },
+                               [](mm_plan *p, BGroup &g) { g.W = p->lp_fwd.W; g.var = p->x_var[0]; g.nthr = std::max(g.nthr, p->lp_fwd.nthr); g.lds = std::max(g.lds, p->lds_fwd); },
+                               [](mm_plan *p) { return x_tiles_max(p); });
+    if (!rc) rc = build_groups(b, b->gxi, xkey, [](mm_plan *p) { return p->tiles_inv; },
+                               [](mm_plan *p, BGroup &g) { g.W = p->lp_inv.W; g.var = p->x_var[1]; g.nthr = std::max(g.nthr, p->lp_inv.nthr); g.lds = std::max(g.lds, p->lds_inv); },
+                               [](mm_plan *p) { return x_tiles_max(p); });
     if (!rc) rc = build_groups(b, b->gy, [](mm_plan *p) { return p->y_ct ? (int)p->L[1] : 0; },
                                [](mm_plan *p) { return p->fp.tiles; },
-                               [](mm_plan *p, BGroup &g) { g.nthr = std::max(g.nthr, p->fp.nthr); g.lds = std::max(g.lds, p->lds_fp); });
+                               [](mm_plan *p, BGroup &g) { g.var = p->y_ct ? p->y_var : 0; g.nthr = std::max(g.nthr, p->fp.nthr); g.lds = std::max(g.lds, p->lds_fp); },
+                               [](mm_plan *p) { return p->fp.tiles; });
     if (!rc) rc = build_groups(b, b->gz, [](mm_plan *p) { return p->z_ct ? (int)p->L[2] : 0; },
                                [](mm_plan *p) { return p->zg.tiles; },
-                               [](mm_plan *p, BGroup &g) { g.nthr = std::max(g.nthr, p->zg.nthr); g.lds = std::max(g.lds, p->lds_z); });
+                               [](mm_plan *p, BGroup &g) { g.nthr = std::max(g.nthr, p->zg.nthr); g.lds = std::max(g.lds, p->lds_z); },
+                               [](mm_plan *p) { return p->zg.tiles; });
     if (!rc) rc = balloc(b, (void **)&b->d_lpf, lf.size() * sizeof(LinePass));
     if (!rc) rc = balloc(b, (void **)&b->d_lpi, li.size() * sizeof(LinePass));
     if (!rc) rc = balloc(b, (void **)&b->d_fp, fp.size() * sizeof(FusedPass));
@@ -1734,6 +2173,10 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
         if (e == hipSuccess) e = hipMemcpy(b->d_lpi, li.data(), li.size() * sizeof(LinePass), hipMemcpyHostToDevice);
         if (e == hipSuccess) e = hipMemcpy(b->d_fp, fp.data(), fp.size() * sizeof(FusedPass), hipMemcpyHostToDevice);
         if (e != hipSuccess) rc = fail(MM_EHIP, "batch tables: %s", hipGetErrorString(e));
+    }
+    if (!rc) {
+        const int tm = tune_mode(o.autotune);
+        rc = precision == MM_F32 ? batch_autotune<float>(b, tm) : batch_autotune<double>(b, tm);
     }
     if (rc) {
         std::string keep = g_last;
@@ -1826,6 +2269,28 @@ int mm_batch_info(const mm_batch *b, int64_t *total_cells, size_t *device_bytes)
     if (total_cells) *total_cells = n;
     if (device_bytes) *device_bytes = by;
     return MM_OK;
+}
+
+int mm_batch_schedule(const mm_batch *b, char *buf, size_t len) {
+    if (!b) return fail(MM_EINVAL, "batch is NULL");
+    std::string t = "{\"groups\": [";
+    bool first = true;
+    auto add = [&](const char *pass, const std::vector<BGroup> &gs) {
+        for (const BGroup &g : gs) {
+            char s[256];
+            snprintf(s, sizeof s, "%s{\"pass\": \"%s\", \"L\": %d, \"specialised\": %d, \"variant\": %d, \"W\": %d, "
+                     "\"geometries\": %zu, \"tiles\": %d}", first ? "" : ", ", pass, g.L ? g.L : 0, g.L ? 1 : 0, g.var, g.W,
+                     g.geo.size(), g.tiles);
+            t += s;
+            first = false;
+        }
+    };
+    add("x_fwd", b->gxf);
+    add("y_fused", b->gy);
+    add("x_inv", b->gxi);
+    add("z", b->gz);
+    t += "]}";
+    return put_text(t, buf, len);
 }
 
 int mm_batch_destroy(mm_batch *b) {

@@ -656,6 +656,19 @@ __global__ void __launch_bounds__(NT) k_fused_y_ct_b(const FusedPass *__restrict
     fused_ct_body<T, L, NT>(descs[e.x], e.y);
 }
 
+// grouped launches of the wave-rotated and register-resident variants
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_cr_b(const FusedPass *__restrict__ descs, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    fused_ct_body<T, L, NT>(descs[e.x], e.y, (int)((blockIdx.x >> 3) % (NT / 64)));
+}
+
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT) k_fused_y_hx_b(const FusedPass *__restrict__ descs, const int2 *__restrict__ map) {
+    const int2 e = map[xcd_tile(blockIdx.x, gridDim.x)];
+    fused_hx_body<T, L, NT>(descs[e.x], e.y);
+}
+
 // ---- fused y pass, persistent, with the next pencil's loads in flight -----
 // The first forward stage's inputs of one pencil (the rows below L/2 of its
 // three components), held in registers between their load and the stage.
@@ -1046,6 +1059,74 @@ hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int
 #undef FB
     return hipGetLastError();
 }
+
+// Grouped x pass in any of the four variants (as launch_line_ct /
+// launch_line_wide for one geometry).
+template <typename T>
+hipError_t launch_line_var_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, int var,
+                             hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    if (var == 3) return launch_line_wide_b<T>(d, map, tiles, L, W, dir, s);
+    const size_t lds = var == 2 ? line_hx_lds(L, W, sizeof(cplx<T>)) : line_ct_lds(L, W, sizeof(cplx<T>));
+#define LVB(LL, WW)                                                                                                   \
+    if (L == LL && W == WW) {                                                                                         \
+        constexpr int NTT = WW * LL / 16;                                                                             \
+        if (var == 2 && ct::nst(LL) >= 2) {                                                                           \
+            if (dir < 0) hipLaunchKernelGGL((k_line_hx_b<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map); \
+            else hipLaunchKernelGGL((k_line_hx_b<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map);       \
+        } else if (dir < 0) hipLaunchKernelGGL((k_line_ct_b<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map); \
+        else hipLaunchKernelGGL((k_line_ct_b<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map);           \
+        return hipGetLastError();                                                                                     \
+    }
+    if constexpr (sizeof(T) == 4) {
+        LVB(64, 16) LVB(64, 32) LVB(128, 16) LVB(128, 32) LVB(256, 16) LVB(256, 32) LVB(512, 16) LVB(512, 32)
+        LVB(1024, 8) LVB(1024, 16) LVB(2048, 4) LVB(2048, 8) LVB(4096, 2) LVB(4096, 4)
+    } else {
+        LVB(64, 16) LVB(64, 32) LVB(128, 16) LVB(128, 32) LVB(256, 16) LVB(256, 32) LVB(512, 8) LVB(512, 16)
+        LVB(1024, 4) LVB(1024, 8) LVB(2048, 2) LVB(2048, 4) LVB(4096, 1) LVB(4096, 2)
+    }
+#undef LVB
+    return hipErrorInvalidValue;
+}
+
+// Grouped fused y pass: variant 0 LDS-resident pencils, 1 register-resident,
+// 2 LDS-resident with rotated waves (the persistent variant has no grouped
+// form).
+template <typename T>
+hipError_t launch_fused_var_b(const FusedPass *d, const int2 *map, int tiles, int L, int var, hipStream_t s) {
+    if (tiles <= 0) return hipSuccess;
+    if (var == 0) return launch_fused_ct_b<T>(d, map, tiles, L, s);
+    if (var == 1) {
+        const size_t lds = fused_hx_lds(L, sizeof(cplx<T>));
+        switch (L) {
+        case 256: hipLaunchKernelGGL((k_fused_y_hx_b<T, 256, 64>), dim3(tiles), dim3(64), lds, s, d, map); break;
+        case 512: hipLaunchKernelGGL((k_fused_y_hx_b<T, 512, 128>), dim3(tiles), dim3(128), lds, s, d, map); break;
+        case 1024: hipLaunchKernelGGL((k_fused_y_hx_b<T, 1024, 192>), dim3(tiles), dim3(192), lds, s, d, map); break;
+        case 2048: hipLaunchKernelGGL((k_fused_y_hx_b<T, 2048, 384>), dim3(tiles), dim3(384), lds, s, d, map); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    if (var == 2) {
+        const size_t lds = fused_ct_lds(L, sizeof(cplx<T>));
+        switch (L) {
+        case 512: hipLaunchKernelGGL((k_fused_y_cr_b<T, 512, 128>), dim3(tiles), dim3(128), lds, s, d, map); break;
+        case 1024: hipLaunchKernelGGL((k_fused_y_cr_b<T, 1024, 256>), dim3(tiles), dim3(256), lds, s, d, map); break;
+        case 2048:
+            hipLaunchKernelGGL((k_fused_y_cr_b<T, 2048, (sizeof(T) == 4 ? 256 : 384)>), dim3(tiles),
+                               dim3(sizeof(T) == 4 ? 256 : 384), lds, s, d, map);
+            break;
+        case 4096: hipLaunchKernelGGL((k_fused_y_cr_b<T, 4096, 768>), dim3(tiles), dim3(768), lds, s, d, map); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+}
+template hipError_t launch_line_var_b<float>(const LinePass *, const int2 *, int, int, int, int, int, hipStream_t);
+template hipError_t launch_line_var_b<double>(const LinePass *, const int2 *, int, int, int, int, int, hipStream_t);
+template hipError_t launch_fused_var_b<float>(const FusedPass *, const int2 *, int, int, int, hipStream_t);
+template hipError_t launch_fused_var_b<double>(const FusedPass *, const int2 *, int, int, int, hipStream_t);
 
 template hipError_t launch_line_ct_b<float>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
 template hipError_t launch_line_ct_b<double>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);

@@ -50,6 +50,12 @@ template <typename T> hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipS
 template <typename T>
 hipError_t launch_line_ct_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s);
 template <typename T> hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int L, hipStream_t s);
+// grouped launches in any variant (x: 0..3 as mm_plan_info; y: 0..2)
+template <typename T>
+hipError_t launch_line_var_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, int var,
+                             hipStream_t s);
+template <typename T>
+hipError_t launch_fused_var_b(const FusedPass *d, const int2 *map, int tiles, int L, int var, hipStream_t s);
 template <typename T>
 hipError_t launch_zfwd_ct_b(const ZFwdArgs *d, const int2 *map, int tiles, int Lz, int src_mode, hipStream_t s);
 template <typename T>

@@ -226,7 +226,7 @@ def test_batch_wide_x_tiles_against_oracle(prec):
 
 
 def test_batch_sweep_64_geometries():
-    """The 64-geometry sweep (FP32, grouped launches, one graph per step):
+    """The 64-geometry sweep (FP32, autotuned grouped launches, one graph per step):
     every geometry's h_eff against the oracle (1e-5), and one RK4 step of
     eight geometries spanning the size range against the oracle's step
     (increment, 1e-5)."""
@@ -236,8 +236,9 @@ def test_batch_sweep_64_geometries():
     geo = synth.batch_geometries(4)
     grids = [g for g, _ in geo]
     Ms = [ms for _, ms in geo]
-    _say("sweep: plans")
-    b = Batch(grids, [D] * len(grids), "f32")
+    _say("sweep: plans (autotuned launch groups)")
+    b = Batch(grids, [D] * len(grids), "f32", autotune="search")
+    _say("sweep: schedule", [(g["pass"], g["L"], g["variant"]) for g in b.schedule()["groups"]])
     m0 = [rounded(synth.random_unit(g, 100 + k), torch.float32) for k, g in enumerate(grids)]
     hs = [h.cpu().numpy() for h in b.h_eff([to_dev(x, torch.float32) for x in m0], Ms, A)]
     ms = [to_dev(x, torch.float32) for x in m0]
@@ -440,3 +441,152 @@ def test_y_pass_variants_against_oracle(n):
             os.environ.pop("MMX_YVAR", None)
         else:
             os.environ["MMX_YVAR"] = old
+
+
+def _factors(L):
+    """The library's default radix list of a 7-smooth length: radix-16 stages
+    with an 8/4/2 tail for the power of two, then 3s, 5s and 7s."""
+    r, p2 = [], 0
+    while L % 2 == 0:
+        L //= 2
+        p2 += 1
+    if p2 == 1:
+        r.append(2)
+    elif p2 > 1:
+        a, rem = divmod(p2, 4)
+        if rem == 1 and a >= 1:
+            r += [16] * (a - 1) + [8, 4]
+        else:
+            r += [16] * a + {3: [8], 2: [4], 1: [2], 0: []}[rem]
+    for q in (3, 5, 7):
+        while L % q == 0:
+            L //= q
+            r.append(q)
+    return r
+
+
+def test_radix_orders_against_oracle():
+    """Runtime-planned transforms in every radix order (MMX_ORDER): all 12
+    orders of the 90-point y line (2,3,3,5) and both orders of the 14-point x
+    and 10-point z lines, FP32 and FP64, h_eff against the oracle; then a plan
+    that searches the orders itself (autotune "search") reports permutations
+    of each length's radices and matches the oracle too."""
+    import itertools
+    import os
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    n = (7, 45, 5)
+    oct_ = oracle.tensor_octant(n, D)
+    m0 = synth.random_unit(n, 31)
+    ref = None
+    old = os.environ.get("MMX_ORDER")
+    try:
+        orders = sorted(set(itertools.permutations(_factors(90))))
+        assert len(orders) == 12
+        runs = [("y", o) for o in orders] + [("x", (7, 2)), ("z", (5, 2))]
+        for ax, o in runs:
+            os.environ["MMX_ORDER"] = "%s:%s" % (ax, ",".join(map(str, o)))
+            for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+                dt = torch.float32 if prec == "f32" else torch.float64
+                plan = DemagPlan(n, D, prec, padding="smooth")
+                L = plan.info()["L"]
+                if ref is None:
+                    assert L == (14, 90, 10), L
+                    ref = oracle.h_eff(m0, MS, A, D, oct_, L)
+                got = plan.schedule()["radix_order"][ax]
+                assert got == ",".join(map(str, o)), (got, o)
+                e = rel_l2(plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A).cpu().numpy(), ref)
+                _say("radix order", ax, o, prec, e)
+                assert e <= tol, (ax, o, prec, e)
+                plan.close()
+    finally:
+        if old is None:
+            os.environ.pop("MMX_ORDER", None)
+        else:
+            os.environ["MMX_ORDER"] = old
+    for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+        dt = torch.float32 if prec == "f32" else torch.float64
+        plan = DemagPlan(n, D, prec, padding="smooth", autotune="search")
+        sch = plan.schedule()
+        for ax, Lv in zip("xyz", (14, 90, 10)):
+            assert sorted(int(v) for v in sch["radix_order"][ax].split(",")) == sorted(_factors(Lv)), sch
+        e = rel_l2(plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A).cpu().numpy(), ref)
+        _say("searched radix orders", prec, sch["radix_order"], e)
+        assert e <= tol
+        plan.close()
+
+
+@pytest.mark.parametrize("xv,yv", [(0, 0), (1, 1), (2, 2), (3, 0)])
+def test_batch_kernel_variants_against_oracle(xv, yv):
+    """Every grouped kernel variant (MMX_XVAR / MMX_YVAR at batch creation:
+    both x tile widths, the half-LDS and wide half-LDS x kernels; the
+    LDS-resident, register-resident and wave-rotated fused y kernels) over
+    geometries with x lines of 2048, 1024 and 256 points and y lines of 128
+    to 1024 points, FP32 and FP64, h_eff against the oracle."""
+    import os
+    import torch
+    from paper_2606_01114_amd import Batch
+    geo = [((600, 4, 2), 8e5), ((300, 5, 3), 6e5), ((100, 40, 3), 1e6), ((20, 300, 2), 7e5)]
+    grids = [g for g, _ in geo]
+    Ms = [ms for _, ms in geo]
+    octs = [oracle.tensor_octant(g, D) for g in grids]
+    m0 = [synth.random_unit(g, 80 + k) for k, g in enumerate(grids)]
+    refs = [oracle.h_eff(m0[k], Ms[k], A, D, octs[k], tuple(_pow2_L(v) for v in g)) for k, g in enumerate(grids)]
+    saved = {k: os.environ.get(k) for k in ("MMX_XVAR", "MMX_YVAR")}
+    try:
+        os.environ["MMX_XVAR"], os.environ["MMX_YVAR"] = str(xv), str(yv)
+        for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+            dt = torch.float32 if prec == "f32" else torch.float64
+            b = Batch(grids, [D] * len(grids), prec)
+            sch = b.schedule()["groups"]
+            xs = {g["variant"] for g in sch if g["pass"] in ("x_fwd", "x_inv") and g["specialised"]}
+            _say("batch variants", xv, yv, prec, [(g["pass"], g["L"], g["variant"], g["W"]) for g in sch])
+            hs = b.h_eff([to_dev(rounded(x, dt), dt) for x in m0], Ms, A)
+            for k, g in enumerate(grids):
+                e = rel_l2(hs[k].cpu().numpy(), refs[k])
+                assert e <= tol, (xv, yv, prec, g, e)
+            assert xv in xs or xv == 3, xs
+            b.close()
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def test_batch_autotune_cache_roundtrip(tmp_path):
+    """A batch created with autotune "search" records a winner per launch
+    group in the schedule cache file; a second batch in "cached" mode reads
+    the same schedule back (no timing), and both match the oracle."""
+    import os
+    import torch
+    from paper_2606_01114_amd import Batch
+    geo = [((300, 5, 3), 6e5), ((100, 40, 3), 1e6), ((20, 300, 2), 7e5)]
+    grids = [g for g, _ in geo]
+    Ms = [ms for _, ms in geo]
+    octs = [oracle.tensor_octant(g, D) for g in grids]
+    m0 = [synth.random_unit(g, 90 + k) for k, g in enumerate(grids)]
+    cache = tmp_path / "schedules.tsv"
+    old = os.environ.get("MMX_AUTOTUNE_CACHE")
+    os.environ["MMX_AUTOTUNE_CACHE"] = str(cache)
+    try:
+        b1 = Batch(grids, [D] * len(grids), "f32", autotune="search")
+        s1 = b1.schedule()
+        b2 = Batch(grids, [D] * len(grids), "f32", autotune="cached")
+        s2 = b2.schedule()
+    finally:
+        if old is None:
+            os.environ.pop("MMX_AUTOTUNE_CACHE", None)
+        else:
+            os.environ["MMX_AUTOTUNE_CACHE"] = old
+    _say("tuned schedule", s1)
+    assert s1 == s2
+    lines = cache.read_text().splitlines()
+    assert any("batch_x_fwd" in ln for ln in lines) and any("batch_y_fused" in ln for ln in lines), lines
+    for b in (b1, b2):
+        hs = b.h_eff([to_dev(rounded(x, torch.float32), torch.float32) for x in m0], Ms, A)
+        for k, g in enumerate(grids):
+            ref = oracle.h_eff(m0[k], Ms[k], A, D, octs[k], tuple(_pow2_L(v) for v in g))
+            assert rel_l2(hs[k].cpu().numpy(), ref) <= 1e-5
+        b.close()
