@@ -290,6 +290,18 @@ int h_eff(mm_plan *plan, const void *m, const void *Ms, double Ms_scalar, double
           unsigned terms, double *energy_out);
 
 /*
+ * mm_llg_stability -- stiffness of the explicit LLG step (host only, no GPU
+ * call): omega_dt = gamma (2A/(mu0 Ms_min)) sum_a 4/d_a^2 dt, the largest
+ * exchange precession rate a grid of cell size `cell` (host double[3]) can
+ * carry, times the step.  Classic RK4 is stable on the imaginary axis up to
+ * 2 sqrt(2) ~ 2.83; a larger value means llg_step will diverge on the
+ * shortest wavelengths.  Ms_min > 0: the smallest Ms of a non-vacuum cell.
+ * The Python binding warns when an llg_step call with scalar Ms exceeds the
+ * bound.  MM_EINVAL for non-finite or non-positive arguments.
+ */
+int mm_llg_stability(const double cell[3], double Ms_min, double A, double gamma, double dt, double *omega_dt);
+
+/*
  * llg_step -- n_steps classic RK4 steps of eq. (1) for unit m:
  *   dm/dt = -gamma/(1+alpha^2) [ m x h + alpha m x (m x h) ],
  *   h = H_demag + H_exchange (+ h_ext).  Follows llg.step(state, dt).

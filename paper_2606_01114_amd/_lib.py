@@ -26,7 +26,7 @@ EXPORTS = [
     "mm_demag_tensor_get", "mm_demag_tensor_set", "mm_demag_spectrum_get",
     "mm_batch_create", "mm_batch_h_eff", "mm_batch_llg_step", "mm_batch_tensor_set", "mm_batch_info",
     "mm_batch_schedule", "mm_batch_destroy", "mm_plan_schedule",
-    "mm_plan_time_passes", "mm_device_copy",
+    "mm_plan_time_passes", "mm_device_copy", "mm_llg_stability",
     "mm_strerror", "mm_last_error",
 ]
 
@@ -87,6 +87,7 @@ def _load():
         "mm_plan_schedule": [vp, ctypes.c_char_p, ctypes.c_size_t],
         "mm_plan_time_passes": [vp, ci, dp],
         "mm_device_copy": [vp, vp, ctypes.c_size_t, vp],
+        "mm_llg_stability": [dp, cd, cd, cd, cd, dp],
     }
     for name, args in sig.items():
         f = getattr(L, name)

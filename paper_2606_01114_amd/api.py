@@ -58,6 +58,32 @@ def _schedule(fn, h):
     return json.loads(buf.value.decode())
 
 
+RK4_IMAG_LIMIT = 2.0 * 2.0 ** 0.5   # classic RK4 is stable on the imaginary axis up to 2 sqrt(2)
+_warned = set()
+
+
+def llg_stability(cell, Ms_min, A, gamma, dt):
+    """omega_max * dt of the exchange term on a grid of this cell size
+    (mm_llg_stability, host only); above RK4_IMAG_LIMIT the step diverges."""
+    c = (ctypes.c_double * 3)(*[float(v) for v in cell])
+    out = ctypes.c_double()
+    check(_lib.lib().mm_llg_stability(c, float(Ms_min), float(A), float(gamma), float(dt), ctypes.byref(out)))
+    return out.value
+
+
+def _stability_warning(cell, Ms, A, gamma, dt):
+    key = (tuple(cell), float(Ms), float(A), float(gamma), float(dt))
+    if key in _warned:
+        return
+    _warned.add(key)
+    w = llg_stability(cell, Ms, A, gamma, dt)
+    if w > RK4_IMAG_LIMIT:
+        import warnings
+        warnings.warn("llg_step: omega_max*dt = %.3g exceeds RK4's stability limit %.3f (cell %s, Ms %g, dt %g): "
+                      "the step will diverge; reduce dt" % (w, RK4_IMAG_LIMIT, tuple(cell), Ms, dt), RuntimeWarning,
+                      stacklevel=3)
+
+
 def plan_bytes(grid, precision="f32", far_radius=16.0, L=None, padding="auto"):
     """(tensor_bytes, workspace_bytes) of a plan for this grid (no GPU call)."""
     opts = _opts(far_radius, L, padding=padding)
@@ -188,6 +214,8 @@ class DemagPlan:
     def llg_step(self, m, Ms, A, alpha, gamma, dt, n_steps=1, h_ext=None, renorm=True, graph=True):
         self._vec(m, "m")
         Mst, Mss = self._ms(Ms)
+        if Mst is None and Mss > 0:
+            _stability_warning(self.cell, Mss, A, gamma, dt)
         self._sync_stream()
         he = (ctypes.c_double * 3)(*[float(v) for v in h_ext]) if h_ext is not None else None
         flags = (0 if renorm else MM_NO_RENORM) | (0 if graph else MM_NO_GRAPH)

@@ -1602,6 +1602,20 @@ static int check_llg(double alpha, double gamma, double dt, const double *hext) 
     return MM_OK;
 }
 
+int mm_llg_stability(const double cell[3], double Ms_min, double A, double gamma, double dt, double *omega_dt) {
+    if (!cell || !omega_dt) return fail(MM_EINVAL, "cell and omega_dt must be non-NULL");
+    for (int a = 0; a < 3; ++a)
+        if (!(cell[a] > 0.0) || !std::isfinite(cell[a])) return fail(MM_EINVAL, "cell[%d] must be finite and > 0", a);
+    if (!(Ms_min > 0.0) || !std::isfinite(Ms_min)) return fail(MM_EINVAL, "Ms_min must be finite and > 0");
+    if (!(A >= 0.0) || !std::isfinite(A)) return fail(MM_EINVAL, "A must be finite and >= 0");
+    if (!(gamma > 0.0) || !std::isfinite(gamma) || !(dt > 0.0) || !std::isfinite(dt))
+        return fail(MM_EINVAL, "gamma and dt must be finite and > 0");
+    double lap = 0.0;
+    for (int a = 0; a < 3; ++a) lap += 4.0 / (cell[a] * cell[a]);
+    *omega_dt = gamma * (2.0 * A / (kMu0 * Ms_min)) * lap * dt;
+    return MM_OK;
+}
+
 int llg_step(mm_plan *p, void *m, const void *Ms, double Ms_scalar, double A, double alpha, double gamma, double dt,
              int n_steps, const double h_ext[3], unsigned flags) {
     int rc = check_plan(p);

@@ -256,3 +256,33 @@ def test_automatic_padding_on_host():
     assert o.pow2_padding == 2
     o.pow2_padding = 3
     assert _bytes((4, 4, 4), F32, ctypes.byref(o))[0] == _lib.MM_EINVAL
+
+
+def test_llg_stability_bound():
+    """The host-side stiffness bound (no GPU): gamma (2A/(mu0 Ms)) sum 4/d^2
+    dt -- 0.99 for the 2.5x2.5x3 nm film at Ms 8e5, 1.97 at Ms 4e5, and a 2 nm
+    cube at Ms 4e5 past RK4's limit -- and its argument checks; the binding
+    warns once for an unstable scalar-Ms configuration."""
+    import math
+    import warnings
+    from paper_2606_01114_amd import RK4_IMAG_LIMIT, llg_stability
+    from paper_2606_01114_amd import api
+    from paper_2606_01114_amd._lib import MM_EINVAL, MMError
+    mu0 = 4e-7 * math.pi
+    d = (2.5e-9, 2.5e-9, 3e-9)
+    for Ms in (8e5, 4e5):
+        w = llg_stability(d, Ms, 1.3e-11, 2.211e5, 1e-13)
+        ref = 2.211e5 * (2 * 1.3e-11 / (mu0 * Ms)) * sum(4 / v ** 2 for v in d) * 1e-13
+        assert abs(w - ref) <= 1e-12 * ref
+    assert llg_stability(d, 8e5, 1.3e-11, 2.211e5, 1e-13) < 1.0 < llg_stability(d, 4e5, 1.3e-11, 2.211e5, 1e-13) < 2.0
+    assert llg_stability((2e-9,) * 3, 4e5, 1.3e-11, 2.211e5, 1e-13) > RK4_IMAG_LIMIT
+    for bad in [((0.0, 1e-9, 1e-9), 8e5, 1e-13), (d, 0.0, 1e-13), (d, 8e5, -1e-13), (d, float("nan"), 1e-13)]:
+        with pytest.raises(MMError) as ei:
+            llg_stability(bad[0], bad[1], 1.3e-11, 2.211e5, bad[2])
+        assert ei.value.code == MM_EINVAL
+    with warnings.catch_warnings(record=True) as rec:
+        warnings.simplefilter("always")
+        api._stability_warning((2e-9,) * 3, 4e5, 1.3e-11, 2.211e5, 1e-13)
+        api._stability_warning((2e-9,) * 3, 4e5, 1.3e-11, 2.211e5, 1e-13)
+        api._stability_warning(d, 8e5, 1.3e-11, 2.211e5, 1e-13)
+    assert len(rec) == 1 and "stability" in str(rec[0].message)
