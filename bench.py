@@ -61,7 +61,7 @@ KERNEL_PATTERNS = {
 KERNEL_SYMBOL = {"z_fwd": "k_zfwd_ct", "x_fwd": "k_line_ct", "y_fused": "k_fused_y_ct", "x_inv": "k_line_ct",
                  "z_inv_stage": "k_zinv_ct", "z_inv_heff": "k_zinv_ct"}
 # y pass variant (mm_plan_info tiles[2]) -> kernel; negative: runtime-planned
-Y_SYMBOL = {0: "k_fused_y_ct", 1: "k_fused_y_hx", 2: "k_fused_y_cr", 3: "k_fused_y_pf"}
+Y_SYMBOL = {0: "k_fused_y_ct", 1: "k_fused_y_hx", 2: "k_fused_y_cr", 3: "k_fused_y_pf", 4: "k_fused_y_pf"}
 
 
 def pass_bytes(grid, L, r):
@@ -184,7 +184,7 @@ def run_gpu(wname, prec, steps, warmup, m_host):
                 tiles=info["tiles"])
 
 
-def run_sweep(steps, warmup, prec="f32"):
+def run_sweep(steps, warmup, prec="f32", padding="pow2"):
     """Aggregate cell-updates/s of the batched sweep (all geometries per graph
     replay) with the autotuned launch groups, the same with the default
     schedule, the groups the tuner chose, and the sweep's algorithmic bytes
@@ -199,14 +199,17 @@ def run_sweep(steps, warmup, prec="f32"):
     dt = torch.float32 if prec == "f32" else torch.float64
     cells = int(sum(np.prod(g) for g in grids))
     # algorithmic bytes: the single-grid pass model of every geometry at its
-    # padded lengths (batches pad each axis to the power of two >= 2n-1)
+    # padded lengths (the power of two >= 2n-1, or the shortest compile-time
+    # length: powers of two and 3*2^k)
     r = 4 if prec == "f32" else 8
-    step_bytes = sum(pass_bytes(g, tuple(_pow2_len(v) for v in g), r)[1] for g in grids)
-    out = {"cells": cells, "geometries": len(grids), "prec": prec, "step_algorithmic_bytes": step_bytes}
+    padlen = _pow2_len if padding == "pow2" else _ct_len
+    step_bytes = sum(pass_bytes(g, tuple(padlen(v, a) for a, v in enumerate(g)), r)[1] for g in grids)
+    out = {"cells": cells, "geometries": len(grids), "prec": prec, "padding": padding,
+           "step_algorithmic_bytes": step_bytes}
     for mode in ("off", "search"):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        b = Batch(grids, [WORKLOADS["sweep"]["cell"]] * len(grids), prec, autotune=mode)
+        b = Batch(grids, [WORKLOADS["sweep"]["cell"]] * len(grids), prec, autotune=mode, padding=padding)
         torch.cuda.synchronize()
         setup = time.perf_counter() - t0
         ms = [torch.tensor(synth.random_unit(g, 100 + k), dtype=dt, device="cuda") for k, g in enumerate(grids)]
@@ -234,7 +237,7 @@ def run_sweep(steps, warmup, prec="f32"):
     return out
 
 
-def _pow2_len(n):
+def _pow2_len(n, axis=0):
     """Smallest power of two >= 2n-1 (1 for one cell): a batch's padding."""
     if n == 1:
         return 1
@@ -242,6 +245,18 @@ def _pow2_len(n):
     while L < 2 * n - 1:
         L *= 2
     return L
+
+
+def _ct_len(n, axis=0):
+    """Shortest length >= 2n-1 with compile-time FP32 kernels (powers of two;
+    3*2^k: x, y 384, 768, 1536, z 768), as the library's padding mode 3."""
+    if n == 1:
+        return 1
+    odd = (384, 768, 1536) if axis < 2 else (768,)
+    lim = 2048 if axis == 2 else 4096
+    c = [L for L in [1 << k for k in range(13)] if L <= lim] + list(odd)
+    ok = [L for L in c if L >= 2 * n - 1]
+    return min(ok) if ok else _pow2_len(n)
 
 
 def run_grad(prec="f32", steps=200, every=20):
@@ -640,6 +655,8 @@ def main():
                     help="skip the film, sweep, gradient and small-grid runs of the default workload")
     ap.add_argument("--fields-n", default="350", help="cube edge of the fields workload (a comma list sweeps sizes)")
     ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
+    ap.add_argument("--padding", default="pow2", choices=["pow2", "ct"],
+                    help="sweep padding: powers of two, or the shortest compile-time lengths (also 3*2^k)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path",
@@ -651,7 +668,7 @@ def main():
         print("bench.py needs an MI355X (no GPU visible)", file=sys.stderr)
         sys.exit(2)
     if args.workload == "sweep":
-        r = run_sweep(args.steps, args.warmup, args.prec)
+        r = run_sweep(args.steps, args.warmup, args.prec, args.padding)
         print(json.dumps({"metric": METRIC, "value": r["Mcell_updates_per_s"], "unit": "Mcell-updates/s",
                           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": r["ms_per_step"],
                           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": args.prec,

@@ -35,7 +35,7 @@
  * Threading: a plan is not thread-safe; distinct plans are independent.
  *
  * Test hooks (environment, read at plan creation; every choice computes the
- * same result): MMX_XVAR=0..3 and MMX_YVAR=0..3 force an x or y pass variant
+ * same result): MMX_XVAR=0..3 and MMX_YVAR=0..4 force an x or y pass variant
  * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
  * pass, MMX_ORDER="x:4,5,5;y:2,3,3,5" sets the radix order of runtime-planned
  * (non-power-of-two) axes, MMX_TEST_FAIL_ALLOC makes every device
@@ -103,12 +103,14 @@ typedef struct mm_plan_opts {
     int pow2_padding;   /* for axes without an explicit L.  0: the 7-smooth
                            length (1 if n == 1, 2n if n is 7-smooth, else
                            the smallest 7-smooth length >= 2n-1); 1: the
-                           smallest power of two >= 2n-1 (compile-time
-                           power-of-two kernels; what mm_batch_create uses);
-                           2 (default): the power of two when it is at most
-                           1.75 times the 7-smooth length and no longer than
-                           the compile-time kernels take (x, y 4096; z and
-                           an FP64 y 2048), else the 7-smooth length. */
+                           smallest power of two >= 2n-1 (what
+                           mm_batch_create uses without opts); 3: the
+                           smallest length >= 2n-1 with compile-time
+                           kernels: powers of two (x, y up to 4096; z and an
+                           FP64 y up to 2048) and 3 * 2^k (x, y: 384, 768,
+                           1536; z: 768); 2 (default): that length when it
+                           is at most 1.75 times the 7-smooth length, else
+                           the 7-smooth length (runtime-planned kernels). */
 } mm_plan_opts;
 
 int mm_plan_opts_default(mm_plan_opts *opts);
@@ -257,8 +259,9 @@ int mm_plan_set_stt(mm_plan *plan, double j, double P, double lambda, double eps
  * y variants (power-of-two y lengths) 0 the LDS-resident pencil per
  * workgroup, 1 the register-resident pencil with half-line exchanges, 2 the
  * LDS-resident pencil with the waves' butterflies rotated per workgroup, 3
- * the persistent kernel with the next pencil's loads in flight; -W: the
- * runtime-planned kernel with W pencils per tile. */
+ * the persistent kernel with the next pencil's loads in flight, 4 the same
+ * held to three waves per SIMD; -W: the runtime-planned kernel with W
+ * pencils per tile. */
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 
 /*

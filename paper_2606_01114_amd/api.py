@@ -25,7 +25,7 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else None
 
 
-_PADDING = {"auto": 2, "smooth": 0, "pow2": 1}
+_PADDING = {"auto": 2, "smooth": 0, "pow2": 1, "ct": 3}
 
 
 def _opts(far_radius=16.0, L=None, autotune=False, padding="auto"):
@@ -339,7 +339,11 @@ class Batch:
     """Many independent geometries advanced by grouped launches (one HIP graph
     per step of all of them)."""
 
-    def __init__(self, grids, cells, precision="f32", far_radius=16.0, pow2_padding=True, autotune=False):
+    def __init__(self, grids, cells, precision="f32", far_radius=16.0, pow2_padding=True, autotune=False,
+                 padding=None):
+        """padding: "pow2" (the default, as pow2_padding=True), "smooth" (as
+        pow2_padding=False), "ct" (shortest length with compile-time
+        kernels: powers of two and 3*2^k) or "auto"."""
         self.grids = [tuple(int(v) for v in g) for g in grids]
         self.cells = [tuple(float(v) for v in c) for c in cells]
         self.prec = _prec(precision)
@@ -350,7 +354,7 @@ class Batch:
         opts = PlanOpts()
         check(_lib.lib().mm_plan_opts_default(ctypes.byref(opts)))
         opts.far_radius = float(far_radius)
-        opts.pow2_padding = 1 if pow2_padding else 0
+        opts.pow2_padding = _PADDING[padding] if padding is not None else (1 if pow2_padding else 0)
         opts.autotune = _tune_mode(autotune)
         self._h = ctypes.c_void_p()
         check(_lib.lib().mm_batch_create(ctypes.byref(self._h), n, G, C, self.prec, _stream(), ctypes.byref(opts)))

@@ -384,24 +384,34 @@ __device__ void lds_fft(cplx<T> *buf, int nlines, int pitch, const FftDesc &f, c
 }
 
 
-// ---- compile-time plans for power-of-two lengths ---------------------------
-// Same factorisation as the host planner: radix-16 stages with an 8/4/2 tail
-// (an exponent = 1 mod 4 ends in 8, 4 rather than 16, 2).
+// ---- compile-time plans ------------------------------------------------------
+// Lengths 2^k, or 2^k q with one odd radix q in {3, 5, 7} as the last
+// stage.  Same factorisation as the host planner: the power of two as
+// radix-16 stages with an 8/4/2 tail (an exponent = 1 mod 4 ends in 8, 4
+// rather than 16, 2), then q.  The first stage is then always even, so a
+// line whose upper half is zero skips half of its loads.
 namespace ct {
 constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
-constexpr int nst(int L) {
+constexpr int odd_part(int L) { return (L >= 2 && L % 2 == 0) ? odd_part(L / 2) : L; }
+constexpr int pow2_part(int L) { return L / odd_part(L); }
+constexpr int nst2(int L) {
     const int p = ilog2(L), a = p / 4, rem = p % 4;
     return p == 0 ? 0 : p == 1 ? 1 : (rem == 1 && a >= 1) ? a + 1 : a + (rem ? 1 : 0);
 }
-constexpr int rad(int L, int s) {
+constexpr int rad2(int L, int s) {
     const int p = ilog2(L), a = p / 4, rem = p % 4;
     return p == 1 ? 2
            : (rem == 1 && a >= 1) ? (s < a - 1 ? 16 : (s == a - 1 ? 8 : 4))
                                   : (s < a ? 16 : (rem == 3 ? 8 : rem == 2 ? 4 : 2));
 }
+constexpr int nst(int L) { return nst2(pow2_part(L)) + (odd_part(L) > 1 ? 1 : 0); }
+constexpr int rad(int L, int s) { return s < nst2(pow2_part(L)) ? rad2(pow2_part(L), s) : odd_part(L); }
 constexpr int ns_before(int L, int s) { return s == 0 ? 1 : ns_before(L, s - 1) * rad(L, s - 1); }
 constexpr int twoff(int L, int s) { return s == 0 ? 0 : twoff(L, s - 1) + ns_before(L, s - 1) * (rad(L, s - 1) - 1); }
 constexpr bool is_pow2(int L) { return L >= 1 && (L & (L - 1)) == 0; }
+constexpr bool is_ct_len(int L) {
+    return L >= 1 && (odd_part(L) == 1 || odd_part(L) == 3 || odd_part(L) == 5 || odd_part(L) == 7);
+}
 }  // namespace ct
 
 // One Stockham stage with every size known at compile time.  NLMAX lines at

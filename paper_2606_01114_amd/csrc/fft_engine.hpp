@@ -14,11 +14,17 @@ namespace ct {
 constexpr int prad(int L, bool rev, int s) { return rev ? rad(L, nst(L) - 1 - s) : rad(L, s); }
 constexpr int pns(int L, bool rev, int s) { return s == 0 ? 1 : pns(L, rev, s - 1) * prad(L, rev, s - 1); }
 constexpr int ptw(int L, bool rev, int s) { return s == 0 ? 0 : ptw(L, rev, s - 1) + pns(L, rev, s - 1) * (prad(L, rev, s - 1) - 1); }
-// Within a line, position p is stored at p + p/16 (lines of 32 or more):
-// the radix-R scatter of the early Stockham stages then spreads over the
-// LDS banks instead of hitting every 16th word.
-constexpr int swz(int L, int p) { return L >= 32 ? p + (p >> 4) : p; }
-constexpr int line_len(int L) { return L >= 32 ? L + L / 16 : L; }
+// Within a line, position p is stored at p + p/16: the radix-R scatter of
+// the early Stockham stages then spreads over the LDS banks instead of
+// hitting every 16th word.  Power-of-two lines of 32 or more use it; a line
+// with an odd radix uses it when every stage's read stride L/R is a multiple
+// of 16 (so that the offset form below holds), else it is stored plainly.
+constexpr bool swz_strides(int L, int s) {
+    return s >= nst(L) ? true : ((L / rad(L, s)) % 16 == 0 && swz_strides(L, s + 1));
+}
+constexpr bool swz_ok(int L) { return L >= 32 && (is_pow2(L) || swz_strides(L, 0)); }
+constexpr int swz(int L, int p) { return swz_ok(L) ? p + (p >> 4) : p; }
+constexpr int line_len(int L) { return swz_ok(L) ? L + L / 16 : L; }
 // LDS pitch of a line of csz-byte values: the swizzled length plus a shift
 // that spreads the NL interleaved lines over the banks.  LDS serves 128 bytes
 // (32 four-byte banks) per cycle, i.e. 16 lanes of a 64-bit access or 8 lanes
@@ -34,14 +40,21 @@ constexpr int lds_pitch(int L, int NL, int csz) {
 }
 }  // namespace ct
 
-template <int L> __device__ __forceinline__ int sw(int p) { return L >= 32 ? p + (p >> 4) : p; }
+template <int L> __device__ __forceinline__ int sw(int p) { return ct::swz_ok(L) ? p + (p >> 4) : p; }
 
 // Offset form of the swizzle: sw(a + b) = sw(a) + swc(b) whenever
 // (a mod 16) + (b mod 16) < 16.  Every access of a power-of-two Stockham stage
 // has that form (a = j or the butterfly's output base, b = a multiple of the
 // stride that stays within the 16-block), so per-element addresses become
 // compile-time offsets from one per-butterfly base.
-template <int L> __device__ __forceinline__ constexpr int swc(int b) { return L >= 32 ? b + (b >> 4) : b; }
+template <int L> __device__ __forceinline__ constexpr int swc(int b) { return ct::swz_ok(L) ? b + (b >> 4) : b; }
+
+// LDS slot of position base + r, r < R, of a radix-R output block starting at
+// base (a multiple of R): the offset form for R a power of two up to 16, the
+// whole swizzle otherwise (a block of odd length can straddle a 16-block)
+template <int L, int R> __device__ __forceinline__ int swb(int base, int r) {
+    return (R & (R - 1)) == 0 ? sw<L>(base) + swc<L>(r) : sw<L>(base + r);
+}
 
 // One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
 // 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
@@ -62,8 +75,10 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
     constexpr int U = (TOT + NT - 1) / NT;
     constexpr int TWO = ct::ptw(L, REV, S);
     constexpr int RI = PR == 1 ? R / 2 : R;   // inputs read
-    constexpr int RO = PR == 2 ? R / 2 : R;   // outputs written
-    static_assert(PR != 1 || Ns == 1, "a zero upper half applies to a first stage");
+    // outputs written: an odd last radix computes and hands over all of its
+    // outputs (the storer's range check drops rows past the kept half)
+    constexpr int RO = (PR == 2 && R % 2 == 0) ? R / 2 : R;
+    static_assert(PR != 1 || (Ns == 1 && R % 2 == 0), "a zero upper half applies to an even first stage");
     static_assert(PR != 2 || Ns * R == L, "a half output applies to a last stage");
     const C *t = tw + TWO;
     C v[U][R];
@@ -88,6 +103,11 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
         }
     }
     if (IN && OUT) __syncthreads();
+    // the offset form of the swizzle holds for the output block d + r Ns when
+    // Ns is a multiple of 16 or a power of two with a power-of-two radix;
+    // otherwise (the stage after an odd radix in reversed order) each slot
+    // is swizzled whole
+    constexpr bool WOFF = (Ns % 16 == 0) || (ct::is_pow2(Ns) && ct::is_pow2(R));
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int b = tid + u * NT;
@@ -97,7 +117,7 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
             const int sd = line * P + sw<L>(d);
 #pragma unroll
             for (int r = 0; r < RO; ++r) {
-                if (OUT) lds[sd + swc<L>(r * Ns)] = v[u][r];
+                if (OUT) lds[WOFF ? sd + swc<L>(r * Ns) : line * P + sw<L>(d + r * Ns)] = v[u][r];
                 else st(line, d + r * Ns, v[u][r]);
             }
         }

@@ -68,21 +68,39 @@ int64_t default_L(int64_t n) {
     return L;
 }
 
-// Automatic padding of one axis: the power of two when it is at most 1.75
-// times the 7-smooth length and within the compile-time kernels' lengths
-// (x and y up to 4096, an FP64 y pencil and z up to 2048), else the 7-smooth
-// length.  The compile-time kernels move the extra padded bytes faster than
-// the runtime-planned mixed-radix kernels move the smaller problem (FP64
-// demag of an N^3 cube: N = 350, 1024^3 16.0 ms against 700^3 26.3 ms;
-// N = 160, 512^3 1.69 ms against 320^3 2.22 ms; but N = 260, 1024^3 12.6 ms
-// against 525^3 11.0 ms).
-int64_t auto_L(int64_t n, int axis, int precision) {
-    const int64_t s = default_L(n), q = pow2_L(n);
+// Lengths an axis has compile-time kernels for: powers of two (x and y up to
+// 4096, an FP64 y pencil and z up to 2048) and 3 * 2^k (x and y: 384, 768,
+// 1536; z: 768).
+bool ct_len_ok(int64_t L, int axis, int precision) {
     const int64_t lim = axis == 2 ? 2048 : (axis == 1 && precision == MM_F64 ? 2048 : 4096);
-    return (q <= lim && 4 * q <= 7 * s) ? q : s;
+    if ((L & (L - 1)) == 0) return L <= lim;
+    return axis == 2 ? L == 768 : (L == 384 || L == 768 || L == 1536);
 }
 
-// radices for a 7-smooth length (power-of-two part as 16s with an 8/4/2 tail)
+// the smallest compile-time length >= 2n-1 (a power of two past the table)
+int64_t ct_L(int64_t n, int axis, int precision) {
+    if (n == 1) return 1;
+    int64_t best = 0;
+    for (int64_t q = 1; q <= 4096; q <<= 1)
+        for (int64_t m : {1, 3}) {
+            const int64_t L = q * m;
+            if (L >= 2 * n - 1 && ct_len_ok(L, axis, precision) && (!best || L < best)) best = L;
+        }
+    return best ? best : pow2_L(n);
+}
+
+// Automatic padding of one axis: the shortest compile-time length when it is
+// at most 1.75 times the 7-smooth length, else the 7-smooth length.  The
+// compile-time kernels move the extra padded bytes faster than the
+// runtime-planned mixed-radix kernels move the smaller problem (FP64 demag of
+// an N^3 cube with powers of two only: N = 350, 1024^3 16.0 ms against 700^3
+// 26.3 ms; N = 160, 512^3 1.69 ms against 320^3 2.22 ms; but N = 260, 1024^3
+// 12.6 ms against 525^3 11.0 ms).
+int64_t auto_L(int64_t n, int axis, int precision) {
+    const int64_t s = default_L(n), q = ct_L(n, axis, precision);
+    return (ct_len_ok(q, axis, precision) && 4 * q <= 7 * s) ? q : s;
+}
+
 std::vector<int> factorize(int L) {
     std::vector<int> r;
     int p2 = 0;
@@ -273,6 +291,11 @@ void free_all(mm_plan *p) {
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
+// blocks of the z-inverse pass (its per-block reduction partials)
+int zinv_tiles(const mm_plan *p) {
+    return p->z_ct ? zinv_ct_tiles(p->zg.nx, p->zg.ny, p->zg.Lz, p->zg.ygrp) : p->zg.tiles;
+}
+
 // Scratch bytes of the entry points that need more than the plan's workspace:
 // [0] llg_step_adjoint, [1] llg_rkf45_step, [2] mm_minimize_bb.
 void scratch_need(int64_t ncell, size_t rsz, int tiles, size_t out[3]) {
@@ -383,9 +406,9 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     (void)app(make_fft(Ly, true));   // reversed radix order, right after y's table (fused inverse)
     const size_t oz = app(p->fz);
     p->tw_off[0] = ox; p->tw_off[1] = oy; p->tw_off[2] = oz;
-    // folded z transform (power-of-two Lz): table of length Lz/2, then exp(-2 pi i k / Lz), k <= Lz/2
+    // folded z transform (compile-time Lz): table of length Lz/2, then exp(-2 pi i k / Lz), k <= Lz/2
     size_t ozh = 0;
-    if (Lz >= 2 && (Lz & (Lz - 1)) == 0) {
+    if (zct_cols(Lz) > 0) {
         ozh = app(make_fft(Lz / 2));
         for (int k = 0; k <= Lz / 2; ++k) {
             const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)k / (long double)Lz;
@@ -478,9 +501,12 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     z.f = p->fz.d; z.tw = twc + oz; z.twh = twc + ozh; z.S1 = p->S1;
     p->lds_z = std::max<size_t>((size_t)((3 * P + 1) / 2) * pz * csz, 16 * 4 * sizeof(double) + 64);
     if (p->z_ct) p->lds_z = std::max(p->lds_z, zct_lds(Lz, csz));
+    // grouped z-inverse tile order for the compile-time kernels (x
+    // neighbours' rows read while still in L2); linear runs for short rows
+    z.ygrp = (p->z_ct && ny >= P) ? (int)std::min<int64_t>(4, (ny + P - 1) / P) : 0;
     if ((size_t)((3 * P + 1) / 2) * pz * csz > kLdsMax) return fail(MM_ENOTSUP, "z length %d too long", Lz);
     // energy partials
-    if ((rc = dalloc(p, (void **)&p->epart, (size_t)z.tiles * 2 * sizeof(double)))) return rc;
+    if ((rc = dalloc(p, (void **)&p->epart, (size_t)std::max(z.tiles, zinv_tiles(p)) * 2 * sizeof(double)))) return rc;
     if (!stencil_shape((int)p->n[0], (int)p->n[1], (int)p->n[2], z.tiles, &p->st_cx, &p->st_nqb, &p->st_blocks))
         p->st_blocks = 0;
     if ((rc = dalloc(p, (void **)&p->esum, 2 * sizeof(double)))) return rc;
@@ -577,7 +603,7 @@ hipError_t launch_y(mm_plan *p) {
 std::vector<int> y_variants(int Ly) {
     std::vector<int> v{0};
     if (fused_hx_threads(Ly) > 0) v.push_back(1);
-    for (int k = 2; k <= 3; ++k)
+    for (int k = 2; k <= 4; ++k)
         if (fused_pf_available(Ly, k)) v.push_back(k);
     return v;
 }
@@ -1010,7 +1036,7 @@ int heff_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, double A, 
     ZInvArgs a;
     fill_common(p, a, terms, Ms, Ms_s, A);
     a.m = m; a.h_out = h; a.epart = E ? p->epart : nullptr;
-    int nblk = p->zg.tiles;
+    int nblk = zinv_tiles(p);
     if (!(terms & MM_DEMAG) && ((terms & MM_EXCHANGE) || p->dmi_kind) && p->st_blocks > 0) {
         // no transform, neighbours needed: the stencil kernel streams m once
         // (local terms alone take the z pass's epilogue, which loads no neighbours)
@@ -1117,7 +1143,7 @@ int llg_adjoint_impl(mm_plan *p, const void *m, const void *Ms, double Ms_s, dou
     const int64_t ncell = p->n[0] * p->n[1] * p->n[2];
     int rc;
     size_t need[3];
-    scratch_need(ncell, sizeof(T), p->zg.tiles, need);
+    scratch_need(ncell, sizeof(T), zinv_tiles(p), need);
     // the caller's fixed region (checked large enough), else the plan's scratch
     void *scr = fixed_scr;
     if (!scr && (rc = get_scratch(p, need[0], &scr))) return rc;
@@ -1178,7 +1204,7 @@ int rkf45_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, doubl
     const size_t f3 = (size_t)p->n[0] * p->n[1] * p->n[2] * 3 * sizeof(T);
     int rc;
     size_t need[3];
-    scratch_need(p->n[0] * p->n[1] * p->n[2], sizeof(T), p->zg.tiles, need);
+    scratch_need(p->n[0] * p->n[1] * p->n[2], sizeof(T), zinv_tiles(p), need);
     void *K = nullptr;
     if ((rc = get_scratch(p, need[1], &K))) return rc;
     void *cand = static_cast<char *>(K) + 6 * f3;
@@ -1206,7 +1232,7 @@ int rkf45_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, doubl
         a.epart = p->epart;
         HIPCK(zinv_any<T>(p, a, EPI_TAB));
     }
-    HIPCK(launch_max_reduce(p->epart, p->zg.tiles, p->esum, p->stream));
+    HIPCK(launch_max_reduce(p->epart, zinv_tiles(p), p->esum, p->stream));
     double e = 0.0;
     HIPCK(hipMemcpyAsync(&e, p->esum, sizeof e, hipMemcpyDeviceToHost, p->stream));
     HIPCK(hipStreamSynchronize(p->stream));
@@ -1223,14 +1249,14 @@ int bb_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, const do
     const size_t f3 = align256((size_t)ncell * 3 * sizeof(T));
     int rc;
     size_t need[3];
-    scratch_need(ncell, sizeof(T), p->zg.tiles, need);
+    scratch_need(ncell, sizeof(T), zinv_tiles(p), need);
     void *scr = nullptr;
     if ((rc = get_scratch(p, need[2], &scr))) return rc;
     char *base = static_cast<char *>(scr);
     T *mprev = reinterpret_cast<T *>(base);
     T *g[2] = {reinterpret_cast<T *>(base + f3), reinterpret_cast<T *>(base + 2 * f3)};
     double *part = reinterpret_cast<double *>(base + 3 * f3);
-    double *tot = reinterpret_cast<double *>(base + 3 * f3 + align256((size_t)p->zg.tiles * 4 * sizeof(double)));
+    double *tot = reinterpret_cast<double *>(base + 3 * f3 + align256((size_t)zinv_tiles(p) * 4 * sizeof(double)));
     double torque = 0.0;
     int k = 0;
     for (;; ++k) {
@@ -1246,7 +1272,7 @@ int bb_impl(mm_plan *p, void *m, const void *Ms, double Ms_s, double A, const do
         a.bb_prev = k >= 1;
         a.bb_part = part;
         HIPCK(zinv_any<T>(p, a, EPI_BB));
-        HIPCK(launch_bb_reduce(part, p->zg.tiles, tot, p->stream));
+        HIPCK(launch_bb_reduce(part, zinv_tiles(p), tot, p->stream));
         double s[4];
         HIPCK(hipMemcpyAsync(s, tot, sizeof s, hipMemcpyDeviceToHost, p->stream));
         HIPCK(hipStreamSynchronize(p->stream));
@@ -1324,11 +1350,12 @@ int plan_params(const int64_t grid[3], const double cell[3], int precision, cons
     mm_plan_opts_default(&o);
     if (opts) o = *opts;
     if (!std::isfinite(o.far_radius)) return fail(MM_EINVAL, "far_radius must be finite");
-    if (o.pow2_padding < 0 || o.pow2_padding > 2) return fail(MM_EINVAL, "pow2_padding must be 0, 1 or 2");
+    if (o.pow2_padding < 0 || o.pow2_padding > 3) return fail(MM_EINVAL, "pow2_padding must be 0, 1, 2 or 3");
     for (int a = 0; a < 3; ++a) {
         L[a] = o.L[a] > 0 ? o.L[a]
                : o.pow2_padding == 1 ? pow2_L(grid[a])
                : o.pow2_padding == 2 ? auto_L(grid[a], a, precision)
+               : o.pow2_padding == 3 ? ct_L(grid[a], a, precision)
                                      : default_L(grid[a]);
         if (L[a] < 2 * grid[a] - 1 || !is_7smooth(L[a]))
             return fail(MM_EINVAL, "L[%d]=%lld must be 7-smooth and >= 2n-1 = %lld", a, (long long)L[a], (long long)(2 * grid[a] - 1));
@@ -1514,7 +1541,7 @@ int mm_plan_scratch_bytes(const int64_t grid[3], int precision, const mm_plan_op
     for (int a = 0; a < 3; ++a) { q.n[a] = grid[a]; q.d[a] = 1.0; q.L[a] = L[a]; }
     rc = precision == MM_F32 ? setup_plan<float>(&q, &o) : setup_plan<double>(&q, &o);
     if (rc) return rc;
-    scratch_need(grid[0] * grid[1] * grid[2], q.rsz, q.zg.tiles, bytes_out);
+    scratch_need(grid[0] * grid[1] * grid[2], q.rsz, zinv_tiles(&q), bytes_out);
     return MM_OK;
 }
 
@@ -1671,7 +1698,7 @@ int llg_step_adjoint_noalloc(mm_plan *p, const void *m, const void *Ms, double M
     if ((rc = check_material(Ms, Ms_scalar, A, MM_DEMAG | MM_EXCHANGE))) return rc;
     if ((rc = check_llg(alpha, gamma, dt, h_ext))) return rc;
     size_t need[3];
-    scratch_need(p->n[0] * p->n[1] * p->n[2], p->rsz, p->zg.tiles, need);
+    scratch_need(p->n[0] * p->n[1] * p->n[2], p->rsz, zinv_tiles(p), need);
     if (need[0] > (size_t)MM_NOALLOC_SCRATCH_BYTES)
         return fail(MM_ENOTSUP, "llg_step_adjoint_noalloc needs %zu bytes of fixed scratch for this grid; the "
                                 "library holds %zu (use llg_step_adjoint)", need[0], (size_t)MM_NOALLOC_SCRATCH_BYTES);
@@ -2141,8 +2168,13 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
     int rc = MM_OK;
     for (int g = 0; g < count && !rc; ++g) {
         mm_plan *p = nullptr;
-        rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &o);
+        mm_plan_opts og = o;
+        og.autotune = 0;   // the batch tunes its grouped launches itself
+        rc = demag_tensor_init(&p, grids[g], cells[g], precision, hip_stream, &og);
         if (!rc) b->plans.push_back(p);
+        // one tile map serves the grouped z-forward and z-inverse launches:
+        // linear z tiles for both
+        if (!rc) p->zg.ygrp = 0;
         // default grouped x launches (the tuner may change them): the
         // half-LDS kernel on wide tiles for lines of 1024 points or more, the
         // narrow full-LDS kernel below; the MMX_XVAR / MMX_YVAR test hooks

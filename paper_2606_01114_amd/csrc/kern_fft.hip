@@ -297,11 +297,10 @@ __device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restr
     for (int u = 0; u < UJ; ++u) {
         const int j = tid + u * NT;
         if (j < NB) {
-            const int sj = sw<L>(j * R);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[c * P + sj + swc<L>(r)] = v[u][c][r];
+                for (int r = 0; r < R; ++r) lds[c * P + swb<L, R>(j * R, r)] = v[u][c][r];
         }
     }
     __syncthreads();
@@ -386,11 +385,10 @@ __device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__r
     for (int u = 0; u < UJ; ++u) {
         const int j = tid + u * NT;
         if (j < NB) {
-            const int sj = sw<L>(j * R);
 #pragma unroll
             for (int c = 0; c < 3; ++c)
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[c * P + sj + swc<L>(r)] = v[u][c][r];
+                for (int r = 0; r < R; ++r) lds[c * P + swb<L, R>(j * R, r)] = v[u][c][r];
         }
     }
     __syncthreads();
@@ -722,8 +720,8 @@ struct PencilInputs {
 // xcd_tile, so each XCD's workgroups (gridDim.x a multiple of 8) walk that
 // XCD's contiguous run of pencils side by side.  EARLY: fetch the pencil's
 // tensor values when the pencil starts (else at the product).
-template <typename T, int L, int NT, bool EARLY>
-__global__ void __launch_bounds__(NT) k_fused_y_pf(const FusedPass a) {
+template <typename T, int L, int NT, bool EARLY, int MINW = 1>
+__global__ void __launch_bounds__(NT, MINW) k_fused_y_pf(const FusedPass a) {
     using C = cplx<T>;
     extern __shared__ __align__(16) unsigned char smem[];
     C *lds = reinterpret_cast<C *>(smem);
@@ -812,12 +810,14 @@ static int line_ct_w(int L, bool f32, int variant) {
     int w;
     switch (L) {
     case 64: case 128: case 256: w = 16; break;
-    case 512: w = f32 ? 16 : 8; break;
-    case 1024: w = f32 ? 8 : 4; break;
-    case 2048: w = f32 ? 4 : 2; break;
+    case 384: case 512: w = f32 ? 16 : 8; break;
+    case 768: case 1024: w = f32 ? 8 : 4; break;
+    case 1536: case 2048: w = f32 ? 4 : 2; break;
     case 4096: w = f32 ? 2 : 1; break;
     default: return 0;
     }
+    // the half-LDS kernels (variants 2, 3) exchange half lines: even radices only
+    if (variant >= 2 && (L & (L - 1))) return 0;
     if (variant == 3) return L >= 1024 ? 4 * w : 0;
     return variant ? 2 * w : w;
 }
@@ -832,11 +832,15 @@ int line_ct_shape(int L, size_t csz, int variant, int *W, int *NT) {
 
 #define LINE_CASE(LL, WW)                                                                                             \
     if (a.f.L == LL && W == WW) {                                                                                     \
-        if (half && ct::nst(LL) >= 2) {                                                                               \
-            const size_t lh = line_hx_lds(LL, WW, sizeof(cplx<T>));                                                   \
-            if (dir < 0) hipLaunchKernelGGL((k_line_hx<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lh, s, a); \
-            else hipLaunchKernelGGL((k_line_hx<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lh, s, a);       \
-        } else if (dir < 0) hipLaunchKernelGGL((k_line_ct<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a); \
+        if constexpr (ct::is_pow2(LL) && ct::nst(LL) >= 2) {                                                          \
+            if (half) {                                                                                               \
+                const size_t lh = line_hx_lds(LL, WW, sizeof(cplx<T>));                                               \
+                if (dir < 0) hipLaunchKernelGGL((k_line_hx<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lh, s, a); \
+                else hipLaunchKernelGGL((k_line_hx<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lh, s, a);       \
+                return hipGetLastError();                                                                             \
+            }                                                                                                         \
+        }                                                                                                             \
+        if (dir < 0) hipLaunchKernelGGL((k_line_ct<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a); \
         else hipLaunchKernelGGL((k_line_ct<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, a);       \
         return hipGetLastError();                                                                                     \
     }
@@ -850,10 +854,12 @@ hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStrea
         LINE_CASE(64, 16) LINE_CASE(64, 32) LINE_CASE(128, 16) LINE_CASE(128, 32) LINE_CASE(256, 16) LINE_CASE(256, 32)
         LINE_CASE(512, 16) LINE_CASE(512, 32) LINE_CASE(1024, 8) LINE_CASE(1024, 16) LINE_CASE(2048, 4) LINE_CASE(2048, 8)
         LINE_CASE(4096, 2) LINE_CASE(4096, 4)
+        LINE_CASE(384, 16) LINE_CASE(384, 32) LINE_CASE(768, 8) LINE_CASE(768, 16) LINE_CASE(1536, 4) LINE_CASE(1536, 8)
     } else {
         LINE_CASE(64, 16) LINE_CASE(64, 32) LINE_CASE(128, 16) LINE_CASE(128, 32) LINE_CASE(256, 16) LINE_CASE(256, 32)
         LINE_CASE(512, 8) LINE_CASE(512, 16) LINE_CASE(1024, 4) LINE_CASE(1024, 8) LINE_CASE(2048, 2) LINE_CASE(2048, 4)
         LINE_CASE(4096, 1) LINE_CASE(4096, 2)
+        LINE_CASE(384, 8) LINE_CASE(384, 16) LINE_CASE(768, 4) LINE_CASE(768, 8) LINE_CASE(1536, 2) LINE_CASE(1536, 4)
     }
     return hipErrorInvalidValue;
 }
@@ -910,8 +916,11 @@ int fused_ct_threads(int L, size_t csz) {
     case 64: return 64;
     case 128: return 64;
     case 256: return 64;
+    case 384: return 128;
     case 512: return 128;
+    case 768: return 256;
     case 1024: return 256;
+    case 1536: return 512;
     case 2048: return csz == 8 ? 256 : 384;
     case 4096: return 768;
     default: return 0;
@@ -931,6 +940,7 @@ hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
     switch (a.f.L) {
         FCASE(64, 64) FCASE(128, 64) FCASE(256, 64) FCASE(512, 128) FCASE(1024, 256)
         FCASE(2048, (sizeof(T) == 4 ? 256 : 384)) FCASE(4096, 768)
+        FCASE(384, 128) FCASE(768, 256) FCASE(1536, 512)
     default: return hipErrorInvalidValue;
     }
 #undef FCASE
@@ -940,20 +950,20 @@ hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
 // Persistent fused pass (k_fused_y_pf): as many workgroups as fit on the
 // device at once (a multiple of 8, so every XCD gets the same number), each
 // walking pencils with the next one's loads in flight.
-template <typename T, int L, int NT, bool EARLY>
+template <typename T, int L, int NT, bool EARLY, int MINW = 1>
 hipError_t launch_fused_pf_k(const FusedPass &a, hipStream_t s) {
     const size_t lds = fused_ct_lds(L, sizeof(cplx<T>));
     int dev = 0, ncu = 0, per_cu = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_fused_y_pf<T, L, NT, EARLY>),
-                                                         NT, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&k_fused_y_pf<T, L, NT, EARLY, MINW>), NT, lds);
     if (e != hipSuccess) return e;
     int G = std::max(1, per_cu) * std::max(1, ncu);
     G = std::max(8, G - G % 8);
     G = std::min(G, a.npos);
-    hipLaunchKernelGGL((k_fused_y_pf<T, L, NT, EARLY>), dim3(G), dim3(NT), lds, s, a);
+    hipLaunchKernelGGL((k_fused_y_pf<T, L, NT, EARLY, MINW>), dim3(G), dim3(NT), lds, s, a);
     return hipGetLastError();
 }
 
@@ -961,8 +971,11 @@ hipError_t launch_fused_pf_k(const FusedPass &a, hipStream_t s) {
 // variant 3: k_fused_y_pf (persistent, next pencil's loads in flight; in
 // FP32 with one radix-16 butterfly per thread, 384 threads for 2048 points,
 // and the tensor fetched at the product, which keeps it under 168 VGPRs)
+// variant 4: the persistent kernel with 256 threads held to three waves per
+// SIMD (2048-point FP32 pencils)
 int fused_pf_available(int L, int var) {
-    if (var == 2) return L >= 256 && L <= 4096 && fused_ct_threads(L, 8) > 64;
+    if (var == 2) return L >= 256 && L <= 4096 && (L & (L - 1)) == 0 && fused_ct_threads(L, 8) > 64;
+    if (var == 4) return L == 2048;
     return var == 3 && (L == 1024 || L == 2048);
 }
 
@@ -983,6 +996,11 @@ hipError_t launch_fused_pf(const FusedPass &a, int var, hipStream_t s) {
         return hipGetLastError();
     }
     constexpr bool F32 = sizeof(T) == 4;
+    if (var == 4) {
+        if (a.f.L != 2048) return hipErrorInvalidValue;
+        if constexpr (F32) return launch_fused_pf_k<T, 2048, 256, false, 3>(a, s);
+        else return launch_fused_pf_k<T, 2048, 384, false>(a, s);
+    }
     switch (a.f.L) {
     case 1024: return launch_fused_pf_k<T, 1024, 256, F32>(a, s);
     case 2048: return launch_fused_pf_k<T, 2048, 384, false>(a, s);
@@ -1023,27 +1041,8 @@ hipError_t launch_fused_hx(const FusedPass &a, hipStream_t s) {
 template hipError_t launch_fused_hx<float>(const FusedPass &, hipStream_t);
 template hipError_t launch_fused_hx<double>(const FusedPass &, hipStream_t);
 
-// grouped launches of the specialised kernels (descriptor table + tile map;
-// every geometry in the group has the same transform length)
-template <typename T>
-hipError_t launch_line_ct_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s) {
-    if (tiles <= 0) return hipSuccess;
-    const size_t lds = line_ct_lds(L, W, sizeof(cplx<T>));
-#define LINE_B(LL, WW)                                                                                                \
-    if (L == LL && W == WW) {                                                                                         \
-        if (dir < 0) hipLaunchKernelGGL((k_line_ct_b<T, LL, -1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, d, map); \
-        else hipLaunchKernelGGL((k_line_ct_b<T, LL, +1, (WW * LL / 16), WW>), dim3(tiles), dim3(WW * LL / 16), lds, s, d, map);       \
-        return hipGetLastError();                                                                                     \
-    }
-    if constexpr (sizeof(T) == 4) {
-        LINE_B(64, 16) LINE_B(128, 16) LINE_B(256, 16) LINE_B(512, 16) LINE_B(1024, 8) LINE_B(2048, 4) LINE_B(4096, 2)
-    } else {
-        LINE_B(64, 16) LINE_B(128, 16) LINE_B(256, 16) LINE_B(512, 8) LINE_B(1024, 4) LINE_B(2048, 2) LINE_B(4096, 1)
-    }
-#undef LINE_B
-    return hipErrorInvalidValue;
-}
-
+// grouped launch of the specialised fused kernel (descriptor table + tile
+// map; every geometry in the group has the same transform length)
 template <typename T>
 hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int L, hipStream_t s) {
     if (tiles <= 0) return hipSuccess;
@@ -1054,6 +1053,7 @@ hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int
         break;
     switch (L) {
         FB(64, 64) FB(128, 64) FB(256, 64) FB(512, 128) FB(1024, 256) FB(2048, (sizeof(T) == 4 ? 256 : 384)) FB(4096, 768)
+        FB(384, 128) FB(768, 256) FB(1536, 512)
     default: return hipErrorInvalidValue;
     }
 #undef FB
@@ -1071,19 +1071,25 @@ hipError_t launch_line_var_b(const LinePass *d, const int2 *map, int tiles, int 
 #define LVB(LL, WW)                                                                                                   \
     if (L == LL && W == WW) {                                                                                         \
         constexpr int NTT = WW * LL / 16;                                                                             \
-        if (var == 2 && ct::nst(LL) >= 2) {                                                                           \
-            if (dir < 0) hipLaunchKernelGGL((k_line_hx_b<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map); \
-            else hipLaunchKernelGGL((k_line_hx_b<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map);       \
-        } else if (dir < 0) hipLaunchKernelGGL((k_line_ct_b<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map); \
+        if constexpr (ct::is_pow2(LL) && ct::nst(LL) >= 2) {                                                          \
+            if (var == 2) {                                                                                           \
+                if (dir < 0) hipLaunchKernelGGL((k_line_hx_b<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map); \
+                else hipLaunchKernelGGL((k_line_hx_b<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map);   \
+                return hipGetLastError();                                                                             \
+            }                                                                                                         \
+        }                                                                                                             \
+        if (dir < 0) hipLaunchKernelGGL((k_line_ct_b<T, LL, -1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map);  \
         else hipLaunchKernelGGL((k_line_ct_b<T, LL, +1, NTT, WW>), dim3(tiles), dim3(NTT), lds, s, d, map);           \
         return hipGetLastError();                                                                                     \
     }
     if constexpr (sizeof(T) == 4) {
         LVB(64, 16) LVB(64, 32) LVB(128, 16) LVB(128, 32) LVB(256, 16) LVB(256, 32) LVB(512, 16) LVB(512, 32)
         LVB(1024, 8) LVB(1024, 16) LVB(2048, 4) LVB(2048, 8) LVB(4096, 2) LVB(4096, 4)
+        LVB(384, 16) LVB(384, 32) LVB(768, 8) LVB(768, 16) LVB(1536, 4) LVB(1536, 8)
     } else {
         LVB(64, 16) LVB(64, 32) LVB(128, 16) LVB(128, 32) LVB(256, 16) LVB(256, 32) LVB(512, 8) LVB(512, 16)
         LVB(1024, 4) LVB(1024, 8) LVB(2048, 2) LVB(2048, 4) LVB(4096, 1) LVB(4096, 2)
+        LVB(384, 8) LVB(384, 16) LVB(768, 4) LVB(768, 8) LVB(1536, 2) LVB(1536, 4)
     }
 #undef LVB
     return hipErrorInvalidValue;
@@ -1128,8 +1134,6 @@ template hipError_t launch_line_var_b<double>(const LinePass *, const int2 *, in
 template hipError_t launch_fused_var_b<float>(const FusedPass *, const int2 *, int, int, int, hipStream_t);
 template hipError_t launch_fused_var_b<double>(const FusedPass *, const int2 *, int, int, int, hipStream_t);
 
-template hipError_t launch_line_ct_b<float>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
-template hipError_t launch_line_ct_b<double>(const LinePass *, const int2 *, int, int, int, int, hipStream_t);
 template hipError_t launch_fused_ct_b<float>(const FusedPass *, const int2 *, int, int, hipStream_t);
 template hipError_t launch_fused_ct_b<double>(const FusedPass *, const int2 *, int, int, hipStream_t);
 template hipError_t launch_line_pass<float>(const LinePass *, const int2 *, int, int, size_t, int, bool, hipStream_t);

@@ -149,6 +149,39 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
     }
 }
 
+// Tiles of the z-inverse pass with the exchange epilogue.  Linear runs of P
+// positions (ygrp = 0), or P positions of one x row with the tiles ordered
+// by groups of ygrp y-blocks, x fastest within a group: the tiles that hold a
+// cell's x neighbours (one x row apart) then run at the same time as it, so
+// the neighbours' m rows come from L2 instead of being fetched again.
+// Returns the tile's first position and width (0 for the padding tiles of a
+// last, incomplete group).
+__host__ __device__ inline int ztile_count(int nx, int ny, int P, int ygrp) {
+    if (ygrp <= 0) return (int)(((int64_t)nx * ny + P - 1) / P);
+    const int ty = (ny + P - 1) / P;
+    return ((ty + ygrp - 1) / ygrp) * nx * ygrp;
+}
+
+__device__ __forceinline__ void ztile(const ZGeom &g, int P, uint32_t blk, int64_t &pos0, int &wp) {
+    const int64_t npos = (int64_t)g.nx * g.ny;
+    if (g.ygrp <= 0) {
+        pos0 = (int64_t)blk * P;
+        wp = (int)min((int64_t)P, npos - pos0);
+        return;
+    }
+    const int ty = (g.ny + P - 1) / P, G = g.ygrp;
+    const uint32_t per = (uint32_t)g.nx * (uint32_t)G;
+    const uint32_t yo = blk / per, rem = blk - yo * per;
+    const int x = (int)(rem / (uint32_t)G), yb = (int)(yo * G + (rem - (uint32_t)x * G));
+    if (yb >= ty) {
+        pos0 = 0;
+        wp = 0;
+        return;
+    }
+    pos0 = (int64_t)x * g.ny + (int64_t)yb * P;
+    wp = min(P, g.ny - yb * P);
+}
+
 template <typename T, int N, int EPI, bool LOC>
 __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     using C = cplx<T>;
@@ -162,11 +195,14 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     const ZGeom &g = a.g;
     const int tid = threadIdx.x;
     const int64_t npos = (int64_t)g.nx * g.ny;
-    const int64_t pos0 = (int64_t)blk * P;
-    const int wp = (int)min((int64_t)P, npos - pos0);
+    int64_t pos0;
+    int wp;
+    ztile(g, P, blk, pos0, wp);
     const int w3 = 3 * wp;
     const int nz = g.nz, ny = g.ny;
-    const bool demag = (a.terms & 1u) != 0;
+    // a padding tile (wp = 0) loads and stores nothing but still takes part
+    // in the block reductions below
+    const bool demag = (a.terms & 1u) != 0 && wp > 0;
     const C *tw = reinterpret_cast<const C *>(g.twh);
     const C *wt = tw + (N > 1 ? N - 1 : 0);
     if (demag) {
@@ -235,7 +271,7 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     if (EPI == EPI_HEFF && a.epart) block_energy(acc.v[0], acc.v[1], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_TAB && a.tab_last) block_max(acc.v[0], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_BB) block_bb(acc, reinterpret_cast<double *>(smem), a.bb_part + 4 * (int64_t)blk, tid);
-    if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c) {
+    if ((EPI == EPI_STAGE || EPI == EPI_TAB) && a.next_r2c && wp > 0) {
         // 3. the next stage's source, already folded in LDS: clear the slots
         //    between the last cell and the transform's input half, then
         //    transform forward
@@ -281,7 +317,7 @@ __global__ void __launch_bounds__(zthreads(N)) k_zinv_ct_b(const ZInvArgs *__res
 
 // ---------------- launchers -------------------------------------------------
 int zct_cols(int Lz) {
-    if (Lz < 2 || Lz > 2048 || (Lz & (Lz - 1))) return 0;
+    if (Lz < 2 || Lz > 2048 || ((Lz & (Lz - 1)) && Lz != 768)) return 0;
     return zcols(Lz / 2);
 }
 
@@ -291,7 +327,7 @@ size_t zct_lds(int Lz, size_t csz) {
 }
 
 #define ZN_CASES(M)                                                                                                   \
-    M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(512) M(1024)
+    M(1) M(2) M(4) M(8) M(16) M(32) M(64) M(128) M(256) M(384) M(512) M(1024)
 
 template <typename T>
 hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s) {
@@ -311,10 +347,12 @@ hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s) {
     return hipGetLastError();
 }
 
+int zinv_ct_tiles(int nx, int ny, int Lz, int ygrp) { return ztile_count(nx, ny, zcols(Lz / 2), ygrp); }
+
 template <typename T>
 hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s) {
     const int N = a.g.Lz / 2;
-    const int tiles = (int)(((int64_t)a.g.nx * a.g.ny + zcols(N) - 1) / zcols(N));
+    const int tiles = ztile_count(a.g.nx, a.g.ny, zcols(N), a.g.ygrp);
     const size_t lds = zct_lds(a.g.Lz, sizeof(cplx<T>));
     const bool loc = a.dmi_kind != 0 || a.ku_pref != 0.0 || a.stt_pref != 0.0;
 #define ZL(NN, E, L) hipLaunchKernelGGL((k_zinv_ct<T, NN, E, L>), dim3(tiles), dim3(zthreads(NN)), lds, s, a)

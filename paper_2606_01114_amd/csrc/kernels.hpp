@@ -44,11 +44,11 @@ hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s)
 // compile-time z passes (power-of-two Lz in [2, 2048]); zct_cols returns the
 // cell columns per tile (0 if no specialisation), zct_lds the LDS bytes
 int zct_cols(int Lz);
+// tiles of the compile-time z-inverse pass (ZGeom::ygrp order)
+int zinv_ct_tiles(int nx, int ny, int Lz, int ygrp);
 size_t zct_lds(int Lz, size_t csz);
 template <typename T> hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s);
 template <typename T> hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s);
-template <typename T>
-hipError_t launch_line_ct_b(const LinePass *d, const int2 *map, int tiles, int L, int W, int dir, hipStream_t s);
 template <typename T> hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int L, hipStream_t s);
 // grouped launches in any variant (x: 0..3 as mm_plan_info; y: 0..2)
 template <typename T>

@@ -42,8 +42,11 @@ struct FusedPass {
 // Field constants for the z passes and the fused epilogue.
 struct ZGeom {
     int nx, ny, nz, Lz, hz;
-    int P, tiles, pitch, nthr; // positions (x,y columns) per tile, ...
-    int pad_;
+    int P, tiles, pitch, nthr; // positions (x,y columns) per tile, linear tiles, ...
+    // z-inverse tiles of the compile-time kernels: 0 = linear runs of P
+    // positions; > 0 = P positions of one x row, ordered in groups of ygrp
+    // y-blocks with x fastest within a group (see ztile)
+    int ygrp;
     FftDesc f;                 // length Lz
     const void *tw;
     const void *twh;           // power-of-two Lz: table of length Lz/2, then exp(-2 pi i k/Lz), k <= Lz/2

@@ -225,9 +225,10 @@ def test_set_stt_rejects_bad_arguments_on_host():
 
 
 def test_automatic_padding_on_host():
-    """The default padding takes the power of two when it is at most 1.75
-    times the 7-smooth length and within the compile-time kernels' lengths
-    (x, y 4096; z and an FP64 y 2048); 0 keeps the 7-smooth lengths."""
+    """The default padding takes the shortest compile-time length (powers of
+    two: x, y 4096, z and an FP64 y 2048; 3*2^k: x, y 384, 768, 1536, z 768)
+    when it is at most 1.75 times the 7-smooth length; 0 keeps the 7-smooth
+    lengths, 1 powers of two, 3 the compile-time lengths unconditionally."""
     from paper_2606_01114_amd import _lib
 
     def tensor_L(grid, prec, pad=None):
@@ -245,16 +246,22 @@ def test_automatic_padding_on_host():
         return (L[0] // 2 + 1) * (L[1] // 2 + 1) * (L[2] // 2 + 1) * 6 * r
 
     F32, F64 = _lib.MM_F32, _lib.MM_F64
-    assert tensor_L((350, 350, 350), F64) == octant((1024, 1024, 1024), 8)
+    assert tensor_L((350, 350, 350), F64) == octant((768, 768, 768), 8)
     assert tensor_L((350, 350, 350), F64, 0) == octant((700, 700, 700), 8)
-    assert tensor_L((300, 6, 2), F32) == octant((1024, 16, 4), 4)
-    assert tensor_L((260, 6, 2), F32) == octant((525, 16, 4), 4)
+    assert tensor_L((350, 350, 350), F64, 1) == octant((1024, 1024, 1024), 8)
+    assert tensor_L((300, 6, 2), F32) == octant((768, 16, 4), 4)
+    assert tensor_L((260, 6, 2), F32) == octant((768, 16, 4), 4)
+    assert tensor_L((150, 180, 3), F32) == octant((384, 384, 8), 4)
+    assert tensor_L((700, 5, 400), F32) == octant((1536, 16, 1024), 4)
     assert tensor_L((4, 1500, 1100), F32) == octant((8, 4096, 2205), 4)
     assert tensor_L((4, 1500, 3), F64) == octant((8, 3000, 8), 8)
+    assert tensor_L((4, 1100, 3), F32, 3) == octant((8, 4096, 8), 4)
+    assert tensor_L((4, 4, 700), F32, 3) == octant((8, 8, 2048), 4)
+    assert tensor_L((4, 4, 1500), F32, 3) == octant((8, 8, 4096), 4)   # past the compile-time z lengths
     o = _lib.PlanOpts()
     _lib.lib().mm_plan_opts_default(ctypes.byref(o))
     assert o.pow2_padding == 2
-    o.pow2_padding = 3
+    o.pow2_padding = 4
     assert _bytes((4, 4, 4), F32, ctypes.byref(o))[0] == _lib.MM_EINVAL
 
 

@@ -327,12 +327,13 @@ def test_x_pass_variants_against_oracle():
     """Every variant of the specialised x pass, selected with MMX_XVAR at plan
     creation: two tile widths (0, 1), the half-LDS kernel (2) and the
     half-LDS kernel on tiles twice as wide (3, lines of 1024 and 2048
-    points), with ragged last tiles, FP32 and FP64, against the oracle's
-    h_eff."""
+    points), with ragged last tiles, and both tile widths of the 768-point
+    line with a radix-3 stage, FP32 and FP64, against the oracle's h_eff."""
     import os
     import torch
     from paper_2606_01114_amd import DemagPlan
     cases = [((64, 500, 16), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-9))),
+             ((300, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 0, 1e-9), ("f64", 1, 1e-9))),
              ((400, 40, 3), (("f32", 3, 1e-5), ("f64", 3, 1e-9), ("f32", 2, 1e-5))),
              ((1024, 8, 2), (("f32", 3, 1e-5), ("f64", 3, 1e-9)))]
     old = os.environ.get("MMX_XVAR")
@@ -363,16 +364,20 @@ def test_x_pass_variants_against_oracle():
             os.environ["MMX_XVAR"] = old
 
 
-@pytest.mark.parametrize("n", [(2048, 6, 2), (6, 2048, 2), (3, 4, 1024), (1000, 5, 3)])
-def test_longest_specialised_lengths(n):
+@pytest.mark.parametrize("n,Lset", [((2048, 6, 2), None), ((6, 2048, 2), None), ((3, 4, 1024), None),
+                                    ((1000, 5, 3), None), ((700, 5, 3), (1536, 16, 8)), ((6, 350, 2), (16, 768, 4)),
+                                    ((4, 3, 350), (8, 8, 768)), ((150, 180, 3), (384, 384, 8))])
+def test_longest_specialised_lengths(n, Lset):
     """The longest compile-time transforms (x and y length 4096, z length
     2048: x tiles of one or two columns, the 768-thread fused y pencil, the
-    1024-point folded z line) and a long non-power-of-two x line (runtime
-    planned), FP32 and FP64, h_eff and one RK4 step against the oracle."""
+    1024-point folded z line), the compile-time lengths with a radix-3 stage
+    (x 1536, y 768, z 768 folded to 384, x and y 384) and a long
+    non-power-of-two x line (runtime planned), FP32 and FP64, h_eff and one
+    RK4 step against the oracle."""
     import torch
     from paper_2606_01114_amd import DemagPlan
     oct_ = oracle.tensor_octant(n, D)
-    L = tuple(oracle.default_L(v) for v in n)
+    L = tuple(Lset) if Lset else tuple(oracle.default_L(v) for v in n)
     m0 = synth.random_unit(n, 23)
     Ms = synth.ms_field(n, 24)
     _say("long lengths", n, L)
@@ -384,11 +389,17 @@ def test_longest_specialised_lengths(n):
             # a 4096-long FP64 pencil of three components exceeds the LDS
             from paper_2606_01114_amd._lib import MM_ENOTSUP, MMError
             with pytest.raises(MMError) as ei:
-                DemagPlan(n, D, prec, padding="smooth")
+                DemagPlan(n, D, prec, padding="smooth", L=Lset)
             assert ei.value.code == MM_ENOTSUP
             continue
-        plan = DemagPlan(n, D, prec, padding="smooth")
+        plan = DemagPlan(n, D, prec, padding="smooth", L=Lset)
         assert tuple(plan.info()["L"]) == L
+        if Lset:
+            # the lengths with a radix-3 stage run the compile-time kernels
+            sch = plan.schedule()
+            for key, Lv in (("x_fwd", L[0]), ("y_fused", L[1]), ("z", L[2])):
+                if Lv % 3 == 0:
+                    assert sch[key]["specialised"], (key, sch)
         mr = rounded(m0, dt)
         Msr = to_dev(rounded(Ms, dt), dt)
         h = plan.h_eff(to_dev(mr, dt), Msr, A)
@@ -408,7 +419,8 @@ def test_y_pass_variants_against_oracle(n):
     """Every specialised y pass, selected with MMX_YVAR at plan creation: the
     LDS-resident pencil (0), the register-resident one with half-line
     exchanges (1), the LDS-resident pencil with rotated waves (2) and the
-    persistent kernel with the next pencil's loads in flight (3), for every
+    persistent kernel with the next pencil's loads in flight (3; 4: held to
+    three waves per SIMD), for every
     length each has (a variant a length lacks leaves the default in place),
     FP32 and FP64, against the oracle's h_eff; the persistent kernel's
     grid walks more pencils than it has workgroups."""
@@ -421,14 +433,14 @@ def test_y_pass_variants_against_oracle(n):
     ref = oracle.h_eff(m0, MS, A, D, oct_, L)
     old = os.environ.get("MMX_YVAR")
     try:
-        for var in (0, 1, 2, 3):
+        for var in (0, 1, 2, 3, 4):
             os.environ["MMX_YVAR"] = str(var)
             for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
                 dt = torch.float32 if prec == "f32" else torch.float64
                 plan = DemagPlan(n, D, prec)
                 Ly = plan.info()["L"][1]
                 has = {0: Ly & (Ly - 1) == 0, 1: Ly in (256, 512, 1024, 2048), 2: Ly in (512, 1024, 2048, 4096),
-                       3: Ly in (1024, 2048)}[var]
+                       3: Ly in (1024, 2048), 4: Ly == 2048}[var]
                 yv = plan.info()["tiles"][2]
                 assert yv == (var if has else 0), (var, Ly, yv)
                 h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
