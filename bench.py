@@ -53,7 +53,7 @@ PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
 KERNEL_PATTERNS = {
     "z_fwd": [r"k_zfwd_ct<float", r"k_zfwd<float"],
     "x_fwd": [r"k_line_(ct|hx)<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
-    "y_fused": [r"k_fused_y_(ct|hx)<float", r"k_fused_y<float"],
+    "y_fused": [r"k_fused_y_(ct|cr|hx|pf)<float", r"k_fused_y<float"],
     "x_inv": [r"k_line_(ct|hx)<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
     "z_inv_stage": [r"k_zinv_ct<float, \d+, 1,", r"k_zinv<float, 1>"],
     "z_inv_heff": [r"k_zinv_ct<float, \d+, 0,", r"k_zinv<float, 0>"],
@@ -184,7 +184,7 @@ def run_gpu(wname, prec, steps, warmup, m_host):
                 tiles=info["tiles"])
 
 
-def run_sweep(steps, warmup, prec="f32", padding="pow2"):
+def run_sweep(steps, warmup, prec="f32", padding="ct"):
     """Aggregate cell-updates/s of the batched sweep (all geometries per graph
     replay) with the autotuned launch groups, the same with the default
     schedule, the groups the tuner chose, and the sweep's algorithmic bytes
@@ -296,11 +296,12 @@ PAPER_FIELD_MS = {
 }
 
 
-def run_fields(prec, N, steps, warmup, paddings=("smooth", "pow2")):
+def run_fields(prec, N, steps, warmup, paddings=("smooth", "pow2", "auto")):
     """Per-field evaluation time on an N x N x N cube as the paper times its
     field terms (each term alone, FP64 by default): demag, exchange and the
-    Slonczewski spin-transfer torque, for the 7-smooth padding 2N and the
-    power-of-two padding (or the given paddings)."""
+    Slonczewski spin-transfer torque, for the 7-smooth padding 2N (runtime
+    planned), the power-of-two padding and the default padding (the
+    shortest compile-time length, 3*2^k included), or the given paddings."""
     import numpy as np
     import torch
     import synth
@@ -655,8 +656,9 @@ def main():
                     help="skip the film, sweep, gradient and small-grid runs of the default workload")
     ap.add_argument("--fields-n", default="350", help="cube edge of the fields workload (a comma list sweeps sizes)")
     ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
-    ap.add_argument("--padding", default="pow2", choices=["pow2", "ct"],
-                    help="sweep padding: powers of two, or the shortest compile-time lengths (also 3*2^k)")
+    ap.add_argument("--padding", default="ct", choices=["pow2", "ct"],
+                    help="sweep padding: the shortest compile-time lengths (powers of two and 3*2^k), or powers "
+                         "of two only")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: the library has no multi-GPU path",
