@@ -56,6 +56,17 @@ template <int L, int R> __device__ __forceinline__ int swb(int base, int r) {
     return (R & (R - 1)) == 0 ? sw<L>(base) + swc<L>(r) : sw<L>(base + r);
 }
 
+// Twiddle exp(-2 pi i k r / (Ns R)) of a stage in table form TM (see
+// eng_stage_la); tt = the stage-ordered table at butterfly class k.
+template <int L, int Ns, int R, int TM, class C>
+__device__ __forceinline__ C stage_tw(const C *__restrict__ tw, const C *__restrict__ tt, int k, int r) {
+    if constexpr (TM == 1) {
+        return tw[k * (r * (L / (Ns * R)))];
+    } else {
+        return tt[r - 1];
+    }
+}
+
 // One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
 // 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
 // line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB: groups of LA lines
@@ -63,9 +74,12 @@ template <int L, int R> __device__ __forceinline__ int swb(int base, int r) {
 // column).  P = LDS pitch of a line.  PR = 1: the line's upper half
 // (positions >= L/2, i.e. inputs r >= R/2 of a first stage) is zero and not
 // loaded; PR = 2: only the lower half of the output is stored (outputs
-// r < R/2 of a last stage).
+// r < R/2 of a last stage).  TM = 0: tw is the stage-ordered twiddle table
+// (tw + TWO + k (R-1) + r-1 holds exp(-2 pi i k r / (Ns R))); TM = 1: tw is a
+// table of the L roots exp(-2 pi i m / L) (in LDS), entry k r L / (Ns R), the
+// same for both radix orders.
 template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int LA, int P, int PR = 0,
-          class Ld, class St>
+          int TM = 0, class Ld, class St>
 __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
     using C = cplx<T>;
     constexpr int R = ct::prad(L, REV, S);
@@ -91,10 +105,11 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
 #pragma unroll
             for (int r = 0; r < RI; ++r) v[u][r] = IN ? lds[sj + swc<L>(r * NB)] : ld(line, j + r * NB);
             if (Ns > 1) {
-                const C *tt = t + (j % Ns) * (R - 1);
+                const int k = j % Ns;
+                const C *tt = t + k * (R - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
-                    C w = tt[r - 1];
+                    C w = stage_tw<L, Ns, R, TM>(tw, tt, k, r);
                     if (DIR > 0) w = cconj(w);
                     v[u][r] = cmul(v[u][r], w);
                 }
@@ -286,9 +301,10 @@ __device__ __forceinline__ void eng_fft_hx(cplx<T> *lds, const cplx<T> *__restri
     }
 }
 
-template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int PR = 0, class Ld, class St>
+template <typename T, int L, bool REV, int S, int DIR, int NT, int NL, int IN, int OUT, int PR = 0, int TM = 0,
+          class Ld, class St>
 __device__ __forceinline__ void eng_stage(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid, const Ld &ld, const St &st) {
-    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL, (int)sizeof(cplx<T>)), PR>(lds, tw, tid, ld, st);
+    eng_stage_la<T, L, REV, S, DIR, NT, NL, IN, OUT, NL, ct::lds_pitch(L, NL, (int)sizeof(cplx<T>)), PR, TM>(lds, tw, tid, ld, st);
 }
 
 // stages [S, E) LDS -> LDS with interleave LA and pitch P
@@ -332,14 +348,14 @@ __device__ __forceinline__ void eng_fft_la(cplx<T> *lds, const cplx<T> *__restri
     }
 }
 
-// stages [S, E) all LDS -> LDS
-template <typename T, int L, bool REV, int S, int E, int DIR, int NT, int NL>
+// stages [S, E) all LDS -> LDS (TM as for eng_stage_la)
+template <typename T, int L, bool REV, int S, int E, int DIR, int NT, int NL, int TM = 0>
 __device__ __forceinline__ void eng_mid(cplx<T> *lds, const cplx<T> *__restrict__ tw, int tid) {
     if constexpr (S < E) {
         auto nold = [](int, int) { return cplx<T>(); };
         auto nost = [](int, int, cplx<T>) {};
-        eng_stage<T, L, REV, S, DIR, NT, NL, 1, 1>(lds, tw, tid, nold, nost);
-        eng_mid<T, L, REV, S + 1, E, DIR, NT, NL>(lds, tw, tid);
+        eng_stage<T, L, REV, S, DIR, NT, NL, 1, 1, 0, TM>(lds, tw, tid, nold, nost);
+        eng_mid<T, L, REV, S + 1, E, DIR, NT, NL, TM>(lds, tw, tid);
     }
 }
 

@@ -404,6 +404,13 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     auto app = [&](const HostFft &f) { size_t off = tw.size() / 2; auto v = round_tw<T>(f); tw.insert(tw.end(), v.begin(), v.end()); return off; };
     const size_t ox = app(p->fx), oy = app(p->fy);
     (void)app(make_fft(Ly, true));   // reversed radix order, right after y's table (fused inverse)
+    // the Ly roots exp(-2 pi i m / Ly): twiddles of either radix order by index
+    const size_t oroots = tw.size() / 2;
+    for (int m = 0; m < Ly; ++m) {
+        const long double ang = -2.0L * 3.14159265358979323846264338327950288L * (long double)m / (long double)Ly;
+        tw.push_back((T)cosl(ang));
+        tw.push_back((T)sinl(ang));
+    }
     const size_t oz = app(p->fz);
     p->tw_off[0] = ox; p->tw_off[1] = oy; p->tw_off[2] = oz;
     // folded z transform (compile-time Lz): table of length Lz/2, then exp(-2 pi i k / Lz), k <= Lz/2
@@ -477,7 +484,7 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
         if ((v == 1 && fused_hx_threads(Ly) > 0) || fused_pf_available(Ly, v)) p->y_var = v;
     }
     if (p->y_ct) Wp = 1;
-    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy;
+    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy; q.roots = twc + oroots;
     q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;
     q.npos = npen; q.W = Wp; q.tiles = (npen + Wp - 1) / Wp;
     q.pitch = p->y_ct ? Ly + 1 : py;
@@ -603,7 +610,7 @@ hipError_t launch_y(mm_plan *p) {
 std::vector<int> y_variants(int Ly) {
     std::vector<int> v{0};
     if (fused_hx_threads(Ly) > 0) v.push_back(1);
-    for (int k = 2; k <= 4; ++k)
+    for (int k = 2; k <= 5; ++k)
         if (fused_pf_available(Ly, k)) v.push_back(k);
     return v;
 }

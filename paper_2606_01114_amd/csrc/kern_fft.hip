@@ -259,7 +259,7 @@ __global__ void __launch_bounds__(1024) k_fused_y(const FusedPass *__restrict__ 
 // stage, all in registers (the inverse runs its radices in reversed order, so
 // its first stage reads exactly the positions the last forward stage
 // produced).  Reads and writes LDS; ends with a barrier.
-template <typename T, int L, int NT, class Pr>
+template <typename T, int L, int NT, class Pr, int TM = 0>
 __device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restrict__ twf, int tid, const Pr &prod) {
     using C = cplx<T>;
     constexpr int NS = ct::nst(L);
@@ -280,9 +280,10 @@ __device__ __forceinline__ void conv_middle(cplx<T> *lds, const cplx<T> *__restr
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sj + swc<L>(r * NB)];
                 if (Nsf > 1) {
-                    const C *tt = twf + TWM + (j % Nsf) * (R - 1);
+                    const int k = j % Nsf;
+                    const C *tt = twf + TWM + k * (R - 1);
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
+                    for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], stage_tw<L, Nsf, R, TM>(twf, tt, k, r));
                 }
                 Dft<R, -1, C>::run(v[u][c]);
             }
@@ -339,8 +340,9 @@ struct PencilTensor {
     }
 };
 
-// conv_middle with the tensor already in registers
-template <typename T, int L, int NT>
+// conv_middle with the tensor already in registers (TM: twiddle table form,
+// as for eng_stage_la)
+template <typename T, int L, int NT, int TM = 0>
 __device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__restrict__ twf, int tid,
                                                 const PencilTensor<T, L, NT> &pt) {
     using C = cplx<T>;
@@ -362,9 +364,10 @@ __device__ __forceinline__ void conv_middle_pre(cplx<T> *lds, const cplx<T> *__r
 #pragma unroll
                 for (int r = 0; r < R; ++r) v[u][c][r] = lds[c * P + sj + swc<L>(r * NB)];
                 if (Nsf > 1) {
-                    const C *tt = twf + TWM + (j % Nsf) * (R - 1);
+                    const int k = j % Nsf;
+                    const C *tt = twf + TWM + k * (R - 1);
 #pragma unroll
-                    for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], tt[r - 1]);
+                    for (int r = 1; r < R; ++r) v[u][c][r] = cmul(v[u][c][r], stage_tw<L, Nsf, R, TM>(twf, tt, k, r));
                 }
                 Dft<R, -1, C>::run(v[u][c]);
             }
@@ -777,6 +780,75 @@ __global__ void __launch_bounds__(NT, MINW) k_fused_y_pf(const FusedPass a) {
     }
 }
 
+// Persistent fused pass with the twiddles in LDS: the Ly roots
+// exp(-2 pi i m / Ly) sit behind the pencil, copied once per workgroup, so no
+// radix stage waits on a global twiddle load.  The only global loads are the
+// next pencil's first-stage inputs, issued right after the first stage, and
+// the current pencil's tensor values (EARLY: issued with them, so the forward
+// stages cover their latency; else at the product, which saves registers).
+// Waits on global loads complete in issue order, so a twiddle load between
+// the prefetch and its use would wait for the prefetch too.
+template <typename T, int L, int NT, bool EARLY>
+__global__ void __launch_bounds__(NT) k_fused_y_pt(const FusedPass a) {
+    using C = cplx<T>;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    constexpr int NS = ct::nst(L);
+    static_assert(NS >= 2, "fused pencil needs two or more radix stages");
+    constexpr int P = ct::lds_pitch(L, 3, (int)sizeof(C));
+    C *roots = lds + 3 * P;
+    const unsigned rot = (blockIdx.x >> 3) % (NT / 64);
+    const int tid = (NT & (NT - 1)) == 0 ? (int)(threadIdx.x ^ (64u * rot)) : (int)((threadIdx.x + 64u * rot) % (unsigned)NT);
+    const int n = a.n, G = (int)gridDim.x, npos = a.npos;
+    int v = (int)blockIdx.x;
+    if (v >= npos) return;
+    {
+        const C *rg = reinterpret_cast<const C *>(a.roots);
+        for (int i = (int)threadIdx.x; i < L; i += NT) roots[i] = rg[i];
+    }
+    auto pencil = [&](int vv) {
+        const int p = (int)xcd_tile((uint32_t)vv, (uint32_t)npos);
+        const int kz = p / a.Lx;
+        return make_int2(kz, pair_kx(p - kz * a.Lx, a.Lx));
+    };
+    auto rsrc = [&](int2 qq) {
+        C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)qq.x * a.Lx + qq.y) * (3 * n);
+        return make_rsrc(pen, (uint32_t)(3 * n) * sizeof(C));
+    };
+    PencilInputs<T, L, NT> in;
+    int2 q = pencil(v);
+    in.load(rsrc(q), tid);
+    auto nold = [](int, int) { return C(); };
+    for (; v < npos; v += G) {
+        const BufRsrc rp = rsrc(q);
+        auto st = [&](int c, int pos, C x) { buf_store(rp, (uint32_t)(pos * 3 + c) * sizeof(C), x); };
+        const bool rx = q.y > a.Lx / 2;
+        const T *Trow = reinterpret_cast<const T *>(a.tensor) + ((int64_t)q.x * a.hxp + (rx ? a.Lx - q.y : q.y)) * a.hyp * 6;
+        const T sx = rx ? T(-1) : T(1);
+        // the previous pencil's last stage has finished reading LDS (first
+        // pencil: the roots are in place)
+        __syncthreads();
+        in.stage0(lds, tid);
+        PencilTensor<T, L, (EARLY ? NT : 1)> pt;
+        if constexpr (EARLY) pt.load(Trow, sx, tid);
+        const int vn = v + G;
+        const int2 qn = vn < npos ? pencil(vn) : q;
+        if (vn < npos) in.load(rsrc(qn), tid);
+        eng_mid<T, L, false, 1, NS - 1, -1, NT, 3, 1>(lds, roots, tid);
+        if constexpr (EARLY) {
+            conv_middle_pre<T, L, NT, 1>(lds, roots, tid, pt);
+        } else {
+            PencilProduct<T, L> pr;
+            pr.Trow = Trow;
+            pr.sx = sx;
+            conv_middle<T, L, NT, PencilProduct<T, L>, 1>(lds, roots, tid, pr);
+        }
+        eng_mid<T, L, true, 1, NS - 1, +1, NT, 3, 1>(lds, roots, tid);
+        eng_stage<T, L, true, NS - 1, +1, NT, 3, 1, 0, 2, 1>(lds, roots, tid, nold, st);
+        q = qn;
+    }
+}
+
 // ---------------- launchers -------------------------------------------------
 template <typename T>
 hipError_t launch_line_pass(const LinePass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
@@ -967,16 +1039,36 @@ hipError_t launch_fused_pf_k(const FusedPass &a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// k_fused_y_pt: the pencil and the root table in LDS, a resident grid as
+// for k_fused_y_pf
+template <typename T, int L, int NT, bool EARLY>
+hipError_t launch_fused_pt_k(const FusedPass &a, hipStream_t s) {
+    const size_t lds = fused_ct_lds(L, sizeof(cplx<T>)) + (size_t)L * sizeof(cplx<T>);
+    int dev = 0, ncu = 0, per_cu = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(&k_fused_y_pt<T, L, NT, EARLY>),
+                                                         NT, lds);
+    if (e != hipSuccess) return e;
+    int G = std::max(1, per_cu) * std::max(1, ncu);
+    G = std::max(8, G - G % 8);
+    G = std::min(G, a.npos);
+    hipLaunchKernelGGL((k_fused_y_pt<T, L, NT, EARLY>), dim3(G), dim3(NT), lds, s, a);
+    return hipGetLastError();
+}
+
 // variant 2: k_fused_y_cr (one pencil per workgroup, waves rotated);
 // variant 3: k_fused_y_pf (persistent, next pencil's loads in flight; in
 // FP32 with one radix-16 butterfly per thread, 384 threads for 2048 points,
 // and the tensor fetched at the product, which keeps it under 168 VGPRs)
 // variant 4: the persistent kernel with 256 threads held to three waves per
 // SIMD (2048-point FP32 pencils)
+// variant 5: k_fused_y_pt (persistent, twiddles from a root table in LDS)
 int fused_pf_available(int L, int var) {
     if (var == 2) return L >= 256 && L <= 4096 && (L & (L - 1)) == 0 && fused_ct_threads(L, 8) > 64;
     if (var == 4) return L == 2048;
-    return var == 3 && (L == 1024 || L == 2048);
+    return (var == 3 || var == 5) && (L == 1024 || L == 2048);
 }
 
 template <typename T>
@@ -996,6 +1088,11 @@ hipError_t launch_fused_pf(const FusedPass &a, int var, hipStream_t s) {
         return hipGetLastError();
     }
     constexpr bool F32 = sizeof(T) == 4;
+    if (var == 5) {
+        if (a.f.L == 2048) return launch_fused_pt_k<T, 2048, (F32 ? 256 : 384), false>(a, s);
+        if (a.f.L == 1024) return launch_fused_pt_k<T, 1024, 256, true>(a, s);
+        return hipErrorInvalidValue;
+    }
     if (var == 4) {
         if (a.f.L != 2048) return hipErrorInvalidValue;
         if constexpr (F32) return launch_fused_pf_k<T, 2048, 256, false, 3>(a, s);

@@ -420,7 +420,8 @@ def test_y_pass_variants_against_oracle(n):
     LDS-resident pencil (0), the register-resident one with half-line
     exchanges (1), the LDS-resident pencil with rotated waves (2) and the
     persistent kernel with the next pencil's loads in flight (3; 4: held to
-    three waves per SIMD), for every
+    three waves per SIMD; 5: with its twiddles from a root table in LDS),
+    for every
     length each has (a variant a length lacks leaves the default in place),
     FP32 and FP64, against the oracle's h_eff; the persistent kernel's
     grid walks more pencils than it has workgroups."""
@@ -433,14 +434,14 @@ def test_y_pass_variants_against_oracle(n):
     ref = oracle.h_eff(m0, MS, A, D, oct_, L)
     old = os.environ.get("MMX_YVAR")
     try:
-        for var in (0, 1, 2, 3, 4):
+        for var in (0, 1, 2, 3, 4, 5):
             os.environ["MMX_YVAR"] = str(var)
             for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
                 dt = torch.float32 if prec == "f32" else torch.float64
                 plan = DemagPlan(n, D, prec)
                 Ly = plan.info()["L"][1]
                 has = {0: Ly & (Ly - 1) == 0, 1: Ly in (256, 512, 1024, 2048), 2: Ly in (512, 1024, 2048, 4096),
-                       3: Ly in (1024, 2048), 4: Ly == 2048}[var]
+                       3: Ly in (1024, 2048), 4: Ly == 2048, 5: Ly in (1024, 2048)}[var]
                 yv = plan.info()["tiles"][2]
                 assert yv == (var if has else 0), (var, Ly, yv)
                 h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
