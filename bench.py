@@ -201,7 +201,7 @@ def run_sweep(steps, warmup, prec="f32", padding="ct"):
     cells = int(sum(np.prod(g) for g in grids))
     # algorithmic bytes: the single-grid pass model of every geometry at its
     # padded lengths (the power of two >= 2n-1, or the shortest compile-time
-    # length: powers of two and 3*2^k)
+    # length: powers of two and q*2^k with one odd radix q)
     r = 4 if prec == "f32" else 8
     padlen = _pow2_len if padding == "pow2" else _ct_len
     step_bytes = sum(pass_bytes(g, tuple(padlen(v, a) for a, v in enumerate(g)), r)[1] for g in grids)
@@ -248,12 +248,16 @@ def _pow2_len(n, axis=0):
     return L
 
 
+# lengths with one odd radix that have compile-time kernels (x and y; z: 768)
+CT_ODD_XY = (96, 160, 192, 224, 320, 384, 448, 640, 768, 896, 1280, 1536, 1792)
+
+
 def _ct_len(n, axis=0):
-    """Shortest length >= 2n-1 with compile-time FP32 kernels (powers of two;
-    3*2^k: x, y 384, 768, 1536, z 768), as the library's padding mode 3."""
+    """Shortest length >= 2n-1 with compile-time FP32 kernels (powers of two
+    and CT_ODD_XY on x and y, 768 on z), as the library's padding mode 3."""
     if n == 1:
         return 1
-    odd = (384, 768, 1536) if axis < 2 else (768,)
+    odd = CT_ODD_XY if axis < 2 else (768,)
     lim = 2048 if axis == 2 else 4096
     c = [L for L in [1 << k for k in range(13)] if L <= lim] + list(odd)
     ok = [L for L in c if L >= 2 * n - 1]

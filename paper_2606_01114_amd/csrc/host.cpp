@@ -69,12 +69,18 @@ int64_t default_L(int64_t n) {
 }
 
 // Lengths an axis has compile-time kernels for: powers of two (x and y up to
-// 4096, an FP64 y pencil and z up to 2048) and 3 * 2^k (x and y: 384, 768,
-// 1536; z: 768).
+// 4096, an FP64 y pencil and z up to 2048) and q * 2^k with one odd radix q
+// (x and y: 96, 160, 192, 224, 320, 384, 448, 640, 768, 896, 1280, 1536,
+// 1792; z: 768).
 bool ct_len_ok(int64_t L, int axis, int precision) {
     const int64_t lim = axis == 2 ? 2048 : (axis == 1 && precision == MM_F64 ? 2048 : 4096);
     if ((L & (L - 1)) == 0) return L <= lim;
-    return axis == 2 ? L == 768 : (L == 384 || L == 768 || L == 1536);
+    if (axis == 2) return L == 768;
+    switch (L) {
+    case 96: case 160: case 192: case 224: case 320: case 384: case 448:
+    case 640: case 768: case 896: case 1280: case 1536: case 1792: return true;
+    default: return false;
+    }
 }
 
 // the smallest compile-time length >= 2n-1 (a power of two past the table)
@@ -82,7 +88,7 @@ int64_t ct_L(int64_t n, int axis, int precision) {
     if (n == 1) return 1;
     int64_t best = 0;
     for (int64_t q = 1; q <= 4096; q <<= 1)
-        for (int64_t m : {1, 3}) {
+        for (int64_t m : {1, 3, 5, 7}) {
             const int64_t L = q * m;
             if (L >= 2 * n - 1 && ct_len_ok(L, axis, precision) && (!best || L < best)) best = L;
         }

@@ -881,10 +881,10 @@ hipError_t launch_fused_y(const FusedPass *d_descs, const int2 *d_map, int tiles
 static int line_ct_w(int L, bool f32, int variant) {
     int w;
     switch (L) {
-    case 64: case 128: case 256: w = 16; break;
-    case 384: case 512: w = f32 ? 16 : 8; break;
-    case 768: case 1024: w = f32 ? 8 : 4; break;
-    case 1536: case 2048: w = f32 ? 4 : 2; break;
+    case 64: case 96: case 128: case 160: case 192: case 224: case 256: w = 16; break;
+    case 320: case 384: case 448: case 512: w = f32 ? 16 : 8; break;
+    case 640: case 768: case 896: case 1024: w = f32 ? 8 : 4; break;
+    case 1280: case 1536: case 1792: case 2048: w = f32 ? 4 : 2; break;
     case 4096: w = f32 ? 2 : 1; break;
     default: return 0;
     }
@@ -927,11 +927,19 @@ hipError_t launch_line_ct(const LinePass &a, int tiles, int W, int dir, hipStrea
         LINE_CASE(512, 16) LINE_CASE(512, 32) LINE_CASE(1024, 8) LINE_CASE(1024, 16) LINE_CASE(2048, 4) LINE_CASE(2048, 8)
         LINE_CASE(4096, 2) LINE_CASE(4096, 4)
         LINE_CASE(384, 16) LINE_CASE(384, 32) LINE_CASE(768, 8) LINE_CASE(768, 16) LINE_CASE(1536, 4) LINE_CASE(1536, 8)
+        LINE_CASE(96, 16) LINE_CASE(96, 32) LINE_CASE(160, 16) LINE_CASE(160, 32) LINE_CASE(192, 16) LINE_CASE(192, 32)
+        LINE_CASE(224, 16) LINE_CASE(224, 32) LINE_CASE(320, 16) LINE_CASE(320, 32) LINE_CASE(448, 16) LINE_CASE(448, 32)
+        LINE_CASE(640, 8) LINE_CASE(640, 16) LINE_CASE(896, 8) LINE_CASE(896, 16) LINE_CASE(1280, 4) LINE_CASE(1280, 8)
+        LINE_CASE(1792, 4) LINE_CASE(1792, 8)
     } else {
         LINE_CASE(64, 16) LINE_CASE(64, 32) LINE_CASE(128, 16) LINE_CASE(128, 32) LINE_CASE(256, 16) LINE_CASE(256, 32)
         LINE_CASE(512, 8) LINE_CASE(512, 16) LINE_CASE(1024, 4) LINE_CASE(1024, 8) LINE_CASE(2048, 2) LINE_CASE(2048, 4)
         LINE_CASE(4096, 1) LINE_CASE(4096, 2)
         LINE_CASE(384, 8) LINE_CASE(384, 16) LINE_CASE(768, 4) LINE_CASE(768, 8) LINE_CASE(1536, 2) LINE_CASE(1536, 4)
+        LINE_CASE(96, 16) LINE_CASE(96, 32) LINE_CASE(160, 16) LINE_CASE(160, 32) LINE_CASE(192, 16) LINE_CASE(192, 32)
+        LINE_CASE(224, 16) LINE_CASE(224, 32) LINE_CASE(320, 8) LINE_CASE(320, 16) LINE_CASE(448, 8) LINE_CASE(448, 16)
+        LINE_CASE(640, 4) LINE_CASE(640, 8) LINE_CASE(896, 4) LINE_CASE(896, 8) LINE_CASE(1280, 2) LINE_CASE(1280, 4)
+        LINE_CASE(1792, 2) LINE_CASE(1792, 4)
     }
     return hipErrorInvalidValue;
 }
@@ -988,11 +996,14 @@ int fused_ct_threads(int L, size_t csz) {
     case 64: return 64;
     case 128: return 64;
     case 256: return 64;
-    case 384: return 128;
+    case 96: case 160: case 192: case 224: case 320: return 64;
+    case 384: case 448: case 640: return 128;
     case 512: return 128;
+    case 896: return 192;
     case 768: return 256;
-    case 1024: return 256;
+    case 1024: case 1280: return 256;
     case 1536: return 512;
+    case 1792: return 384;
     case 2048: return csz == 8 ? 256 : 384;
     case 4096: return 768;
     default: return 0;
@@ -1013,6 +1024,8 @@ hipError_t launch_fused_ct(const FusedPass &a, hipStream_t s) {
         FCASE(64, 64) FCASE(128, 64) FCASE(256, 64) FCASE(512, 128) FCASE(1024, 256)
         FCASE(2048, (sizeof(T) == 4 ? 256 : 384)) FCASE(4096, 768)
         FCASE(384, 128) FCASE(768, 256) FCASE(1536, 512)
+        FCASE(96, 64) FCASE(160, 64) FCASE(192, 64) FCASE(224, 64) FCASE(320, 64) FCASE(448, 128) FCASE(640, 128)
+        FCASE(896, 192) FCASE(1280, 256) FCASE(1792, 384)
     default: return hipErrorInvalidValue;
     }
 #undef FCASE
@@ -1151,6 +1164,8 @@ hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int
     switch (L) {
         FB(64, 64) FB(128, 64) FB(256, 64) FB(512, 128) FB(1024, 256) FB(2048, (sizeof(T) == 4 ? 256 : 384)) FB(4096, 768)
         FB(384, 128) FB(768, 256) FB(1536, 512)
+        FB(96, 64) FB(160, 64) FB(192, 64) FB(224, 64) FB(320, 64) FB(448, 128) FB(640, 128) FB(896, 192)
+        FB(1280, 256) FB(1792, 384)
     default: return hipErrorInvalidValue;
     }
 #undef FB
@@ -1183,10 +1198,16 @@ hipError_t launch_line_var_b(const LinePass *d, const int2 *map, int tiles, int 
         LVB(64, 16) LVB(64, 32) LVB(128, 16) LVB(128, 32) LVB(256, 16) LVB(256, 32) LVB(512, 16) LVB(512, 32)
         LVB(1024, 8) LVB(1024, 16) LVB(2048, 4) LVB(2048, 8) LVB(4096, 2) LVB(4096, 4)
         LVB(384, 16) LVB(384, 32) LVB(768, 8) LVB(768, 16) LVB(1536, 4) LVB(1536, 8)
+        LVB(96, 16) LVB(96, 32) LVB(160, 16) LVB(160, 32) LVB(192, 16) LVB(192, 32) LVB(224, 16) LVB(224, 32)
+        LVB(320, 16) LVB(320, 32) LVB(448, 16) LVB(448, 32) LVB(640, 8) LVB(640, 16) LVB(896, 8) LVB(896, 16)
+        LVB(1280, 4) LVB(1280, 8) LVB(1792, 4) LVB(1792, 8)
     } else {
         LVB(64, 16) LVB(64, 32) LVB(128, 16) LVB(128, 32) LVB(256, 16) LVB(256, 32) LVB(512, 8) LVB(512, 16)
         LVB(1024, 4) LVB(1024, 8) LVB(2048, 2) LVB(2048, 4) LVB(4096, 1) LVB(4096, 2)
         LVB(384, 8) LVB(384, 16) LVB(768, 4) LVB(768, 8) LVB(1536, 2) LVB(1536, 4)
+        LVB(96, 16) LVB(96, 32) LVB(160, 16) LVB(160, 32) LVB(192, 16) LVB(192, 32) LVB(224, 16) LVB(224, 32)
+        LVB(320, 8) LVB(320, 16) LVB(448, 8) LVB(448, 16) LVB(640, 4) LVB(640, 8) LVB(896, 4) LVB(896, 8)
+        LVB(1280, 2) LVB(1280, 4) LVB(1792, 2) LVB(1792, 4)
     }
 #undef LVB
     return hipErrorInvalidValue;

@@ -226,9 +226,10 @@ def test_set_stt_rejects_bad_arguments_on_host():
 
 def test_automatic_padding_on_host():
     """The default padding takes the shortest compile-time length (powers of
-    two: x, y 4096, z and an FP64 y 2048; 3*2^k: x, y 384, 768, 1536, z 768)
-    when it is at most 1.75 times the 7-smooth length; 0 keeps the 7-smooth
-    lengths, 1 powers of two, 3 the compile-time lengths unconditionally."""
+    two: x, y 4096, z and an FP64 y 2048; one odd radix: x, y 96 ... 1792,
+    z 768) when it is at most 1.75 times the 7-smooth length; 0 keeps the
+    7-smooth lengths, 1 powers of two, 3 the compile-time lengths
+    unconditionally."""
     from paper_2606_01114_amd import _lib
 
     def tensor_L(grid, prec, pad=None):
@@ -249,10 +250,14 @@ def test_automatic_padding_on_host():
     assert tensor_L((350, 350, 350), F64) == octant((768, 768, 768), 8)
     assert tensor_L((350, 350, 350), F64, 0) == octant((700, 700, 700), 8)
     assert tensor_L((350, 350, 350), F64, 1) == octant((1024, 1024, 1024), 8)
-    assert tensor_L((300, 6, 2), F32) == octant((768, 16, 4), 4)
-    assert tensor_L((260, 6, 2), F32) == octant((768, 16, 4), 4)
-    assert tensor_L((150, 180, 3), F32) == octant((384, 384, 8), 4)
+    assert tensor_L((300, 6, 2), F32) == octant((640, 16, 4), 4)
+    assert tensor_L((260, 6, 2), F32) == octant((640, 16, 4), 4)
+    assert tensor_L((330, 6, 2), F32) == octant((768, 16, 4), 4)
+    assert tensor_L((150, 180, 3), F32) == octant((320, 384, 8), 4)
+    assert tensor_L((100, 220, 3), F64) == octant((224, 448, 8), 8)
+    assert tensor_L((400, 5, 400), F32) == octant((896, 16, 1024), 4)
     assert tensor_L((700, 5, 400), F32) == octant((1536, 16, 1024), 4)
+    assert tensor_L((850, 640, 3), F32) == octant((1792, 1280, 8), 4)
     assert tensor_L((4, 1500, 1100), F32) == octant((8, 4096, 2205), 4)
     assert tensor_L((4, 1500, 3), F64) == octant((8, 3000, 8), 8)
     assert tensor_L((4, 1100, 3), F32, 3) == octant((8, 4096, 8), 4)
@@ -293,3 +298,25 @@ def test_llg_stability_bound():
         api._stability_warning((2e-9,) * 3, 4e5, 1.3e-11, 2.211e5, 1e-13)
         api._stability_warning(d, 8e5, 1.3e-11, 2.211e5, 1e-13)
     assert len(rec) == 1 and "stability" in str(rec[0].message)
+
+
+def test_bench_padding_table_matches_library():
+    """The benchmark's byte model pads a sweep geometry the way the library's
+    padding mode 3 does: for every n up to 1100 on x and y and up to 700 on
+    z, the length its table gives equals the one the library plans (read back
+    from the tensor octant of an n x 1 x 1 grid)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    from paper_2606_01114_amd import _lib
+    o = _lib.PlanOpts()
+    _lib.lib().mm_plan_opts_default(ctypes.byref(o))
+    o.pow2_padding = 3
+    for axis, top in ((0, 1100), (1, 1100), (2, 700)):
+        for n in range(2, top):
+            g = [1, 1, 1]
+            g[axis] = n
+            rc, t, _ = _bytes(tuple(g), _lib.MM_F32, ctypes.byref(o))
+            assert rc == _lib.MM_OK
+            Lh = t // (6 * 4)   # L/2 + 1 along the axis, 1 elsewhere
+            assert 2 * (Lh - 1) == bench._ct_len(n, axis), (axis, n, 2 * (Lh - 1), bench._ct_len(n, axis))

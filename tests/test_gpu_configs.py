@@ -327,14 +327,16 @@ def test_x_pass_variants_against_oracle():
     """Every variant of the specialised x pass, selected with MMX_XVAR at plan
     creation: two tile widths (0, 1), the half-LDS kernel (2) and the
     half-LDS kernel on tiles twice as wide (3, lines of 1024 and 2048
-    points), with ragged last tiles, and both tile widths of the 768-point
-    line with a radix-3 stage, FP32 and FP64, against the oracle's h_eff."""
+    points), with ragged last tiles, and both tile widths of the 640-point
+    line with a radix-5 stage and the 768-point line with a radix-3 stage,
+    FP32 and FP64, against the oracle's h_eff."""
     import os
     import torch
     from paper_2606_01114_amd import DemagPlan
     cases = [((64, 500, 16), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-9))),
              ((300, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 0, 1e-9), ("f64", 1, 1e-9))),
-             ((400, 40, 3), (("f32", 3, 1e-5), ("f64", 3, 1e-9), ("f32", 2, 1e-5))),
+             ((350, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 1, 1e-9))),
+             ((480, 40, 3), (("f32", 3, 1e-5), ("f64", 3, 1e-9), ("f32", 2, 1e-5))),
              ((1024, 8, 2), (("f32", 3, 1e-5), ("f64", 3, 1e-9)))]
     old = os.environ.get("MMX_XVAR")
     try:
@@ -366,14 +368,19 @@ def test_x_pass_variants_against_oracle():
 
 @pytest.mark.parametrize("n,Lset", [((2048, 6, 2), None), ((6, 2048, 2), None), ((3, 4, 1024), None),
                                     ((1000, 5, 3), None), ((700, 5, 3), (1536, 16, 8)), ((6, 350, 2), (16, 768, 4)),
-                                    ((4, 3, 350), (8, 8, 768)), ((150, 180, 3), (384, 384, 8))])
+                                    ((4, 3, 350), (8, 8, 768)), ((150, 180, 3), (384, 384, 8)),
+                                    ((150, 180, 3), (320, 448, 8)), ((300, 420, 2), (640, 896, 4)),
+                                    ((600, 5, 3), (1280, 16, 8)), ((6, 800, 2), (16, 1792, 4)),
+                                    ((800, 6, 2), (1792, 16, 4)), ((45, 70, 3), (96, 160, 8)),
+                                    ((90, 100, 3), (192, 224, 8))])
 def test_longest_specialised_lengths(n, Lset):
     """The longest compile-time transforms (x and y length 4096, z length
     2048: x tiles of one or two columns, the 768-thread fused y pencil, the
-    1024-point folded z line), the compile-time lengths with a radix-3 stage
-    (x 1536, y 768, z 768 folded to 384, x and y 384) and a long
-    non-power-of-two x line (runtime planned), FP32 and FP64, h_eff and one
-    RK4 step against the oracle."""
+    1024-point folded z line), the compile-time lengths with one odd radix
+    (radix 3: x 1536, y 768, z 768 folded to 384, x and y 384, 96, 192;
+    radix 5: 160, 320, 640, 1280; radix 7: 224, 448, 896, 1792 on x and y)
+    and a long non-power-of-two x line (runtime planned), FP32 and FP64,
+    h_eff and one RK4 step against the oracle."""
     import torch
     from paper_2606_01114_amd import DemagPlan
     oct_ = oracle.tensor_octant(n, D)
@@ -395,10 +402,10 @@ def test_longest_specialised_lengths(n, Lset):
         plan = DemagPlan(n, D, prec, padding="smooth", L=Lset)
         assert tuple(plan.info()["L"]) == L
         if Lset:
-            # the lengths with a radix-3 stage run the compile-time kernels
+            # the lengths with an odd radix run the compile-time kernels
             sch = plan.schedule()
             for key, Lv in (("x_fwd", L[0]), ("y_fused", L[1]), ("z", L[2])):
-                if Lv % 3 == 0:
+                if Lv & (Lv - 1):
                     assert sch[key]["specialised"], (key, sch)
         mr = rounded(m0, dt)
         Msr = to_dev(rounded(Ms, dt), dt)
