@@ -248,16 +248,18 @@ def _pow2_len(n, axis=0):
     return L
 
 
-# lengths with one odd radix that have compile-time kernels (x and y; z: 768)
+# lengths with one odd radix that have compile-time kernels (x and y; z up
+# to 896)
 CT_ODD_XY = (96, 160, 192, 224, 320, 384, 448, 640, 768, 896, 1280, 1536, 1792)
+CT_ODD_Z = tuple(L for L in CT_ODD_XY if L <= 896)
 
 
 def _ct_len(n, axis=0):
     """Shortest length >= 2n-1 with compile-time FP32 kernels (powers of two
-    and CT_ODD_XY on x and y, 768 on z), as the library's padding mode 3."""
+    and CT_ODD_XY on x and y, CT_ODD_Z on z), as the library's padding mode 3."""
     if n == 1:
         return 1
-    odd = CT_ODD_XY if axis < 2 else (768,)
+    odd = CT_ODD_XY if axis < 2 else CT_ODD_Z
     lim = 2048 if axis == 2 else 4096
     c = [L for L in [1 << k for k in range(13)] if L <= lim] + list(odd)
     ok = [L for L in c if L >= 2 * n - 1]

@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmmx.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["kern_fft.hip", "kern_z.hip", "kern_zct.hip", "kern_tensor.hip", "kern_stencil.hip", "kern_scratch.hip", "host.cpp"]
+SOURCES = ["kern_fft.hip", "kern_z.hip", "kern_zct.hip", "kern_zct_hi.hip", "kern_zct_odd_a.hip", "kern_zct_odd_b.hip",
+           "kern_tensor.hip", "kern_stencil.hip", "kern_scratch.hip", "host.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-command-line-argument"]

@@ -71,14 +71,14 @@ int64_t default_L(int64_t n) {
 // Lengths an axis has compile-time kernels for: powers of two (x and y up to
 // 4096, an FP64 y pencil and z up to 2048) and q * 2^k with one odd radix q
 // (x and y: 96, 160, 192, 224, 320, 384, 448, 640, 768, 896, 1280, 1536,
-// 1792; z: 768).
+// 1792; z the same up to 896).
 bool ct_len_ok(int64_t L, int axis, int precision) {
     const int64_t lim = axis == 2 ? 2048 : (axis == 1 && precision == MM_F64 ? 2048 : 4096);
     if ((L & (L - 1)) == 0) return L <= lim;
-    if (axis == 2) return L == 768;
     switch (L) {
     case 96: case 160: case 192: case 224: case 320: case 384: case 448:
-    case 640: case 768: case 896: case 1280: case 1536: case 1792: return true;
+    case 640: case 768: case 896: return true;
+    case 1280: case 1536: case 1792: return axis != 2;
     default: return false;
     }
 }

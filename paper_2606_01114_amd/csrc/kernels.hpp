@@ -41,7 +41,8 @@ template <typename T>
 hipError_t launch_zinv_batch(const ZInvArgs *d, const int2 *map, int tiles, int nthr, int epi, size_t lds_bytes,
                              hipStream_t s);
 hipError_t launch_copy16(const void *src, void *dst, int64_t n16, hipStream_t s);
-// compile-time z passes (power-of-two Lz in [2, 2048]); zct_cols returns the
+// compile-time z passes (power-of-two Lz in [2, 2048] and Lz = 96, 160, 192,
+// 224, 320, 384, 448, 640, 768, 896); zct_cols returns the
 // cell columns per tile (0 if no specialisation), zct_lds the LDS bytes
 int zct_cols(int Lz);
 // tiles of the compile-time z-inverse pass (ZGeom::ygrp order)
@@ -49,6 +50,27 @@ int zinv_ct_tiles(int nx, int ny, int Lz, int ygrp);
 size_t zct_lds(int Lz, size_t csz);
 template <typename T> hipError_t launch_zfwd_ct(const ZFwdArgs &a, int src_mode, hipStream_t s);
 template <typename T> hipError_t launch_zinv_ct(const ZInvArgs &a, int epi, hipStream_t s);
+// the longer folded lengths (kern_zct_hi.hip) and those with an odd radix
+// (kern_zct_odd_a/b.hip), called in turn by the four launchers above and
+// below; hipErrorInvalidValue for a length they do not have
+template <typename T> hipError_t launch_zfwd_ct_hi(const ZFwdArgs &a, int src_mode, size_t lds, hipStream_t s);
+template <typename T> hipError_t launch_zinv_ct_hi(const ZInvArgs &a, int epi, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_zfwd_ct_b_hi(const ZFwdArgs *d, const int2 *map, int tiles, int Lz, int src_mode, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_zinv_ct_b_hi(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, size_t lds, hipStream_t s);
+template <typename T> hipError_t launch_zfwd_ct_odd_a(const ZFwdArgs &a, int src_mode, size_t lds, hipStream_t s);
+template <typename T> hipError_t launch_zinv_ct_odd_a(const ZInvArgs &a, int epi, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_zfwd_ct_b_odd_a(const ZFwdArgs *d, const int2 *map, int tiles, int Lz, int src_mode, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_zinv_ct_b_odd_a(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, size_t lds, hipStream_t s);
+template <typename T> hipError_t launch_zfwd_ct_odd_b(const ZFwdArgs &a, int src_mode, size_t lds, hipStream_t s);
+template <typename T> hipError_t launch_zinv_ct_odd_b(const ZInvArgs &a, int epi, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_zfwd_ct_b_odd_b(const ZFwdArgs *d, const int2 *map, int tiles, int Lz, int src_mode, size_t lds, hipStream_t s);
+template <typename T>
+hipError_t launch_zinv_ct_b_odd_b(const ZInvArgs *d, const int2 *map, int tiles, int Lz, int epi, size_t lds, hipStream_t s);
 template <typename T> hipError_t launch_fused_ct_b(const FusedPass *d, const int2 *map, int tiles, int L, hipStream_t s);
 // grouped launches in any variant (x: 0..3 as mm_plan_info; y: 0..2)
 template <typename T>

@@ -227,7 +227,7 @@ def test_set_stt_rejects_bad_arguments_on_host():
 def test_automatic_padding_on_host():
     """The default padding takes the shortest compile-time length (powers of
     two: x, y 4096, z and an FP64 y 2048; one odd radix: x, y 96 ... 1792,
-    z 768) when it is at most 1.75 times the 7-smooth length; 0 keeps the
+    z 96 ... 896) when it is at most 1.75 times the 7-smooth length; 0 keeps the
     7-smooth lengths, 1 powers of two, 3 the compile-time lengths
     unconditionally."""
     from paper_2606_01114_amd import _lib
@@ -255,10 +255,13 @@ def test_automatic_padding_on_host():
     assert tensor_L((330, 6, 2), F32) == octant((768, 16, 4), 4)
     assert tensor_L((150, 180, 3), F32) == octant((320, 384, 8), 4)
     assert tensor_L((100, 220, 3), F64) == octant((224, 448, 8), 8)
-    assert tensor_L((400, 5, 400), F32) == octant((896, 16, 1024), 4)
-    assert tensor_L((700, 5, 400), F32) == octant((1536, 16, 1024), 4)
+    assert tensor_L((400, 5, 400), F32) == octant((896, 16, 896), 4)
+    assert tensor_L((700, 5, 400), F32) == octant((1536, 16, 896), 4)
+    assert tensor_L((160, 160, 160), F64) == octant((320, 320, 320), 8)
+    assert tensor_L((5, 5, 500), F32) == octant((16, 16, 1024), 4)
     assert tensor_L((850, 640, 3), F32) == octant((1792, 1280, 8), 4)
     assert tensor_L((4, 1500, 1100), F32) == octant((8, 4096, 2205), 4)
+    assert tensor_L((4, 4, 700), F32) == octant((8, 8, 2048), 4)
     assert tensor_L((4, 1500, 3), F64) == octant((8, 3000, 8), 8)
     assert tensor_L((4, 1100, 3), F32, 3) == octant((8, 4096, 8), 4)
     assert tensor_L((4, 4, 700), F32, 3) == octant((8, 8, 2048), 4)

@@ -195,6 +195,50 @@ def test_batch_against_oracle_and_plans(prec, pow2):
 
 
 @pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_batch_odd_radix_lengths_against_oracle(prec):
+    """A batch padded to the compile-time lengths (padding="ct") whose axes
+    take lengths with an odd radix on x, y and z (96, 160, 224, 320 and
+    powers of two): the grouped x, fused y and z kernels at those lengths,
+    h_eff and one RK4 step of every geometry against the oracle (FP64 with
+    the tensors held equal, 1e-12; FP32 1e-5)."""
+    import torch
+    from paper_2606_01114_amd import Batch
+    grids = [(45, 6, 48), (6, 70, 80), (100, 5, 10), (5, 110, 112), (150, 3, 4)]
+    want = [(96, 16, 96), (16, 160, 160), (224, 16, 32), (16, 224, 224), (320, 8, 8)]
+    Ms = [4e5 + 1.5e5 * k for k in range(len(grids))]
+    dt = torch.float32 if prec == "f32" else torch.float64
+    tol = 1e-12 if prec == "f64" else 1e-5
+    octs = [oracle.tensor_octant(g, D) for g in grids]
+    b = Batch(grids, [D] * len(grids), prec, padding="ct")
+    lens = sorted({(g["pass"], g["L"]) for g in b.schedule()["groups"]})
+    _say("batch odd lengths", prec, lens)
+    for axis, key in ((0, "x_fwd"), (1, "y_fused"), (2, "z")):
+        for w in want:
+            if w[axis] & (w[axis] - 1):
+                assert (key, w[axis]) in lens, (key, w[axis], lens)
+    if prec == "f64":
+        for k in range(len(grids)):
+            b.tensor_set(k, octs[k])
+    m0 = [rounded(synth.random_unit(g, 60 + k), dt) for k, g in enumerate(grids)]
+    ms = [to_dev(x, dt) for x in m0]
+    hs = b.h_eff(ms, Ms, A)
+    for k, g in enumerate(grids):
+        L = tuple(oracle.default_L(v) for v in g)
+        ref = oracle.h_eff(m0[k], Ms[k], A, D, octs[k], L)
+        e = rel_l2(hs[k].cpu().numpy(), ref)
+        _say("batch odd", prec, g, "h_eff rel-L2", e)
+        assert e <= tol, (g, e)
+    b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=1)
+    for k, g in enumerate(grids):
+        L = tuple(oracle.default_L(v) for v in g)
+        ref = oracle.rk4_step(m0[k], Ms[k], A, D, octs[k], L, ALPHA, GAMMA, DT)
+        e = rel_l2(ms[k].cpu().numpy() - m0[k], ref - m0[k])
+        _say("batch odd", prec, g, "step rel-L2", e)
+        assert e <= tol, (g, e)
+    b.close()
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_wide_x_tiles_against_oracle(prec):
     """A batch whose x lines are 2048 and 1024 points long runs the grouped
     half-LDS x kernel on wide tiles (and 64 points the full-LDS one): h_eff
@@ -372,13 +416,18 @@ def test_x_pass_variants_against_oracle():
                                     ((150, 180, 3), (320, 448, 8)), ((300, 420, 2), (640, 896, 4)),
                                     ((600, 5, 3), (1280, 16, 8)), ((6, 800, 2), (16, 1792, 4)),
                                     ((800, 6, 2), (1792, 16, 4)), ((45, 70, 3), (96, 160, 8)),
-                                    ((90, 100, 3), (192, 224, 8))])
+                                    ((90, 100, 3), (192, 224, 8)), ((5, 4, 45), (16, 8, 96)),
+                                    ((6, 3, 80), (16, 8, 160)), ((4, 4, 95), (8, 8, 192)),
+                                    ((4, 3, 100), (8, 8, 224)), ((4, 5, 160), (8, 16, 320)),
+                                    ((4, 4, 220), (8, 8, 448)), ((4, 4, 300), (8, 8, 640)),
+                                    ((3, 4, 400), (8, 8, 896))])
 def test_longest_specialised_lengths(n, Lset):
     """The longest compile-time transforms (x and y length 4096, z length
     2048: x tiles of one or two columns, the 768-thread fused y pencil, the
     1024-point folded z line), the compile-time lengths with one odd radix
     (radix 3: x 1536, y 768, z 768 folded to 384, x and y 384, 96, 192;
-    radix 5: 160, 320, 640, 1280; radix 7: 224, 448, 896, 1792 on x and y)
+    radix 5: 160, 320, 640, 1280; radix 7: 224, 448, 896, 1792 on x and y;
+    z 96 ... 896, folded to half that length)
     and a long non-power-of-two x line (runtime planned), FP32 and FP64,
     h_eff and one RK4 step against the oracle."""
     import torch
