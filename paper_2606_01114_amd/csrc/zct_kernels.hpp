@@ -304,9 +304,13 @@ __global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct_b(const ZFwdArgs *__res
 }
 
 // LOC: the plan carries DMI, anisotropy or spin-transfer torque (a separate
-// instantiation keeps the plain exchange epilogue free of those registers)
+// instantiation keeps the plain exchange epilogue free of those registers).
+// The FP64 RK4-stage form without local terms is held to three waves per
+// SIMD (168 VGPRs; it spills 20 of its 191 and still runs 7% faster than at
+// two waves); the other forms would spill far more.
 template <typename T, int N, int EPI, bool LOC>
-__global__ void __launch_bounds__(zthreads(N)) k_zinv_ct(const ZInvArgs a) {
+__global__ void __launch_bounds__(zthreads(N), (sizeof(T) == 8 && EPI == EPI_STAGE && !LOC) ? 3 : 1)
+k_zinv_ct(const ZInvArgs a) {
     zinv_ct_body<T, N, EPI, LOC>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
