@@ -124,17 +124,25 @@ def src_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(kernel, workload, prec):
-    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
-    taken on the current kernel sources; else None."""
+def load_traffic(pname, workload, prec, symbol=None):
+    """HBM bytes per launch of pass `pname` from committed rocprofv3 counter
+    runs, if they were taken on the current kernel sources and (given the
+    running kernel's `symbol`) on that kernel; else None."""
     p = os.path.join(ROOT, "profiles", "traffic.json")
     try:
         with open(p) as f:
             t = json.load(f)
-        e = t.get("%s/%s/%s" % (workload, prec, kernel))
-        if e and e.get("src_hash") == src_hash():
+        e = t.get("%s/%s/%s" % (workload, prec, pname))
+        if not e or e.get("src_hash") != src_hash():
+            return None
+        if symbol is None or (symbol + "<") in e["kernel"]:
             return e["bytes_per_launch"]
-    except (OSError, ValueError):
+        # another variant of the pass: its own counters (the tuner's trial
+        # launches), the most dispatched one of that kernel
+        cand = [(v["dispatches"], v["bytes_per_launch"]) for k, v in e.get("variants", {}).items()
+                if (symbol + "<") in k]
+        return max(cand)[1] if cand else None
+    except (OSError, ValueError, KeyError):
         pass
     return None
 
@@ -636,9 +644,11 @@ def traffic_from(fetch_csv, write_csv, workload, prec):
             wk = sorted((k for k in w if re.search(pat, k)), key=lambda k: -w[k][1])
             if fk and wk:
                 by = f[fk[0]][0] * 1024.0 / kf + w[wk[0]][0] * 1024.0 / kw
+                variants = {k: {"bytes_per_launch": f[k][0] * 1024.0 / kf + w[k][0] * 1024.0 / kw,
+                                "dispatches": min(f[k][1], w[k][1])} for k in fk if k in w}
                 out["%s/%s/%s" % (workload, prec, pname)] = {
                     "bytes_per_launch": by, "kernel": fk[0], "fetch_KiB": f[fk[0]][0], "write_KiB": w[wk[0]][0],
-                    "copy_scale_fetch": kf, "copy_scale_write": kw, "src_hash": h}
+                    "copy_scale_fetch": kf, "copy_scale_write": kw, "src_hash": h, "variants": variants}
                 break
     with open(path, "w") as fh:
         json.dump(out, fh, indent=1, sort_keys=True)
@@ -757,7 +767,7 @@ def main():
             sym[pname] = "k_line_hx"
     roof = {"bound": "hbm", "kernel": sym[dom] + " (" + dom + ")", "achieved": ach / 1e9,
             "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": ach / HBM_PEAK,
-            "traffic": load_traffic(dom, args.workload, args.prec),
+            "traffic": load_traffic(dom, args.workload, args.prec, sym[dom]),
             "algorithmic_bytes_per_launch": pb[dom], "launch_ms": res["passes"][dom]}
     extra = {
         "ms_per_step_events": ms_step,
