@@ -316,7 +316,7 @@ def run_fields(prec, N, steps, warmup, paddings=("smooth", "pow2", "auto")):
     field terms (each term alone, FP64 by default): demag, exchange and the
     Slonczewski spin-transfer torque, for the 7-smooth padding 2N (runtime
     planned), the power-of-two padding and the default padding (the
-    shortest compile-time length, 3*2^k included), or the given paddings."""
+    shortest compile-time length, odd-radix lengths included), or the given paddings."""
     import numpy as np
     import torch
     import synth
@@ -674,7 +674,7 @@ def main():
     ap.add_argument("--fields-n", default="350", help="cube edge of the fields workload (a comma list sweeps sizes)")
     ap.add_argument("--fields-f32", action="store_true", help="fields workload in FP32 (default FP64)")
     ap.add_argument("--padding", default="ct", choices=["pow2", "ct"],
-                    help="sweep padding: the shortest compile-time lengths (powers of two and 3*2^k), or powers "
+                    help="sweep padding: the shortest compile-time lengths (powers of two and q*2^k, q = 3, 5, 7), or powers "
                          "of two only")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -107,8 +107,10 @@ typedef struct mm_plan_opts {
                            mm_batch_create uses without opts); 3: the
                            smallest length >= 2n-1 with compile-time
                            kernels: powers of two (x, y up to 4096; z and an
-                           FP64 y up to 2048) and 3 * 2^k (x, y: 384, 768,
-                           1536; z: 768); 2 (default): that length when it
+                           FP64 y up to 2048) and q * 2^k with one odd radix
+                           q = 3, 5, 7 (x, y: 96, 160, 192, 224, 320, 384,
+                           448, 640, 768, 896, 1280, 1536, 1792; z: the same
+                           up to 896); 2 (default): that length when it
                            is at most 1.75 times the 7-smooth length, else
                            the 7-smooth length (runtime-planned kernels). */
 } mm_plan_opts;

@@ -343,7 +343,7 @@ class Batch:
                  padding=None):
         """padding: "pow2" (the default, as pow2_padding=True), "smooth" (as
         pow2_padding=False), "ct" (shortest length with compile-time
-        kernels: powers of two and 3*2^k) or "auto"."""
+        kernels: powers of two and q*2^k with q = 3, 5, 7) or "auto"."""
         self.grids = [tuple(int(v) for v in g) for g in grids]
         self.cells = [tuple(float(v) for v in c) for c in cells]
         self.prec = _prec(precision)
