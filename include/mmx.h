@@ -39,7 +39,9 @@
  * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
  * pass, MMX_ORDER="x:4,5,5;y:2,3,3,5" sets the radix order of runtime-planned
  * (non-power-of-two) axes, MMX_TEST_FAIL_ALLOC makes every device
- * allocation fail (MM_ENOMEM).  The autotuner reads MMX_AUTOTUNE and
+ * allocation fail (MM_ENOMEM), MMX_NO_FANOUT runs a batch's launch groups of
+ * one pass one after the other on its stream instead of side by side.  The
+ * autotuner reads MMX_AUTOTUNE and
  * MMX_AUTOTUNE_CACHE (mm_plan_opts.autotune).
  */
 #ifndef MMX_H
@@ -439,9 +441,13 @@ int mm_demag_spectrum_get(mm_plan *plan, double *host_spectrum);
  * Batched parameter sweep: `count` independent geometries, each with its own
  * grid, padded lengths, tensor and scalar Ms, advanced together.  Every pass
  * is a grouped launch over a ragged table of tiles -- one launch per distinct
- * padded length (geometries sharing a power-of-two length run the specialised
+ * padded length (geometries sharing a compile-time length run the specialised
  * kernels; all others share one runtime-planned launch) -- and one step of all
- * geometries is captured in one HIP graph.  opts NULL selects power-of-two
+ * geometries is captured in one HIP graph.  The launch groups of one pass
+ * touch disjoint geometries and run side by side: the batch forks up to three
+ * internal streams of its own from the caller's stream with events and joins
+ * them back before the next pass (parallel branches of the graph), so every
+ * call stays ordered on the caller's stream.  opts NULL selects power-of-two
  * padding; opts->autotune times every kernel variant of each launch group
  * (forward and inverse x separately) on the batch's own buffers.
  *   grids[count][3], cells[count][3]: host arrays

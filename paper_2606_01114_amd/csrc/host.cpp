@@ -1895,6 +1895,12 @@ struct mm_batch {
     hipStream_t cap = nullptr;
     hipGraphExec_t gexec = nullptr;
     std::vector<unsigned char> gkey, akey;
+    // the launch groups of one pass run side by side: up to kSide more
+    // streams, forked from and joined back to `stream` by events
+    static constexpr int kSide = 3;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr, join[kSide] = {};
+    bool fanout = true;
 };
 
 namespace {
@@ -1911,6 +1917,11 @@ int balloc(mm_batch *b, void **out, size_t bytes) {
 void batch_free(mm_batch *b) {
     if (b->gexec) { (void)hipGraphExecDestroy(b->gexec); b->gexec = nullptr; }
     if (b->cap) { (void)hipStreamDestroy(b->cap); b->cap = nullptr; }
+    for (int k = 0; k < mm_batch::kSide; ++k) {
+        if (b->side[k]) { (void)hipStreamDestroy(b->side[k]); b->side[k] = nullptr; }
+        if (b->join[k]) { (void)hipEventDestroy(b->join[k]); b->join[k] = nullptr; }
+    }
+    if (b->fork) { (void)hipEventDestroy(b->fork); b->fork = nullptr; }
     for (void *q : b->allocs) (void)hipFree(q);
     b->allocs.clear();
     for (mm_plan *p : b->plans) if (p) { free_all(p); delete p; }
@@ -1947,43 +1958,86 @@ int batch_args(mm_batch *b, void *const *m_ptrs, const double *Ms, double A, dou
     return MM_OK;
 }
 
-template <typename T>
-int batch_zfwd(mm_batch *b) {
-    for (const BGroup &g : b->gz) {
-        if (g.L) HIPCK(launch_zfwd_ct_b<T>(b->d_zf, g.map, g.tiles, g.L, SRC_MS_M, b->stream));
-        else HIPCK(launch_zfwd_batch<T>(b->d_zf, g.map, g.tiles, g.nthr, SRC_MS_M, g.lds, b->stream));
+// Launch the groups of one pass.  With fan-out, the groups (which touch
+// disjoint geometries) are spread over `stream` and up to kSide side streams,
+// the heaviest first onto the least loaded stream (tiles as the measure of
+// work), after an event that forks the side streams from `stream`, and
+// `stream` waits for every side stream's join event before the next pass; in
+// a captured graph this makes them parallel branches.
+template <class F>
+int batch_pass(mm_batch *b, const std::vector<BGroup> &gs, const F &launch) {
+    int ng = 0;
+    for (const BGroup &g : gs) ng += g.tiles > 0;
+    if (!b->fanout || ng < 2) {
+        for (const BGroup &g : gs) HIPCK(launch(g, b->stream));
+        return MM_OK;
+    }
+    if (!b->fork) {
+        HIPCK(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (int k = 0; k < mm_batch::kSide; ++k) {
+            HIPCK(hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking));
+            HIPCK(hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming));
+        }
+    }
+    const int nl = std::min(ng, 1 + mm_batch::kSide);
+    std::vector<int> order;
+    for (int i = 0; i < (int)gs.size(); ++i)
+        if (gs[i].tiles > 0) order.push_back(i);
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gs[x].tiles > gs[y].tiles; });
+    std::vector<long long> load(nl, 0);
+    std::vector<int> lane(gs.size(), 0);
+    for (int i : order) {
+        const int l = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        lane[i] = l;
+        load[l] += gs[i].tiles;
+    }
+    HIPCK(hipEventRecord(b->fork, b->stream));
+    for (int l = 1; l < nl; ++l) HIPCK(hipStreamWaitEvent(b->side[l - 1], b->fork, 0));
+    for (int i : order) HIPCK(launch(gs[i], lane[i] ? b->side[lane[i] - 1] : b->stream));
+    for (int l = 1; l < nl; ++l) {
+        HIPCK(hipEventRecord(b->join[l - 1], b->side[l - 1]));
+        HIPCK(hipStreamWaitEvent(b->stream, b->join[l - 1], 0));
     }
     return MM_OK;
+}
+
+template <typename T>
+int batch_zfwd(mm_batch *b) {
+    return batch_pass(b, b->gz, [&](const BGroup &g, hipStream_t s) {
+        if (g.L) return launch_zfwd_ct_b<T>(b->d_zf, g.map, g.tiles, g.L, SRC_MS_M, s);
+        return launch_zfwd_batch<T>(b->d_zf, g.map, g.tiles, g.nthr, SRC_MS_M, g.lds, s);
+    });
 }
 
 template <typename T>
 int batch_zinv(mm_batch *b, const ZInvArgs *d, int epi) {
-    for (const BGroup &g : b->gz) {
-        if (g.L) HIPCK(launch_zinv_ct_b<T>(d, g.map, g.tiles, g.L, epi, b->stream));
-        else HIPCK(launch_zinv_batch<T>(d, g.map, g.tiles, g.nthr, epi, g.lds, b->stream));
-    }
-    return MM_OK;
+    return batch_pass(b, b->gz, [&](const BGroup &g, hipStream_t s) {
+        if (g.L) return launch_zinv_ct_b<T>(d, g.map, g.tiles, g.L, epi, s);
+        return launch_zinv_batch<T>(d, g.map, g.tiles, g.nthr, epi, g.lds, s);
+    });
 }
 
 template <typename T>
-hipError_t batch_x_group(mm_batch *b, const BGroup &g, int dir) {
+hipError_t batch_x_group(mm_batch *b, const BGroup &g, int dir, hipStream_t s) {
     const LinePass *d = dir < 0 ? b->d_lpf : b->d_lpi;
-    if (g.L) return launch_line_var_b<T>(d, g.map, g.tiles, g.L, g.W, dir, g.var, b->stream);
-    return launch_line_pass<T>(d, g.map, g.tiles, g.nthr, g.lds, dir, false, b->stream);
+    if (g.L) return launch_line_var_b<T>(d, g.map, g.tiles, g.L, g.W, dir, g.var, s);
+    return launch_line_pass<T>(d, g.map, g.tiles, g.nthr, g.lds, dir, false, s);
 }
 
 template <typename T>
-hipError_t batch_y_group(mm_batch *b, const BGroup &g) {
-    if (g.L) return launch_fused_var_b<T>(b->d_fp, g.map, g.tiles, g.L, g.var, b->stream);
-    return launch_fused_y<T>(b->d_fp, g.map, g.tiles, g.nthr, g.lds, b->stream);
+hipError_t batch_y_group(mm_batch *b, const BGroup &g, hipStream_t s) {
+    if (g.L) return launch_fused_var_b<T>(b->d_fp, g.map, g.tiles, g.L, g.var, s);
+    return launch_fused_y<T>(b->d_fp, g.map, g.tiles, g.nthr, g.lds, s);
 }
 
 template <typename T>
 int batch_xyx(mm_batch *b) {
-    for (const BGroup &g : b->gxf) HIPCK(batch_x_group<T>(b, g, -1));
-    for (const BGroup &g : b->gy) HIPCK(batch_y_group<T>(b, g));
-    for (const BGroup &g : b->gxi) HIPCK(batch_x_group<T>(b, g, +1));
-    return MM_OK;
+    int rc;
+    if ((rc = batch_pass(b, b->gxf, [&](const BGroup &g, hipStream_t s) { return batch_x_group<T>(b, g, -1, s); })))
+        return rc;
+    if ((rc = batch_pass(b, b->gy, [&](const BGroup &g, hipStream_t s) { return batch_y_group<T>(b, g, s); })))
+        return rc;
+    return batch_pass(b, b->gxi, [&](const BGroup &g, hipStream_t s) { return batch_x_group<T>(b, g, +1, s); });
 }
 
 template <typename T>
@@ -2119,7 +2173,7 @@ int batch_autotune(mm_batch *b, int mode) {
             for (int v : cand) {
                 if ((rc = apply(v))) break;
                 float ms = 0.f;
-                if ((rc = time3(b->stream, ev.a, ev.b, [&] { return batch_x_group<T>(b, g, d == 0 ? -1 : +1); }, &ms))) break;
+                if ((rc = time3(b->stream, ev.a, ev.b, [&] { return batch_x_group<T>(b, g, d == 0 ? -1 : +1, b->stream); }, &ms))) break;
                 if (ms < best) { best = ms; bestv = v; }
             }
             if (!rc) rc = apply(bestv);
@@ -2145,7 +2199,7 @@ int batch_autotune(mm_batch *b, int mode) {
         for (int v : cand) {
             g.var = v;
             float ms = 0.f;
-            if ((rc = time3(b->stream, ev.a, ev.b, [&] { return batch_y_group<T>(b, g); }, &ms))) break;
+            if ((rc = time3(b->stream, ev.a, ev.b, [&] { return batch_y_group<T>(b, g, b->stream); }, &ms))) break;
             if (ms < best) { best = ms; bestv = v; }
         }
         g.var = bestv;
@@ -2178,6 +2232,7 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
     mm_batch *b = new (std::nothrow) mm_batch();
     if (!b) return fail(MM_ENOMEM, "batch allocation");
     b->count = count; b->prec = precision; b->stream = (hipStream_t)hip_stream;
+    b->fanout = !getenv("MMX_NO_FANOUT");
     int rc = MM_OK;
     for (int g = 0; g < count && !rc; ++g) {
         mm_plan *p = nullptr;
