@@ -238,6 +238,49 @@ def test_batch_odd_radix_lengths_against_oracle(prec):
     b.close()
 
 
+def test_batch_groups_side_by_side_match_serial():
+    """The launch groups of a pass run side by side on the batch's internal
+    streams (parallel branches of the step's graph); the same batch with the
+    groups one after the other (MMX_NO_FANOUT at creation) gives bit-identical
+    fields and steps, through the graph and through direct launches, on 16
+    uneven geometries of the sweep recipe (several groups per pass)."""
+    import os
+    import torch
+    from paper_2606_01114_amd import Batch
+    geo = synth.batch_geometries(4)[:16]
+    grids = [g for g, _ in geo]
+    Ms = [ms for _, ms in geo]
+    m0 = [to_dev(rounded(synth.random_unit(g, 300 + k), torch.float32), torch.float32) for k, g in enumerate(grids)]
+    outs = []
+    old = os.environ.get("MMX_NO_FANOUT")
+    try:
+        for serial in (False, True):
+            if serial:
+                os.environ["MMX_NO_FANOUT"] = "1"
+            else:
+                os.environ.pop("MMX_NO_FANOUT", None)
+            b = Batch(grids, [D] * len(grids), "f32", padding="ct")
+            groups = b.schedule()["groups"]
+            assert sum(g["pass"] == "x_fwd" for g in groups) >= 3, groups
+            hs = [h.clone() for h in b.h_eff(m0, Ms, A)]
+            ms = [x.clone() for x in m0]
+            b.llg_step(ms, Ms, A, ALPHA, GAMMA, DT, n_steps=2)
+            md = [x.clone() for x in m0]
+            b.llg_step(md, Ms, A, ALPHA, GAMMA, DT, n_steps=2, graph=False)
+            torch.cuda.synchronize()
+            outs.append((hs, ms, md))
+            b.close()
+    finally:
+        if old is None:
+            os.environ.pop("MMX_NO_FANOUT", None)
+        else:
+            os.environ["MMX_NO_FANOUT"] = old
+    for k in range(len(grids)):
+        for part in range(3):
+            assert torch.equal(outs[0][part][k], outs[1][part][k]), (k, part)
+    _say("batch side by side: %d geometries bit-identical to the serial order" % len(grids))
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_batch_wide_x_tiles_against_oracle(prec):
     """A batch whose x lines are 2048 and 1024 points long runs the grouped
