@@ -53,7 +53,7 @@ PASS_NAMES = ["z_fwd", "x_fwd", "y_fused", "x_inv", "z_inv_stage", "z_inv_heff"]
 KERNEL_PATTERNS = {
     "z_fwd": [r"k_zfwd_ct<float", r"k_zfwd<float"],
     "x_fwd": [r"k_line_(ct|hx)<float, \d+, -1,", r"k_line_pass<float, -1, false>"],
-    "y_fused": [r"k_fused_y_(ct|cr|hx|pf|pt)<float", r"k_fused_y<float"],
+    "y_fused": [r"k_fused_y_(ct|cr|hx|pf|pt|h2)<float", r"k_fused_y<float"],
     "x_inv": [r"k_line_(ct|hx)<float, \d+, 1,", r"k_line_pass<float, 1, false>"],
     "z_inv_stage": [r"k_zinv_ct<float, \d+, 1,", r"k_zinv<float, 1>"],
     "z_inv_heff": [r"k_zinv_ct<float, \d+, 0,", r"k_zinv<float, 0>"],
@@ -62,7 +62,7 @@ KERNEL_SYMBOL = {"z_fwd": "k_zfwd_ct", "x_fwd": "k_line_ct", "y_fused": "k_fused
                  "z_inv_stage": "k_zinv_ct", "z_inv_heff": "k_zinv_ct"}
 # y pass variant (mm_plan_info tiles[2]) -> kernel; negative: runtime-planned
 Y_SYMBOL = {0: "k_fused_y_ct", 1: "k_fused_y_hx", 2: "k_fused_y_cr", 3: "k_fused_y_pf", 4: "k_fused_y_pf",
-            5: "k_fused_y_pt"}
+            5: "k_fused_y_pt", 6: "k_fused_y_h2"}
 
 
 def pass_bytes(grid, L, r):

@@ -35,7 +35,7 @@
  * Threading: a plan is not thread-safe; distinct plans are independent.
  *
  * Test hooks (environment, read at plan creation; every choice computes the
- * same result): MMX_XVAR=0..3 and MMX_YVAR=0..5 force an x or y pass variant
+ * same result): MMX_XVAR=0..3 and MMX_YVAR=0..6 force an x or y pass variant
  * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
  * pass, MMX_ORDER="x:4,5,5;y:2,3,3,5" sets the radix order of runtime-planned
  * (non-power-of-two) axes, MMX_TEST_FAIL_ALLOC makes every device
@@ -265,7 +265,9 @@ int mm_plan_set_stt(mm_plan *plan, double j, double P, double lambda, double eps
  * LDS-resident pencil with the waves' butterflies rotated per workgroup, 3
  * the persistent kernel with the next pencil's loads in flight, 4 the same
  * held to three waves per SIMD, 5 the persistent kernel with its twiddles
- * read from a table of the Ly roots of unity in LDS; -W: the runtime-planned
+ * read from a table of the Ly roots of unity in LDS, 6 the pencil split
+ * into its even and odd half-spectra, run one after the other through an LDS
+ * pencil of Ly/2 positions (Ly 1024 to 4096); -W: the runtime-planned
  * kernel with W pencils per tile. */
 int mm_plan_info(const mm_plan *plan, int64_t L[3], size_t *device_bytes, int tiles[5]);
 

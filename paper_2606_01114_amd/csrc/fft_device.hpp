@@ -48,6 +48,21 @@ template <> __device__ __forceinline__ float2 buf_load<float2>(BufRsrc r, uint32
 template <> __device__ __forceinline__ double2 buf_load<double2>(BufRsrc r, uint32_t off) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
+// non-temporal forms (streaming hint: the line is not kept in the caches
+// for reuse), for data a kernel touches once
+template <typename C> __device__ __forceinline__ C buf_load_nt(BufRsrc r, uint32_t off);
+template <> __device__ __forceinline__ float2 buf_load_nt<float2>(BufRsrc r, uint32_t off) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 2));
+}
+template <> __device__ __forceinline__ double2 buf_load_nt<double2>(BufRsrc r, uint32_t off) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2));
+}
+__device__ __forceinline__ void buf_store_nt(BufRsrc r, uint32_t off, float2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 2);
+}
+__device__ __forceinline__ void buf_store_nt(BufRsrc r, uint32_t off, double2 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, 2);
+}
 __device__ __forceinline__ void buf_store(BufRsrc r, uint32_t off, float2 v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
 }

@@ -67,8 +67,12 @@ __device__ __forceinline__ C stage_tw(const C *__restrict__ tw, const C *__restr
     }
 }
 
-// One stage.  IN: 0 = from the loader, 1 = from LDS; OUT: 0 = to the storer,
-// 1 = to LDS.  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
+// One stage.  IN: 0 = from the loader, 1 = from LDS, 2 = from the loader
+// with the thread's butterfly round u and input index r as well
+// (ld(u, r, line, pos)); OUT: 0 = to the storer,
+// 1 = to LDS, 2 = to the storer with the thread's butterfly round u and
+// output index r as well (st(u, r, line, pos, C), so that a caller can keep
+// the outputs in a register array).  ld(line, pos) -> C; st(line, pos, C).  Butterfly b maps to
 // line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB: groups of LA lines
 // are interleaved (LA = NL: all lines; LA = 3: the components of one cell
 // column).  P = LDS pitch of a line.  PR = 1: the line's upper half
@@ -103,7 +107,11 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
             const int line = b % LA + LA * (b / (LA * NB)), j = (b / LA) % NB;
             const int sj = line * P + sw<L>(j);
 #pragma unroll
-            for (int r = 0; r < RI; ++r) v[u][r] = IN ? lds[sj + swc<L>(r * NB)] : ld(line, j + r * NB);
+            for (int r = 0; r < RI; ++r) {
+                if constexpr (IN == 1) v[u][r] = lds[sj + swc<L>(r * NB)];
+                else if constexpr (IN == 2) v[u][r] = ld(u, r, line, j + r * NB);
+                else v[u][r] = ld(line, j + r * NB);
+            }
             if (Ns > 1) {
                 const int k = j % Ns;
                 const C *tt = t + k * (R - 1);
@@ -117,7 +125,7 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
             PDft<R, DIR, PR, C>::run(v[u]);
         }
     }
-    if (IN && OUT) __syncthreads();
+    if (IN == 1 && OUT == 1) __syncthreads();
     // the offset form of the swizzle holds for the output block d + r Ns when
     // Ns is a multiple of 16 or a power of two with a power-of-two radix;
     // otherwise (the stage after an odd radix in reversed order) each slot
@@ -132,12 +140,13 @@ __device__ __forceinline__ void eng_stage_la(cplx<T> *lds, const cplx<T> *__rest
             const int sd = line * P + sw<L>(d);
 #pragma unroll
             for (int r = 0; r < RO; ++r) {
-                if (OUT) lds[WOFF ? sd + swc<L>(r * Ns) : line * P + sw<L>(d + r * Ns)] = v[u][r];
+                if constexpr (OUT == 1) lds[WOFF ? sd + swc<L>(r * Ns) : line * P + sw<L>(d + r * Ns)] = v[u][r];
+                else if constexpr (OUT == 2) st(u, r, line, d + r * Ns, v[u][r]);
                 else st(line, d + r * Ns, v[u][r]);
             }
         }
     }
-    if (OUT) __syncthreads();
+    if (OUT == 1) __syncthreads();
 }
 
 // ---- register-resident transform with half-line LDS exchanges -------------

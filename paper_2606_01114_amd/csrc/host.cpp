@@ -417,6 +417,13 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
         tw.push_back((T)cosl(ang));
         tw.push_back((T)sinl(ang));
     }
+    // stage-ordered tables of Ly/2 (forward, then reversed order) for the
+    // fused pass in two half-spectra
+    size_t ohalf = 0;
+    if (fused_pf_available(Ly, 6)) {
+        ohalf = app(make_fft(Ly / 2, false));
+        (void)app(make_fft(Ly / 2, true));
+    }
     const size_t oz = app(p->fz);
     p->tw_off[0] = ox; p->tw_off[1] = oy; p->tw_off[2] = oz;
     // folded z transform (compile-time Lz): table of length Lz/2, then exp(-2 pi i k / Lz), k <= Lz/2
@@ -484,19 +491,24 @@ int setup_plan(mm_plan *p, const mm_plan_opts *o) {
     for (int w : {8, 4, 2, 1}) {
         if (w <= std::max(1, npen) && (size_t)3 * w * py * csz <= kLdsTarget && fft_threads(p->fy.d, 3 * w, 3 * w * Ly) <= 1024) { Wp = w; break; }
     }
-    p->y_ct = fused_ct_threads(Ly, csz) > 0 && fused_ct_lds(Ly, csz) <= kLdsMax && !getenv("MMX_NO_CT");
-    if (p->y_ct && getenv("MMX_YVAR")) {
+    // a y length whose LDS pencil does not fit one workgroup runs as two
+    // half-spectra (variant 6, half the LDS) where that kernel has it
+    const bool y_full = fused_ct_lds(Ly, csz) <= kLdsMax;
+    const bool y_half = fused_pf_available(Ly, 6) && fused_ct_lds(Ly / 2, csz) <= kLdsMax;
+    p->y_ct = fused_ct_threads(Ly, csz) > 0 && (y_full || y_half) && !getenv("MMX_NO_CT");
+    if (p->y_ct && !y_full) p->y_var = 6;
+    if (p->y_ct && y_full && getenv("MMX_YVAR")) {
         const int v = atoi(getenv("MMX_YVAR"));
         if ((v == 1 && fused_hx_threads(Ly) > 0) || fused_pf_available(Ly, v)) p->y_var = v;
     }
     if (p->y_ct) Wp = 1;
-    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy; q.roots = twc + oroots;
+    q.data = p->S2; q.tensor = p->tensor; q.tw = twc + oy; q.roots = twc + oroots; q.twh = ohalf ? twc + ohalf : nullptr;
     q.n = (int)ny; q.Lx = Lx; q.Ly = Ly; q.hz = p->hz; q.hxp = p->hx; q.hyp = p->hy;
     q.npos = npen; q.W = Wp; q.tiles = (npen + Wp - 1) / Wp;
     q.pitch = p->y_ct ? Ly + 1 : py;
     q.nthr = p->y_ct ? fused_ct_threads(Ly, csz) : fft_threads(p->fy.d, 3 * Wp, 3 * Wp * Ly);
     q.f = p->fy.d;
-    p->lds_fp = p->y_ct ? fused_ct_lds(Ly, csz) : (size_t)3 * Wp * q.pitch * csz;
+    p->lds_fp = p->y_ct ? fused_ct_lds(y_full ? Ly : Ly / 2, csz) : (size_t)3 * Wp * q.pitch * csz;
     if (p->lds_fp > kLdsMax) return fail(MM_ENOTSUP, "y length %d too long for one workgroup", Ly);
     // z passes: P positions (even) per tile, about 512 cells per tile
     ZGeom &z = p->zg;
@@ -613,10 +625,11 @@ hipError_t launch_y(mm_plan *p) {
 }
 
 // the fused y pass variants a plan of y length Ly can run
-std::vector<int> y_variants(int Ly) {
+std::vector<int> y_variants(int Ly, size_t csz) {
+    if (fused_ct_lds(Ly, csz) > kLdsMax) return fused_pf_available(Ly, 6) ? std::vector<int>{6} : std::vector<int>{};
     std::vector<int> v{0};
     if (fused_hx_threads(Ly) > 0) v.push_back(1);
-    for (int k = 2; k <= 5; ++k)
+    for (int k = 2; k <= 6; ++k)
         if (fused_pf_available(Ly, k)) v.push_back(k);
     return v;
 }
@@ -826,7 +839,7 @@ int autotune_x(mm_plan *p, int mode) {
 // and persistent (next pencil's loads in flight) pencil kernels.
 template <typename T>
 int autotune_y(mm_plan *p, int mode) {
-    const std::vector<int> cand = y_variants((int)p->L[1]);
+    const std::vector<int> cand = y_variants((int)p->L[1], 2 * p->rsz);
     if (!p->y_ct || cand.size() < 2) return MM_OK;
     const std::string key = tune_key(p->device, p->prec, "y_fused", (int)p->L[1], (long long)p->fp.npos * p->L[1]);
     std::string got;
@@ -2254,7 +2267,9 @@ int mm_batch_create(mm_batch **out, int count, const int64_t (*grids)[3], const 
                                   line_hx_lds((int)p->L[0], W, csz) <= kLdsMax ? 3 : 0;
             if (p->x_var[0] != v || p->x_var[1] != v) rc = configure_x(p, v);
         }
-        // grouped y launches have variants 0..2
+        // grouped y launches have variants 0..2, with the whole pencil in LDS
+        if (!rc && p->y_ct && fused_ct_lds((int)p->L[1], 2 * p->rsz) > kLdsMax)
+            rc = fail(MM_ENOTSUP, "y length %d: no grouped kernel holds its pencil", (int)p->L[1]);
         if (!rc && (!getenv("MMX_YVAR") || p->y_var > 2)) p->y_var = 0;
     }
     std::vector<LinePass> lf, li;

@@ -849,6 +849,87 @@ __global__ void __launch_bounds__(NT) k_fused_y_pt(const FusedPass a) {
     }
 }
 
+// ---- fused y pass in two half-spectra --------------------------------------
+// The upper half of each y line is zero and only the lower half of the result
+// is kept, so the Ly-point convolution splits exactly into two of Ly/2
+// points: the even frequencies ky = 2m are the Ly/2-point DFT of x_n, the odd
+// ones ky = 2m+1 the Ly/2-point DFT of w^n x_n (w = exp(-2 pi i / Ly)), and
+// each kept output is the even half's Ly/2-point inverse plus w^-n times the
+// odd half's.  A workgroup runs the two halves one after the other through an
+// LDS pencil of Ly/2 positions (half the LDS of k_fused_y_ct, so that more
+// pencils share a CU).  The first stage's inputs stay in registers for the
+// odd half and the even half's outputs until the odd half's are added, so the
+// pencil is read and written once.  Those reads and writes carry the
+// streaming hint: the caches then keep the tensor row, which both halves read
+// (and the neighbouring pencil, kx -> Lx - kx, after them).
+template <typename T, int L, int H> struct HalfProduct {
+    PencilProduct<T, L> pr;
+    __device__ __forceinline__ void operator()(int m, cplx<T> &x, cplx<T> &y, cplx<T> &z) const { pr(2 * m + H, x, y, z); }
+};
+
+template <typename T, int L, int NT, int H, int U, int R, int UI, int RI>
+__device__ __forceinline__ void h2_half(cplx<T> *lds, const FusedPass &a, const BufRsrc &rp, const PencilProduct<T, L> &pr,
+                                        cplx<T> (&acc)[U][R], cplx<T> (&xin)[UI][RI], int tid) {
+    using C = cplx<T>;
+    constexpr int M = L / 2;
+    constexpr int NS = ct::nst(M);
+    const C *twh = reinterpret_cast<const C *>(a.twh);
+    const C *twhr = twh + (M - 1);
+    const C *roots = reinterpret_cast<const C *>(a.roots);
+    auto ld = [&](int u, int r, int c, int pos) -> C {
+        if constexpr (H == 0) {
+            xin[u][r] = buf_load_nt<C>(rp, (uint32_t)(pos * 3 + c) * sizeof(C));
+            return xin[u][r];
+        } else {
+            return cmul(xin[u][r], roots[pos]);
+        }
+    };
+    auto nost = [](int, int, C) {};
+    auto nold = [](int, int) { return C(); };
+    eng_stage<T, M, false, 0, -1, NT, 3, 2, 1>(lds, twh, tid, ld, nost);
+    eng_mid<T, M, false, 1, NS - 1, -1, NT, 3>(lds, twh, tid);
+    HalfProduct<T, L, H> hp{pr};
+    conv_middle<T, M, NT>(lds, twh, tid, hp);
+    eng_mid<T, M, true, 1, NS - 1, +1, NT, 3>(lds, twhr, tid);
+    auto st = [&](int u, int r, int c, int pos, C v) {
+        if constexpr (H == 0) acc[u][r] = v;
+        else buf_store_nt(rp, (uint32_t)(pos * 3 + c) * sizeof(C), cadd(acc[u][r], cmul(cconj(roots[pos]), v)));
+    };
+    eng_stage<T, M, true, NS - 1, +1, NT, 3, 1, 2>(lds, twhr, tid, nold, st);
+}
+
+// 2048 points: held to three waves per SIMD, i.e. three 52 KB pencils of 256
+// threads per CU in FP64
+template <typename T, int L, int NT>
+__global__ void __launch_bounds__(NT, L == 2048 ? 3 : 1) k_fused_y_h2(const FusedPass a) {
+    using C = cplx<T>;
+    constexpr int M = L / 2;
+    constexpr int NS = ct::nst(M);
+    static_assert(ct::is_pow2(L) && NS >= 2, "two or more radix stages per half-spectrum");
+    // outputs per thread of the last inverse stage (reversed radix order)
+    constexpr int RL = ct::prad(M, true, NS - 1);
+    constexpr int UL = (3 * (M / RL) + NT - 1) / NT;
+    // inputs per thread of the first forward stage
+    constexpr int R0 = ct::prad(M, false, 0);
+    constexpr int U0 = (3 * (M / R0) + NT - 1) / NT;
+    extern __shared__ __align__(16) unsigned char smem[];
+    C *lds = reinterpret_cast<C *>(smem);
+    const int tid = (int)threadIdx.x;
+    const int p = (int)xcd_tile(blockIdx.x, gridDim.x);
+    const int n = a.n;
+    const int kz = p / a.Lx, kx = pair_kx(p - kz * a.Lx, a.Lx);
+    C *pen = reinterpret_cast<C *>(a.data) + ((int64_t)kz * a.Lx + kx) * (3 * n);
+    // rows past n (the zero padding) read as zero and are not written
+    const BufRsrc rp = make_rsrc(pen, (uint32_t)(3 * n) * sizeof(C));
+    const PencilProduct<T, L> pr = pencil_product<T, L>(a, kz, kx);
+    C acc[UL][RL];
+    C xin[U0][R0];
+    h2_half<T, L, NT, 0>(lds, a, rp, pr, acc, xin, tid);
+    // the even half's last stage has finished reading LDS
+    __syncthreads();
+    h2_half<T, L, NT, 1>(lds, a, rp, pr, acc, xin, tid);
+}
+
 // ---------------- launchers -------------------------------------------------
 template <typename T>
 hipError_t launch_line_pass(const LinePass *d_descs, const int2 *d_map, int tiles, int nthr, size_t lds_bytes,
@@ -1078,9 +1159,11 @@ hipError_t launch_fused_pt_k(const FusedPass &a, hipStream_t s) {
 // variant 4: the persistent kernel with 256 threads held to three waves per
 // SIMD (2048-point FP32 pencils)
 // variant 5: k_fused_y_pt (persistent, twiddles from a root table in LDS)
+// variant 6: k_fused_y_h2 (two half-spectra through an LDS pencil of Ly/2)
 int fused_pf_available(int L, int var) {
     if (var == 2) return L >= 256 && L <= 4096 && (L & (L - 1)) == 0 && fused_ct_threads(L, 8) > 64;
     if (var == 4) return L == 2048;
+    if (var == 6) return L == 1024 || L == 2048 || L == 4096;
     return (var == 3 || var == 5) && (L == 1024 || L == 2048);
 }
 
@@ -1101,6 +1184,20 @@ hipError_t launch_fused_pf(const FusedPass &a, int var, hipStream_t s) {
         return hipGetLastError();
     }
     constexpr bool F32 = sizeof(T) == 4;
+    if (var == 6) {
+        if (!a.twh) return hipErrorInvalidValue;
+        const size_t lds = fused_ct_lds(a.f.L / 2, sizeof(cplx<T>));
+#define HCASE2(LL, NTT)                                                                                               \
+    case LL:                                                                                                          \
+        hipLaunchKernelGGL((k_fused_y_h2<T, LL, NTT>), dim3(a.npos), dim3(NTT), lds, s, a);                         \
+        break;
+        switch (a.f.L) {
+            HCASE2(1024, 128) HCASE2(2048, 256) HCASE2(4096, (F32 ? 256 : 384))
+        default: return hipErrorInvalidValue;
+        }
+#undef HCASE2
+        return hipGetLastError();
+    }
     if (var == 5) {
         if (a.f.L == 2048) return launch_fused_pt_k<T, 2048, (F32 ? 256 : 384), false>(a, s);
         if (a.f.L == 1024) return launch_fused_pt_k<T, 1024, 256, true>(a, s);

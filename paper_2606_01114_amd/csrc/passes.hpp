@@ -33,6 +33,8 @@ struct FusedPass {
     const void *tensor;        // [kz][kx'][ky'][6], pre-scaled, kx' <= Lx/2, ky' <= Ly/2
     const void *tw;
     const void *roots;         // exp(-2 pi i m / Ly), m < Ly (compile-time Ly)
+    const void *twh;           // stage-ordered tables of length Ly/2, forward then reversed radix order
+                               // (compile-time Ly with a half-spectrum kernel; else null)
     int n;                     // rows present along y (ny)
     int Lx, Ly, hz, hxp, hyp;  // hxp = Lx/2+1, hyp = Ly/2+1
     int npos;                  // pencils = hz*Lx

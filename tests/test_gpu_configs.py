@@ -484,15 +484,18 @@ def test_longest_specialised_lengths(n, Lset):
     ref_s = oracle.rk4_step(m0, Ms, A, D, oct_, L, ALPHA, GAMMA, DT)
     for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
         dt = torch.float32 if prec == "f32" else torch.float64
-        if prec == "f64" and L[1] == 4096:
-            # a 4096-long FP64 pencil of three components exceeds the LDS
-            from paper_2606_01114_amd._lib import MM_ENOTSUP, MMError
-            with pytest.raises(MMError) as ei:
-                DemagPlan(n, D, prec, padding="smooth", L=Lset)
-            assert ei.value.code == MM_ENOTSUP
-            continue
         plan = DemagPlan(n, D, prec, padding="smooth", L=Lset)
         assert tuple(plan.info()["L"]) == L
+        if prec == "f64" and L[1] == 4096:
+            # a 4096-long FP64 pencil of three components exceeds the LDS:
+            # it runs as two half-spectra of 2048 points (y variant 6), and a
+            # batch, whose grouped kernels hold the whole pencil, refuses it
+            assert plan.info()["tiles"][2] == 6
+            from paper_2606_01114_amd import Batch
+            from paper_2606_01114_amd._lib import MM_ENOTSUP, MMError
+            with pytest.raises(MMError) as ei:
+                Batch([n], [D], prec)
+            assert ei.value.code == MM_ENOTSUP
         if Lset:
             # the lengths with an odd radix run the compile-time kernels
             sch = plan.schedule()
@@ -513,17 +516,19 @@ def test_longest_specialised_lengths(n, Lset):
         plan.close()
 
 
-@pytest.mark.parametrize("n", [(6, 128, 3), (5, 256, 2), (4, 512, 2), (3, 1024, 2), (40, 600, 6), (200, 512, 8)])
+@pytest.mark.parametrize("n", [(6, 128, 3), (5, 256, 2), (4, 512, 2), (3, 1024, 2), (40, 600, 6), (200, 512, 8),
+                               (2, 2048, 2)])
 def test_y_pass_variants_against_oracle(n):
     """Every specialised y pass, selected with MMX_YVAR at plan creation: the
     LDS-resident pencil (0), the register-resident one with half-line
-    exchanges (1), the LDS-resident pencil with rotated waves (2) and the
+    exchanges (1), the LDS-resident pencil with rotated waves (2), the
     persistent kernel with the next pencil's loads in flight (3; 4: held to
-    three waves per SIMD; 5: with its twiddles from a root table in LDS),
-    for every
+    three waves per SIMD; 5: with its twiddles from a root table in LDS) and
+    the pencil split into its even and odd half-spectra (6), for every
     length each has (a variant a length lacks leaves the default in place),
-    FP32 and FP64, against the oracle's h_eff; the persistent kernel's
-    grid walks more pencils than it has workgroups."""
+    FP32 (1e-5) and FP64 with the oracle's tensor held (1e-12), against the
+    oracle's h_eff; the persistent kernel's grid walks more pencils than it
+    has workgroups."""
     import os
     import torch
     from paper_2606_01114_amd import DemagPlan
@@ -533,16 +538,22 @@ def test_y_pass_variants_against_oracle(n):
     ref = oracle.h_eff(m0, MS, A, D, oct_, L)
     old = os.environ.get("MMX_YVAR")
     try:
-        for var in (0, 1, 2, 3, 4, 5):
+        for var in (0, 1, 2, 3, 4, 5, 6):
             os.environ["MMX_YVAR"] = str(var)
-            for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+            for prec, tol in (("f32", 1e-5), ("f64", 1e-12)):
                 dt = torch.float32 if prec == "f32" else torch.float64
                 plan = DemagPlan(n, D, prec)
+                if prec == "f64":
+                    plan.tensor_set(oct_)
                 Ly = plan.info()["L"][1]
                 has = {0: Ly & (Ly - 1) == 0, 1: Ly in (256, 512, 1024, 2048), 2: Ly in (512, 1024, 2048, 4096),
-                       3: Ly in (1024, 2048), 4: Ly == 2048, 5: Ly in (1024, 2048)}[var]
+                       3: Ly in (1024, 2048), 4: Ly == 2048, 5: Ly in (1024, 2048), 6: Ly in (1024, 2048, 4096)}[var]
+                # a whole 4096-point FP64 pencil exceeds the LDS: only the
+                # half-spectrum kernel runs it
+                full = not (prec == "f64" and Ly == 4096)
+                has = has and (full or var == 6)
                 yv = plan.info()["tiles"][2]
-                assert yv == (var if has else 0), (var, Ly, yv)
+                assert yv == (var if has else (0 if full else 6)), (var, Ly, yv)
                 h = plan.h_eff(to_dev(rounded(m0, dt), dt), MS, A)
                 e = rel_l2(h.cpu().numpy(), ref)
                 _say("y variant", var, prec, n, e)
