@@ -224,6 +224,20 @@ def test_set_stt_rejects_bad_arguments_on_host():
     assert L.mm_plan_set_stt(None, 1e11, 0.4, 1.0, 0.0, 1e-9, pv) == _lib.MM_EINVAL
 
 
+def test_longest_y_lines_on_host():
+    """An FP64 y line of 4096 points (whose whole three-component pencil
+    would need 209 KB of LDS) is planned as two half-spectra of 2048 points;
+    y lines of 8192 points are refused in either precision (no GPU)."""
+    from paper_2606_01114_amd import _lib
+    o = _lib.PlanOpts()
+    _lib.lib().mm_plan_opts_default(ctypes.byref(o))
+    o.pow2_padding = 1
+    for prec in (_lib.MM_F32, _lib.MM_F64):
+        rc, t, _ = _bytes((4, 2048, 3), prec, ctypes.byref(o))
+        assert rc == _lib.MM_OK and t == 5 * 2049 * 5 * 6 * (4 if prec == _lib.MM_F32 else 8)
+        assert _bytes((4, 4096, 3), prec, ctypes.byref(o))[0] == _lib.MM_ENOTSUP
+
+
 def test_automatic_padding_on_host():
     """The default padding takes the shortest compile-time length (powers of
     two: x, y 4096, z and an FP64 y 2048; one odd radix: x, y 96 ... 1792,
