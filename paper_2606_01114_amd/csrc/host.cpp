@@ -913,6 +913,14 @@ int set_order(mm_plan *p, int a, const std::vector<int> &o) {
     if ((int)tw.size() != 2 * (L - 1)) return fail(MM_EINVAL, "radix order does not factor L=%d", L);
     cplx<T> *base = reinterpret_cast<cplx<T> *>(p->twT) + p->tw_off[a];
     HIPCK(hipMemcpy(base, tw.data(), tw.size() * sizeof(T), hipMemcpyHostToDevice));
+    // the FP64 table of the tensor transforms (x, y, z tables of L-1 entries
+    // each) follows the new order too, so that a later mm_demag_tensor_set
+    // builds the spectrum with matching descriptors and twiddles
+    const std::vector<double> tw64 = round_tw<double>(h);
+    size_t off64 = 0;
+    for (int b = 0; b < a; ++b) off64 += (size_t)std::max<int64_t>(p->L[b] - 1, 0);
+    HIPCK(hipMemcpy(reinterpret_cast<double2 *>(p->tw64) + off64, tw64.data(), tw64.size() * sizeof(double),
+                    hipMemcpyHostToDevice));
     p->order[a] = o;
     if (a == 0) {
         p->fx = h;

@@ -368,8 +368,10 @@ def test_gradient_small_against_oracle_adjoint():
     gfin = np.zeros(n + (3,))
     gfin[..., 2] = 1.0 / np.prod(n)
     _, gref, mref = oracle.rk4_run_grad_Ms(m0, Ms, A, D, oct_, L, ALPHA, GAMMA, DT, steps, gfin)
-    assert rel_l2(mT.detach().cpu().numpy() - m0, mref - m0) <= 1e-10
-    assert rel_l2(Mst.grad.cpu().numpy(), gref) <= 1e-9
+    em = rel_l2(mT.detach().cpu().numpy() - m0, mref - m0)
+    eg = rel_l2(Mst.grad.cpu().numpy(), gref)
+    _say("20-step run rel-L2 %.3e, gradient rel-L2 %.3e" % (em, eg))
+    assert em <= 1e-12 and eg <= 1e-12
 
 
 def test_gradient_c5_against_fd():
@@ -416,15 +418,16 @@ def test_x_pass_variants_against_oracle():
     half-LDS kernel on tiles twice as wide (3, lines of 1024 and 2048
     points), with ragged last tiles, and both tile widths of the 640-point
     line with a radix-5 stage and the 768-point line with a radix-3 stage,
-    FP32 and FP64, against the oracle's h_eff."""
+    FP32 (1e-5) and FP64 with the oracle's tensor held (1e-12), against the
+    oracle's h_eff."""
     import os
     import torch
     from paper_2606_01114_amd import DemagPlan
-    cases = [((64, 500, 16), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-9))),
-             ((300, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 0, 1e-9), ("f64", 1, 1e-9))),
-             ((350, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 1, 1e-9))),
-             ((480, 40, 3), (("f32", 3, 1e-5), ("f64", 3, 1e-9), ("f32", 2, 1e-5))),
-             ((1024, 8, 2), (("f32", 3, 1e-5), ("f64", 3, 1e-9)))]
+    cases = [((64, 500, 16), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f32", 2, 1e-5), ("f64", 2, 1e-12))),
+             ((300, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 0, 1e-12), ("f64", 1, 1e-12))),
+             ((350, 40, 3), (("f32", 0, 1e-5), ("f32", 1, 1e-5), ("f64", 1, 1e-12))),
+             ((480, 40, 3), (("f32", 3, 1e-5), ("f64", 3, 1e-12), ("f32", 2, 1e-5))),
+             ((1024, 8, 2), (("f32", 3, 1e-5), ("f64", 3, 1e-12)))]
     old = os.environ.get("MMX_XVAR")
     try:
         for n, runs in cases:
@@ -435,6 +438,8 @@ def test_x_pass_variants_against_oracle():
                 os.environ["MMX_XVAR"] = str(var)
                 dt = torch.float32 if prec == "f32" else torch.float64
                 plan = DemagPlan(n, D, prec)
+                if prec == "f64":
+                    plan.tensor_set(oct_)
                 info = plan.info()
                 L = tuple(info["L"])
                 if ref is None:
@@ -471,8 +476,9 @@ def test_longest_specialised_lengths(n, Lset):
     (radix 3: x 1536, y 768, z 768 folded to 384, x and y 384, 96, 192;
     radix 5: 160, 320, 640, 1280; radix 7: 224, 448, 896, 1792 on x and y;
     z 96 ... 896, folded to half that length)
-    and a long non-power-of-two x line (runtime planned), FP32 and FP64,
-    h_eff and one RK4 step against the oracle."""
+    and a long non-power-of-two x line (runtime planned), FP32 (1e-5) and
+    FP64 with the oracle's tensor held (1e-12), h_eff and one RK4 step
+    against the oracle."""
     import torch
     from paper_2606_01114_amd import DemagPlan
     oct_ = oracle.tensor_octant(n, D)
@@ -482,9 +488,11 @@ def test_longest_specialised_lengths(n, Lset):
     _say("long lengths", n, L)
     ref_h = oracle.h_eff(m0, Ms, A, D, oct_, L)
     ref_s = oracle.rk4_step(m0, Ms, A, D, oct_, L, ALPHA, GAMMA, DT)
-    for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+    for prec, tol in (("f32", 1e-5), ("f64", 1e-12)):
         dt = torch.float32 if prec == "f32" else torch.float64
         plan = DemagPlan(n, D, prec, padding="smooth", L=Lset)
+        if prec == "f64":
+            plan.tensor_set(oct_)
         assert tuple(plan.info()["L"]) == L
         if prec == "f64" and L[1] == 4096:
             # a 4096-long FP64 pencil of three components exceeds the LDS:
@@ -591,7 +599,8 @@ def _factors(L):
 def test_radix_orders_against_oracle():
     """Runtime-planned transforms in every radix order (MMX_ORDER): all 12
     orders of the 90-point y line (2,3,3,5) and both orders of the 14-point x
-    and 10-point z lines, FP32 and FP64, h_eff against the oracle; then a plan
+    and 10-point z lines, FP32 (1e-5) and FP64 with the oracle's tensor held
+    (1e-12), h_eff against the oracle; then a plan
     that searches the orders itself (autotune "search") reports permutations
     of each length's radices and matches the oracle too."""
     import itertools
@@ -609,9 +618,11 @@ def test_radix_orders_against_oracle():
         runs = [("y", o) for o in orders] + [("x", (7, 2)), ("z", (5, 2))]
         for ax, o in runs:
             os.environ["MMX_ORDER"] = "%s:%s" % (ax, ",".join(map(str, o)))
-            for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+            for prec, tol in (("f32", 1e-5), ("f64", 1e-12)):
                 dt = torch.float32 if prec == "f32" else torch.float64
                 plan = DemagPlan(n, D, prec, padding="smooth")
+                if prec == "f64":
+                    plan.tensor_set(oct_)
                 L = plan.info()["L"]
                 if ref is None:
                     assert L == (14, 90, 10), L
@@ -627,9 +638,11 @@ def test_radix_orders_against_oracle():
             os.environ.pop("MMX_ORDER", None)
         else:
             os.environ["MMX_ORDER"] = old
-    for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+    for prec, tol in (("f32", 1e-5), ("f64", 1e-12)):
         dt = torch.float32 if prec == "f32" else torch.float64
         plan = DemagPlan(n, D, prec, padding="smooth", autotune="search")
+        if prec == "f64":
+            plan.tensor_set(oct_)
         sch = plan.schedule()
         for ax, Lv in zip("xyz", (14, 90, 10)):
             assert sorted(int(v) for v in sch["radix_order"][ax].split(",")) == sorted(_factors(Lv)), sch
@@ -645,7 +658,8 @@ def test_batch_kernel_variants_against_oracle(xv, yv):
     both x tile widths, the half-LDS and wide half-LDS x kernels; the
     LDS-resident, register-resident and wave-rotated fused y kernels) over
     geometries with x lines of 2048, 1024 and 256 points and y lines of 128
-    to 1024 points, FP32 and FP64, h_eff against the oracle."""
+    to 1024 points, FP32 (1e-5) and FP64 with the oracle's tensors held
+    (1e-12), h_eff against the oracle."""
     import os
     import torch
     from paper_2606_01114_amd import Batch
@@ -658,9 +672,12 @@ def test_batch_kernel_variants_against_oracle(xv, yv):
     saved = {k: os.environ.get(k) for k in ("MMX_XVAR", "MMX_YVAR")}
     try:
         os.environ["MMX_XVAR"], os.environ["MMX_YVAR"] = str(xv), str(yv)
-        for prec, tol in (("f32", 1e-5), ("f64", 1e-9)):
+        for prec, tol in (("f32", 1e-5), ("f64", 1e-12)):
             dt = torch.float32 if prec == "f32" else torch.float64
             b = Batch(grids, [D] * len(grids), prec)
+            if prec == "f64":
+                for k in range(len(grids)):
+                    b.tensor_set(k, octs[k])
             sch = b.schedule()["groups"]
             xs = {g["variant"] for g in sch if g["pass"] in ("x_fwd", "x_inv") and g["specialised"]}
             _say("batch variants", xv, yv, prec, [(g["pass"], g["L"], g["variant"], g["W"]) for g in sch])
