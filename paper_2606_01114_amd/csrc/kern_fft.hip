@@ -109,17 +109,9 @@ __device__ __forceinline__ void line_ct_body(const LinePass &a, int tile) {
     const BufRsrc ro = make_rsrc(out, (uint32_t)(n_out - 1) * orow + (uint32_t)(a.inner - c0) * sizeof(C));
     // columns past the tile's width (last tile of a row) are loaded from the
     // next row or as zero and never stored
-    // the inverse pass reads and writes with the streaming hint (every byte
-    // is touched once; measured 3-5% faster, the forward pass no faster)
-    auto ld = [&](int line, int pos) -> C {
-        const uint32_t off = (uint32_t)pos * ir + (uint32_t)line * sizeof(C);
-        if constexpr (DIR > 0) return buf_load_nt<C>(ri, off);
-        else return buf_load<C>(ri, off);
-    };
+    auto ld = [&](int line, int pos) -> C { return buf_load<C>(ri, (uint32_t)pos * ir + (uint32_t)line * sizeof(C)); };
     auto st = [&](int line, int pos, C v) {
-        const uint32_t off = (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff);
-        if constexpr (DIR > 0) buf_store_nt(ro, off, v);
-        else buf_store(ro, off, v);
+        buf_store(ro, (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff), v);
     };
     // forward: input rows n_in <= L/2; inverse: output rows n_out <= L/2
     eng_fft<T, L, false, DIR, NT, W, DIR < 0 ? 1 : 2>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
@@ -153,17 +145,9 @@ __device__ __forceinline__ void line_hx_body(const LinePass &a, int tile) {
     C *out = reinterpret_cast<C *>(a.out) + (int64_t)o * a.out_outer + c0;
     const BufRsrc ri = make_rsrc(in, (uint32_t)(a.n_in - 1) * ir + (uint32_t)(a.inner - c0) * sizeof(C));
     const BufRsrc ro = make_rsrc(out, (uint32_t)(a.n_out - 1) * orow + (uint32_t)(a.inner - c0) * sizeof(C));
-    // the inverse pass reads and writes with the streaming hint (every byte
-    // is touched once; measured 3-5% faster, the forward pass no faster)
-    auto ld = [&](int line, int pos) -> C {
-        const uint32_t off = (uint32_t)pos * ir + (uint32_t)line * sizeof(C);
-        if constexpr (DIR > 0) return buf_load_nt<C>(ri, off);
-        else return buf_load<C>(ri, off);
-    };
+    auto ld = [&](int line, int pos) -> C { return buf_load<C>(ri, (uint32_t)pos * ir + (uint32_t)line * sizeof(C)); };
     auto st = [&](int line, int pos, C v) {
-        const uint32_t off = (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff);
-        if constexpr (DIR > 0) buf_store_nt(ro, off, v);
-        else buf_store(ro, off, v);
+        buf_store(ro, (uint32_t)pos * orow + (line < wc ? (uint32_t)line * sizeof(C) : kBufOff), v);
     };
     eng_fft_hx<T, L, DIR, NT, W, DIR < 0 ? 1 : 2>(lds, reinterpret_cast<const C *>(a.tw), (int)threadIdx.x, ld, st);
 }
