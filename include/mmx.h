@@ -451,7 +451,9 @@ int mm_demag_spectrum_get(mm_plan *plan, double *host_spectrum);
  * them back before the next pass (parallel branches of the graph), so every
  * call stays ordered on the caller's stream.  opts NULL selects power-of-two
  * padding; opts->autotune times every kernel variant of each launch group
- * (forward and inverse x separately) on the batch's own buffers.
+ * (forward and inverse x separately) on the batch's own buffers.  A geometry
+ * whose whole three-component y pencil exceeds the LDS (FP64 y length 4096,
+ * which single plans run as two half-spectra) is refused with MM_ENOTSUP.
  *   grids[count][3], cells[count][3]: host arrays
  *   m_ptrs[count]: host array of device pointers, each (nx,ny,nz,3)
  *   h_ptrs[count]: host array of device pointers for mm_batch_h_eff
