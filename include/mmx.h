@@ -39,7 +39,8 @@
  * (see mm_plan_info), MMX_NO_CT selects the runtime-planned kernels for every
  * pass, MMX_ORDER="x:4,5,5;y:2,3,3,5" sets the radix order of runtime-planned
  * (non-power-of-two) axes, MMX_TEST_FAIL_ALLOC makes every device
- * allocation fail (MM_ENOMEM), MMX_NO_FANOUT runs a batch's launch groups of
+ * allocation fail (MM_ENOMEM), MMX_NO_I32 keeps 64-bit cell indices in the
+ * compile-time z-inverse kernels, MMX_NO_FANOUT runs a batch's launch groups of
  * one pass one after the other on its stream instead of side by side.  The
  * autotuner reads MMX_AUTOTUNE and
  * MMX_AUTOTUNE_CACHE (mm_plan_opts.autotune).

@@ -224,6 +224,7 @@ struct mm_plan {
     ZGeom zg{};
     size_t lds_fwd = 0, lds_inv = 0, lds_fp = 0, lds_z = 0;
     bool x_ct = false, y_ct = false, z_ct = false;   // power-of-two specialised kernels in use
+    bool i32 = false;          // the compile-time z-inverse kernels may index cells and S1 in 32 bits
     int y_var = 0;                                   // specialised y pass: 0 LDS-resident pencil, 1 register-resident
     int x_var[2] = {0, 0};                          // variants of the forward / inverse x pass (0, 1: tile widths; 2: half-LDS; 3: half-LDS, wide tiles)
     int tiles_fwd = 0, tiles_inv = 0;
@@ -1029,6 +1030,7 @@ hipError_t zinv_any(mm_plan *p, const ZInvArgs &a, int epi) {
 void fill_common(mm_plan *p, ZInvArgs &a, unsigned terms, const void *Ms, double Ms_s, double A) {
     std::memset(&a, 0, sizeof a);
     a.g = p->zg;
+    a.i32 = p->i32 ? 1 : 0;
     a.terms = terms;
     a.Ms = Ms; a.Ms_scalar = Ms_s;
     a.ex_pref = 2.0 * A / kMu0;
@@ -1424,6 +1426,13 @@ int demag_tensor_init(mm_plan **out, const int64_t grid[3], const double cell[3]
     p->P = o.far_radius;
     for (int a = 0; a < 3; ++a) { p->n[a] = grid[a]; p->d[a] = cell[a]; p->L[a] = L[a]; }
     rc = precision == MM_F32 ? setup_plan<float>(p, &o) : setup_plan<double>(p, &o);
+    // 32-bit indices: 3 values per cell and 3 complex values per (kz, x, y)
+    // of S1 below 2^31 (MMX_NO_I32: test hook keeping 64-bit indices)
+    {
+        const uint64_t cells = (uint64_t)grid[0] * grid[1] * grid[2];
+        const uint64_t s1 = (uint64_t)p->hz * grid[0] * grid[1];
+        p->i32 = 3 * cells < (uint64_t(1) << 31) && 3 * s1 < (uint64_t(1) << 31) && !getenv("MMX_NO_I32");
+    }
     if (!rc) rc = compute_tensor(p);
     const int tm = tune_mode(o.autotune);
     if (!rc && tm) rc = precision == MM_F32 ? autotune_x<float>(p, tm) : autotune_x<double>(p, tm);

@@ -108,6 +108,7 @@ struct ZInvArgs {
     // last stage writes the solution m_n + dt sum_j tab_a[j] k_j (renormalised
     // when renorm) to cand and the per-block max over cells and components of
     // |dt sum_j tab_e[j] k_j| to epart[2 blk]
+    int i32;                   // every cell and S1 index fits in a signed 32-bit int (compile-time z kernels)
     int tab_s, tab_last;
     double tab_a[8], tab_e[8];   // weights of the earlier stages j < tab_s
     double tab_as, tab_es;       // weights of this stage's own derivative

@@ -27,11 +27,11 @@ constexpr int zthreads(int N) { return 256; }
 // unfold: X[k] = E[k] + W^k O[k], E = (Z[k] + conj Z[N-k])/2, O = (Z[k] - conj Z[N-k])/(2i),
 // W = exp(-2 pi i / 2N); since E[N-k] = conj E[k] and O[N-k] = conj O[k], one
 // pair (Z[k], Z[N-k]) gives X[k] and X[N-k].  Written to S1 [kz][pos][c].
-template <typename T, int N, int NT, int NL, int PT>
+template <typename T, int N, int NT, int NL, int PT, typename I = int64_t>
 __device__ __forceinline__ void zunfold_store(const cplx<T> *lds, const ZGeom &g, int64_t pos0, int w3,
                                               const cplx<T> *__restrict__ wt, int tid) {
     using C = cplx<T>;
-    const int64_t npos3 = (int64_t)g.nx * g.ny * 3;
+    const I npos3 = (I)g.nx * (I)g.ny * 3;
     C *S1 = reinterpret_cast<C *>(g.S1) + pos0 * 3;
     const T h = T(0.5);
     constexpr int NE = (N / 2 + 1) * NL;
@@ -106,21 +106,21 @@ __device__ __forceinline__ void zfwd_ct_body(const ZFwdArgs &a, uint32_t tile) {
 // loads are issued before either's arithmetic.  The demag field sample z of
 // component c sits in line 3 pl + c, slot z/2, real part for even z; the next
 // stage's source is written back to the same place.
-template <typename T, int N, int EPI, bool MSV, bool LOC>
+template <typename T, int N, int EPI, bool MSV, bool LOC, typename I>
 __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int64_t pos0, int ncells, bool demag,
                                            Acc4 &acc, int tid) {
     constexpr int NT = zthreads(N), PT = zpitch(N);
     const ZGeom &g = a.g;
     const int nz = g.nz, ny = g.ny;
-    auto where = [&](int e, int &pl, int &z, int64_t &cell, int &i, int &j) {
+    auto where = [&](int e, int &pl, int &z, I &cell, int &i, int &j) {
         pl = (int)fdiv((uint32_t)e, g.dnz);
         z = e - pl * nz;
-        const int64_t pos = pos0 + pl;
+        const I pos = (I)pos0 + (I)pl;
         i = (int)fdiv((uint32_t)pos, g.dny);
-        j = (int)(pos - (int64_t)i * ny);
-        cell = pos * nz + z;
+        j = (int)(pos - (I)i * (I)ny);
+        cell = pos * (I)nz + (I)z;
     };
-    auto finish = [&](int pl, int z, const CellIn<T> &in) {
+    auto finish = [&](int pl, int z, const CellIn<T, I> &in) {
         T hd[3] = {T(0), T(0), T(0)};
         if (demag) {
 #pragma unroll
@@ -137,9 +137,9 @@ __device__ __forceinline__ void zepi_cells(const ZInvArgs &a, cplx<T> *lds, int6
         const int e1 = e0 + NT;
         const bool two = e1 < ncells;
         int pl0, z0, i0, j0, pl1 = 0, z1 = 0, i1 = 0, j1 = 0;
-        int64_t c0, c1 = 0;
+        I c0, c1 = 0;
         where(e0, pl0, z0, c0, i0, j0);
-        CellIn<T> in0, in1;
+        CellIn<T, I> in0, in1;
         cell_load<T, EPI, MSV, LOC>(a, c0, i0, j0, z0, in0);
         if (two) {
             where(e1, pl1, z1, c1, i1, j1);
@@ -183,7 +183,8 @@ __device__ __forceinline__ void ztile(const ZGeom &g, int P, uint32_t blk, int64
     wp = min(P, g.ny - yb * P);
 }
 
-template <typename T, int N, int EPI, bool LOC>
+// I: type of the cell and S1 indices (int when they fit, see CellIn)
+template <typename T, int N, int EPI, bool LOC, typename I = int64_t>
 __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     using C = cplx<T>;
     constexpr int NT = zthreads(N), P = zcols(N), NL = 3 * P, PT = zpitch(N);
@@ -211,7 +212,7 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
         //    real), folded at once:
         //    Z[k] = (X[k] + conj X[N-k]) + i conj(W^k) (X[k] - conj X[N-k])
         //    Loads of CH iterations are issued before their arithmetic.
-        const int64_t npos3 = npos * 3;
+        const I npos3 = (I)npos * 3;
         const C *S1 = reinterpret_cast<const C *>(g.S1) + pos0 * 3;
         constexpr int NE = (N / 2 + 1) * NL;
         constexpr int CH = sizeof(T) == 4 ? 8 : 4;
@@ -223,8 +224,8 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
                 if (e < NE) {
                     const int k = e / NL, l = e - k * NL;
                     const int lc = min(l, w3 - 1);
-                    xk[u] = S1[k * npos3 + lc];
-                    xm[u] = S1[(N - k) * npos3 + lc];
+                    xk[u] = S1[(I)k * npos3 + (I)lc];
+                    xm[u] = S1[(I)(N - k) * npos3 + (I)lc];
                     wk[u] = wt[k];
                     wm[u] = wt[N - k];
                 }
@@ -267,8 +268,8 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
     //    3 pl + c, slot z/2, real part for even z
     Acc4 acc;
     const int ncells = wp * nz;
-    if (a.Ms) zepi_cells<T, N, EPI, true, LOC>(a, lds, pos0, ncells, demag, acc, tid);
-    else zepi_cells<T, N, EPI, false, LOC>(a, lds, pos0, ncells, demag, acc, tid);
+    if (a.Ms) zepi_cells<T, N, EPI, true, LOC, I>(a, lds, pos0, ncells, demag, acc, tid);
+    else zepi_cells<T, N, EPI, false, LOC, I>(a, lds, pos0, ncells, demag, acc, tid);
     if (EPI == EPI_HEFF && a.epart) block_energy(acc.v[0], acc.v[1], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_TAB && a.tab_last) block_max(acc.v[0], reinterpret_cast<double *>(smem), a.epart + 2 * (int64_t)blk, tid);
     if (EPI == EPI_BB) block_bb(acc, reinterpret_cast<double *>(smem), a.bb_part + 4 * (int64_t)blk, tid);
@@ -288,7 +289,7 @@ __device__ __forceinline__ void zinv_ct_body(const ZInvArgs &a, uint32_t blk) {
         auto nold = [](int, int) { return C(); };
         auto nost = [](int, int, C) {};
         eng_fft_la<T, N, -1, NT, NL, 3, PT, 1, 1, HALF ? 1 : 0>(lds, tw, tid, nold, nost);
-        zunfold_store<T, N, NT, NL, PT>(lds, g, pos0, w3, wt, tid);
+        zunfold_store<T, N, NT, NL, PT, I>(lds, g, pos0, w3, wt, tid);
     }
 }
 
@@ -308,10 +309,14 @@ __global__ void __launch_bounds__(zthreads(N)) k_zfwd_ct_b(const ZFwdArgs *__res
 // The FP64 RK4-stage form without local terms is held to three waves per
 // SIMD (168 VGPRs; it spills 20 of its 191 and still runs 7% faster than at
 // two waves); the other forms would spill far more.
-template <typename T, int N, int EPI, bool LOC>
+// I32: cell and S1 indices in 32 bits (the host sets ZInvArgs::i32 when
+// every index fits); used by the RK4-stage forms, whose epilogue it makes
+// 4-5% faster in FP32 (the h_eff form measured no faster, in FP64 slower).
+template <typename T, int N, int EPI, bool LOC, bool I32 = false>
 __global__ void __launch_bounds__(zthreads(N), (sizeof(T) == 8 && EPI == EPI_STAGE && !LOC) ? 3 : 1)
 k_zinv_ct(const ZInvArgs a) {
-    zinv_ct_body<T, N, EPI, LOC>(a, xcd_tile(blockIdx.x, gridDim.x));
+    if constexpr (I32) zinv_ct_body<T, N, EPI, LOC, int>(a, xcd_tile(blockIdx.x, gridDim.x));
+    else zinv_ct_body<T, N, EPI, LOC>(a, xcd_tile(blockIdx.x, gridDim.x));
 }
 
 template <typename T, int N, int EPI>
@@ -334,14 +339,18 @@ hipError_t zinv_launch_n(const ZInvArgs &a, int epi, size_t lds, hipStream_t s) 
     const int tiles = ztile_count(a.g.nx, a.g.ny, zcols(NN), a.g.ygrp);
     const bool loc = a.dmi_kind != 0 || a.ku_pref != 0.0 || a.stt_pref != 0.0;
 #define ZL(E, L) hipLaunchKernelGGL((k_zinv_ct<T, NN, E, L>), dim3(tiles), dim3(zthreads(NN)), lds, s, a)
+#define ZL32(E, L) hipLaunchKernelGGL((k_zinv_ct<T, NN, E, L, true>), dim3(tiles), dim3(zthreads(NN)), lds, s, a)
     if (epi == EPI_HEFF && loc) ZL(EPI_HEFF, true);
     else if (epi == EPI_HEFF) ZL(EPI_HEFF, false);
+    else if (epi == EPI_STAGE && loc && a.i32) ZL32(EPI_STAGE, true);
     else if (epi == EPI_STAGE && loc) ZL(EPI_STAGE, true);
+    else if (epi == EPI_STAGE && a.i32) ZL32(EPI_STAGE, false);
     else if (epi == EPI_STAGE) ZL(EPI_STAGE, false);
     else if (epi == EPI_TAB && loc) ZL(EPI_TAB, true);
     else if (epi == EPI_TAB) ZL(EPI_TAB, false);
     else if (epi == EPI_BB) ZL(EPI_BB, true);
     else ZL(EPI_ADJ, false);
+#undef ZL32
 #undef ZL
     return hipGetLastError();
 }

@@ -15,8 +15,8 @@ __device__ __forceinline__ void cross3(const T a[3], const T b[3], T o[3]) {
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
-template <typename T>
-__device__ __forceinline__ T ms_at(const T *Ms, T Ms_s, int64_t cell) { return Ms ? Ms[cell] : Ms_s; }
+template <typename T, typename I>
+__device__ __forceinline__ T ms_at(const T *Ms, T Ms_s, I cell) { return Ms ? Ms[cell] : Ms_s; }
 
 // Reciprocal and reciprocal square root: the hardware approximations (about
 // one ulp) in FP32, correctly rounded division in FP64.
@@ -43,20 +43,24 @@ struct Acc4 {
 // stages of the largest Butcher tableau the stage epilogue runs (RKF45: 6)
 constexpr int kMaxTabStages = 6;
 
-template <typename T>
+// I: type of the cell index (int64_t, or int when 3 x cells < 2^31 so that
+// every index computation stays in 32 bits; a signed type, whose overflow
+// the compiler may assume away, so that it still merges the three component
+// loads of a cell into one and folds constant offsets)
+template <typename T, typename I = int64_t>
 struct CellIn {
-    int64_t cell;
+    I cell;
     T msi, mi[3], mnb[6][3], msn[6], mn[3], ac[3], gi[3], gnb[6][3], kj[kMaxTabStages - 1][3], mp[3], gp[3];
 };
 
-template <typename T, int EPI, bool MSV, bool LOC = true>
-__device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i, int j, int z, CellIn<T> &in) {
+template <typename T, int EPI, bool MSV, bool LOC = true, typename I>
+__device__ __forceinline__ void cell_load(const ZInvArgs &a, I cell, int i, int j, int z, CellIn<T, I> &in) {
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const int64_t sx = (int64_t)ny * nz, sy = nz;
+    const I sx = (I)ny * (I)nz, sy = (I)nz;
     const bool exch = (a.terms & 2u) != 0 || (LOC && a.dmi_kind != 0);   // both read the six neighbours
     const T *Ms = reinterpret_cast<const T *>(a.Ms);
     const T *mfield = reinterpret_cast<const T *>(EPI == EPI_STAGE || EPI == EPI_TAB ? a.ms_in : a.m);
-    int64_t nc[6];
+    I nc[6];
     nc[0] = i > 0 ? cell - sx : cell;
     nc[1] = i < nx - 1 ? cell + sx : cell;
     nc[2] = j > 0 ? cell - sy : cell;
@@ -120,12 +124,12 @@ __device__ __forceinline__ void cell_load(const ZInvArgs &a, int64_t cell, int i
 
 // hd = demag field at the cell (0 if not requested).  Returns in src_next the
 // next stage's z-transform source Ms * m_next (EPI_STAGE only).
-template <typename T, int EPI, bool MSV, bool LOC = true>
-__device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T> &in, const T hd[3], Acc4 &acc,
+template <typename T, int EPI, bool MSV, bool LOC = true, typename I>
+__device__ __forceinline__ void cell_compute(const ZInvArgs &a, const CellIn<T, I> &in, const T hd[3], Acc4 &acc,
                                              T src_next[3]) {
     const bool exch = (a.terms & 2u) != 0, demag = (a.terms & 1u) != 0;
     const T exp_ = T(a.ex_pref);
-    const int64_t cell = in.cell;
+    const I cell = in.cell;
     const T msi = in.msi;
     const T *mi = in.mi;
     // ---- exchange field (and DMI, eq. (3), added to it for the dynamics)

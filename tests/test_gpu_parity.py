@@ -765,3 +765,44 @@ def test_stream_switch_orders_work():
     torch.cuda.synchronize()
     assert torch.equal(a, b) and torch.equal(hc, hc2)
     plan.close()
+
+
+def test_z_index_widths_agree():
+    """The compile-time RK4-stage z-inverse kernels in 32-bit and 64-bit cell
+    indexing (MMX_NO_I32 at plan creation) give bit-identical RK4 steps
+    (graph replay) and steps with local terms, FP32 and FP64, on a grid with
+    ragged z tiles (h_eff, 64-bit in both, as a control)."""
+    import os
+    import torch
+    from paper_2606_01114_amd import DemagPlan
+    n, d = (37, 29, 6), (2.5e-9, 2e-9, 3e-9)
+    m0 = synth.random_unit(n, 71)
+    Ms = synth.ms_field(n, 72)
+    out = {}
+    old = os.environ.get("MMX_NO_I32")
+    try:
+        for key in ("i32", "i64"):
+            if key == "i64":
+                os.environ["MMX_NO_I32"] = "1"
+            else:
+                os.environ.pop("MMX_NO_I32", None)
+            for prec in ("f32", "f64"):
+                dt = torch.float32 if prec == "f32" else torch.float64
+                plan = DemagPlan(n, d, prec)
+                Msd = to_dev(Ms, dt)
+                h = plan.h_eff(to_dev(m0, dt), Msd, A)
+                m = to_dev(m0, dt)
+                plan.llg_step(m, Msd, A, ALPHA, GAMMA, 2e-14, n_steps=3)
+                plan.set_anisotropy(4e5, (0.0, 0.6, 0.8))
+                m2 = to_dev(m0, dt)
+                plan.llg_step(m2, Msd, A, ALPHA, GAMMA, 2e-14, n_steps=2, graph=False)
+                out[key, prec] = (h.cpu(), m.cpu(), m2.cpu())
+                plan.close()
+    finally:
+        if old is None:
+            os.environ.pop("MMX_NO_I32", None)
+        else:
+            os.environ["MMX_NO_I32"] = old
+    for prec in ("f32", "f64"):
+        for a, b in zip(out["i32", prec], out["i64", prec]):
+            assert torch.equal(a, b), prec
